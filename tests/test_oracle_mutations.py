@@ -1,0 +1,67 @@
+"""The oracle's pins must catch plausible mistakes (CPU only).
+
+Each case plants one mistake in a copy of the oracle's C source, builds it in
+a temporary directory, points the oracle wrapper at it and runs the pin that
+should catch it; the pin must fail.  Nothing here touches the GPU.
+"""
+import ctypes
+import os
+import subprocess
+import tempfile
+
+import pytest
+
+import oracle
+from tests import test_oracle_pins as pins
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "pulda_oracle.c")
+
+MUTATIONS = [
+    # (name, original text, planted mistake, pins that must fail)
+    ("philox_wrong_half", "uint32_t n0 = hi1 ^ c1 ^ k0;", "uint32_t n0 = hi0 ^ c1 ^ k0;",
+     [pins.test_philox_matches_rocrand]),
+    ("vose_residual", "p[g] = (p[g] + p[s]) - 1.0;", "p[g] = p[g] - p[s];",
+     [lambda: pins.test_vose_induced_law("random")]),
+    ("poisson_support_short", "ceil(lam + 10.0 * sqrt(lam) + 10.0)", "ceil(lam + 1.0 * sqrt(lam) + 1.0)",
+     [pins.test_pois_tables_exact_law]),
+    ("gaussian_no_rounding", "floor(lam + sqrt(lam) * g + 0.5)", "floor(lam + sqrt(lam) * g)",
+     [lambda: pins.test_rounded_gaussian_closed_form(150)]),
+    ("prior_rate_inverted", "double e = -log(1.0 - u53(r[0], r[1])) / beta;",
+     "double e = -log(1.0 - u53(r[0], r[1])) * (1.0 / (2.0 * beta));",
+     [pins.test_prior_marks_binomial_and_uniform]),
+    ("prior_marks_overwrite_counted", "if (n[(size_t)pos * V + v] == 0) {", "if (1) {",
+     [pins.test_prior_marks_ignore_counted_cells]),
+    ("no_alpha_part", "double sa = M->sigma_a[v];", "double sa = 0.0;",
+     [lambda: pins.test_token_law_enumeration("overlap")]),
+    ("b_part_transposed", "double b = (double)M->phi[(size_t)k * V + v] * (double)m[k];\n        if (b > 0.0) {\n            c += b;\n            last = k;",
+     "double b = (double)M->phi[(size_t)k * V + (v + 1) % V] * (double)m[k];\n        if (b > 0.0) {\n            c += b;\n            last = k;",
+     [lambda: pins.test_token_law_enumeration("overlap")]),
+    ("token_not_removed", "if (--m[kold] == 0) kd--;", "(void)0;",
+     [pins.test_within_document_chain_stationary_law]),
+    ("loglik_sign", "word -= lgamma((double)nk[k] + Vb);", "word += lgamma((double)nk[k] + Vb);",
+     [pins.test_loglik_independent_evaluation, pins.test_loglik_closed_form_uniform_priors]),
+    ("foldin_theta_no_prior", "theta[k] = (float)(((double)acc[k] / (double)(S - burn_in) + alpha[k])",
+     "theta[k] = (float)(((double)acc[k] / (double)(S - burn_in))",
+     [pins.test_foldin_outputs_definition]),
+    ("normalise_wrong_row", "phi[(size_t)k * V + v] = g > 0 ? (float)((double)g / (double)s) : 0.0f;",
+     "phi[(size_t)k * V + v] = g > 0 ? (float)((double)g / (double)(s + 1)) : 0.0f;",
+     [pins.test_phi_normalise_definition]),
+]
+
+
+@pytest.mark.parametrize("name,old,new,checks", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_pin_catches_mutation(name, old, new, checks, monkeypatch):
+    src = open(SRC).read()
+    assert old in src, name
+    d = tempfile.mkdtemp(prefix="oracle_mut_")
+    c_path = os.path.join(d, "m.c")
+    so_path = os.path.join(d, "m.so")
+    with open(c_path, "w") as f:
+        f.write(src.replace(old, new, 1))
+    subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-o", so_path, c_path, "-lm"])
+    lib = ctypes.CDLL(so_path)
+    oracle._declare(lib)
+    monkeypatch.setattr(oracle, "_lib", lib)
+    for check in checks:
+        with pytest.raises(AssertionError):
+            check()

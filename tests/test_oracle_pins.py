@@ -1,0 +1,504 @@
+"""Pins of the CPU oracle to things other than itself (no GPU).
+
+Each test checks the oracle against what the paper or the mathematics fixes:
+closed forms, exact enumeration, brute force on tiny inputs, or an
+independent implementation (rocRAND's Philox, scipy's special functions).
+The paper prints no worked numeric example for the sampler, so there are no
+paper-value fixtures; see tests/golden/README.md.
+"""
+import math
+import os
+import shutil
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+from scipy import special, stats
+
+import oracle
+
+TWO32 = 4294967296.0
+
+
+def slot_probs(n):
+    """P(mulhi(r, n) = j) for r uniform on 32 bits."""
+    j = np.arange(n + 1, dtype=object)
+    edges = [-((-int(x) * (1 << 32)) // n) for x in j]   # ceil(j 2^32 / n)
+    return np.array([(edges[i + 1] - edges[i]) / TWO32 for i in range(n)])
+
+
+def alias_law(thr, alias, n_out=None):
+    """Exact law of x = (r_b < thr[j]) ? j : alias[j], j = mulhi(r_a, n)."""
+    n = len(thr)
+    ps = slot_probs(n)
+    keep = thr.astype(np.float64) / TWO32
+    out = np.zeros(n_out or n)
+    np.add.at(out, np.arange(n), ps * keep)
+    np.add.at(out, alias, ps * (1.0 - keep))
+    return out
+
+
+def chisq_p(observed, expected, min_expected=5.0):
+    """Chi-square p-value after merging low-expectation cells into one."""
+    observed = np.asarray(observed, float)
+    expected = np.asarray(expected, float)
+    big = expected >= min_expected
+    o = list(observed[big])
+    e = list(expected[big])
+    if (~big).any():
+        o.append(observed[~big].sum())
+        e.append(expected[~big].sum())
+    o, e = np.array(o), np.array(e)
+    e = e * o.sum() / e.sum()
+    chi = ((o - e) ** 2 / e).sum()
+    return stats.chi2.sf(chi, len(o) - 1)
+
+
+# --------------------------------------------------------------------------
+# Philox4x32-10 against rocRAND's independent implementation (run on the host)
+# --------------------------------------------------------------------------
+ROCRAND_PROG = r"""
+#include <rocrand/rocrand_philox4x32_10.h>
+#include <cstdio>
+int main() {
+  unsigned c0, c1, c2, c3, k0, k1;
+  while (scanf("%u %u %u %u %u %u", &c0, &c1, &c2, &c3, &k0, &k1) == 6) {
+    unsigned long long seed = (unsigned long long)k0 | ((unsigned long long)k1 << 32);
+    unsigned long long sub = (unsigned long long)c2 | ((unsigned long long)c3 << 32);
+    /* the engine's offset counts 32-bit outputs (4 per counter step), so it
+       reaches counter words (c0, c1 mod 2^30) directly; the top two bits of
+       c1 are added by skips of 2^61 counter steps (2^63 outputs) each */
+    unsigned long long off = 4ull * ((unsigned long long)c0 | ((unsigned long long)(c1 & 0x3FFFFFFFu) << 32));
+    rocrand_device::philox4x32_10_engine e(seed, sub, off);
+    for (unsigned j = 0; j < 2u * (c1 >> 30); j++) e.discard(1ull << 63);
+    uint4 r = e.next4();
+    printf("%u %u %u %u\n", r.x, r.y, r.z, r.w);
+  }
+  return 0;
+}
+"""
+
+
+def _rocrand_runner():
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc) or not os.path.exists("/opt/rocm/include/rocrand/rocrand_philox4x32_10.h"):
+        pytest.skip("hipcc / rocRAND headers not available")
+    d = tempfile.mkdtemp(prefix="philox_pin_")
+    src = os.path.join(d, "r.cpp")
+    exe = os.path.join(d, "r")
+    with open(src, "w") as f:
+        f.write(ROCRAND_PROG)
+    subprocess.check_call([hipcc, "-x", "hip", "--offload-host-only", "-O1", src, "-o", exe])
+    return exe
+
+
+def test_philox_matches_rocrand():
+    exe = _rocrand_runner()
+    rng = np.random.default_rng(11)
+    cases = [(0, 0, 0, 0, 0, 0), (0xFFFFFFFF,) * 6, (1, 2, 3, 4, 5, 6)]
+    for _ in range(500):
+        cases.append(tuple(int(x) for x in rng.integers(0, 2**32, size=6, dtype=np.uint64)))
+    inp = "\n".join(" ".join(str(x) for x in c) for c in cases) + "\n"
+    out = subprocess.run([exe], input=inp, capture_output=True, text=True, check=True).stdout.split("\n")
+    for c, line in zip(cases, out):
+        want = [int(x) for x in line.split()]
+        got = oracle.philox(c[:4], c[4:]).tolist()
+        assert got == want, (c, got, want)
+
+
+def test_philox_uniform_bytes():
+    vals = np.concatenate([oracle.philox([i, 7, 3, 1], [123, 456]) for i in range(4000)])
+    counts = np.bincount((vals >> 24).astype(np.int64), minlength=256)
+    assert chisq_p(counts, np.full(256, len(vals) / 256)) > 1e-4
+
+
+# --------------------------------------------------------------------------
+# Walker/Vose alias tables: the exact law a table induces equals w / W
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("case", ["random", "heavy", "equal", "single", "zeros", "two"])
+def test_vose_induced_law(case):
+    rng = np.random.default_rng(3)
+    w = {"random": rng.random(300), "heavy": rng.pareto(0.7, 500) + 1e-12, "equal": np.ones(64),
+         "single": np.array([2.5]), "zeros": np.array([0.0, 1.0, 0.0, 3.0, 0.5]),
+         "two": np.array([1e-9, 1.0])}[case]
+    thr, alias = oracle.vose(w)
+    law = alias_law(thr, alias)
+    n = len(w)
+    assert np.max(np.abs(law - w / w.sum())) <= 3 * n / TWO32 + 1e-12
+    # zero-weight entries are never returned
+    zero = w == 0
+    assert np.all(law[zero] <= n / TWO32)
+
+
+# --------------------------------------------------------------------------
+# Poisson(beta + l) tables (Section 3.4) against the Poisson pmf
+# --------------------------------------------------------------------------
+def test_pois_tables_exact_law():
+    beta = 0.01
+    for l in range(1, 101):
+        thr, alias = oracle.pois_table(beta, l)
+        n = len(thr)
+        lam = beta + l
+        assert n == math.ceil(lam + 10 * math.sqrt(lam) + 10) + 1
+        law = alias_law(thr, alias)
+        ref = stats.poisson.pmf(np.arange(n), lam)
+        assert np.max(np.abs(law - ref)) <= 3 * n / TWO32 + 1e-15, l
+        assert stats.poisson.sf(n - 1, lam) < 1e-20
+
+
+def _cells_with_count(l, R, seed=5, t=1):
+    n = np.full((1, R), l, np.int32)
+    return oracle.phi_counts(n, 0.01, 100, seed, t)[0]
+
+
+@pytest.mark.parametrize("l", [1, 7, 100])
+def test_pois_alias_draws_chisq(l):
+    g = _cells_with_count(l, 200000)
+    lam = 0.01 + l
+    xs = np.arange(g.max() + 2)
+    obs = np.bincount(g, minlength=len(xs))[: len(xs)]
+    assert chisq_p(obs, stats.poisson.pmf(xs, lam) * len(g)) > 1e-4
+
+
+@pytest.mark.parametrize("l", [101, 150, 1000, 50000])
+def test_rounded_gaussian_closed_form(l):
+    """l > L: x = max(0, floor(lam + sqrt(lam) g + 1/2)); P(x) from the normal CDF."""
+    g = _cells_with_count(l, 200000, seed=9)
+    lam = 0.01 + l
+    sd = math.sqrt(lam)
+    lo, hi = g.min(), g.max()
+    xs = np.arange(lo, hi + 1)
+    p = stats.norm.cdf((xs + 0.5 - lam) / sd) - stats.norm.cdf((xs - 0.5 - lam) / sd)
+    obs = np.bincount(g - lo, minlength=len(xs))
+    assert chisq_p(obs, p * len(g)) > 1e-4
+    assert abs(g.mean() - lam) < 5 * sd / math.sqrt(len(g))
+
+
+# --------------------------------------------------------------------------
+# Zero-count cells: geometric jumps give iid Bernoulli(1 - e^-beta) marks
+# --------------------------------------------------------------------------
+def test_prior_marks_binomial_and_uniform():
+    beta, K, V = 0.01, 1000, 3000
+    n = np.zeros((K, V), np.int32)
+    g = oracle.phi_counts(n, beta, 100, 21, 4)
+    q = -math.expm1(-beta)
+    nz = g > 0
+    per_col = nz.sum(axis=0)
+    tot = nz.sum()
+    mean = K * V * q
+    assert abs(tot - mean) < 5 * math.sqrt(mean * (1 - q))
+    ks = np.arange(per_col.max() + 1)
+    assert chisq_p(np.bincount(per_col), stats.binom.pmf(ks, K, q) * V) > 1e-4
+    pos_hist = np.bincount(np.nonzero(nz)[0] // 50, minlength=K // 50)
+    assert chisq_p(pos_hist, np.full(K // 50, tot / (K // 50))) > 1e-4
+    # values: zero-truncated Pois(beta)
+    vals = g[nz]
+    xs = np.arange(1, 7)
+    ztp = stats.poisson.pmf(xs, beta) / (-math.expm1(-beta))
+    p2 = ztp[1:].sum()
+    k2 = int((vals >= 2).sum())
+    assert abs(k2 - len(vals) * p2) < 5 * math.sqrt(len(vals) * p2) + 2
+
+
+def test_prior_marks_ignore_counted_cells():
+    """Counted cells keep their own Pois(beta + l) draw; zero cells still mark at rate q."""
+    beta, K, V = 0.01, 1000, 3000
+    n = np.zeros((K, V), np.int32)
+    n[::2, :] = 1
+    g = oracle.phi_counts(n, beta, 100, 33, 2)
+    q = -math.expm1(-beta)
+    zero_cells = g[1::2, :]
+    frac = (zero_cells > 0).mean()
+    cnt = zero_cells.size
+    assert abs(frac - q) < 5 * math.sqrt(q * (1 - q) / cnt)
+    counted = g[::2, :].ravel()
+    xs = np.arange(counted.max() + 1)
+    assert chisq_p(np.bincount(counted), stats.poisson.pmf(xs, beta + 1) * len(counted)) > 1e-4
+
+
+def test_ztp_thresholds():
+    beta = 0.01
+    T = oracle.ztp_thresholds(beta)
+    xs = np.arange(1, 6)
+    cdf = np.cumsum(stats.poisson.pmf(xs, beta)) / stats.poisson.sf(0, beta)
+    assert np.all(np.abs(T / TWO32 - cdf) <= 2.0 / TWO32)
+
+
+# --------------------------------------------------------------------------
+# Whole PPU row: exact finite moments from the hierarchical representation
+# (Section 3.3, proof of the convergence theorem): given pi = sum gamma >= 1,
+# the counts are Multinomial(pi, F), so E x = F, Var x_v = F_v(1-F_v) E[1/pi],
+# Cov = -F_i F_j E[1/pi], with pi ~ Pois(varpi) conditioned on pi >= 1.
+# --------------------------------------------------------------------------
+def test_ppu_row_exact_moments():
+    beta = 0.01
+    row = np.array([0, 1, 1, 3], np.int32)
+    R = 400000
+    n = np.tile(row, (R, 1))
+    g = oracle.phi_counts(n, beta, 100, 77, 3).astype(np.float64)
+    s = g.sum(axis=1)
+    keep = s > 0
+    x = g[keep] / s[keep][:, None]
+    varpi = (row + beta).sum()
+    F = (row + beta) / varpi
+    ps = np.arange(1, 200)
+    e_inv = (stats.poisson.pmf(ps, varpi) / ps).sum() / stats.poisson.sf(0, varpi)
+    assert abs(e_inv - 0.2578) < 5e-3          # far from 1/varpi = 0.198 and the Dirichlet's
+    var = F * (1 - F) * e_inv
+    m = x.mean(axis=0)
+    assert np.all(np.abs(m - F) < 5 * np.sqrt(var / len(x)))
+    dev2 = (x - m) ** 2
+    v_hat = dev2.mean(axis=0)
+    se = dev2.std(axis=0) / np.sqrt(len(x))
+    assert np.all(np.abs(v_hat - var) < 5 * se), (v_hat, var, se)
+    # the bound is tight enough to tell E[1/pi] from 1/varpi on the counted cells
+    assert np.all(np.abs(v_hat[1:] - F[1:] * (1 - F[1:]) / varpi) > 10 * se[1:])
+    cov = np.cov(x[:, 1], x[:, 3])[0, 1]
+    assert abs(cov / (-F[1] * F[3] * e_inv) - 1) < 0.03
+    # conditional on the row sum, the counts are Multinomial(s, F)
+    sel = g[s == 5]
+    keys = [tuple(r) for r in sel.astype(int)]
+    from collections import Counter
+    cnt = Counter(keys)
+    outcomes = sorted(cnt)
+    exp = np.array([stats.multinomial.pmf(o, 5, F) for o in outcomes])
+    allp = sum(stats.multinomial.pmf(o, 5, F) for o in _compositions(5, 4))
+    assert abs(allp - 1) < 1e-12
+    obs = np.array([cnt[o] for o in outcomes])
+    missing = 1 - exp.sum()
+    assert chisq_p(np.append(obs, 0), np.append(exp, missing) * len(sel)) > 1e-4
+
+
+def _compositions(total, parts):
+    if parts == 1:
+        yield (total,)
+        return
+    for i in range(total + 1):
+        for rest in _compositions(total - i, parts - 1):
+            yield (i,) + rest
+
+
+def test_phi_normalise_definition():
+    rng = np.random.default_rng(2)
+    gam = rng.poisson(0.7, size=(7, 50)).astype(np.int32)
+    gam[3] = 0
+    S, phi, empty = oracle.phi_normalise(gam)
+    assert empty == 1 and S[3] == 0 and not phi[3].any()
+    assert np.array_equal(S, gam.sum(axis=1))
+    for k in range(7):
+        if S[k]:
+            ref = (gam[k].astype(np.float64) / S[k]).astype(np.float32)
+            assert np.array_equal(phi[k], ref)
+
+
+# --------------------------------------------------------------------------
+# Per-word a-part tables (Section 3.5): law alpha_k phi_kv / sigma_a
+# --------------------------------------------------------------------------
+def _random_phi(K, V, seed, density=0.3):
+    rng = np.random.default_rng(seed)
+    gam = (rng.random((K, V)) < density) * rng.integers(1, 30, size=(K, V))
+    gam = gam.astype(np.int32)
+    gam[0, :] += 1
+    return oracle.phi_normalise(gam)[1]
+
+
+def test_word_tables_law_and_sigma():
+    K, V = 40, 60
+    phi = _random_phi(K, V, 4)
+    phi[:, 5] = 0           # an empty column
+    alpha = np.linspace(0.05, 0.3, K)
+    wt = oracle.word_tables(alpha, phi)
+    assert wt.colptr[6] == wt.colptr[5]
+    for v in range(V):
+        a, b = wt.colptr[v], wt.colptr[v + 1]
+        ks = np.nonzero(phi[:, v])[0]
+        assert np.array_equal(wt.topic[a:b], ks)
+        if b == a:
+            continue
+        w = alpha[ks] * phi[ks, v].astype(np.float64)
+        assert abs(wt.sigma_a[v] - math.fsum(w)) <= 1e-15 * len(w) * wt.sigma_a[v]
+        slots = np.searchsorted(ks, wt.alias_topic[a:b])
+        law = alias_law(wt.thr[a:b], slots)
+        assert np.max(np.abs(law - w / w.sum())) <= 3 * (b - a) / TWO32 + 1e-12
+
+
+# --------------------------------------------------------------------------
+# One token draw, exhaustively over all 2^24 values of u (Section 3.5):
+# P(z = k) = phi_kv (alpha_k + m_k) / sum_j phi_jv (alpha_j + m_j)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("mcase", ["zero", "overlap", "disjoint", "big"])
+def test_token_law_enumeration(mcase):
+    K, V = 12, 4
+    phi = _random_phi(K, V, 8, density=0.5)
+    alpha = np.full(K, 0.1)
+    wt = oracle.word_tables(alpha, phi)
+    rng = np.random.default_rng(1)
+    for v in range(V):
+        col = phi[:, v].astype(np.float64)
+        if mcase == "zero":
+            m = np.zeros(K, np.int32)
+        elif mcase == "overlap":
+            m = rng.integers(0, 4, K).astype(np.int32)
+        elif mcase == "disjoint":
+            m = np.where(col > 0, 0, 3).astype(np.int32)
+        else:
+            m = rng.integers(0, 3000, K).astype(np.int32)
+        mb, ma = oracle.token_pmf(phi, wt, v, m)
+        a, b = wt.colptr[v], wt.colptr[v + 1]
+        slots = np.searchsorted(wt.topic[a:b], wt.alias_topic[a:b])
+        alaw = np.zeros(K)
+        alaw[wt.topic[a:b]] = alias_law(wt.thr[a:b], slots)
+        got = mb + ma * alaw
+        want = col * (alpha + m)
+        want /= want.sum()
+        assert np.max(np.abs(got - want)) <= 3.0 / 2**24 + 3 * (b - a) / TWO32, (v, got, want)
+        assert abs(ma - (col * alpha).sum() / (col * (alpha + m)).sum()) <= 2.0 / 2**24
+
+
+# --------------------------------------------------------------------------
+# Within-document chain, brute force on a tiny document: with Phi fixed, the
+# sequential Gibbs chain over z_d (m^{-i} semantics) has stationary law
+# p(z_d | w_d, Phi, alpha) propto prod_i phi_{z_i, w_i} prod_k Gamma(alpha_k + m_k).
+# --------------------------------------------------------------------------
+def _tiny_chain_setup():
+    K, V = 3, 4
+    gam = np.array([[5, 1, 0, 2], [1, 4, 3, 0], [2, 2, 2, 6]], np.int32)
+    S, phi, _ = oracle.phi_normalise(gam)
+    alpha = np.array([0.1, 0.5, 0.3])
+    wt = oracle.word_tables(alpha, phi)
+    doc = np.array([0, 1, 2, 3, 1], np.int32)
+    states = np.array(np.meshgrid(*[np.arange(K)] * len(doc), indexing="ij")).reshape(len(doc), -1).T
+    logp = np.zeros(len(states))
+    for s_idx, st in enumerate(states):
+        mk = np.bincount(st, minlength=K)
+        lp = sum(np.log(float(phi[st[i], doc[i]])) if phi[st[i], doc[i]] > 0 else -np.inf
+                 for i in range(len(doc)))
+        logp[s_idx] = lp + special.gammaln(alpha + mk).sum()
+    p = np.exp(logp - logp.max())
+    p /= p.sum()
+    return K, V, phi, alpha, wt, doc, states, p
+
+
+def _state_index(zs, K):
+    idx = np.zeros(len(zs), np.int64)
+    for i in range(zs.shape[1]):
+        idx = idx * K + zs[:, i]
+    return idx
+
+
+def test_within_document_chain_stationary_law():
+    K, V, phi, alpha, wt, doc, states, p = _tiny_chain_setup()
+    R = 40000
+    doc_off = np.arange(R + 1, dtype=np.int64) * len(doc)
+    words = np.tile(doc, R)
+    z = oracle.init_z(len(words), K, 5)
+    for t in range(1, 21):
+        z, deg, _, _ = oracle.z_step(doc_off, words, z, 5, t, phi, wt, K, V)
+        assert deg == 0
+    idx = _state_index(z.reshape(R, len(doc)).astype(np.int64), K)
+    obs = np.bincount(idx, minlength=len(states))
+    assert chisq_p(obs, p * R) > 1e-4
+
+
+def test_foldin_chain_stationary_law():
+    K, V, phi, alpha, wt, doc, states, p = _tiny_chain_setup()
+    R = 20000
+    finals = np.zeros((R, len(doc)), np.int64)
+    for r in range(R):
+        theta, ll, kept, dropped, zf = oracle.foldin(phi, wt, alpha, 9, r, doc, S=12, burn_in=6)
+        finals[r] = zf
+    obs = np.bincount(_state_index(finals, K), minlength=len(states))
+    assert chisq_p(obs, p * R) > 1e-4
+
+
+def test_foldin_outputs_definition():
+    K, V = 10, 30
+    phi = _random_phi(K, V, 12, density=0.4)
+    phi[:, 7] = 0
+    alpha = np.full(K, 0.1)
+    wt = oracle.word_tables(alpha, phi)
+    words = np.array([1, 7, 3, 3, 45, 2, 7, 9, 0], np.int32)  # word 7: empty column; 45: out of range
+    theta, ll, kept, dropped, zf = oracle.foldin(phi, wt, alpha, 3, 17, words, S=20, burn_in=10)
+    assert dropped == 3 and kept == 6
+    assert np.all(zf[[1, 4, 6]] == 0xFFFF)
+    assert abs(theta.astype(np.float64).sum() - 1.0) < 1e-6
+    keep = zf != 0xFFFF
+    zk = zf[keep].astype(np.int64)
+    mk = np.bincount(zk, minlength=K)
+    A = alpha.sum()
+    ref = np.log(phi[zk, words[keep]].astype(np.float64)).sum() + special.gammaln(A) - special.gammaln(kept + A) \
+        + (special.gammaln(mk + alpha) - special.gammaln(alpha))[mk > 0].sum()
+    assert abs(ll - ref) <= 1e-12 * abs(ref)
+
+
+# --------------------------------------------------------------------------
+# Counts (Table 1) and initial state
+# --------------------------------------------------------------------------
+def test_counts_bruteforce_and_invariants():
+    from paper_1704_03581_amd import synth
+    c = synth.small_random(200, 300, 17, 40.0, seed=3)
+    z = oracle.init_z(c.N, c.K, 8)
+    n, nk, m = oracle.counts(c.doc_off, c.words, z, c.K, c.V)
+    ref = np.zeros((c.K, c.V), np.int64)
+    np.add.at(ref, (z.astype(np.int64), c.words.astype(np.int64)), 1)
+    assert np.array_equal(n, ref)
+    assert np.array_equal(n.sum(axis=0), np.bincount(c.words, minlength=c.V))      # sum_k n_kv = c_v
+    assert np.array_equal(m.sum(axis=1), c.lengths())                               # sum_k m_dk = N_d
+    assert np.array_equal(n.sum(axis=1), nk) and np.array_equal(m.sum(axis=0), nk)  # n_k both ways
+    assert nk.sum() == c.N and z.max() < c.K
+
+
+def test_init_uniform():
+    z = oracle.init_z(200000, 20, 4)
+    assert chisq_p(np.bincount(z, minlength=20), np.full(20, 10000.0)) > 1e-4
+
+
+# --------------------------------------------------------------------------
+# Log joint: independent evaluation and a closed form
+# --------------------------------------------------------------------------
+def test_loglik_independent_evaluation():
+    from paper_1704_03581_amd import synth
+    c = synth.small_random(50, 80, 6, 20.0, seed=5)
+    z = oracle.init_z(c.N, c.K, 2)
+    alpha = np.linspace(0.05, 0.5, c.K)
+    beta = 0.03
+    got = oracle.loglik(c.doc_off, c.words, z, alpha, beta, c.K, c.V)
+    n = np.zeros((c.K, c.V))
+    np.add.at(n, (z.astype(int), c.words.astype(int)), 1)
+    nk = n.sum(axis=1)
+    lw = c.K * special.gammaln(c.V * beta) - special.gammaln(nk + c.V * beta).sum() \
+        + (special.gammaln(n[n > 0] + beta) - special.gammaln(beta)).sum()
+    A = alpha.sum()
+    ld = 0.0
+    for d in range(c.D):
+        zz = z[c.doc_off[d]:c.doc_off[d + 1]].astype(int)
+        mk = np.bincount(zz, minlength=c.K)
+        ld += special.gammaln(A) - special.gammaln(len(zz) + A) \
+            + (special.gammaln(mk + alpha) - special.gammaln(alpha))[mk > 0].sum()
+    assert abs(got - (lw + ld)) <= 1e-11 * abs(lw + ld)
+
+
+def test_loglik_closed_form_uniform_priors():
+    """alpha = beta = 1, one topic, V = 2, document (0, 1): p(w|z) = 1/2 * 1/3."""
+    ll = oracle.loglik(np.array([0, 2]), np.array([0, 1]), np.array([0, 0]), np.array([1.0]), 1.0, 1, 2)
+    assert abs(ll - math.log(1.0 / 6.0)) < 1e-14
+
+
+# --------------------------------------------------------------------------
+# The whole sweep on a small corpus: the sparse facts the method relies on
+# --------------------------------------------------------------------------
+def test_sweep_invariants_and_column_nonzeros():
+    from paper_1704_03581_amd import synth
+    c = synth.small_random(300, 400, 30, 60.0, seed=6)
+    s = oracle.Sampler(c.doc_off, c.words, c.K, c.V, seed=3)
+    ll0 = s.loglik()
+    for t in range(1, 6):
+        s.phi_step(t)
+        # expected nonzeros of column v: sum_k (1 - P(Pois(beta + n_kv) = 0))
+        expect = (1 - np.exp(-(s.beta + s.n.astype(np.float64)))).sum()
+        got = (s.gam > 0).sum()
+        assert abs(got - expect) < 5 * math.sqrt(expect)
+        s.z_step(t)
+        assert np.array_equal(s.n.sum(axis=0), np.bincount(c.words, minlength=c.V))
+    assert s.loglik() > ll0
