@@ -1,0 +1,313 @@
+/*
+ * pulda.h -- C ABI of libpulda.so: the Polya-urn partially collapsed Gibbs
+ * sampler for LDA (Terenin, Magnusson, Jonsson, Draper, "Polya Urn Latent
+ * Dirichlet Allocation: a doubly sparse massively parallel sampler",
+ * arXiv 1704.03581), on one AMD Instinct MI355X (gfx950).
+ *
+ * Model and notation (Section 1, Table 1): D documents, vocabulary V, K topics,
+ * N tokens; word type v(i) and topic indicator z_i of token i; n : K x V
+ * topic-word counts; m : D x K document-topic counts; alpha (1 x K) and beta
+ * (symmetric scalar here) the Dirichlet priors.
+ *
+ * One sweep is Algorithm 2 (Section 3):
+ *   Phi-step  phi_k ~ PPU(n_k + beta) for every topic k (Definition of the
+ *             Poisson Polya urn, Section 3.3): gamma_kv ~ Pois(beta + n_kv),
+ *             phi_kv = gamma_kv / sum_v gamma_kv; Pois(beta + l) by Walker alias
+ *             tables for l <= L and by rounded Gaussian draws for l > L
+ *             (Section 3.4);
+ *   z-step    z_i drawn with P(z_i = k) propto phi_{k,v(i)} alpha_k +
+ *             phi_{k,v(i)} m^{-i}_{d,k}, sequentially within each document,
+ *             documents in parallel (Section 3.5: a-part from a per-word
+ *             alias table, b-part summed over the smaller of the document's
+ *             and the word's nonzero topics);
+ *   counts    n and m rebuilt from z (Table 1: statistics of the current
+ *             iteration).
+ *
+ * Random numbers come from Philox4x32-10 (Salmon et al., SC'11) keyed by the
+ * model seed, with counters naming what is drawn (token index and sweep t,
+ * or word, topic and t), so every result is a deterministic function of
+ * (corpus, seed, state, t) and independent of the schedule.
+ *
+ * Conventions for every function below:
+ *  - Every function returns a pulda_status.  Nothing aborts and no C++
+ *    exception crosses the ABI.  pulda_last_error() gives a message for the
+ *    last failure on the calling thread.
+ *  - Argument errors are detected on the host before any launch; the call
+ *    then changes no state (PULDA_ERR_INVALID_ARG).  Calls out of order (a
+ *    z-step before init, a sweep before upload) return PULDA_ERR_STATE.
+ *    HIP failures return PULDA_ERR_DEVICE.
+ *  - "_dev" pointers are device (HBM) pointers owned by the caller; "_host"
+ *    pointers are host memory, read or written before the call returns.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued
+ *    on it and the call returns without waiting, except where a function is
+ *    documented as synchronising (it then waits for that stream).
+ *  - The library allocates no device memory.  A plan (and a fold-in server)
+ *    carves all its device buffers from one caller-owned workspace.
+ *  - One plan must not be used from two threads at the same time; distinct
+ *    plans are independent.
+ */
+#ifndef PULDA_H
+#define PULDA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pulda_status;
+
+enum {
+    PULDA_OK = 0,
+    PULDA_ERR_INVALID_ARG = -1,  /* bad argument; nothing was launched */
+    PULDA_ERR_STATE = -2,        /* call out of order */
+    PULDA_ERR_DEVICE = -3,       /* a HIP call or kernel launch failed */
+    PULDA_ERR_NO_MEMORY = -4,    /* the bound workspace is smaller than required */
+    PULDA_ERR_CAPACITY = -5,     /* fold-in: no free slot or arena space now; retry later */
+    PULDA_ERR_CORPUS = -6        /* corpus content invalid (offsets, word ids, length) */
+};
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char *pulda_last_error(void);
+/* Library version string. */
+const char *pulda_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* Model and plan                                                            */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t K;               /* topics, 1 <= K <= 4096 */
+    int32_t V;               /* vocabulary size, >= 1; K * V < 2^31 */
+    double beta;             /* symmetric prior on each phi_k (Table 1), > 0 */
+    double alpha;            /* symmetric prior on each theta_d, > 0; used when alpha_k is NULL */
+    const double *alpha_k;   /* optional host vector of K priors alpha_k > 0 (copied), or NULL */
+    int32_t L;               /* Poisson alias tables for rates beta + l, 1 <= l <= L (Section 3.4); 1..1000 */
+    uint64_t seed;           /* Philox key */
+} pulda_model_desc;
+
+typedef struct pulda_plan pulda_plan;
+
+/* Create a plan for a corpus of D documents and N tokens (D >= 0, N >= 0,
+ * N < 2^40).  *out receives the plan (host object, freed by
+ * pulda_plan_destroy). */
+pulda_status pulda_plan_create(const pulda_model_desc *desc, int64_t D, int64_t N, pulda_plan **out);
+
+/* Bytes of device workspace the plan needs (256-byte aligned start). */
+pulda_status pulda_plan_workspace_bytes(const pulda_plan *plan, int64_t *bytes);
+
+/* Bind a caller-owned device workspace of `bytes` bytes.  It must stay
+ * allocated and untouched by the caller until the plan is destroyed.
+ * PULDA_ERR_NO_MEMORY if bytes is below pulda_plan_workspace_bytes. */
+pulda_status pulda_plan_bind(pulda_plan *plan, void *workspace_dev, int64_t bytes);
+
+void pulda_plan_destroy(pulda_plan *plan);
+
+/* ------------------------------------------------------------------------ */
+/* Corpus and state                                                          */
+/* ------------------------------------------------------------------------ */
+
+/* Attach the corpus (Section 1): documents as CSR, doc_off_dev[D+1] (int64,
+ * doc_off[0] = 0, non-decreasing, doc_off[D] = N) and words_dev[N] (int32 word
+ * ids in [0, V)); tokens of a document are sampled in this stored order.
+ * Both arrays stay owned by the caller and must stay valid and unmodified
+ * while the plan uses them.  Synchronises: validates the content on the
+ * device (PULDA_ERR_CORPUS for bad offsets, word ids, or a document longer
+ * than 65535 tokens) and orders documents by length for the z-step
+ * schedule. */
+pulda_status pulda_corpus_upload(pulda_plan *plan, const int64_t *doc_off_dev, const int32_t *words_dev,
+                                 void *stream);
+
+/* Initial state: z0_dev[N] (uint16 topics < K, copied) or, with NULL, z_i
+ * uniform on {0..K-1} from Philox counter (i, 0, tag 0).  Rebuilds n. */
+pulda_status pulda_init(pulda_plan *plan, const uint16_t *z0_dev, void *stream);
+
+/* Replace z by z_dev[N] (uint16, < K; copied) and rebuild n: resume from a
+ * checkpoint or teacher-force a state. */
+pulda_status pulda_set_z(pulda_plan *plan, const uint16_t *z_dev, void *stream);
+
+/* Copy z (uint16[N]) into z_dev. */
+pulda_status pulda_get_z(const pulda_plan *plan, uint16_t *z_dev, void *stream);
+
+/* Replace the topic-word counts by n_dev[V*K] (int32 >= 0, word-major:
+ * n[v*K + k]).  Used to build a Phi from counts held elsewhere (a serving
+ * model) without a corpus. */
+pulda_status pulda_set_counts(pulda_plan *plan, const int32_t *n_dev, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Algorithm 2                                                               */
+/* ------------------------------------------------------------------------ */
+
+/* Phi-step of sweep t (t >= 1) from the current counts n: draws gamma, the
+ * row sums S_k, phi = fp32(gamma / S_k) (fp64 quotient), the CSC of Phi's
+ * nonzeros by word, each word's alias table over alpha_k phi_kv and
+ * sigma_a(v) = sum_k alpha_k phi_kv (Sections 3.3-3.5).  A row with S_k = 0
+ * stays empty (the PPU is defined for a nonzero sum only). */
+pulda_status pulda_phi_step(pulda_plan *plan, uint32_t t, void *stream);
+
+/* z-step of sweep t with the current Phi, followed by the count rebuild of
+ * n.  A token whose word has an empty Phi column (0/0 conditional) keeps its
+ * topic and is counted in pulda_sweep_stats.degenerate_tokens. */
+pulda_status pulda_z_step(pulda_plan *plan, uint32_t t, void *stream);
+
+/* n_sweeps sweeps t_first, t_first+1, ...: Phi-step, z-step, and the log
+ * joint of each sweep's state.  If ll_host is non-NULL it receives
+ * n_sweeps values and the call synchronises; otherwise it is asynchronous.
+ * With graph replay enabled (pulda_set_graph) one captured sweep is
+ * replayed with a device-side sweep counter. */
+pulda_status pulda_sweep(pulda_plan *plan, uint32_t t_first, int32_t n_sweeps, double *ll_host, void *stream);
+
+/* Collapsed log joint log p(w | z, beta) + log p(z | alpha) of the current
+ * state (the per-iteration log-posterior trace of Section 4), fp64.
+ * Synchronises. */
+pulda_status pulda_loglik(pulda_plan *plan, double *ll_host, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Counts and Phi export / import                                            */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t *n_colptr_dev;   /* [V+1] */
+    uint16_t *n_topic_dev;   /* [nnz_n] ascending within each word */
+    int32_t *n_count_dev;    /* [nnz_n] */
+    int64_t *nk_dev;         /* [K] n_k = sum_v n_kv */
+    int64_t *m_rowptr_dev;   /* [D+1] */
+    uint16_t *m_topic_dev;   /* [nnz_m] ascending within each document */
+    int32_t *m_count_dev;    /* [nnz_m] */
+} pulda_counts_view;
+
+/* Numbers of nonzeros of n and m for the current z.  Synchronises. */
+pulda_status pulda_counts_sizes(pulda_plan *plan, int64_t *nnz_n, int64_t *nnz_m, void *stream);
+
+/* Write n (CSC by word) and m (CSR by document) of the current z into the
+ * caller's buffers, sized by pulda_counts_sizes.  Synchronises. */
+pulda_status pulda_counts(pulda_plan *plan, const pulda_counts_view *out, void *stream);
+
+/* Dense counts: n_dev[V*K] (int32, word-major) and nk_dev[K] (int64); either
+ * may be NULL. */
+pulda_status pulda_get_counts_dense(pulda_plan *plan, int32_t *n_dev, int64_t *nk_dev, void *stream);
+
+typedef struct {
+    int64_t *colptr_dev;        /* [V+1] */
+    uint16_t *topic_dev;        /* [nnz] ascending within each word */
+    int32_t *gamma_dev;         /* [nnz] Poisson draws (export only; may be NULL) */
+    float *phi_dev;             /* [nnz] */
+    uint32_t *alias_thr_dev;    /* [nnz] keep entry e when r < thr (0xFFFFFFFF: always) */
+    uint16_t *alias_topic_dev;  /* [nnz] topic drawn otherwise */
+    double *sigma_a_dev;        /* [V] */
+    int64_t *S_dev;             /* [K] row sums of gamma (export only; may be NULL) */
+} pulda_phi_view;
+
+/* Number of nonzeros of Phi after the last Phi-step.  Synchronises. */
+pulda_status pulda_phi_nnz(pulda_plan *plan, int64_t *nnz, void *stream);
+/* Write Phi (CSC by word), its alias tables and sigma_a. */
+pulda_status pulda_get_phi(pulda_plan *plan, const pulda_phi_view *out, void *stream);
+/* Load Phi from the caller (e.g. a trained model for fold-in); gamma_dev and
+ * S_dev are ignored.  colptr_dev[V] must not exceed K * V. */
+pulda_status pulda_set_phi(pulda_plan *plan, const pulda_phi_view *in, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Statistics, schedule, graph replay                                        */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t degenerate_tokens;  /* last z-step: tokens with an empty Phi column */
+    int64_t sum_J;              /* last z-step: sum over tokens of min(K_d^{-i}, K_v^Phi) */
+    int64_t sum_A;              /* last z-step: tokens drawn from the a-part */
+    int64_t nnz_phi;            /* last Phi-step */
+    int64_t empty_rows;         /* last Phi-step: topics with S_k = 0 */
+} pulda_sweep_stats;
+
+/* Counters of the last Phi-step and z-step.  Synchronises. */
+pulda_status pulda_stats(pulda_plan *plan, pulda_sweep_stats *out, void *stream);
+
+/* z-step schedule: documents are ordered by decreasing length and split
+ * into n_buckets length buckets; bucket b holds documents with length >=
+ * min_len[b] (min_len decreasing, last 0) and is processed by groups of
+ * group[b] lanes (16, 32 or 64) with docs_per_item[b] documents per work
+ * item (a multiple of 64 / group).  Results do not depend on the schedule
+ * except through fp64 rounding order. */
+pulda_status pulda_set_schedule(pulda_plan *plan, int32_t n_buckets, const int32_t *min_len_host,
+                                const int32_t *group_host, const int32_t *docs_per_item_host);
+pulda_status pulda_get_schedule(const pulda_plan *plan, int32_t cap, int32_t *n_buckets, int32_t *min_len_host,
+                                int32_t *group_host, int32_t *docs_per_item_host);
+
+/* Time each candidate group size on each bucket (z-step at sweep t, reps
+ * repetitions, current Phi) and keep the fastest.  Restores z and n.
+ * Synchronises. */
+pulda_status pulda_autotune(pulda_plan *plan, uint32_t t, int32_t reps, void *stream);
+
+/* Enable (1) or disable (0) replaying a captured sweep in pulda_sweep. */
+pulda_status pulda_set_graph(pulda_plan *plan, int32_t enable);
+
+/* ------------------------------------------------------------------------ */
+/* Fold-in serving (theta inference for new documents against a fixed Phi)  */
+/* ------------------------------------------------------------------------ */
+/* A request is one new document.  Tokens whose word is out of range or has
+ * an empty Phi column are dropped and counted.  The kept tokens start from
+ * topics drawn with Philox counter (p, request_id, 0, tag 4) and run `sweeps`
+ * sweeps of the z-step's token draw with counters (p, request_id, s, tag 5),
+ * p the token's position in the request; the topic counts are averaged over
+ * sweeps after `burn_in`:
+ *   theta_k = (mean m_k + alpha_k) / (kept + sum alpha),
+ * and the log-likelihood of the final state is
+ *   sum_p ln phi[z_p][w_p] + ln Gamma(A) - ln Gamma(kept + A)
+ *   + sum_k [ln Gamma(m_k + alpha_k) - ln Gamma(alpha_k)].
+ * Results depend only on (Phi, seed, request_id, words): they are the same
+ * whether a request runs alone or among others.  request_id must be unique
+ * among requests in flight. */
+typedef struct {
+    int32_t sweeps;       /* >= 1 */
+    int32_t burn_in;      /* 0 <= burn_in < sweeps */
+    int32_t max_slots;    /* requests resident at once */
+    int32_t arena_tokens; /* device token capacity shared by resident requests */
+    int32_t max_len;      /* longest accepted request, <= arena_tokens, <= 65535 */
+    int32_t group;        /* lanes per request: 16, 32 or 64 */
+    uint64_t seed;
+} pulda_foldin_desc;
+
+typedef struct pulda_foldin pulda_foldin;
+
+typedef struct {
+    uint32_t request_id;
+    int32_t kept;
+    int32_t dropped;
+    int32_t pad;
+    double loglik;
+} pulda_foldin_result;
+
+/* Create a server over the plan's current Phi (which it reads; the plan
+ * must outlive the server and its Phi must not change meanwhile). */
+pulda_status pulda_foldin_create(const pulda_plan *model, const pulda_foldin_desc *desc, pulda_foldin **out);
+pulda_status pulda_foldin_workspace_bytes(const pulda_foldin *f, int64_t *bytes);
+pulda_status pulda_foldin_bind(pulda_foldin *f, void *workspace_dev, int64_t bytes);
+void pulda_foldin_destroy(pulda_foldin *f);
+
+/* Admit a request: copies words_host[len] into a free slot's arena region.
+ * PULDA_ERR_CAPACITY when no slot or no contiguous arena space is free now
+ * (the request is not admitted; retry after a poll).  PULDA_ERR_INVALID_ARG
+ * if len > max_len or len < 0. */
+pulda_status pulda_foldin_submit(pulda_foldin *f, uint32_t request_id, const int32_t *words_host, int32_t len,
+                                 void *stream);
+
+/* Advance every resident request by up to `quantum` sweeps in one launch
+ * (asynchronous). */
+pulda_status pulda_foldin_step(pulda_foldin *f, int32_t quantum, void *stream);
+
+/* Collect finished requests (at most cap): results into out[], theta into
+ * theta_host[cap * K] (row j for out[j]); frees their slots.  Synchronises. */
+pulda_status pulda_foldin_poll(pulda_foldin *f, pulda_foldin_result *out, float *theta_host, int32_t cap,
+                               int32_t *n_done, void *stream);
+
+/* Resident and free slot counts. */
+pulda_status pulda_foldin_occupancy(const pulda_foldin *f, int32_t *resident, int32_t *free_slots,
+                                    int32_t *free_tokens);
+
+/* The plain per-document sampler: runs one request alone, all sweeps in one
+ * launch, and waits for it (uses the server's workspace; the server must be
+ * empty).  Same results as the batched path. */
+pulda_status pulda_foldin_run_one(pulda_foldin *f, uint32_t request_id, const int32_t *words_host, int32_t len,
+                                  float *theta_host, pulda_foldin_result *out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PULDA_H */

@@ -70,7 +70,7 @@ def _declare(L):
                             i64p, u16p, u32p, u16p, f64p, i64p]
     L.or_z_step.restype = C.c_int64
     L.or_replay.argtypes = [C.c_int64, C.c_int32, C.c_int32, i64p, i32p, u16p, u16p, C.c_uint64, C.c_uint32,
-                            f32p, i64p, u16p, u32p, u16p, f64p, C.c_double, i64p, f64p, i64p]
+                            f32p, i64p, u16p, u32p, u16p, f64p, C.c_double, i64p, f64p, i64p, i64p, C.c_int64]
     L.or_loglik.argtypes = [C.c_int64, C.c_int32, C.c_int32, i64p, i32p, u16p, f64p, C.c_double]
     L.or_loglik.restype = C.c_double
     L.or_foldin.argtypes = [C.c_int32, C.c_int32, f32p, i64p, u16p, u32p, u16p, f64p, f64p, C.c_uint64,
@@ -195,10 +195,11 @@ def z_step(doc_off, words, z, seed, t, phi, wt, K, V):
     return z, int(deg), int(stats[0]), int(stats[1])
 
 
-def replay(doc_off, words, z_before, z_after, seed, t, phi, wt, K, V, tol=1e-6):
+def replay(doc_off, words, z_before, z_after, seed, t, phi, wt, K, V, tol=1e-6, docs=None):
     """Teacher-forced check of another implementation's z-step.
 
-    Returns dict(agree, ties, bad, degenerate, worst_rel, first_bad)."""
+    Returns dict(agree, ties, bad, degenerate, worst_rel, first_bad).  With
+    ``docs`` only those documents are checked."""
     doc_off = _c(doc_off, np.int64)
     words = _c(words, np.int32)
     zb = _c(z_before, np.uint16)
@@ -207,9 +208,11 @@ def replay(doc_off, words, z_before, z_after, seed, t, phi, wt, K, V, tol=1e-6):
     out = np.zeros(4, np.int64)
     worst = np.zeros(1, np.float64)
     first = np.zeros(1, np.int64)
+    dl = None if docs is None else _c(docs, np.int64)
     lib().or_replay(len(doc_off) - 1, K, V, _p(doc_off, C.c_int64), _p(words, C.c_int32), _p(zb, C.c_uint16),
                     _p(za, C.c_uint16), seed, t, *_model_args(phi, wt), tol, _p(out, C.c_int64),
-                    _p(worst, C.c_double), _p(first, C.c_int64))
+                    _p(worst, C.c_double), _p(first, C.c_int64),
+                    _p(dl, C.c_int64) if dl is not None else None, 0 if dl is None else len(dl))
     return dict(agree=int(out[0]), ties=int(out[1]), bad=int(out[2]), degenerate=int(out[3]),
                 worst_rel=float(worst[0]), first_bad=int(first[0]))
 

@@ -447,20 +447,24 @@ int64_t or_z_step(int64_t D, int32_t K, int32_t V, const int64_t *doc_off, const
 /* that would have produced the other side's topic (its a-part slot with the  */
 /* same r1, r2, or its b-part interval).  out[0] = agreements, out[1] = ties, */
 /* out[2] = other disagreements, out[3] = degenerate tokens; worst[0] =       */
-/* largest relative distance seen among disagreements.                       */
+/* largest relative distance seen among disagreements.  With docs != NULL    */
+/* only the listed documents are checked (each is independent given Phi).     */
 /* ------------------------------------------------------------------------ */
 void or_replay(int64_t D, int32_t K, int32_t V, const int64_t *doc_off, const int32_t *words,
                const uint16_t *z_before, const uint16_t *z_after, uint64_t seed, uint32_t t,
                const float *phi, const int64_t *colptr, const uint16_t *topic, const uint32_t *thr,
                const uint16_t *alias_topic, const double *sigma_a, double tol, int64_t out[4],
-               double worst[1], int64_t *first_bad /* token index or -1 */)
+               double worst[1], int64_t *first_bad /* token index or -1 */,
+               const int64_t *docs, int64_t n_docs /* documents to check; docs == NULL: all D */)
 {
     or_model M = {K, V, phi, colptr, topic, thr, alias_topic, sigma_a};
     int32_t *m = (int32_t *)malloc(sizeof(int32_t) * (size_t)K);
     out[0] = out[1] = out[2] = out[3] = 0;
     worst[0] = 0.0;
     *first_bad = -1;
-    for (int64_t d = 0; d < D; d++) {
+    int64_t nd = docs ? n_docs : D;
+    for (int64_t di = 0; di < nd; di++) {
+        int64_t d = docs ? docs[di] : di;
         memset(m, 0, sizeof(int32_t) * (size_t)K);
         for (int64_t i = doc_off[d]; i < doc_off[d + 1]; i++) m[z_before[i]]++;
         for (int64_t i = doc_off[d]; i < doc_off[d + 1]; i++) {

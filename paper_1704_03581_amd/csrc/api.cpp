@@ -1,0 +1,1060 @@
+// C ABI of libpulda.so (declared in include/pulda.h).
+//
+// Host side of the sampler: argument checks, the workspace layout, the
+// Poisson alias tables of Section 3.4 (built once on the host), the z-step
+// schedule (documents ordered by length, split into length buckets and work
+// items), graph capture of a sweep, and the fold-in server's slot and arena
+// bookkeeping.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/pulda.h"
+#include "internal.h"
+
+using namespace pulda;
+
+namespace {
+
+thread_local std::string g_error;
+
+pulda_status fail(pulda_status code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                               \
+    do {                                                                                            \
+        hipError_t e_ = (expr);                                                                     \
+        if (e_ != hipSuccess) return fail(PULDA_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int64_t ALIGN = 256;
+int64_t align_up(int64_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+// Walker alias table by Vose's method: scaled probabilities p_j = (w_j n) / W
+// (W the ascending sum), work lists of small (p < 1) and large entries in
+// ascending order, first-in first-out; entries never paired keep
+// probability 1 (threshold 0xFFFFFFFF, alias = self).
+void alias_table(const std::vector<double> &w, std::vector<uint32_t> &thr, std::vector<int32_t> &alias)
+{
+    const int32_t n = (int32_t)w.size();
+    double W = 0.0;
+    for (double x : w) W += x;
+    std::vector<double> p(n);
+    std::vector<int32_t> work_small, work_large;
+    work_small.reserve(2 * n);
+    thr.assign(n, 0xFFFFFFFFu);
+    alias.resize(n);
+    for (int32_t j = 0; j < n; ++j) {
+        p[j] = (w[j] * (double)n) / W;
+        alias[j] = j;
+        (p[j] < 1.0 ? work_small : work_large).push_back(j);
+    }
+    size_t si = 0, li = 0;
+    while (si < work_small.size() && li < work_large.size()) {
+        const int32_t s = work_small[si++];
+        const int32_t g = work_large[li];
+        thr[s] = (uint32_t)std::floor(p[s] * 4294967296.0);
+        alias[s] = g;
+        p[g] = (p[g] + p[s]) - 1.0;
+        if (p[g] < 1.0) {
+            ++li;
+            work_small.push_back(g);
+        }
+    }
+}
+
+// Pois(beta + l), l = 1..L, on x = 0..X_l, X_l = ceil(lam + 10 sqrt(lam) + 10)
+void poisson_tables(double beta, int32_t L, std::vector<int32_t> &off, std::vector<uint64_t> &packed)
+{
+    off.assign(L + 2, 0);
+    packed.clear();
+    for (int32_t l = 1; l <= L; ++l) {
+        const double lam = beta + (double)l;
+        const int32_t n = (int32_t)std::ceil(lam + 10.0 * std::sqrt(lam) + 10.0) + 1;
+        std::vector<double> pmf(n);
+        for (int32_t x = 0; x < n; ++x) pmf[x] = std::exp((double)x * std::log(lam) - lam - std::lgamma((double)x + 1.0));
+        std::vector<uint32_t> thr;
+        std::vector<int32_t> alias;
+        alias_table(pmf, thr, alias);
+        off[l] = (int32_t)packed.size();
+        for (int32_t x = 0; x < n; ++x) packed.push_back((uint64_t)thr[x] | ((uint64_t)(uint32_t)alias[x] << 32));
+    }
+    off[L + 1] = (int32_t)packed.size();
+}
+
+// zero-truncated Pois(beta): T_x = floor(2^32 P(X <= x | X >= 1)), x = 1..5
+void ztp_thresholds(double beta, uint32_t T[5])
+{
+    const double norm = -std::expm1(-beta);
+    double cdf = 0.0, term = std::exp(-beta);
+    for (int x = 1; x <= 5; ++x) {
+        term = term * beta / (double)x;
+        cdf += term;
+        const double t = std::floor((cdf / norm) * 4294967296.0);
+        T[x - 1] = t >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)t;
+    }
+}
+
+struct Layout {
+    int64_t total = 0;
+    int64_t take(int64_t bytes)
+    {
+        const int64_t at = total;
+        total = align_up(total + (bytes > 0 ? bytes : 1));
+        return at;
+    }
+};
+
+}  // namespace
+
+struct pulda_plan {
+    // model
+    int32_t K = 0, V = 0, L = 100;
+    double beta = 0.01, A = 0.0;
+    uint64_t seed = 0;
+    std::vector<double> alpha;
+    int64_t D = 0, N = 0;
+    // workspace
+    uint8_t *ws = nullptr;
+    int64_t ws_need = 0;
+    struct {
+        int64_t z, n, gam, phid, colcnt, colptr, ctopic, cphi, calias, sigma_a, S, nk, alpha, pois, pois_off,
+            doc_order, items, queue, stats, ll_part, ll_out, ll_hist, tptr, err, scratch, cnt_a, ptr_a, cnt_b,
+            ptr_b, zsave;
+    } off;
+    int64_t cap = 0, items_cap = 0, hist_cap = 4096;
+    int32_t n_part_words = 1024, n_part_docs = 1024;
+    std::vector<int32_t> pois_off_h;
+    std::vector<uint64_t> pois_h;
+    uint32_t ztp[5];
+    // device views
+    DevModel m{};
+    DevCorpus c{};
+    WorkItem *items = nullptr;
+    int32_t *queue = nullptr;
+    unsigned long long *stats = nullptr;
+    double *ll_part = nullptr, *ll_out = nullptr, *ll_hist = nullptr;
+    uint32_t *tptr = nullptr, *hist_idx = nullptr;
+    int32_t *err = nullptr;
+    int64_t *cnt_a = nullptr, *ptr_a = nullptr, *cnt_b = nullptr, *ptr_b = nullptr;
+    uint16_t *zsave = nullptr;
+    // schedule
+    std::vector<int32_t> len_sorted;  // lengths in doc_order
+    std::vector<int32_t> min_len{1024, 256, 64, 0}, group{64, 64, 32, 16}, dpi{1, 2, 8, 32};
+    int32_t n_items = 0;
+    int32_t n_waves = 0;
+    // state
+    bool bound = false, uploaded = false, have_z = false, have_phi = false;
+    // graph replay
+    bool graph_on = false;
+    hipGraphExec_t gexec = nullptr;
+    hipStream_t gstream = nullptr;
+};
+
+struct pulda_foldin {
+    const pulda_plan *model = nullptr;
+    pulda_foldin_desc desc{};
+    int64_t ws_need = 0;
+    struct {
+        int64_t slots, kept, words, pos, z, acc, theta, ll, active;
+    } off;
+    uint8_t *ws = nullptr;
+    DevFoldin f{};
+    int32_t *active_dev = nullptr;
+    FoldSlot *slots_dev = nullptr;
+    // host bookkeeping
+    std::vector<FoldSlot> slots;      // control mirror
+    std::vector<int32_t> resident;    // 1 if the slot holds a request
+    std::vector<std::pair<int32_t, int32_t>> free_blocks;  // arena [off, len), by offset
+    int32_t free_tokens = 0;
+};
+
+extern "C" {
+
+const char *pulda_last_error(void) { return g_error.c_str(); }
+const char *pulda_version(void) { return "pulda 0.1 (gfx950)"; }
+
+pulda_status pulda_plan_create(const pulda_model_desc *desc, int64_t D, int64_t N, pulda_plan **out)
+{
+    if (!desc || !out) return fail(PULDA_ERR_INVALID_ARG, "null argument");
+    *out = nullptr;
+    if (desc->K < 1 || desc->K > 4096) return fail(PULDA_ERR_INVALID_ARG, "K=%d outside 1..4096", desc->K);
+    if (desc->V < 1) return fail(PULDA_ERR_INVALID_ARG, "V=%d must be >= 1", desc->V);
+    if ((int64_t)desc->K * desc->V >= (1ll << 31)) return fail(PULDA_ERR_INVALID_ARG, "K*V must be < 2^31");
+    if (!(desc->beta > 0.0) || !std::isfinite(desc->beta)) return fail(PULDA_ERR_INVALID_ARG, "beta must be > 0");
+    if (desc->L < 1 || desc->L > 1000) return fail(PULDA_ERR_INVALID_ARG, "L=%d outside 1..1000", desc->L);
+    if (D < 0 || N < 0 || N >= (1ll << 40) || D >= (1ll << 31))
+        return fail(PULDA_ERR_INVALID_ARG, "bad corpus size D=%lld N=%lld", (long long)D, (long long)N);
+    std::vector<double> alpha(desc->K);
+    for (int32_t k = 0; k < desc->K; ++k) {
+        alpha[k] = desc->alpha_k ? desc->alpha_k[k] : desc->alpha;
+        if (!(alpha[k] > 0.0) || !std::isfinite(alpha[k])) return fail(PULDA_ERR_INVALID_ARG, "alpha must be > 0");
+    }
+    pulda_plan *p = new pulda_plan();
+    p->K = desc->K;
+    p->V = desc->V;
+    p->L = desc->L;
+    p->beta = desc->beta;
+    p->seed = desc->seed;
+    p->alpha = alpha;
+    p->A = 0.0;
+    for (double a : alpha) p->A += a;
+    p->D = D;
+    p->N = N;
+    poisson_tables(p->beta, p->L, p->pois_off_h, p->pois_h);
+    ztp_thresholds(p->beta, p->ztp);
+
+    const int64_t VK = (int64_t)p->V * p->K;
+    p->cap = VK;
+    p->items_cap = D + 64;
+    Layout L;
+    p->off.z = L.take(N * 2);
+    p->off.n = L.take(VK * 4);
+    p->off.gam = L.take(VK * 4);
+    p->off.phid = L.take(VK * 4);
+    p->off.colcnt = L.take((int64_t)p->V * 4);
+    p->off.colptr = L.take(((int64_t)p->V + 1) * 4);
+    p->off.ctopic = L.take(p->cap * 2);
+    p->off.cphi = L.take(p->cap * 4);
+    p->off.calias = L.take(p->cap * 8);
+    p->off.sigma_a = L.take((int64_t)p->V * 8);
+    p->off.S = L.take((int64_t)p->K * 8);
+    p->off.nk = L.take((int64_t)p->K * 8);
+    p->off.alpha = L.take((int64_t)p->K * 8);
+    p->off.pois = L.take((int64_t)p->pois_h.size() * 8);
+    p->off.pois_off = L.take((int64_t)p->pois_off_h.size() * 4);
+    p->off.doc_order = L.take(D * 4);
+    p->off.items = L.take(p->items_cap * (int64_t)sizeof(WorkItem));
+    p->off.queue = L.take(16);
+    p->off.stats = L.take(ST_COUNT * 8);
+    p->off.ll_part = L.take((int64_t)(p->n_part_words + p->n_part_docs) * 8);
+    p->off.ll_out = L.take(8);
+    p->off.ll_hist = L.take(p->hist_cap * 8);
+    p->off.tptr = L.take(16);
+    p->off.err = L.take(16);
+    p->off.scratch = L.take((((int64_t)p->V + 1023) / 1024 + (D + 1023) / 1024 + 8) * 8);
+    p->off.cnt_a = L.take(((int64_t)p->V + 2) * 8);
+    p->off.ptr_a = L.take(((int64_t)p->V + 2) * 8);
+    p->off.cnt_b = L.take((D + 2) * 8);
+    p->off.ptr_b = L.take((D + 2) * 8);
+    p->off.zsave = L.take(N * 2);
+    p->ws_need = L.total;
+    *out = p;
+    return PULDA_OK;
+}
+
+pulda_status pulda_plan_workspace_bytes(const pulda_plan *plan, int64_t *bytes)
+{
+    if (!plan || !bytes) return fail(PULDA_ERR_INVALID_ARG, "null argument");
+    *bytes = plan->ws_need;
+    return PULDA_OK;
+}
+
+pulda_status pulda_plan_bind(pulda_plan *p, void *workspace_dev, int64_t bytes)
+{
+    if (!p || !workspace_dev) return fail(PULDA_ERR_INVALID_ARG, "null argument");
+    if ((uintptr_t)workspace_dev % ALIGN) return fail(PULDA_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    if (bytes < p->ws_need)
+        return fail(PULDA_ERR_NO_MEMORY, "workspace of %lld bytes, need %lld", (long long)bytes, (long long)p->ws_need);
+    uint8_t *w = (uint8_t *)workspace_dev;
+    p->ws = w;
+    DevModel &m = p->m;
+    m.K = p->K;
+    m.V = p->V;
+    m.L = p->L;
+    m.beta = p->beta;
+    m.key0 = (uint32_t)p->seed;
+    m.key1 = (uint32_t)(p->seed >> 32);
+    m.alpha = (const double *)(w + p->off.alpha);
+    m.n = (int32_t *)(w + p->off.n);
+    m.nk = (unsigned long long *)(w + p->off.nk);
+    m.gam = (int32_t *)(w + p->off.gam);
+    m.S = (unsigned long long *)(w + p->off.S);
+    m.phid = (float *)(w + p->off.phid);
+    m.colcnt = (int32_t *)(w + p->off.colcnt);
+    m.colptr = (int32_t *)(w + p->off.colptr);
+    m.ctopic = (uint16_t *)(w + p->off.ctopic);
+    m.cphi = (float *)(w + p->off.cphi);
+    m.calias = (uint64_t *)(w + p->off.calias);
+    m.sigma_a = (double *)(w + p->off.sigma_a);
+    m.pois = (const uint64_t *)(w + p->off.pois);
+    m.pois_off = (const int32_t *)(w + p->off.pois_off);
+    std::memcpy(m.ztp, p->ztp, sizeof(m.ztp));
+    p->tptr = (uint32_t *)(w + p->off.tptr);
+    p->hist_idx = p->tptr + 1;
+    m.tptr = p->tptr;
+    m.scratch = (long long *)(w + p->off.scratch);
+    p->c.D = p->D;
+    p->c.N = p->N;
+    p->c.z = (uint16_t *)(w + p->off.z);
+    p->c.doc_order = (const int32_t *)(w + p->off.doc_order);
+    p->items = (WorkItem *)(w + p->off.items);
+    p->queue = (int32_t *)(w + p->off.queue);
+    p->stats = (unsigned long long *)(w + p->off.stats);
+    p->ll_part = (double *)(w + p->off.ll_part);
+    p->ll_out = (double *)(w + p->off.ll_out);
+    p->ll_hist = (double *)(w + p->off.ll_hist);
+    p->err = (int32_t *)(w + p->off.err);
+    p->cnt_a = (int64_t *)(w + p->off.cnt_a);
+    p->ptr_a = (int64_t *)(w + p->off.ptr_a);
+    p->cnt_b = (int64_t *)(w + p->off.cnt_b);
+    p->ptr_b = (int64_t *)(w + p->off.ptr_b);
+    p->zsave = (uint16_t *)(w + p->off.zsave);
+    // constant tables (synchronous copies from host memory)
+    HIP_TRY(hipMemcpy((void *)m.alpha, p->alpha.data(), p->K * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy((void *)m.pois, p->pois_h.data(), p->pois_h.size() * 8, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy((void *)m.pois_off, p->pois_off_h.data(), p->pois_off_h.size() * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemset(p->stats, 0, ST_COUNT * 8));
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, dev));
+    p->n_waves = prop.multiProcessorCount * 20;
+    p->bound = true;
+    p->uploaded = p->have_z = p->have_phi = false;
+    return PULDA_OK;
+}
+
+void pulda_plan_destroy(pulda_plan *p)
+{
+    if (!p) return;
+    if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+    delete p;
+}
+
+// smallest group size whose lanes can own all K topics with <= 64 topics each
+static int32_t min_group(int32_t K)
+{
+    for (int32_t g : {16, 32, 64})
+        if ((int64_t)g * 64 >= K) return g;
+    return 64;
+}
+
+static pulda_status build_items(pulda_plan *p)
+{
+    const int32_t gmin = min_group(p->K);
+    for (size_t b = 0; b < p->group.size(); ++b) {
+        if (p->group[b] < gmin) {
+            const int32_t per_group = p->dpi[b] / (64 / p->group[b]);
+            p->group[b] = gmin;
+            p->dpi[b] = std::max(1, per_group) * (64 / gmin);
+        }
+    }
+    std::vector<WorkItem> items;
+    const int32_t nb = (int32_t)p->min_len.size();
+    int64_t pos = 0;
+    for (int32_t b = 0; b < nb; ++b) {
+        const int64_t start = pos;
+        while (pos < p->D && p->len_sorted[pos] >= p->min_len[b]) ++pos;
+        const int32_t per = p->dpi[b];
+        for (int64_t s = start; s < pos; s += per) {
+            WorkItem w;
+            w.first = (int32_t)s;
+            w.count = (int32_t)std::min<int64_t>(per, pos - s);
+            w.group = p->group[b];
+            w.pad = b;
+            items.push_back(w);
+        }
+    }
+    if ((int64_t)items.size() > p->items_cap) return fail(PULDA_ERR_INVALID_ARG, "schedule yields too many work items");
+    p->n_items = (int32_t)items.size();
+    if (!items.empty())
+        HIP_TRY(hipMemcpy(p->items, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
+    if (p->gexec) {
+        (void)hipGraphExecDestroy(p->gexec);
+        p->gexec = nullptr;
+    }
+    return PULDA_OK;
+}
+
+pulda_status pulda_corpus_upload(pulda_plan *p, const int64_t *doc_off_dev, const int32_t *words_dev, void *stream)
+{
+    if (!p || (!doc_off_dev) || (!words_dev && p->N > 0)) return fail(PULDA_ERR_INVALID_ARG, "null argument");
+    if (!p->bound) return fail(PULDA_ERR_STATE, "plan has no workspace bound");
+    hipStream_t s = (hipStream_t)stream;
+    p->c.doc_off = doc_off_dev;
+    p->c.words = words_dev;
+    HIP_TRY(launch_fill_u32((uint32_t *)p->err, 0u, 4, s));
+    HIP_TRY(launch_validate(p->c, p->V, p->err, s));
+    int32_t err[4];
+    HIP_TRY(hipMemcpyAsync(err, p->err, sizeof(err), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (err[0] || err[1] || err[2]) {
+        p->uploaded = false;
+        return fail(PULDA_ERR_CORPUS, "invalid corpus: %d bad offsets, %d word ids outside [0,%d), %d documents over "
+                    "65535 tokens", err[0], err[1], p->V, err[2]);
+    }
+    // order documents by decreasing length (counting sort, stable in d)
+    std::vector<int64_t> off(p->D + 1);
+    HIP_TRY(hipMemcpy(off.data(), doc_off_dev, (p->D + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
+    std::vector<int64_t> hist(65537, 0);
+    for (int64_t d = 0; d < p->D; ++d) hist[off[d + 1] - off[d]]++;
+    std::vector<int64_t> start(65537, 0);
+    int64_t run = 0;
+    for (int32_t l = 65536; l >= 0; --l) {
+        start[l] = run;
+        run += hist[l];
+    }
+    std::vector<int32_t> order(p->D);
+    p->len_sorted.assign(p->D, 0);
+    for (int64_t d = 0; d < p->D; ++d) {
+        const int64_t l = off[d + 1] - off[d];
+        const int64_t at = start[l]++;
+        order[at] = (int32_t)d;
+        p->len_sorted[at] = (int32_t)l;
+    }
+    if (p->D) HIP_TRY(hipMemcpy((void *)p->c.doc_order, order.data(), p->D * 4, hipMemcpyHostToDevice));
+    pulda_status st = build_items(p);
+    if (st != PULDA_OK) return st;
+    p->uploaded = true;
+    p->have_z = false;
+    return PULDA_OK;
+}
+
+pulda_status pulda_init(pulda_plan *p, const uint16_t *z0_dev, void *stream)
+{
+    if (!p) return fail(PULDA_ERR_INVALID_ARG, "null argument");
+    if (!p->uploaded) return fail(PULDA_ERR_STATE, "no corpus uploaded");
+    hipStream_t s = (hipStream_t)stream;
+    if (z0_dev) {
+        if (p->N) {
+            HIP_TRY(hipMemcpyAsync(p->c.z, z0_dev, p->N * 2, hipMemcpyDeviceToDevice, s));
+            HIP_TRY(launch_fill_u32((uint32_t *)p->err, 0u, 4, s));
+            HIP_TRY(launch_check_u16_below(p->c.z, p->N, (uint32_t)p->K, p->err, s));
+            int32_t bad = 0;
+            HIP_TRY(hipMemcpyAsync(&bad, p->err, 4, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            if (bad) {
+                p->have_z = false;
+                return fail(PULDA_ERR_INVALID_ARG, "%d topics in z are >= K=%d", bad, p->K);
+            }
+        }
+    } else {
+        HIP_TRY(launch_init_z(p->c, p->K, p->m.key0, p->m.key1, s));
+    }
+    HIP_TRY(launch_count_rebuild(p->c, p->m, s));
+    p->have_z = true;
+    return PULDA_OK;
+}
+
+pulda_status pulda_set_z(pulda_plan *p, const uint16_t *z_dev, void *stream)
+{
+    if (!p || (!z_dev && p->N > 0)) return fail(PULDA_ERR_INVALID_ARG, "null argument");
+    return pulda_init(p, z_dev, stream);
+}
+
+pulda_status pulda_get_z(const pulda_plan *p, uint16_t *z_dev, void *stream)
+{
+    if (!p || (!z_dev && p->N > 0)) return fail(PULDA_ERR_INVALID_ARG, "null argument");
+    if (!p->have_z) return fail(PULDA_ERR_STATE, "no state (call pulda_init)");
+    if (p->N) HIP_TRY(hipMemcpyAsync(z_dev, p->c.z, p->N * 2, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    return PULDA_OK;
+}
+
+pulda_status pulda_set_counts(pulda_plan *p, const int32_t *n_dev, void *stream)
+{
+    if (!p || !n_dev) return fail(PULDA_ERR_INVALID_ARG, "null argument");
+    if (!p->bound) return fail(PULDA_ERR_STATE, "plan has no workspace bound");
+    HIP_TRY(hipMemcpyAsync(p->m.n, n_dev, (size_t)p->V * p->K * 4, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    p->have_z = false;
+    return PULDA_OK;
+}
+
+static pulda_status enqueue_phi(pulda_plan *p, hipStream_t s)
+{
+    HIP_TRY(launch_phi_step(p->m, p->stats, s));
+    return PULDA_OK;
+}
+
+static pulda_status enqueue_z(pulda_plan *p, hipStream_t s)
+{
+    HIP_TRY(launch_z_step(p->c, p->m, p->items, p->n_items, p->n_waves, p->queue, p->stats, s));
+    return PULDA_OK;
+}
+
+static bool counts_ready(const pulda_plan *p) { return p->have_z || !p->uploaded; }
+
+pulda_status pulda_phi_step(pulda_plan *p, uint32_t t, void *stream)
+{
+    if (!p) return fail(PULDA_ERR_INVALID_ARG, "null argument");
+    if (!p->bound) return fail(PULDA_ERR_STATE, "plan has no workspace bound");
+    if (t == 0) return fail(PULDA_ERR_INVALID_ARG, "sweeps are numbered from t = 1");
+    (void)counts_ready;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(launch_fill_u32(p->tptr, t, 1, s));
+    pulda_status st = enqueue_phi(p, s);
+    if (st == PULDA_OK) p->have_phi = true;
+    return st;
+}
+
+pulda_status pulda_z_step(pulda_plan *p, uint32_t t, void *stream)
+{
+    if (!p) return fail(PULDA_ERR_INVALID_ARG, "null argument");
+    if (!p->have_z) return fail(PULDA_ERR_STATE, "no state (call pulda_init)");
+    if (!p->have_phi) return fail(PULDA_ERR_STATE, "no Phi (call pulda_phi_step or pulda_set_phi)");
+    if (t == 0) return fail(PULDA_ERR_INVALID_ARG, "sweeps are numbered from t = 1");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(launch_fill_u32(p->tptr, t, 1, s));
+    return enqueue_z(p, s);
+}
+
+static pulda_status enqueue_sweep_body(pulda_plan *p, hipStream_t s)
+{
+    pulda_status st = enqueue_phi(p, s);
+    if (st != PULDA_OK) return st;
+    st = enqueue_z(p, s);
+    if (st != PULDA_OK) return st;
+    HIP_TRY(launch_loglik(p->c, p->m, p->A, p->ll_part, p->n_part_words, p->n_part_docs, p->ll_out, p->ll_hist,
+                          p->hist_idx, s));
+    HIP_TRY(launch_advance(p->tptr, p->hist_idx, s));
+    return PULDA_OK;
+}
+
+pulda_status pulda_sweep(pulda_plan *p, uint32_t t_first, int32_t n_sweeps, double *ll_host, void *stream)
+{
+    if (!p) return fail(PULDA_ERR_INVALID_ARG, "null argument");
+    if (!p->have_z) return fail(PULDA_ERR_STATE, "no state (call pulda_init)");
+    if (t_first == 0 || n_sweeps < 0) return fail(PULDA_ERR_INVALID_ARG, "bad sweep range");
+    hipStream_t s = (hipStream_t)stream;
+    int32_t done = 0;
+    while (done < n_sweeps) {
+        const int32_t chunk = (int32_t)std::min<int64_t>(n_sweeps - done, p->hist_cap);
+        HIP_TRY(launch_fill_u32(p->tptr, t_first + (uint32_t)done, 1, s));
+        HIP_TRY(launch_fill_u32(p->hist_idx, 0u, 1, s));
+        if (p->graph_on) {
+            if (!p->gexec || p->gstream != s) {
+                if (p->gexec) {
+                    (void)hipGraphExecDestroy(p->gexec);
+                    p->gexec = nullptr;
+                }
+                hipGraph_t graph;
+                HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+                pulda_status st = enqueue_sweep_body(p, s);
+                hipError_t ec = hipStreamEndCapture(s, &graph);
+                if (st != PULDA_OK) return st;
+                if (ec != hipSuccess) return fail(PULDA_ERR_DEVICE, "graph capture: %s", hipGetErrorString(ec));
+                ec = hipGraphInstantiate(&p->gexec, graph, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(graph);
+                if (ec != hipSuccess) return fail(PULDA_ERR_DEVICE, "graph instantiate: %s", hipGetErrorString(ec));
+                p->gstream = s;
+            }
+            for (int32_t i = 0; i < chunk; ++i) HIP_TRY(hipGraphLaunch(p->gexec, s));
+        } else {
+            for (int32_t i = 0; i < chunk; ++i) {
+                pulda_status st = enqueue_sweep_body(p, s);
+                if (st != PULDA_OK) return st;
+            }
+        }
+        if (ll_host) {
+            HIP_TRY(hipMemcpyAsync(ll_host + done, p->ll_hist, chunk * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+        }
+        done += chunk;
+    }
+    p->have_phi = true;
+    return PULDA_OK;
+}
+
+pulda_status pulda_loglik(pulda_plan *p, double *ll_host, void *stream)
+{
+    if (!p || !ll_host) return fail(PULDA_ERR_INVALID_ARG, "null argument");
+    if (!p->have_z) return fail(PULDA_ERR_STATE, "no state (call pulda_init)");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(launch_loglik(p->c, p->m, p->A, p->ll_part, p->n_part_words, p->n_part_docs, p->ll_out, nullptr,
+                          nullptr, s));
+    HIP_TRY(hipMemcpyAsync(ll_host, p->ll_out, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return PULDA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// counts and Phi export / import
+// ---------------------------------------------------------------------------
+static pulda_status count_sizes(pulda_plan *p, hipStream_t s, int64_t *nnz_n, int64_t *nnz_m)
+{
+    HIP_TRY(launch_n_colcount(p->m, p->cnt_a, s));
+    HIP_TRY(launch_scan_i64(p->cnt_a, p->ptr_a, p->V, p->m.scratch, s));
+    HIP_TRY(launch_counts_m(p->c, p->K, p->cnt_b, nullptr, nullptr, 0, s));
+    HIP_TRY(launch_scan_i64(p->cnt_b, p->ptr_b, p->D, p->m.scratch + (p->V + 1023) / 1024 + 2, s));
+    HIP_TRY(hipMemcpyAsync(nnz_n, p->ptr_a + p->V, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(nnz_m, p->ptr_b + p->D, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return PULDA_OK;
+}
+
+pulda_status pulda_counts_sizes(pulda_plan *p, int64_t *nnz_n, int64_t *nnz_m, void *stream)
+{
+    if (!p || !nnz_n || !nnz_m) return fail(PULDA_ERR_INVALID_ARG, "null argument");
+    if (!p->have_z) return fail(PULDA_ERR_STATE, "no state (call pulda_init)");
+    return count_sizes(p, (hipStream_t)stream, nnz_n, nnz_m);
+}
+
+pulda_status pulda_counts(pulda_plan *p, const pulda_counts_view *o, void *stream)
+{
+    if (!p || !o || !o->n_colptr_dev || !o->n_topic_dev || !o->n_count_dev || !o->m_rowptr_dev || !o->m_topic_dev ||
+        !o->m_count_dev)
+        return fail(PULDA_ERR_INVALID_ARG, "null argument");
+    if (!p->have_z) return fail(PULDA_ERR_STATE, "no state (call pulda_init)");
+    hipStream_t s = (hipStream_t)stream;
+    int64_t nn, nm;
+    pulda_status st = count_sizes(p, s, &nn, &nm);
+    if (st != PULDA_OK) return st;
+    HIP_TRY(hipMemcpyAsync(o->n_colptr_dev, p->ptr_a, (p->V + 1) * 8, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(o->m_rowptr_dev, p->ptr_b, (p->D + 1) * 8, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(launch_counts_csc(p->m, p->ptr_a, o->n_topic_dev, o->n_count_dev, nullptr, s));
+    HIP_TRY(launch_counts_m(p->c, p->K, p->ptr_b, o->m_topic_dev, o->m_count_dev, 1, s));
+    if (o->nk_dev) {
+        HIP_TRY(launch_row_sums(p->m.n, p->V, p->K, p->m.nk, s));
+        HIP_TRY(hipMemcpyAsync(o->nk_dev, p->m.nk, p->K * 8, hipMemcpyDeviceToDevice, s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    return PULDA_OK;
+}
+
+pulda_status pulda_get_counts_dense(pulda_plan *p, int32_t *n_dev, int64_t *nk_dev, void *stream)
+{
+    if (!p) return fail(PULDA_ERR_INVALID_ARG, "null argument");
+    if (!p->bound) return fail(PULDA_ERR_STATE, "plan has no workspace bound");
+    hipStream_t s = (hipStream_t)stream;
+    if (n_dev) HIP_TRY(hipMemcpyAsync(n_dev, p->m.n, (size_t)p->V * p->K * 4, hipMemcpyDeviceToDevice, s));
+    if (nk_dev) {
+        HIP_TRY(launch_row_sums(p->m.n, p->V, p->K, p->m.nk, s));
+        HIP_TRY(hipMemcpyAsync(nk_dev, p->m.nk, p->K * 8, hipMemcpyDeviceToDevice, s));
+    }
+    return PULDA_OK;
+}
+
+pulda_status pulda_phi_nnz(pulda_plan *p, int64_t *nnz, void *stream)
+{
+    if (!p || !nnz) return fail(PULDA_ERR_INVALID_ARG, "null argument");
+    if (!p->have_phi) return fail(PULDA_ERR_STATE, "no Phi");
+    hipStream_t s = (hipStream_t)stream;
+    int32_t v;
+    HIP_TRY(hipMemcpyAsync(&v, p->m.colptr + p->V, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *nnz = v;
+    return PULDA_OK;
+}
+
+pulda_status pulda_get_phi(pulda_plan *p, const pulda_phi_view *o, void *stream)
+{
+    if (!p || !o || !o->colptr_dev || !o->topic_dev || !o->phi_dev || !o->alias_thr_dev || !o->alias_topic_dev ||
+        !o->sigma_a_dev)
+        return fail(PULDA_ERR_INVALID_ARG, "null argument");
+    if (!p->have_phi) return fail(PULDA_ERR_STATE, "no Phi");
+    hipStream_t s = (hipStream_t)stream;
+    int32_t *gam_e = o->gamma_dev;
+    if (!gam_e) return fail(PULDA_ERR_INVALID_ARG, "gamma_dev is required for export");
+    HIP_TRY(launch_export_phi(p->m, o->colptr_dev, o->topic_dev, gam_e, o->phi_dev, o->alias_thr_dev,
+                              o->alias_topic_dev, s));
+    HIP_TRY(hipMemcpyAsync(o->sigma_a_dev, p->m.sigma_a, p->V * 8, hipMemcpyDeviceToDevice, s));
+    if (o->S_dev) HIP_TRY(hipMemcpyAsync(o->S_dev, p->m.S, p->K * 8, hipMemcpyDeviceToDevice, s));
+    return PULDA_OK;
+}
+
+pulda_status pulda_set_phi(pulda_plan *p, const pulda_phi_view *in, void *stream)
+{
+    if (!p || !in || !in->colptr_dev || !in->topic_dev || !in->phi_dev || !in->alias_thr_dev ||
+        !in->alias_topic_dev || !in->sigma_a_dev)
+        return fail(PULDA_ERR_INVALID_ARG, "null argument");
+    if (!p->bound) return fail(PULDA_ERR_STATE, "plan has no workspace bound");
+    hipStream_t s = (hipStream_t)stream;
+    int64_t nnz;
+    HIP_TRY(hipMemcpyAsync(&nnz, in->colptr_dev + p->V, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    int64_t first = 0;
+    HIP_TRY(hipMemcpy(&first, in->colptr_dev, 8, hipMemcpyDeviceToHost));
+    if (first != 0) return fail(PULDA_ERR_INVALID_ARG, "colptr[0] must be 0");
+    if (nnz < 0 || nnz > p->cap) return fail(PULDA_ERR_INVALID_ARG, "Phi has %lld nonzeros, capacity %lld",
+                                             (long long)nnz, (long long)p->cap);
+    HIP_TRY(launch_fill_u32((uint32_t *)p->err, 0u, 4, s));
+    HIP_TRY(launch_check_phi(in->colptr_dev, p->V, in->topic_dev, in->alias_topic_dev, (uint32_t)p->K, p->err, s));
+    int32_t bad = 0;
+    HIP_TRY(hipMemcpyAsync(&bad, p->err, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (bad) return fail(PULDA_ERR_INVALID_ARG, "Phi has %d malformed columns or topics >= K", bad);
+    HIP_TRY(launch_import_phi(p->m, in->colptr_dev, in->topic_dev, in->phi_dev, in->alias_thr_dev,
+                              in->alias_topic_dev, s));
+    HIP_TRY(hipMemcpyAsync(p->m.sigma_a, in->sigma_a_dev, p->V * 8, hipMemcpyDeviceToDevice, s));
+    p->have_phi = true;
+    return PULDA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// statistics, schedule, autotuning, graph
+// ---------------------------------------------------------------------------
+pulda_status pulda_stats(pulda_plan *p, pulda_sweep_stats *out, void *stream)
+{
+    if (!p || !out) return fail(PULDA_ERR_INVALID_ARG, "null argument");
+    if (!p->bound) return fail(PULDA_ERR_STATE, "plan has no workspace bound");
+    unsigned long long st[ST_COUNT];
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipMemcpyAsync(st, p->stats, sizeof(st), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    out->degenerate_tokens = (int64_t)st[ST_DEGENERATE];
+    out->sum_J = (int64_t)st[ST_SUM_J];
+    out->sum_A = (int64_t)st[ST_SUM_A];
+    out->nnz_phi = (int64_t)st[ST_NNZ_PHI];
+    out->empty_rows = (int64_t)st[ST_EMPTY_ROWS];
+    return PULDA_OK;
+}
+
+pulda_status pulda_set_schedule(pulda_plan *p, int32_t nb, const int32_t *min_len, const int32_t *group,
+                                const int32_t *dpi)
+{
+    if (!p || nb < 1 || !min_len || !group || !dpi) return fail(PULDA_ERR_INVALID_ARG, "bad schedule");
+    for (int32_t b = 0; b < nb; ++b) {
+        if (group[b] != 16 && group[b] != 32 && group[b] != 64)
+            return fail(PULDA_ERR_INVALID_ARG, "group size %d not in {16, 32, 64}", group[b]);
+        if (dpi[b] < 1 || dpi[b] % (64 / group[b])) return fail(PULDA_ERR_INVALID_ARG, "docs per item %d", dpi[b]);
+        if (b > 0 && min_len[b] >= min_len[b - 1]) return fail(PULDA_ERR_INVALID_ARG, "min_len must decrease");
+        if ((1 << (int)std::ceil(std::log2((double)((p->K + group[b] - 1) / group[b])))) > 64)
+            return fail(PULDA_ERR_INVALID_ARG, "group %d too small for K=%d", group[b], p->K);
+    }
+    if (min_len[nb - 1] != 0) return fail(PULDA_ERR_INVALID_ARG, "last bucket must start at length 0");
+    p->min_len.assign(min_len, min_len + nb);
+    p->group.assign(group, group + nb);
+    p->dpi.assign(dpi, dpi + nb);
+    if (p->uploaded) return build_items(p);
+    return PULDA_OK;
+}
+
+pulda_status pulda_get_schedule(const pulda_plan *p, int32_t cap, int32_t *nb, int32_t *min_len, int32_t *group,
+                                int32_t *dpi)
+{
+    if (!p || !nb) return fail(PULDA_ERR_INVALID_ARG, "null argument");
+    *nb = (int32_t)p->min_len.size();
+    for (int32_t b = 0; b < *nb && b < cap; ++b) {
+        if (min_len) min_len[b] = p->min_len[b];
+        if (group) group[b] = p->group[b];
+        if (dpi) dpi[b] = p->dpi[b];
+    }
+    return PULDA_OK;
+}
+
+pulda_status pulda_autotune(pulda_plan *p, uint32_t t, int32_t reps, void *stream)
+{
+    if (!p || reps < 1 || t == 0) return fail(PULDA_ERR_INVALID_ARG, "bad argument");
+    if (!p->have_z || !p->have_phi) return fail(PULDA_ERR_STATE, "autotune needs a state and a Phi");
+    hipStream_t s = (hipStream_t)stream;
+    if (p->N) HIP_TRY(hipMemcpyAsync(p->zsave, p->c.z, p->N * 2, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(launch_fill_u32(p->tptr, t, 1, s));
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    const std::vector<int32_t> keep_group = p->group, keep_dpi = p->dpi;
+    const int32_t nb = (int32_t)p->min_len.size();
+    std::vector<int32_t> best_g(keep_group), best_d(keep_dpi);
+    for (int32_t b = 0; b < nb; ++b) {
+        // documents of bucket b
+        int64_t lo = 0, hi = 0;
+        {
+            int64_t pos = 0;
+            for (int32_t bb = 0; bb <= b; ++bb) {
+                lo = pos;
+                while (pos < p->D && p->len_sorted[pos] >= p->min_len[bb]) ++pos;
+            }
+            hi = pos;
+        }
+        if (hi == lo) continue;
+        double mean_len = 0;
+        for (int64_t i = lo; i < hi; ++i) mean_len += p->len_sorted[i];
+        mean_len /= (double)(hi - lo);
+        float best_ms = 1e30f;
+        for (int gsz : {64, 32, 16}) {
+            if ((1 << (int)std::ceil(std::log2((double)((p->K + gsz - 1) / gsz)))) > 64) continue;
+            const int ng = 64 / gsz;
+            int per = (int)std::max(1.0, std::round(4096.0 / std::max(1.0, mean_len) / ng)) * ng;
+            std::vector<WorkItem> items;
+            for (int64_t q = lo; q < hi; q += per)
+                items.push_back({(int32_t)q, (int32_t)std::min<int64_t>(per, hi - q), gsz, b});
+            HIP_TRY(hipMemcpyAsync(p->items, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice, s));
+            float total = 0;
+            for (int r = 0; r <= reps; ++r) {
+                if (p->N) HIP_TRY(hipMemcpyAsync(p->c.z, p->zsave, p->N * 2, hipMemcpyDeviceToDevice, s));
+                HIP_TRY(hipEventRecord(e0, s));
+                HIP_TRY(launch_z_step(p->c, p->m, p->items, (int32_t)items.size(), p->n_waves, p->queue, nullptr, s));
+                HIP_TRY(hipEventRecord(e1, s));
+                HIP_TRY(hipEventSynchronize(e1));
+                float ms;
+                HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                if (r > 0) total += ms;  // first run warms up
+            }
+            if (total < best_ms) {
+                best_ms = total;
+                best_g[b] = gsz;
+                best_d[b] = per;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    p->group = best_g;
+    p->dpi = best_d;
+    pulda_status st = build_items(p);
+    if (st != PULDA_OK) return st;
+    if (p->N) HIP_TRY(hipMemcpyAsync(p->c.z, p->zsave, p->N * 2, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(launch_count_rebuild(p->c, p->m, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return PULDA_OK;
+}
+
+pulda_status pulda_set_graph(pulda_plan *p, int32_t enable)
+{
+    if (!p) return fail(PULDA_ERR_INVALID_ARG, "null argument");
+    p->graph_on = enable != 0;
+    if (!p->graph_on && p->gexec) {
+        (void)hipGraphExecDestroy(p->gexec);
+        p->gexec = nullptr;
+    }
+    return PULDA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// fold-in server
+// ---------------------------------------------------------------------------
+pulda_status pulda_foldin_create(const pulda_plan *model, const pulda_foldin_desc *d, pulda_foldin **out)
+{
+    if (!model || !d || !out) return fail(PULDA_ERR_INVALID_ARG, "null argument");
+    *out = nullptr;
+    if (!model->have_phi) return fail(PULDA_ERR_STATE, "the model has no Phi");
+    if (d->sweeps < 1 || d->burn_in < 0 || d->burn_in >= d->sweeps) return fail(PULDA_ERR_INVALID_ARG, "bad sweeps");
+    if (d->max_slots < 1 || d->arena_tokens < 1 || d->max_len < 1 || d->max_len > d->arena_tokens ||
+        d->max_len > 65535)
+        return fail(PULDA_ERR_INVALID_ARG, "bad capacity");
+    if (d->group != 16 && d->group != 32 && d->group != 64) return fail(PULDA_ERR_INVALID_ARG, "bad group");
+    if ((1 << (int)std::ceil(std::log2((double)((model->K + d->group - 1) / d->group)))) > 64)
+        return fail(PULDA_ERR_INVALID_ARG, "group %d too small for K=%d", d->group, model->K);
+    pulda_foldin *f = new pulda_foldin();
+    f->model = model;
+    f->desc = *d;
+    Layout L;
+    const int64_t S = d->max_slots, T = d->arena_tokens, K = model->K;
+    f->off.slots = L.take(S * (int64_t)sizeof(FoldSlot));
+    f->off.kept = L.take(S * 8);
+    f->off.words = L.take(T * 4);
+    f->off.pos = L.take(T * 4);
+    f->off.z = L.take(T * 2);
+    f->off.acc = L.take(S * K * 4);
+    f->off.theta = L.take(S * K * 4);
+    f->off.ll = L.take(S * 8);
+    f->off.active = L.take(S * 4);
+    f->ws_need = L.total;
+    f->slots.assign(S, FoldSlot{});
+    f->resident.assign(S, 0);
+    f->free_blocks = {{0, (int32_t)T}};
+    f->free_tokens = (int32_t)T;
+    *out = f;
+    return PULDA_OK;
+}
+
+pulda_status pulda_foldin_workspace_bytes(const pulda_foldin *f, int64_t *bytes)
+{
+    if (!f || !bytes) return fail(PULDA_ERR_INVALID_ARG, "null argument");
+    *bytes = f->ws_need;
+    return PULDA_OK;
+}
+
+pulda_status pulda_foldin_bind(pulda_foldin *f, void *ws, int64_t bytes)
+{
+    if (!f || !ws) return fail(PULDA_ERR_INVALID_ARG, "null argument");
+    if ((uintptr_t)ws % ALIGN) return fail(PULDA_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    if (bytes < f->ws_need)
+        return fail(PULDA_ERR_NO_MEMORY, "workspace of %lld bytes, need %lld", (long long)bytes, (long long)f->ws_need);
+    uint8_t *w = (uint8_t *)ws;
+    f->ws = w;
+    f->slots_dev = (FoldSlot *)(w + f->off.slots);
+    f->active_dev = (int32_t *)(w + f->off.active);
+    DevFoldin &F = f->f;
+    F.sweeps = f->desc.sweeps;
+    F.burn_in = f->desc.burn_in;
+    F.group = f->desc.group;
+    F.key0 = (uint32_t)f->desc.seed;
+    F.key1 = (uint32_t)(f->desc.seed >> 32);
+    F.A = f->model->A;
+    F.slots = f->slots_dev;
+    F.kept = (int32_t *)(w + f->off.kept);
+    F.words = (int32_t *)(w + f->off.words);
+    F.pos = (int32_t *)(w + f->off.pos);
+    F.z = (uint16_t *)(w + f->off.z);
+    F.acc = (uint32_t *)(w + f->off.acc);
+    F.theta = (float *)(w + f->off.theta);
+    F.ll = (double *)(w + f->off.ll);
+    return PULDA_OK;
+}
+
+void pulda_foldin_destroy(pulda_foldin *f) { delete f; }
+
+static bool arena_alloc(pulda_foldin *f, int32_t len, int32_t *at)
+{
+    const int32_t need = std::max(len, 1);
+    for (size_t i = 0; i < f->free_blocks.size(); ++i) {
+        auto &b = f->free_blocks[i];
+        if (b.second >= need) {
+            *at = b.first;
+            b.first += need;
+            b.second -= need;
+            if (b.second == 0) f->free_blocks.erase(f->free_blocks.begin() + i);
+            f->free_tokens -= need;
+            return true;
+        }
+    }
+    return false;
+}
+
+static void arena_free(pulda_foldin *f, int32_t at, int32_t len)
+{
+    const int32_t n = std::max(len, 1);
+    auto &fb = f->free_blocks;
+    auto it = std::lower_bound(fb.begin(), fb.end(), std::make_pair(at, 0));
+    it = fb.insert(it, {at, n});
+    f->free_tokens += n;
+    size_t i = it - fb.begin();
+    if (i + 1 < fb.size() && fb[i].first + fb[i].second == fb[i + 1].first) {
+        fb[i].second += fb[i + 1].second;
+        fb.erase(fb.begin() + i + 1);
+    }
+    if (i > 0 && fb[i - 1].first + fb[i - 1].second == fb[i].first) {
+        fb[i - 1].second += fb[i].second;
+        fb.erase(fb.begin() + i);
+    }
+}
+
+pulda_status pulda_foldin_submit(pulda_foldin *f, uint32_t req, const int32_t *words, int32_t len, void *stream)
+{
+    if (!f || (len > 0 && !words)) return fail(PULDA_ERR_INVALID_ARG, "null argument");
+    if (!f->ws) return fail(PULDA_ERR_STATE, "no workspace bound");
+    if (len < 0 || len > f->desc.max_len)
+        return fail(PULDA_ERR_INVALID_ARG, "request length %d outside 0..%d", len, f->desc.max_len);
+    int32_t sid = -1;
+    for (int32_t i = 0; i < f->desc.max_slots; ++i)
+        if (!f->resident[i]) {
+            sid = i;
+            break;
+        }
+    if (sid < 0) return fail(PULDA_ERR_CAPACITY, "no free slot");
+    int32_t at;
+    if (!arena_alloc(f, len, &at)) return fail(PULDA_ERR_CAPACITY, "no arena space for %d tokens", len);
+    hipStream_t s = (hipStream_t)stream;
+    if (len > 0) {
+        hipError_t e = hipMemcpyAsync(f->f.words + at, words, (size_t)len * 4, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) {
+            arena_free(f, at, len);
+            return fail(PULDA_ERR_DEVICE, "copy request: %s", hipGetErrorString(e));
+        }
+    }
+    FoldSlot &sl = f->slots[sid];
+    sl.arena_off = at;
+    sl.len = len;
+    sl.req = req;
+    sl.done = 0;
+    sl.todo = 0;
+    f->resident[sid] = 1;
+    return PULDA_OK;
+}
+
+pulda_status pulda_foldin_step(pulda_foldin *f, int32_t quantum, void *stream)
+{
+    if (!f || quantum < 1) return fail(PULDA_ERR_INVALID_ARG, "bad argument");
+    if (!f->ws) return fail(PULDA_ERR_STATE, "no workspace bound");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<int32_t> active;
+    for (int32_t i = 0; i < f->desc.max_slots; ++i) {
+        FoldSlot &sl = f->slots[i];
+        if (f->resident[i] && sl.done < f->desc.sweeps) {
+            sl.todo = std::min(quantum, f->desc.sweeps - sl.done);
+            active.push_back(i);
+        } else {
+            sl.todo = 0;
+        }
+    }
+    if (active.empty()) return PULDA_OK;
+    HIP_TRY(hipMemcpyAsync(f->slots_dev, f->slots.data(), f->slots.size() * sizeof(FoldSlot), hipMemcpyHostToDevice,
+                           s));
+    HIP_TRY(hipMemcpyAsync(f->active_dev, active.data(), active.size() * 4, hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_foldin_step(f->model->m, f->f, f->active_dev, (int32_t)active.size(), s));
+    for (int32_t i : active) {
+        f->slots[i].done += f->slots[i].todo;
+        f->slots[i].todo = 0;
+    }
+    return PULDA_OK;
+}
+
+pulda_status pulda_foldin_poll(pulda_foldin *f, pulda_foldin_result *out, float *theta, int32_t cap, int32_t *n_done,
+                               void *stream)
+{
+    if (!f || !n_done || (cap > 0 && (!out || !theta))) return fail(PULDA_ERR_INVALID_ARG, "null argument");
+    if (!f->ws) return fail(PULDA_ERR_STATE, "no workspace bound");
+    hipStream_t s = (hipStream_t)stream;
+    const int32_t K = f->model->K;
+    std::vector<int32_t> fin;
+    for (int32_t i = 0; i < f->desc.max_slots && (int32_t)fin.size() < cap; ++i)
+        if (f->resident[i] && f->slots[i].done >= f->desc.sweeps) fin.push_back(i);
+    *n_done = 0;
+    if (fin.empty()) return PULDA_OK;
+    std::vector<int32_t> kept(2 * f->desc.max_slots);
+    std::vector<double> ll(f->desc.max_slots);
+    HIP_TRY(hipMemcpyAsync(kept.data(), f->f.kept, kept.size() * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(ll.data(), f->f.ll, ll.size() * 8, hipMemcpyDeviceToHost, s));
+    for (size_t j = 0; j < fin.size(); ++j)
+        HIP_TRY(hipMemcpyAsync(theta + j * K, f->f.theta + (int64_t)fin[j] * K, K * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (size_t j = 0; j < fin.size(); ++j) {
+        const int32_t i = fin[j];
+        out[j].request_id = f->slots[i].req;
+        out[j].kept = kept[2 * i];
+        out[j].dropped = kept[2 * i + 1];
+        out[j].pad = 0;
+        out[j].loglik = ll[i];
+        f->resident[i] = 0;
+        arena_free(f, f->slots[i].arena_off, f->slots[i].len);
+    }
+    *n_done = (int32_t)fin.size();
+    return PULDA_OK;
+}
+
+pulda_status pulda_foldin_occupancy(const pulda_foldin *f, int32_t *resident, int32_t *free_slots,
+                                    int32_t *free_tokens)
+{
+    if (!f) return fail(PULDA_ERR_INVALID_ARG, "null argument");
+    int32_t r = 0;
+    for (int32_t x : f->resident) r += x;
+    if (resident) *resident = r;
+    if (free_slots) *free_slots = f->desc.max_slots - r;
+    if (free_tokens) *free_tokens = f->free_tokens;
+    return PULDA_OK;
+}
+
+pulda_status pulda_foldin_run_one(pulda_foldin *f, uint32_t req, const int32_t *words, int32_t len, float *theta,
+                                  pulda_foldin_result *out, void *stream)
+{
+    if (!f || !theta || !out) return fail(PULDA_ERR_INVALID_ARG, "null argument");
+    int32_t r = 0;
+    for (int32_t x : f->resident) r += x;
+    if (r) return fail(PULDA_ERR_STATE, "the server holds %d requests", r);
+    pulda_status st = pulda_foldin_submit(f, req, words, len, stream);
+    if (st != PULDA_OK) return st;
+    st = pulda_foldin_step(f, f->desc.sweeps, stream);
+    if (st != PULDA_OK) return st;
+    int32_t n = 0;
+    st = pulda_foldin_poll(f, out, theta, 1, &n, stream);
+    if (st != PULDA_OK) return st;
+    if (n != 1) return fail(PULDA_ERR_DEVICE, "request did not finish");
+    return PULDA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,106 @@
+// Internal declarations shared by the kernels and the C ABI (not installed).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pulda {
+
+// device buffers of one model, carved from the caller's workspace
+struct DevModel {
+    int32_t K, V, L;
+    double beta;
+    uint32_t key0, key1;
+    const double *alpha;          // [K]
+    // counts of the current state (word-major dense: n[v*K + k])
+    int32_t *n;
+    unsigned long long *nk;       // [K]
+    // Phi-step
+    int32_t *gam;                 // [V*K] Poisson draws, word-major dense
+    unsigned long long *S;        // [K] row sums
+    float *phid;                  // [V*K] dense phi, word-major
+    int32_t *colcnt;              // [V]
+    int32_t *colptr;              // [V+1]
+    uint16_t *ctopic;             // [cap] CSC by word, ascending topic
+    float *cphi;                  // [cap]
+    uint64_t *calias;             // [cap] thr | topic << 32 | alias_topic << 48
+    double *sigma_a;              // [V]
+    const uint64_t *pois;         // Poisson alias tables, thr | x_alias << 32
+    const int32_t *pois_off;      // [L+2]
+    uint32_t ztp[5];              // zero-truncated Pois(beta) thresholds
+    const uint32_t *tptr;         // sweep number t, read on the device
+    long long *scratch;           // scan scratch: ceil(max(V, D) / 1024) + 2 entries
+};
+
+struct DevCorpus {
+    int64_t D, N;
+    const int64_t *doc_off;
+    const int32_t *words;
+    uint16_t *z;
+    const int32_t *doc_order;     // documents by decreasing length
+};
+
+// a unit of z-step work: `count` documents of doc_order starting at `first`,
+// processed by groups of `group` lanes
+struct WorkItem {
+    int32_t first, count, group, pad;
+};
+
+enum StatIndex { ST_DEGENERATE = 0, ST_SUM_J = 1, ST_SUM_A = 2, ST_NNZ_PHI = 3, ST_EMPTY_ROWS = 4, ST_TOKENS = 5,
+                 ST_COUNT = 8 };
+
+// launchers (stream-ordered; return the launch status)
+hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long *p, unsigned long long value, int64_t count, hipStream_t s);
+hipError_t launch_validate(const DevCorpus &c, int32_t V, int32_t *err, hipStream_t s);
+hipError_t launch_init_z(const DevCorpus &c, int32_t K, uint32_t key0, uint32_t key1, hipStream_t s);
+hipError_t launch_count_rebuild(const DevCorpus &c, const DevModel &m, hipStream_t s);
+hipError_t launch_row_sums(const int32_t *dense, int32_t V, int32_t K, unsigned long long *out, hipStream_t s);
+hipError_t launch_phi_step(const DevModel &m, unsigned long long *stats, hipStream_t s);
+hipError_t launch_z_step(const DevCorpus &c, const DevModel &m, const WorkItem *items, int32_t n_items,
+                         int32_t n_waves, int32_t *queue, unsigned long long *stats, hipStream_t s);
+hipError_t launch_loglik(const DevCorpus &c, const DevModel &m, double A, double *partials, int32_t n_part_words,
+                         int32_t n_part_docs, double *out, double *hist, const uint32_t *hist_idx, hipStream_t s);
+hipError_t launch_advance(uint32_t *tptr, uint32_t *hist_idx, hipStream_t s);
+hipError_t launch_n_colcount(const DevModel &m, int64_t *cnt, hipStream_t s);
+hipError_t launch_export_phi(const DevModel &m, int64_t *colptr64, uint16_t *topic, int32_t *gam_e, float *phi_e,
+                             uint32_t *thr, uint16_t *alias_topic, hipStream_t s);
+hipError_t launch_import_phi(const DevModel &m, const int64_t *colptr64, const uint16_t *topic, const float *phi_e,
+                             const uint32_t *thr, const uint16_t *alias_topic, hipStream_t s);
+hipError_t launch_counts_csc(const DevModel &m, const int64_t *colptr64, uint16_t *topic, int32_t *cnt,
+                             int32_t *colcnt_scratch, hipStream_t s);
+hipError_t launch_counts_m(const DevCorpus &c, int32_t K, int64_t *rowcnt_or_ptr, uint16_t *topic, int32_t *cnt,
+                           int pass, hipStream_t s);
+hipError_t launch_check_u16_below(const uint16_t *x, int64_t n, uint32_t limit, int32_t *err, hipStream_t s);
+hipError_t launch_check_phi(const int64_t *colptr, int32_t V, const uint16_t *topic, const uint16_t *alias_topic,
+                            uint32_t K, int32_t *err, hipStream_t s);
+hipError_t launch_scan_i64(const int64_t *in, int64_t *out_excl, int64_t n, long long *scratch, hipStream_t s);
+
+// fold-in
+// host-written control of a resident request
+struct FoldSlot {
+    int32_t arena_off;  // first token of the slot's region in the arena
+    int32_t len;        // request length
+    uint32_t req;       // request id
+    int32_t done;       // sweeps completed before this step
+    int32_t todo;       // sweeps to run in this step
+    int32_t pad[3];
+};
+
+struct DevFoldin {
+    int32_t sweeps, burn_in, group;
+    uint32_t key0, key1;
+    double A;
+    const FoldSlot *slots;  // [max_slots] control, written by the host
+    int32_t *kept;          // [2*max_slots] kept, dropped: written by the device
+    int32_t *words;         // arena [arena_tokens]
+    int32_t *pos;           // arena: kept positions
+    uint16_t *z;            // arena
+    uint32_t *acc;          // [max_slots*K]
+    float *theta;           // [max_slots*K]
+    double *ll;             // [max_slots]
+};
+
+hipError_t launch_foldin_step(const DevModel &m, const DevFoldin &f, const int32_t *active, int32_t n_active,
+                              hipStream_t s);
+
+}  // namespace pulda

@@ -1,0 +1,1227 @@
+// HIP kernels of the Polya-urn partially collapsed LDA sampler for gfx950.
+//
+// Algorithm 2 of the paper (Section 3): every sweep draws each topic row
+// phi_k ~ PPU(n_k + beta) (the Phi-step), then every token's topic from
+// P(z_i = k) propto phi_{k,v(i)} (alpha_k + m^{-i}_{d,k}) (the z-step), and the
+// counts n, m are rebuilt from z.  Section 3.4 gives the Poisson draws (alias
+// tables for rates beta + l, l <= L; rounded Gaussian above), Section 3.5 the
+// a/b split of the token conditional and the doubly sparse b-sum.
+//
+// Layouts in HBM (all word-major, so one word's column is contiguous):
+//   n[v*K + k], gam[v*K + k], phid[v*K + k]    dense K x V tables
+//   colptr[v] .. colptr[v+1]                    CSC of Phi's nonzeros by word,
+//     ctopic (u16, ascending), cphi (f32), calias (u64: thr | topic << 32 |
+//     alias topic << 48)
+//   doc_off[d] .. doc_off[d+1]                  CSR tokens, words (i32), z (u16)
+#include <hip/hip_runtime.h>
+
+#include "device.h"
+#include "internal.h"
+
+namespace pulda {
+
+// ---------------------------------------------------------------------------
+// small utilities
+// ---------------------------------------------------------------------------
+__global__ void fill_u32_kernel(uint32_t *p, uint32_t value, int64_t count)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+__global__ void fill_u64_kernel(unsigned long long *p, unsigned long long value, int64_t count)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+static int grid_for(int64_t n, int block, int cap = 65536)
+{
+    int64_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    fill_u32_kernel<<<grid_for(count, 256, 16384), 256, 0, s>>>(p, value, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(unsigned long long *p, unsigned long long value, int64_t count, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    fill_u64_kernel<<<grid_for(count, 256, 16384), 256, 0, s>>>(p, value, count);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// exclusive scans (three passes: block sums, scan of block sums, add-back)
+// ---------------------------------------------------------------------------
+constexpr int SCAN_BLOCK = 1024;
+
+template <typename Tin>
+__global__ void scan_block_sums(const Tin *in, int64_t n, long long *bsum)
+{
+    __shared__ long long part[SCAN_BLOCK / 64];
+    int64_t i = blockIdx.x * (int64_t)SCAN_BLOCK + threadIdx.x;
+    long long x = i < n ? (long long)in[i] : 0;
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long t = 0;
+        for (int w = 0; w < SCAN_BLOCK / 64; ++w) t += part[w];
+        bsum[blockIdx.x] = t;
+    }
+}
+
+__global__ void scan_sums_serial(long long *bsum, int64_t nb, long long *total)
+{
+    // one block: each thread scans a contiguous chunk, then chunk offsets are combined
+    __shared__ long long chunk[1024];
+    int64_t per = (nb + blockDim.x - 1) / blockDim.x;
+    int64_t a = threadIdx.x * per, b = a + per < nb ? a + per : nb;
+    long long t = 0;
+    for (int64_t i = a; i < b; ++i) t += bsum[i];
+    chunk[threadIdx.x] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long run = 0;
+        for (int j = 0; j < (int)blockDim.x; ++j) {
+            long long c = chunk[j];
+            chunk[j] = run;
+            run += c;
+        }
+        if (total) *total = run;
+    }
+    __syncthreads();
+    long long run = chunk[threadIdx.x];
+    for (int64_t i = a; i < b; ++i) {
+        long long c = bsum[i];
+        bsum[i] = run;
+        run += c;
+    }
+}
+
+template <typename Tin, typename Tout>
+__global__ void scan_apply(const Tin *in, int64_t n, const long long *boff, Tout *out)
+{
+    __shared__ long long wsum[SCAN_BLOCK / 64];
+    int64_t i = blockIdx.x * (int64_t)SCAN_BLOCK + threadIdx.x;
+    long long x = i < n ? (long long)in[i] : 0;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    long long incl = x;
+    for (int o = 1; o < 64; o <<= 1) {
+        long long y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    long long before = boff[blockIdx.x];
+    for (int j = 0; j < w; ++j) before += wsum[j];
+    if (i < n) out[i] = (Tout)(before + incl - x);
+    if (i == n - 1) out[n] = (Tout)(before + incl);
+}
+
+template <typename Tin, typename Tout>
+static hipError_t scan_excl(const Tin *in, Tout *out, int64_t n, long long *scratch, long long *total,
+                            hipStream_t s)
+{
+    // out has n + 1 entries; scratch holds ceil(n / SCAN_BLOCK) entries
+    if (n <= 0) {
+        scan_sums_serial<<<1, 64, 0, s>>>(scratch, 0, total);
+        return hipGetLastError();
+    }
+    int64_t nb = (n + SCAN_BLOCK - 1) / SCAN_BLOCK;
+    scan_block_sums<Tin><<<(unsigned)nb, SCAN_BLOCK, 0, s>>>(in, n, scratch);
+    scan_sums_serial<<<1, 1024, 0, s>>>(scratch, nb, total);
+    scan_apply<Tin, Tout><<<(unsigned)nb, SCAN_BLOCK, 0, s>>>(in, n, scratch, out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// corpus validation: monotone offsets from 0 to N, word ids in [0, V),
+// document lengths within the 16-bit per-document count range
+// ---------------------------------------------------------------------------
+__global__ void validate_kernel(const int64_t *doc_off, int64_t D, const int32_t *words, int64_t N, int32_t V,
+                                int32_t *err)
+{
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t d = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; d < D; d += stride) {
+        int64_t a = doc_off[d], b = doc_off[d + 1];
+        if (b < a || a < 0 || b > N) atomicAdd(&err[0], 1);
+        else if (b - a > 65535) atomicAdd(&err[2], 1);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (doc_off[0] != 0 || doc_off[D] != N) atomicAdd(&err[0], 1);
+    }
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += stride) {
+        int32_t w = words[i];
+        if (w < 0 || w >= V) atomicAdd(&err[1], 1);
+    }
+}
+
+hipError_t launch_validate(const DevCorpus &c, int32_t V, int32_t *err, hipStream_t s)
+{
+    validate_kernel<<<grid_for(c.N > c.D ? c.N : c.D, 256, 8192), 256, 0, s>>>(c.doc_off, c.D, c.words, c.N, V, err);
+    return hipGetLastError();
+}
+
+// caller-supplied state and Phi: every topic below K, columns well formed
+__global__ void check_u16_below_kernel(const uint16_t *x, int64_t n, uint32_t limit, int32_t *err)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        if (x[i] >= limit) atomicAdd(err, 1);
+}
+
+hipError_t launch_check_u16_below(const uint16_t *x, int64_t n, uint32_t limit, int32_t *err, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    check_u16_below_kernel<<<grid_for(n, 256, 8192), 256, 0, s>>>(x, n, limit, err);
+    return hipGetLastError();
+}
+
+__global__ void check_phi_kernel(const int64_t *colptr, int32_t V, const uint16_t *topic, const uint16_t *alias_topic,
+                                 uint32_t K, int32_t *err)
+{
+    const int32_t v = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (v >= V) return;
+    const int lane = __lane_id();
+    const int64_t a = colptr[v], b = colptr[v + 1];
+    if (b < a || b - a > (int64_t)K) {
+        if (lane == 0) atomicAdd(err, 1);
+        return;
+    }
+    for (int64_t e = a + lane; e < b; e += 64) {
+        const bool ok = topic[e] < K && alias_topic[e] < K && (e == a || topic[e - 1] < topic[e]);
+        if (!ok) atomicAdd(err, 1);
+    }
+}
+
+hipError_t launch_check_phi(const int64_t *colptr, int32_t V, const uint16_t *topic, const uint16_t *alias_topic,
+                            uint32_t K, int32_t *err, hipStream_t s)
+{
+    check_phi_kernel<<<(V + 3) / 4, 256, 0, s>>>(colptr, V, topic, alias_topic, K, err);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// initial state: z_i uniform on {0..K-1}
+// ---------------------------------------------------------------------------
+__global__ void init_z_kernel(uint16_t *z, int64_t N, int32_t K, uint32_t key0, uint32_t key1)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+        r4 r = philox((uint32_t)i, (uint32_t)((uint64_t)i >> 32), 0u, TAG_INIT, key0, key1);
+        z[i] = (uint16_t)scale32(r.x, (uint32_t)K);
+    }
+}
+
+hipError_t launch_init_z(const DevCorpus &c, int32_t K, uint32_t key0, uint32_t key1, hipStream_t s)
+{
+    if (c.N == 0) return hipSuccess;
+    init_z_kernel<<<grid_for(c.N, 256, 16384), 256, 0, s>>>(c.z, c.N, K, key0, key1);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// count rebuild from z (Table 1): n[v*K + k] += 1 for every token
+// ---------------------------------------------------------------------------
+__global__ void count_tokens_kernel(const int32_t *words, const uint16_t *z, int64_t N, int32_t K, int32_t *n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&n[(int64_t)words[i] * K + z[i]], 1);
+}
+
+hipError_t launch_count_rebuild(const DevCorpus &c, const DevModel &m, hipStream_t s)
+{
+    hipError_t e = launch_fill_u32((uint32_t *)m.n, 0u, (int64_t)m.V * m.K, s);
+    if (e != hipSuccess) return e;
+    if (c.N == 0) return hipSuccess;
+    count_tokens_kernel<<<grid_for(c.N, 256, 16384), 256, 0, s>>>(c.words, c.z, c.N, m.K, m.n);
+    return hipGetLastError();
+}
+
+// column sums of a word-major V x K table: out[k] += sum_v dense[v*K + k]
+constexpr int ROWSUM_COLS = 256;
+
+__global__ void row_sums_kernel(const int32_t *dense, int32_t V, int32_t K, unsigned long long *out)
+{
+    const int32_t v0 = blockIdx.x * ROWSUM_COLS;
+    const int32_t v1 = v0 + ROWSUM_COLS < V ? v0 + ROWSUM_COLS : V;
+    for (int32_t k = threadIdx.x; k < K; k += blockDim.x) {
+        unsigned long long t = 0;
+        for (int32_t v = v0; v < v1; ++v) t += (unsigned long long)(uint32_t)dense[(int64_t)v * K + k];
+        if (t) atomicAdd(&out[k], t);
+    }
+}
+
+hipError_t launch_row_sums(const int32_t *dense, int32_t V, int32_t K, unsigned long long *out, hipStream_t s)
+{
+    hipError_t e = launch_fill_u64(out, 0ull, K, s);
+    if (e != hipSuccess) return e;
+    row_sums_kernel<<<(V + ROWSUM_COLS - 1) / ROWSUM_COLS, 256, 0, s>>>(dense, V, K, out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Phi-step, part 1 (Section 3.4): one wave per word column v.
+//   counted cells (n_kv = l >= 1) draw Pois(beta + l): alias table of l for
+//   l <= L, rounded Gaussian for l > L;
+//   zero-count cells draw Pois(beta); the nonzero ones are reached by
+//   geometric jumps (gap = floor(-ln(1-U)/beta)), 64 jumps per round, their
+//   positions by a wave prefix sum of the jump lengths.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) phi_draw_kernel(DevModel m, int32_t kpad)
+{
+    const uint32_t t = *m.tptr;
+    extern __shared__ int32_t phi_lds[];
+    const int lane = __lane_id();
+    const int w = threadIdx.x >> 6;
+    const int32_t v = blockIdx.x * 4 + w;
+    if (v >= m.V) return;
+    int32_t *g = phi_lds + w * kpad;
+    const int32_t K = m.K;
+    const int32_t *ncol = m.n + (int64_t)v * K;
+    const double two_pi = 6.283185307179586476925286766559;
+
+    for (int32_t k = lane; k < K; k += 64) {
+        const int32_t l = ncol[k];
+        int32_t x = -1;  // -1 marks a zero-count cell
+        if (l > 0) {
+            r4 r = philox((uint32_t)v, (uint32_t)k, t, TAG_PHI_CELL, m.key0, m.key1);
+            if (l <= m.L) {
+                const int32_t off = m.pois_off[l];
+                const uint32_t sz = (uint32_t)(m.pois_off[l + 1] - off);
+                const uint32_t j = scale32(r.x, sz);
+                const uint64_t e = m.pois[off + j];
+                x = (r.y < (uint32_t)e) ? (int32_t)j : (int32_t)(e >> 32);
+            } else {
+                const double lam = m.beta + (double)l;
+                const double rad = sqrt(-2.0 * log(1.0 - unit53(r.x, r.y)));
+                const double gz = rad * cos(two_pi * unit53(r.z, r.w));
+                const double y = floor(lam + sqrt(lam) * gz + 0.5);
+                x = y > 0.0 ? (int32_t)y : 0;
+            }
+        }
+        g[k] = x;
+    }
+    __builtin_amdgcn_wave_barrier();
+
+    long long pos_base = -1;
+    for (uint32_t jb = 0;; jb += 64) {
+        r4 r = philox((uint32_t)v, jb + (uint32_t)lane, t, TAG_PHI_PRIOR, m.key0, m.key1);
+        const double e = -log(1.0 - unit53(r.x, r.y)) / m.beta;
+        // a jump longer than K ends the column whatever its exact length
+        const double capped = e < (double)K ? floor(e) : (double)K;
+        const int32_t step = 1 + (int32_t)capped;
+        const int32_t incl = group_scan_incl_i32<64>(step);
+        const long long pos = pos_base + incl;
+        if (pos < K) {
+            int32_t *cell = &g[pos];
+            if (*cell == -1) {
+                int32_t x = 1;
+#pragma unroll
+                for (int q = 0; q < 5; ++q) x += (r.z >= m.ztp[q]) ? 1 : 0;
+                *cell = x;
+            }
+        }
+        const long long last = pos_base + __builtin_amdgcn_readlane(incl, 63);
+        if (last >= K) break;
+        pos_base = last;
+    }
+    __builtin_amdgcn_wave_barrier();
+
+    int32_t cnt = 0;
+    int32_t *gcol = m.gam + (int64_t)v * K;
+    for (int32_t k = lane; k < K; k += 64) {
+        int32_t x = g[k];
+        x = x > 0 ? x : 0;
+        gcol[k] = x;
+        cnt += x > 0;
+    }
+    cnt = group_scan_incl_i32<64>(cnt);
+    if (lane == 63) m.colcnt[v] = cnt;
+}
+
+// ---------------------------------------------------------------------------
+// Phi-step, part 3: normalise (phi = fp32(gamma / S_k), quotient in fp64),
+// compact the column into the CSC, and build the column's alias table for
+// the a-part (weights alpha_k phi_kv; Vose's construction with FIFO work
+// lists in ascending order; sigma_a = ascending fp64 sum of the weights).
+// One wave per column.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(64) phi_fill_kernel(DevModel m, int32_t kpad)
+{
+    extern __shared__ double fill_lds[];
+    const int32_t v = blockIdx.x;
+    const int lane = __lane_id();
+    const int32_t K = m.K;
+    double *w = fill_lds;                                  // weights, then scaled probabilities
+    uint16_t *tk = (uint16_t *)(w + kpad);                 // topic of entry e
+    uint16_t *small = tk + kpad;                           // entries with p < 1, ascending
+    uint16_t *large = small + kpad;                        // entries with p >= 1, ascending
+    uint16_t *ali = large + kpad;                          // alias entry of e
+    uint32_t *thr = (uint32_t *)(ali + kpad);              // threshold of e
+    __shared__ double W_s;
+
+    const int32_t cb = m.colptr[v];
+    const int32_t *gcol = m.gam + (int64_t)v * K;
+    float *pcol = m.phid + (int64_t)v * K;
+    int32_t run = 0;
+    for (int32_t k0 = 0; k0 < K; k0 += 64) {
+        const int32_t k = k0 + lane;
+        int32_t x = k < K ? gcol[k] : 0;
+        float f = 0.0f;
+        if (x > 0) f = (float)((double)x / (double)m.S[k]);
+        if (k < K) pcol[k] = f;
+        const uint64_t bal = __builtin_amdgcn_ballot_w64(x > 0);
+        if (x > 0) {
+            const int32_t e = run + __builtin_popcountll(bal & ((1ull << lane) - 1ull));
+            m.ctopic[cb + e] = (uint16_t)k;
+            m.cphi[cb + e] = f;
+            tk[e] = (uint16_t)k;
+            w[e] = m.alpha[k] * (double)f;
+        }
+        run += __builtin_popcountll(bal);
+    }
+    const int32_t nv = run;
+    __builtin_amdgcn_wave_barrier();
+    if (nv == 0) {
+        if (lane == 0) m.sigma_a[v] = 0.0;
+        return;
+    }
+    if (lane == 0) {
+        double s = 0.0;
+        for (int32_t e = 0; e < nv; ++e) s += w[e];
+        W_s = s;
+        m.sigma_a[v] = s;
+    }
+    __builtin_amdgcn_wave_barrier();
+    const double W = W_s;
+    int32_t ns = 0, nl = 0;
+    for (int32_t e0 = 0; e0 < nv; e0 += 64) {
+        const int32_t e = e0 + lane;
+        bool is_small = false;
+        if (e < nv) {
+            const double p = (w[e] * (double)nv) / W;
+            w[e] = p;
+            is_small = p < 1.0;
+            thr[e] = 0xFFFFFFFFu;
+            ali[e] = (uint16_t)e;
+        }
+        const uint64_t bs = __builtin_amdgcn_ballot_w64(e < nv && is_small);
+        const uint64_t bl = __builtin_amdgcn_ballot_w64(e < nv && !is_small);
+        const uint64_t below = (1ull << lane) - 1ull;
+        if (e < nv) {
+            if (is_small) small[ns + __builtin_popcountll(bs & below)] = (uint16_t)e;
+            else large[nl + __builtin_popcountll(bl & below)] = (uint16_t)e;
+        }
+        ns += __builtin_popcountll(bs);
+        nl += __builtin_popcountll(bl);
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (lane == 0) {
+        // Vose's pairing.  The FIFO of small entries is the initial small
+        // list followed by large entries in the order they turn small, and a
+        // large entry can only turn small at the head of the large list, so
+        // both lists are walked with one index each.
+        int32_t i = 0, gi = 0;
+        double pg = nl > 0 ? w[large[0]] : 0.0;
+        while (gi < nl) {
+            int32_t s;
+            if (i < ns) s = small[i];
+            else if (i - ns < gi) s = large[i - ns];
+            else break;
+            const int32_t gidx = large[gi];
+            const double ps = w[s];
+            thr[s] = (uint32_t)floor(ps * 4294967296.0);
+            ali[s] = (uint16_t)gidx;
+            pg = (pg + ps) - 1.0;
+            ++i;
+            if (pg < 1.0) {
+                w[gidx] = pg;
+                ++gi;
+                if (gi < nl) pg = w[large[gi]];
+            }
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    for (int32_t e = lane; e < nv; e += 64) {
+        const uint64_t entry = (uint64_t)thr[e] | ((uint64_t)tk[e] << 32) | ((uint64_t)tk[ali[e]] << 48);
+        m.calias[cb + e] = entry;
+    }
+}
+
+__global__ void colptr_finish_kernel(const unsigned long long *S, int32_t K, const long long *total,
+                                     unsigned long long *stats)
+{
+    if (threadIdx.x == 0 && stats) {
+        stats[ST_NNZ_PHI] = (unsigned long long)*total;
+    }
+    unsigned long long empty = 0;
+    for (int32_t k = threadIdx.x; k < K; k += blockDim.x) empty += S[k] == 0;
+    for (int o = 32; o > 0; o >>= 1) empty += __shfl_down(empty, o, 64);
+    if ((threadIdx.x & 63) == 0 && empty && stats) atomicAdd(&stats[ST_EMPTY_ROWS], empty);
+}
+
+hipError_t launch_phi_step(const DevModel &m, unsigned long long *stats, hipStream_t s)
+{
+    const int32_t kpad = (m.K + 63) / 64 * 64;
+    phi_draw_kernel<<<(m.V + 3) / 4, 256, 4 * kpad * sizeof(int32_t), s>>>(m, kpad);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = launch_row_sums(m.gam, m.V, m.K, m.S, s);
+    if (e != hipSuccess) return e;
+    long long *scratch = m.scratch;
+    long long *total = scratch + ((m.V + SCAN_BLOCK - 1) / SCAN_BLOCK) + 1;
+    e = scan_excl<int32_t, int32_t>(m.colcnt, m.colptr, m.V, scratch, total, s);
+    if (e != hipSuccess) return e;
+    if (stats) {
+        e = launch_fill_u64(&stats[ST_EMPTY_ROWS], 0ull, 1, s);
+        if (e != hipSuccess) return e;
+        colptr_finish_kernel<<<1, 256, 0, s>>>(m.S, m.K, total, stats);
+    }
+    const size_t lds = (size_t)kpad * (sizeof(double) + 4 * sizeof(uint16_t) + sizeof(uint32_t));
+    phi_fill_kernel<<<m.V, 64, lds, s>>>(m, kpad);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// z-step (Section 3.5).  A group of G lanes (G = 16, 32, 64) owns one
+// document at a time and walks its tokens in stored order (sequential Gibbs
+// within the document).  The document-topic counts m_d live in LDS; lane g
+// owns topics [g*C, (g+1)*C) (C a power of two, C*G >= K) and keeps a C-bit
+// mask of which of them are nonzero.  For each token:
+//   sigma_b = sum_k phi_kv m_k is taken over the smaller of the document's
+//   nonzero topics (lanes walk their own mask bits, phi from the dense
+//   column) and the word's Phi column (lanes walk a contiguous block of its
+//   CSC entries, m from LDS); either way each lane's entries are in
+//   ascending topic order and a group prefix sum orders the lanes, so the
+//   running sums are ascending in k as the definition requires;
+//   u_sigma = u (sigma_a + sigma_b) < sigma_a draws from the word's alias
+//   table, otherwise the crossing lane (first with prefix > u_sigma -
+//   sigma_a) re-walks its entries to find the topic.
+// m_d is stored interleaved (topic g*C + b at LDS slot b*G + g) so the lanes
+// of a group touch consecutive slots.
+// ---------------------------------------------------------------------------
+struct ZArgs {
+    DevModel m;
+    DevCorpus c;
+    const WorkItem *items;
+    int32_t n_items;
+    int32_t lds_per_wave;   // u16 slots per wave
+    int32_t *queue;
+    unsigned long long *stats;
+    int32_t log2c64, log2c32, log2c16;  // log2 of topics per lane for each group size
+};
+
+struct TokenStats {
+    unsigned long long J, A, degenerate;
+};
+
+// draw one token (group-uniform control flow); returns the new topic
+template <int G>
+__device__ __forceinline__ int32_t draw_token(const DevModel &M, int32_t v, int32_t kold, uint32_t r0, uint32_t r1,
+                                              uint32_t r2, uint16_t *mt, int g, int log2c, uint64_t &mask,
+                                              int32_t &Kd, int32_t *n_out, TokenStats &st)
+{
+    const int32_t C = 1 << log2c;
+    const int32_t K = M.K;
+    // remove token i: m^{-i}
+    const int32_t ob = kold & (C - 1), oo = kold >> log2c;
+    const int32_t oslot = ob * G + oo;
+    const int32_t mo = mt[oslot];
+    __builtin_amdgcn_wave_barrier();
+    if (g == oo) {
+        mt[oslot] = (uint16_t)(mo - 1);
+        if (mo == 1) mask &= ~(1ull << ob);
+    }
+    if (mo == 1) --Kd;
+    __builtin_amdgcn_wave_barrier();
+
+    const int32_t cb = M.colptr[v];
+    const int32_t Kv = M.colptr[v + 1] - cb;
+    if (Kv == 0) {
+        // 0/0 conditional: the token keeps its topic
+        if (g == oo) {
+            mt[oslot] = (uint16_t)mo;
+            if (mo == 1) mask |= 1ull << ob;
+        }
+        if (mo == 1) ++Kd;
+        __builtin_amdgcn_wave_barrier();
+        if (g == 0) {
+            st.degenerate++;
+            if (n_out) atomicAdd(&n_out[(int64_t)v * K + kold], 1);
+        }
+        return kold;
+    }
+    const double sa = M.sigma_a[v];
+    const bool docside = Kd <= Kv;
+    const float *pcol = M.phid + (int64_t)v * K;
+    int32_t e0 = 0, e1 = 0;
+    double p = 0.0;
+    if (docside) {
+        uint64_t mm = mask;
+        while (mm) {
+            const int b = __builtin_ctzll(mm);
+            mm &= mm - 1;
+            p += (double)pcol[(g << log2c) + b] * (double)mt[b * G + g];
+        }
+    } else {
+        const int32_t q = (Kv + G - 1) / G;
+        e0 = g * q;
+        e1 = e0 + q < Kv ? e0 + q : Kv;
+        for (int32_t e = e0; e < e1; ++e) {
+            const int32_t k = M.ctopic[cb + e];
+            p += (double)M.cphi[cb + e] * (double)mt[(k & (C - 1)) * G + (k >> log2c)];
+        }
+    }
+    const double incl = group_scan_incl<G>(p);
+    const double T = group_bcast_f64<G>(incl, G - 1);
+    const double Z = sa + T;
+    const double x = unit24(r0) * Z;
+    int32_t knew;
+    if (x < sa) {
+        const uint32_t j = scale32(r1, (uint32_t)Kv);
+        const uint64_t a = M.calias[cb + j];
+        knew = (r2 < (uint32_t)a) ? (int32_t)((a >> 32) & 0xFFFFu) : (int32_t)(a >> 48);
+        if (g == 0) st.A++;
+    } else {
+        const double y = x - sa;
+        uint64_t bal = group_ballot<G>(incl > y);
+        int f;
+        if (bal) {
+            f = __builtin_ctzll(bal);
+        } else {
+            const uint64_t pos = group_ballot<G>(p > 0.0);
+            f = pos ? 63 - __builtin_clzll(pos) : 0;
+        }
+        int32_t kf = -1;
+        if (g == f) {
+            double c = incl - p;
+            int32_t last = -1;
+            if (docside) {
+                uint64_t mm = mask;
+                while (mm) {
+                    const int b = __builtin_ctzll(mm);
+                    mm &= mm - 1;
+                    const int32_t k = (g << log2c) + b;
+                    const double bv = (double)pcol[k] * (double)mt[b * G + g];
+                    if (bv > 0.0) {
+                        c += bv;
+                        last = k;
+                        if (c > y) {
+                            kf = k;
+                            break;
+                        }
+                    }
+                }
+            } else {
+                for (int32_t e = e0; e < e1; ++e) {
+                    const int32_t k = M.ctopic[cb + e];
+                    const double bv = (double)M.cphi[cb + e] * (double)mt[(k & (C - 1)) * G + (k >> log2c)];
+                    if (bv > 0.0) {
+                        c += bv;
+                        last = k;
+                        if (c > y) {
+                            kf = k;
+                            break;
+                        }
+                    }
+                }
+            }
+            if (kf < 0) kf = last;
+        }
+        knew = group_bcast<G>(kf, f);
+        if (knew < 0) {
+            // no positive b-term survived rounding: the a-part is the whole law
+            const uint32_t j = scale32(r1, (uint32_t)Kv);
+            const uint64_t a = M.calias[cb + j];
+            knew = (r2 < (uint32_t)a) ? (int32_t)((a >> 32) & 0xFFFFu) : (int32_t)(a >> 48);
+        }
+    }
+    if (g == 0) st.J += (unsigned long long)(Kd < Kv ? Kd : Kv);
+    // add token i back with its new topic
+    const int32_t nb = knew & (C - 1), no = knew >> log2c;
+    const int32_t nslot = nb * G + no;
+    const int32_t mn = mt[nslot];
+    __builtin_amdgcn_wave_barrier();
+    if (g == no) {
+        mt[nslot] = (uint16_t)(mn + 1);
+        if (mn == 0) mask |= 1ull << nb;
+    }
+    if (mn == 0) ++Kd;
+    __builtin_amdgcn_wave_barrier();
+    if (g == 0 && n_out) atomicAdd(&n_out[(int64_t)v * K + knew], 1);
+    return knew;
+}
+
+// load a document's topic counts into the group's LDS table and masks
+template <int G>
+__device__ __forceinline__ void load_doc_counts(uint16_t *mt, const uint16_t *z, int64_t s, int64_t e, int g,
+                                                int log2c, uint64_t &mask, int32_t &Kd)
+{
+    const int32_t C = 1 << log2c;
+    for (int32_t i = g; i < C * G; i += G) mt[i] = 0;
+    __builtin_amdgcn_wave_barrier();
+    for (int64_t i = s + g; i < e; i += G) {
+        const int32_t k = z[i];
+        const int32_t slot = (k & (C - 1)) * G + (k >> log2c);
+        uint32_t *word = (uint32_t *)(mt + (slot & ~1));
+        atomicAdd(word, (slot & 1) ? 65536u : 1u);
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    mask = 0;
+    for (int32_t b = 0; b < C; ++b)
+        if (mt[b * G + g]) mask |= 1ull << b;
+    const int32_t cnt = __builtin_popcountll(mask);
+    const int32_t tot = group_scan_incl_i32<G>(cnt);
+    Kd = group_bcast<G>(tot, G - 1);
+}
+
+template <int G>
+__device__ void z_step_item(const ZArgs &a, const WorkItem &w, uint16_t *wave_lds, TokenStats &st)
+{
+    constexpr int NG = 64 / G;
+    const int lane = __lane_id();
+    const int g = lane & (G - 1);
+    const int grp = lane / G;
+    const int log2c = G == 64 ? a.log2c64 : (G == 32 ? a.log2c32 : a.log2c16);
+    const int32_t C = 1 << log2c;
+    uint16_t *mt = wave_lds + grp * (C * G);
+    const DevModel &M = a.m;
+    const uint32_t t = *M.tptr;
+    for (int32_t di = grp; di < w.count; di += NG) {
+        const int32_t d = a.c.doc_order[w.first + di];
+        const int64_t s = a.c.doc_off[d], e = a.c.doc_off[d + 1];
+        if (s == e) continue;
+        uint64_t mask;
+        int32_t Kd;
+        load_doc_counts<G>(mt, a.c.z, s, e, g, log2c, mask, Kd);
+        for (int64_t i0 = s; i0 < e; i0 += G) {
+            const int64_t i = i0 + g;
+            const bool valid = i < e;
+            int32_t wv = 0, zo = 0;
+            uint32_t r0 = 0, r1 = 0, r2 = 0;
+            if (valid) {
+                wv = a.c.words[i];
+                zo = a.c.z[i];
+                const r4 r = philox((uint32_t)i, (uint32_t)((uint64_t)i >> 32), t, TAG_Z, M.key0, M.key1);
+                r0 = r.x;
+                r1 = r.y;
+                r2 = r.z;
+            }
+            int32_t znew = zo;
+            const int nb = (int)((e - i0) < G ? (e - i0) : G);
+            for (int jj = 0; jj < nb; ++jj) {
+                const int32_t v = group_bcast<G>(wv, jj);
+                const int32_t kold = group_bcast<G>(zo, jj);
+                const uint32_t q0 = (uint32_t)group_bcast<G>((int)r0, jj);
+                const uint32_t q1 = (uint32_t)group_bcast<G>((int)r1, jj);
+                const uint32_t q2 = (uint32_t)group_bcast<G>((int)r2, jj);
+                const int32_t k = draw_token<G>(M, v, kold, q0, q1, q2, mt, g, log2c, mask, Kd, M.n, st);
+                if (g == jj) znew = k;
+            }
+            if (valid) a.c.z[i] = (uint16_t)znew;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) z_step_kernel(ZArgs a)
+{
+    extern __shared__ uint16_t z_lds[];
+    const int wave = threadIdx.x >> 6;
+    uint16_t *wave_lds = z_lds + wave * a.lds_per_wave;
+    TokenStats st = {0, 0, 0};
+    while (true) {
+        int item = 0;
+        if (__lane_id() == 0) item = atomicAdd(a.queue, 1);
+        item = __builtin_amdgcn_readlane(item, 0);
+        if (item >= a.n_items) break;
+        const WorkItem w = a.items[item];
+        if (w.group == 64) z_step_item<64>(a, w, wave_lds, st);
+        else if (w.group == 32) z_step_item<32>(a, w, wave_lds, st);
+        else z_step_item<16>(a, w, wave_lds, st);
+    }
+    if (a.stats && (__lane_id() & 15) == 0) {
+        if (st.J) atomicAdd(&a.stats[ST_SUM_J], st.J);
+        if (st.A) atomicAdd(&a.stats[ST_SUM_A], st.A);
+        if (st.degenerate) atomicAdd(&a.stats[ST_DEGENERATE], st.degenerate);
+    }
+}
+
+static int ilog2(int x)
+{
+    int r = 0;
+    while ((1 << r) < x) ++r;
+    return r;
+}
+
+static int topics_per_lane_log2(int K, int G)
+{
+    int c = ilog2((K + G - 1) / G);
+    return c;
+}
+
+hipError_t launch_z_step(const DevCorpus &c, const DevModel &m, const WorkItem *items, int32_t n_items,
+                         int32_t n_waves, int32_t *queue, unsigned long long *stats, hipStream_t s)
+{
+    hipError_t e;
+    if (m.n) {
+        e = launch_fill_u32((uint32_t *)m.n, 0u, (int64_t)m.V * m.K, s);
+        if (e != hipSuccess) return e;
+    }
+    if (stats) {
+        e = launch_fill_u64(stats, 0ull, 3, s);  // degenerate, sum_J, sum_A
+        if (e != hipSuccess) return e;
+    }
+    e = launch_fill_u32((uint32_t *)queue, 0u, 1, s);
+    if (e != hipSuccess) return e;
+    if (n_items == 0) return hipSuccess;
+    ZArgs a;
+    a.m = m;
+    a.c = c;
+    a.items = items;
+    a.n_items = n_items;
+    a.queue = queue;
+    a.stats = stats;
+    a.log2c64 = topics_per_lane_log2(m.K, 64);
+    a.log2c32 = topics_per_lane_log2(m.K, 32);
+    a.log2c16 = topics_per_lane_log2(m.K, 16);
+    // a wave holds 64/G tables of C*G slots: 64*C slots, largest for the
+    // smallest group size that is valid for K (C <= 64)
+    int per_wave = 64 << a.log2c64;
+    if (a.log2c32 <= 6) per_wave = 64 << a.log2c32;
+    if (a.log2c16 <= 6) per_wave = 64 << a.log2c16;
+    a.lds_per_wave = per_wave;
+    const int blocks = (n_waves + 3) / 4;
+    z_step_kernel<<<blocks, 256, 4 * per_wave * sizeof(uint16_t), s>>>(a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Collapsed log joint (Section 4 reports it per iteration):
+//   words: K lgamma(V beta) - sum_k lgamma(n_k + V beta)
+//          + sum_{k,v: n_kv > 0} [lgamma(n_kv + beta) - lgamma(beta)]
+//   docs:  sum_d [lgamma(A) - lgamma(N_d + A)
+//          + sum_{k: m_dk > 0} (lgamma(m_dk + alpha_k) - lgamma(alpha_k))]
+// Partial sums per block in a fixed order, then one fixed-order reduction,
+// so the value is the same on every run.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double block_sum_f64(double x, double *red)
+{
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int wv = 0; wv < (int)(blockDim.x >> 6); ++wv) t += red[wv];
+    return t;
+}
+
+__global__ void __launch_bounds__(256) ll_words_kernel(const int32_t *n, int64_t cells, double beta, double lgb,
+                                                       double *partials)
+{
+    __shared__ double red[4];
+    double acc = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cells; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t c = n[i];
+        if (c > 0) acc += lgamma((double)c + beta) - lgb;
+    }
+    const double t = block_sum_f64(acc, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+__global__ void __launch_bounds__(256) ll_docs_kernel(DevCorpus c, int32_t K, const double *alpha, double A,
+                                                      double lgA, int32_t log2c, double *partials)
+{
+    extern __shared__ uint16_t ll_lds[];
+    __shared__ double red[4];
+    const int lane = __lane_id();
+    const int wv = threadIdx.x >> 6;
+    const int32_t C = 1 << log2c;
+    uint16_t *mt = ll_lds + wv * (64 * C);
+    double acc = 0.0;
+    const int64_t nw = (int64_t)gridDim.x * 4;
+    for (int64_t d = blockIdx.x * 4 + wv; d < c.D; d += nw) {
+        const int64_t s = c.doc_off[d], e = c.doc_off[d + 1];
+        for (int32_t i = lane; i < 64 * C; i += 64) mt[i] = 0;
+        __builtin_amdgcn_wave_barrier();
+        for (int64_t i = s + lane; i < e; i += 64) {
+            const int32_t k = c.z[i];
+            const int32_t slot = (k & (C - 1)) * 64 + (k >> log2c);
+            atomicAdd((uint32_t *)(mt + (slot & ~1)), (slot & 1) ? 65536u : 1u);
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        double part = 0.0;
+        for (int32_t b = 0; b < C; ++b) {
+            const int32_t cnt = mt[b * 64 + lane];
+            if (cnt) {
+                const int32_t k = lane * C + b;
+                part += lgamma((double)cnt + alpha[k]) - lgamma(alpha[k]);
+            }
+        }
+        if (lane == 0) part += lgA - lgamma((double)(e - s) + A);
+        acc += part;
+    }
+    const double t = block_sum_f64(acc, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+__global__ void ll_final_kernel(const double *partials, int32_t np, const unsigned long long *nk, int32_t K,
+                                double Vbeta, double *out, double *hist, const uint32_t *hist_idx)
+{
+    if (threadIdx.x != 0) return;
+    double word = (double)K * lgamma(Vbeta);
+    for (int32_t k = 0; k < K; ++k) word -= lgamma((double)nk[k] + Vbeta);
+    double t = 0.0;
+    for (int32_t i = 0; i < np; ++i) t += partials[i];
+    *out = word + t;
+    if (hist) hist[*hist_idx] = word + t;
+}
+
+__global__ void advance_kernel(uint32_t *tptr, uint32_t *hist_idx)
+{
+    if (threadIdx.x == 0) {
+        *tptr += 1u;
+        *hist_idx += 1u;
+    }
+}
+
+hipError_t launch_advance(uint32_t *tptr, uint32_t *hist_idx, hipStream_t s)
+{
+    advance_kernel<<<1, 64, 0, s>>>(tptr, hist_idx);
+    return hipGetLastError();
+}
+
+hipError_t launch_loglik(const DevCorpus &c, const DevModel &m, double A, double *partials, int32_t n_part_words,
+                         int32_t n_part_docs, double *out, double *hist, const uint32_t *hist_idx, hipStream_t s)
+{
+    hipError_t e = launch_row_sums(m.n, m.V, m.K, m.nk, s);
+    if (e != hipSuccess) return e;
+    ll_words_kernel<<<n_part_words, 256, 0, s>>>(m.n, (int64_t)m.V * m.K, m.beta, lgamma(m.beta), partials);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int log2c = topics_per_lane_log2(m.K, 64);
+    ll_docs_kernel<<<n_part_docs, 256, 4 * 64 * (1 << log2c) * sizeof(uint16_t), s>>>(
+        c, m.K, m.alpha, A, lgamma(A), log2c, partials + n_part_words);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    ll_final_kernel<<<1, 64, 0, s>>>(partials, n_part_words + n_part_docs, m.nk, m.K, (double)m.V * m.beta, out,
+                                     hist, hist_idx);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Phi export / import (parity tests; serving models built elsewhere)
+// ---------------------------------------------------------------------------
+__global__ void export_phi_kernel(DevModel m, int64_t *colptr64, uint16_t *topic, int32_t *gam_e, float *phi_e,
+                                  uint32_t *thr, uint16_t *alias_topic)
+{
+    const int32_t v = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (v >= m.V) return;
+    const int lane = __lane_id();
+    const int32_t a = m.colptr[v], b = m.colptr[v + 1];
+    if (lane == 0) {
+        colptr64[v] = a;
+        if (v == m.V - 1) colptr64[m.V] = b;
+    }
+    for (int32_t e = a + lane; e < b; e += 64) {
+        const int32_t k = m.ctopic[e];
+        topic[e] = (uint16_t)k;
+        phi_e[e] = m.cphi[e];
+        gam_e[e] = m.gam[(int64_t)v * m.K + k];
+        const uint64_t al = m.calias[e];
+        thr[e] = (uint32_t)al;
+        alias_topic[e] = (uint16_t)(al >> 48);
+    }
+}
+
+hipError_t launch_export_phi(const DevModel &m, int64_t *colptr64, uint16_t *topic, int32_t *gam_e, float *phi_e,
+                             uint32_t *thr, uint16_t *alias_topic, hipStream_t s)
+{
+    export_phi_kernel<<<(m.V + 3) / 4, 256, 0, s>>>(m, colptr64, topic, gam_e, phi_e, thr, alias_topic);
+    return hipGetLastError();
+}
+
+__global__ void import_phi_kernel(DevModel m, const int64_t *colptr64, const uint16_t *topic, const float *phi_e,
+                                  const uint32_t *thr, const uint16_t *alias_topic)
+{
+    const int32_t v = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (v >= m.V) return;
+    const int lane = __lane_id();
+    const int64_t a = colptr64[v], b = colptr64[v + 1];
+    if (lane == 0) {
+        m.colptr[v] = (int32_t)a;
+        if (v == m.V - 1) m.colptr[m.V] = (int32_t)b;
+    }
+    float *pcol = m.phid + (int64_t)v * m.K;
+    for (int32_t k = lane; k < m.K; k += 64) pcol[k] = 0.0f;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    for (int64_t e = a + lane; e < b; e += 64) {
+        const int32_t k = topic[e];
+        m.ctopic[e] = (uint16_t)k;
+        m.cphi[e] = phi_e[e];
+        pcol[k] = phi_e[e];
+        m.calias[e] = (uint64_t)thr[e] | ((uint64_t)k << 32) | ((uint64_t)alias_topic[e] << 48);
+    }
+}
+
+hipError_t launch_import_phi(const DevModel &m, const int64_t *colptr64, const uint16_t *topic, const float *phi_e,
+                             const uint32_t *thr, const uint16_t *alias_topic, hipStream_t s)
+{
+    import_phi_kernel<<<(m.V + 3) / 4, 256, 0, s>>>(m, colptr64, topic, phi_e, thr, alias_topic);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// counts export: n as CSC by word (ascending topic), m as CSR by document
+// ---------------------------------------------------------------------------
+__global__ void n_colcount_kernel(const int32_t *n, int32_t V, int32_t K, int64_t *cnt)
+{
+    const int32_t v = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (v >= V) return;
+    const int lane = __lane_id();
+    int32_t c = 0;
+    for (int32_t k = lane; k < K; k += 64) c += n[(int64_t)v * K + k] > 0;
+    c = group_scan_incl_i32<64>(c);
+    if (lane == 63) cnt[v] = c;
+}
+
+__global__ void n_fill_kernel(const int32_t *n, int32_t V, int32_t K, const int64_t *colptr, uint16_t *topic,
+                              int32_t *cnt)
+{
+    const int32_t v = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (v >= V) return;
+    const int lane = __lane_id();
+    int64_t run = colptr[v];
+    for (int32_t k0 = 0; k0 < K; k0 += 64) {
+        const int32_t k = k0 + lane;
+        const int32_t x = k < K ? n[(int64_t)v * K + k] : 0;
+        const uint64_t bal = __builtin_amdgcn_ballot_w64(x > 0);
+        if (x > 0) {
+            const int64_t e = run + __builtin_popcountll(bal & ((1ull << lane) - 1ull));
+            topic[e] = (uint16_t)k;
+            cnt[e] = x;
+        }
+        run += __builtin_popcountll(bal);
+    }
+}
+
+hipError_t launch_counts_csc(const DevModel &m, const int64_t *colptr64, uint16_t *topic, int32_t *cnt,
+                             int32_t *unused, hipStream_t s)
+{
+    (void)unused;
+    n_fill_kernel<<<(m.V + 3) / 4, 256, 0, s>>>(m.n, m.V, m.K, colptr64, topic, cnt);
+    return hipGetLastError();
+}
+
+// pass 0: per-column / per-document nonzero counts (int64) into rowcnt
+// pass 1: fill CSR m with rowptr = rowcnt (already scanned)
+__global__ void m_rows_kernel(DevCorpus c, int32_t K, int32_t log2c, int64_t *rowcnt_or_ptr, uint16_t *topic,
+                              int32_t *cnt, int pass)
+{
+    extern __shared__ uint16_t m_lds[];
+    const int lane = __lane_id();
+    const int wv = threadIdx.x >> 6;
+    const int32_t C = 1 << log2c;
+    uint16_t *mt = m_lds + wv * (64 * C);
+    const int64_t d = blockIdx.x * 4 + wv;
+    if (d >= c.D) return;
+    const int64_t s = c.doc_off[d], e = c.doc_off[d + 1];
+    for (int32_t i = lane; i < 64 * C; i += 64) mt[i] = 0;
+    __builtin_amdgcn_wave_barrier();
+    for (int64_t i = s + lane; i < e; i += 64) {
+        const int32_t k = c.z[i];
+        const int32_t slot = (k & (C - 1)) * 64 + (k >> log2c);
+        atomicAdd((uint32_t *)(mt + (slot & ~1)), (slot & 1) ? 65536u : 1u);
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    int32_t mine = 0;
+    for (int32_t b = 0; b < C; ++b) mine += mt[b * 64 + lane] > 0;
+    const int32_t incl = group_scan_incl_i32<64>(mine);
+    if (pass == 0) {
+        if (lane == 63) rowcnt_or_ptr[d] = incl;
+        return;
+    }
+    int64_t o = rowcnt_or_ptr[d] + incl - mine;
+    for (int32_t b = 0; b < C; ++b) {
+        const int32_t x = mt[b * 64 + lane];
+        if (x > 0) {
+            topic[o] = (uint16_t)(lane * C + b);
+            cnt[o] = x;
+            ++o;
+        }
+    }
+}
+
+hipError_t launch_counts_m(const DevCorpus &c, int32_t K, int64_t *rowcnt_or_ptr, uint16_t *topic, int32_t *cnt,
+                           int pass, hipStream_t s)
+{
+    if (c.D == 0) return hipSuccess;
+    const int log2c = topics_per_lane_log2(K, 64);
+    m_rows_kernel<<<(unsigned)((c.D + 3) / 4), 256, 4 * 64 * (1 << log2c) * sizeof(uint16_t), s>>>(
+        c, K, log2c, rowcnt_or_ptr, topic, cnt, pass);
+    return hipGetLastError();
+}
+
+hipError_t launch_n_colcount(const DevModel &m, int64_t *cnt, hipStream_t s)
+{
+    n_colcount_kernel<<<(m.V + 3) / 4, 256, 0, s>>>(m.n, m.V, m.K, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_i64(const int64_t *in, int64_t *out_excl, int64_t n, long long *scratch, hipStream_t s)
+{
+    return scan_excl<int64_t, int64_t>(in, out_excl, n, scratch, scratch + (n + SCAN_BLOCK - 1) / SCAN_BLOCK, s);
+}
+
+// ---------------------------------------------------------------------------
+// Fold-in (Phi fixed, no count rebuild): each group owns one request slot.
+// On its first step a slot drops tokens whose word is out of range or has an
+// empty Phi column, and draws initial topics; every step then runs `todo`
+// sweeps of the token draw with counters (p, request, sweep), accumulating
+// the topic counts after the burn-in, and the last sweep writes theta and
+// the log-likelihood of the final state.
+// ---------------------------------------------------------------------------
+template <int G>
+__device__ void foldin_slot(const DevModel &M, const DevFoldin &F, int32_t sid, uint16_t *mt, int log2c)
+{
+    const int lane = __lane_id();
+    const int g = lane & (G - 1);
+    const int32_t C = 1 << log2c;
+    const int32_t K = M.K;
+    const FoldSlot sl = F.slots[sid];
+    int32_t *wds = F.words + sl.arena_off;
+    int32_t *pos = F.pos + sl.arena_off;
+    uint16_t *zz = F.z + sl.arena_off;
+    uint32_t *acc = F.acc + (int64_t)sid * K;
+    int32_t kept = 0;
+    if (sl.done == 0) {
+        // drop tokens, compact the kept positions, draw initial topics
+        int32_t run = 0;
+        for (int32_t p0 = 0; p0 < sl.len; p0 += G) {
+            const int32_t p = p0 + g;
+            bool keep = false;
+            if (p < sl.len) {
+                const int32_t v = wds[p];
+                keep = v >= 0 && v < M.V && M.colptr[v + 1] > M.colptr[v];
+            }
+            const uint64_t bal = group_ballot<G>(keep);
+            if (keep) {
+                const int32_t q = run + __builtin_popcountll(bal & ((1ull << g) - 1ull));
+                pos[q] = p;
+                const r4 r = philox((uint32_t)p, sl.req, 0u, TAG_FOLDIN_INIT, F.key0, F.key1);
+                zz[q] = (uint16_t)scale32(r.x, (uint32_t)K);
+            }
+            run += __builtin_popcountll(bal);
+        }
+        kept = run;
+        for (int32_t k = g; k < K; k += G) acc[k] = 0;
+        if (g == 0) {
+            F.kept[2 * sid] = kept;
+            F.kept[2 * sid + 1] = sl.len - kept;
+        }
+        __threadfence();
+    } else {
+        kept = F.kept[2 * sid];
+    }
+    uint64_t mask;
+    int32_t Kd;
+    load_doc_counts<G>(mt, zz, 0, kept, g, log2c, mask, Kd);
+    TokenStats st = {0, 0, 0};
+    for (int32_t s = sl.done + 1; s <= sl.done + sl.todo; ++s) {
+        for (int32_t q0 = 0; q0 < kept; q0 += G) {
+            const int32_t q = q0 + g;
+            const bool valid = q < kept;
+            int32_t wv = 0, zo = 0;
+            uint32_t r0 = 0, r1 = 0, r2 = 0;
+            if (valid) {
+                const int32_t p = pos[q];
+                wv = wds[p];
+                zo = zz[q];
+                const r4 r = philox((uint32_t)p, sl.req, (uint32_t)s, TAG_FOLDIN_Z, F.key0, F.key1);
+                r0 = r.x;
+                r1 = r.y;
+                r2 = r.z;
+            }
+            int32_t znew = zo;
+            const int nb = (kept - q0) < G ? (kept - q0) : G;
+            for (int jj = 0; jj < nb; ++jj) {
+                const int32_t v = group_bcast<G>(wv, jj);
+                const int32_t kold = group_bcast<G>(zo, jj);
+                const uint32_t a0 = (uint32_t)group_bcast<G>((int)r0, jj);
+                const uint32_t a1 = (uint32_t)group_bcast<G>((int)r1, jj);
+                const uint32_t a2 = (uint32_t)group_bcast<G>((int)r2, jj);
+                const int32_t k = draw_token<G>(M, v, kold, a0, a1, a2, mt, g, log2c, mask, Kd, nullptr, st);
+                if (g == jj) znew = k;
+            }
+            if (valid) zz[q] = (uint16_t)znew;
+        }
+        if (s > F.burn_in) {
+            for (int32_t b = 0; b < C; ++b) {
+                const int32_t k = (g << log2c) + b;
+                if (k < K) acc[k] += mt[b * G + g];
+            }
+        }
+    }
+    const int32_t done = sl.done + sl.todo;
+    __threadfence();
+    if (done == F.sweeps) {
+        const double denom = (double)kept + F.A;
+        const double ns = (double)(F.sweeps - F.burn_in);
+        for (int32_t k = g; k < K; k += G)
+            F.theta[(int64_t)sid * K + k] = (float)(((double)acc[k] / ns + M.alpha[k]) / denom);
+        double part = 0.0;
+        for (int32_t q = g; q < kept; q += G) part += log((double)M.phid[(int64_t)wds[pos[q]] * K + zz[q]]);
+        for (int32_t b = 0; b < C; ++b) {
+            const int32_t k = (g << log2c) + b;
+            const int32_t c = mt[b * G + g];
+            if (k < K && c > 0) part += lgamma((double)c + M.alpha[k]) - lgamma(M.alpha[k]);
+        }
+        const double tot = group_bcast_f64<G>(group_scan_incl<G>(part), G - 1);
+        if (g == 0) F.ll[sid] = tot + lgamma(F.A) - lgamma(denom);
+    }
+}
+
+__global__ void __launch_bounds__(256) foldin_step_kernel(DevModel M, DevFoldin F, const int32_t *active,
+                                                          int32_t n_active, int32_t log2c, int32_t per_group)
+{
+    extern __shared__ uint16_t f_lds[];
+    const int lane = __lane_id();
+    const int wave = threadIdx.x >> 6;
+    const int gsz = F.group;
+    const int grp = lane / gsz;
+    const int ngw = 64 / gsz;
+    const int64_t gid = ((int64_t)blockIdx.x * 4 + wave) * ngw + grp;
+    uint16_t *mt = f_lds + (wave * ngw + grp) * per_group;
+    if (gid >= n_active) return;
+    const int32_t sid = active[gid];
+    if (gsz == 64) foldin_slot<64>(M, F, sid, mt, log2c);
+    else if (gsz == 32) foldin_slot<32>(M, F, sid, mt, log2c);
+    else foldin_slot<16>(M, F, sid, mt, log2c);
+}
+
+hipError_t launch_foldin_step(const DevModel &m, const DevFoldin &f, const int32_t *active, int32_t n_active,
+                              hipStream_t s)
+{
+    if (n_active == 0) return hipSuccess;
+    const int log2c = topics_per_lane_log2(m.K, f.group);
+    const int per_group = f.group << log2c;
+    const int ngw = 64 / f.group;
+    const int64_t waves = (n_active + ngw - 1) / ngw;
+    const unsigned blocks = (unsigned)((waves + 3) / 4);
+    foldin_step_kernel<<<blocks, 256, 4 * ngw * per_group * sizeof(uint16_t), s>>>(m, f, active, n_active, log2c,
+                                                                                   per_group);
+    return hipGetLastError();
+}
+
+}  // namespace pulda

@@ -1,0 +1,279 @@
+"""GPU parity: the HIP path, called through the C ABI, against the CPU oracle.
+
+Integers (initial state, counts, Poisson draws, alias tables, CSC layout) must
+match bit for bit; phi and sigma_a too (both sides compute them in fp64 with
+the same operation order).  The z-step is checked by the oracle's
+teacher-forced replay: every token the GPU drew differently must sit within
+1e-6 Z of the boundary between the two topics (a floating-point tie; the GPU
+sums sigma_b in fp64 in a different order), and at least 99.99% of tokens
+must agree.  The log joint must match within 1e-10 relative on the same z.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1704_03581_amd import synth
+from tests.gpu_helpers import assert_phi_equal, oracle_phi, phi_from_gpu, say
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_1704_03581_amd import pulda
+else:  # collected on CPU-only hosts, never run there
+    pulda = None
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _ragged(seed=3):
+    """Empty documents, one-token documents and a repeated-word document."""
+    c = synth.small_random(D=80, V=400, K=24, mean_len=30.0, seed=seed)
+    lens = c.lengths().copy()
+    words = list(np.split(c.words, c.doc_off[1:-1]))
+    words[0] = np.zeros(0, np.int32)
+    words[1] = np.array([7], np.int32)
+    words[2] = np.full(150, 11, np.int32)
+    words[-1] = np.zeros(0, np.int32)
+    lens = np.array([len(w) for w in words])
+    off = np.zeros(len(words) + 1, np.int64)
+    np.cumsum(lens, out=off[1:])
+    return synth.Corpus("ragged", len(words), c.V, c.K, c.alpha, c.beta, off,
+                        np.concatenate(words).astype(np.int32), None)
+
+
+CASES = {
+    "tiny": lambda: synth.generate("tiny", keep_true_z=False),
+    "k100": lambda: synth.small_random(D=120, V=800, K=100, mean_len=220.0, seed=4),
+    "k1000": lambda: synth.small_random(D=50, V=3000, K=1000, mean_len=500.0, seed=5),
+    "ragged": _ragged,
+}
+_cache = {}
+
+
+def corpus(name):
+    if name not in _cache:
+        _cache[name] = CASES[name]()
+    return _cache[name]
+
+
+def make_plan(c, seed=7, **kw):
+    p = pulda.Plan(c.K, c.V, c.D, c.N, alpha=c.alpha, beta=c.beta, seed=seed, **kw)
+    p.upload(c.doc_off, c.words)
+    return p
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_init_and_counts(name):
+    c = corpus(name)
+    say(f"init/counts {name} N={c.N}")
+    p = make_plan(c)
+    p.init()
+    z = p.get_z()
+    assert np.array_equal(z, oracle.init_z(c.N, c.K, 7))
+    n_o, nk_o, m_o = oracle.counts(c.doc_off, c.words, z, c.K, c.V)
+    n_g, nk_g = p.counts_dense()
+    assert np.array_equal(n_g, n_o) and np.array_equal(nk_g, nk_o)
+    cs = p.counts()
+    # CSC of n and CSR of m against the dense oracle tables
+    cols = np.repeat(np.arange(c.V), np.diff(cs["n_colptr"]))
+    assert np.array_equal(n_o.T[n_o.T > 0], cs["n_count"])
+    assert np.array_equal(np.nonzero(n_o.T)[1], cs["n_topic"]) and np.array_equal(np.nonzero(n_o.T)[0], cols)
+    rows = np.repeat(np.arange(c.D), np.diff(cs["m_rowptr"]))
+    assert np.array_equal(m_o[m_o > 0], cs["m_count"])
+    assert np.array_equal(np.nonzero(m_o)[1], cs["m_topic"]) and np.array_equal(np.nonzero(m_o)[0], rows)
+    assert np.array_equal(cs["nk"], nk_o)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_phi_step_bit_exact(name):
+    c = corpus(name)
+    say(f"phi-step {name}")
+    p = make_plan(c, seed=9)
+    p.init()
+    for t in (1, 2):
+        p.phi_step(t)
+        g = p.get_phi()
+        gam, S, phi, wt = oracle_phi(c.doc_off, c.words, p.get_z(), c.K, c.V, c.alpha, c.beta, 100, 9, t)
+        assert_phi_equal(g, gam, S, phi, wt, c.K, c.V)
+        st = p.stats()
+        assert st["nnz_phi"] == len(wt.topic)
+        assert st["empty_rows"] == int((S == 0).sum())
+
+
+@pytest.mark.parametrize("group", [64, 32, 16])
+@pytest.mark.parametrize("name", list(CASES))
+def test_z_step_replay(name, group):
+    c = corpus(name)
+    say(f"z-step {name} group={group}")
+    p = make_plan(c, seed=13)
+    try:
+        p.set_schedule([0], [group], [64 // group * 4])
+    except pulda.PuldaError:
+        pytest.skip(f"group {group} too small for K={c.K}")
+    p.init()
+    z0 = p.get_z()
+    p.phi_step(1)
+    phi, wt = phi_from_gpu(p.get_phi(), c.K, c.V)
+    p.z_step(1)
+    z1 = p.get_z()
+    r = oracle.replay(c.doc_off, c.words, z0, z1, 13, 1, phi, wt, c.K, c.V)
+    say(f"  replay {r}")
+    assert r["bad"] == 0, r
+    assert r["agree"] >= 0.9999 * c.N
+    # counts rebuilt inside the z-step
+    n_o, nk_o, _ = oracle.counts(c.doc_off, c.words, z1, c.K, c.V, with_m=False)
+    assert np.array_equal(p.counts_dense()[0], n_o)
+    # statistics: degenerate tokens and the work count sum_J of the oracle
+    _, deg, sumJ, sumA = oracle.z_step(c.doc_off, c.words, z0, 13, 1, phi, wt, c.K, c.V)
+    st = p.stats()
+    assert st["degenerate_tokens"] == deg
+    if r["ties"] == 0:
+        assert st["sum_J"] == sumJ and st["sum_A"] == sumA
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_loglik(name):
+    c = corpus(name)
+    say(f"loglik {name}")
+    p = make_plan(c, seed=3)
+    p.init()
+    p.sweep(1, 2, want_ll=False)
+    z = p.get_z()
+    ll_o = oracle.loglik(c.doc_off, c.words, z, c.alpha, c.beta, c.K, c.V)
+    assert abs(p.loglik() - ll_o) <= 1e-10 * abs(ll_o)
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_lockstep_tiny(graph):
+    """Sweep by sweep on the tiny corpus: Phi from the GPU's previous state
+    bit-exact, z by replay, the log joint within 1e-10."""
+    c = corpus("tiny")
+    say(f"lockstep tiny graph={graph}")
+    p = make_plan(c, seed=21)
+    p.set_graph(graph)
+    p.init()
+    z_prev = p.get_z()
+    ties = 0
+    for t in range(1, 31):
+        ll = p.sweep(t, 1)[0]
+        g = p.get_phi()
+        gam, S, phi, wt = oracle_phi(c.doc_off, c.words, z_prev, c.K, c.V, c.alpha, c.beta, 100, 21, t)
+        assert_phi_equal(g, gam, S, phi, wt, c.K, c.V)
+        z = p.get_z()
+        r = oracle.replay(c.doc_off, c.words, z_prev, z, 21, t, phi, wt, c.K, c.V)
+        assert r["bad"] == 0, (t, r)
+        ties += r["ties"]
+        ll_o = oracle.loglik(c.doc_off, c.words, z, c.alpha, c.beta, c.K, c.V)
+        assert abs(ll - ll_o) <= 1e-10 * abs(ll_o), (t, ll, ll_o)
+        z_prev = z
+    assert ties <= 1e-4 * 30 * c.N
+
+
+def test_determinism_and_graph_equivalence():
+    c = corpus("k100")
+    say("determinism")
+    zs = []
+    for graph in (False, False, True):
+        p = make_plan(c, seed=31)
+        p.set_graph(graph)
+        p.init()
+        lls = p.sweep(1, 5)
+        zs.append((p.get_z(), lls))
+    assert np.array_equal(zs[0][0], zs[1][0]) and np.array_equal(zs[0][1], zs[1][1])
+    assert np.array_equal(zs[0][0], zs[2][0]) and np.array_equal(zs[0][1], zs[2][1])
+
+
+def test_resume_from_checkpoint():
+    """State is (z, t): 3 + 3 sweeps from a saved z equal 6 sweeps."""
+    c = corpus("k100")
+    say("resume")
+    p = make_plan(c, seed=17)
+    p.init()
+    p.sweep(1, 6, want_ll=False)
+    z_full = p.get_z()
+    q = make_plan(c, seed=17)
+    q.init()
+    q.sweep(1, 3, want_ll=False)
+    zc = q.get_z()
+    r = make_plan(c, seed=17)
+    r.set_z(zc)
+    r.sweep(4, 3, want_ll=False)
+    assert np.array_equal(r.get_z(), z_full)
+
+
+def test_set_phi_roundtrip():
+    """Loading the oracle's Phi gives the same z-step as the GPU's own Phi."""
+    c = corpus("k100")
+    say("set_phi")
+    p = make_plan(c, seed=19)
+    p.init()
+    z0 = p.get_z()
+    gam, S, phi, wt = oracle_phi(c.doc_off, c.words, z0, c.K, c.V, c.alpha, c.beta, 100, 19, 1)
+    p.set_phi(wt.colptr, wt.topic, wt.phi, wt.thr, wt.alias_topic, wt.sigma_a)
+    p.z_step(1)
+    r = oracle.replay(c.doc_off, c.words, z0, p.get_z(), 19, 1, phi, wt, c.K, c.V)
+    assert r["bad"] == 0
+
+
+def test_degenerate_columns():
+    """Small K, large V: many words have empty Phi columns; they keep z."""
+    c = synth.small_random(D=40, V=20000, K=4, mean_len=30.0, seed=8)
+    say("degenerate")
+    p = make_plan(c, seed=2)
+    p.init()
+    z0 = p.get_z()
+    p.phi_step(1)
+    phi, wt = phi_from_gpu(p.get_phi(), c.K, c.V)
+    p.z_step(1)
+    z1 = p.get_z()
+    empty = np.diff(wt.colptr) == 0
+    deg = empty[c.words]
+    assert deg.any()
+    assert np.array_equal(z1[deg], z0[deg])
+    assert p.stats()["degenerate_tokens"] == int(deg.sum())
+    r = oracle.replay(c.doc_off, c.words, z0, z1, 2, 1, phi, wt, c.K, c.V)
+    assert r["bad"] == 0 and r["degenerate"] == int(deg.sum())
+
+
+def test_corpus_validation_errors():
+    say("validation")
+    c = corpus("ragged")
+    p = pulda.Plan(c.K, c.V, c.D, c.N, seed=1)
+    bad = c.words.copy()
+    bad[5] = c.V
+    with pytest.raises(pulda.PuldaError) as e:
+        p.upload(c.doc_off, bad)
+    assert e.value.status == pulda.ERR_CORPUS
+    off = c.doc_off.copy()
+    off[3], off[4] = off[4], off[3] - 1
+    with pytest.raises(pulda.PuldaError) as e:
+        p.upload(off, c.words)
+    assert e.value.status == pulda.ERR_CORPUS
+    with pytest.raises(pulda.PuldaError) as e:
+        p.z_step(1)
+    assert e.value.status == pulda.ERR_STATE
+    p.upload(c.doc_off, c.words)
+    p.init()
+    p.phi_step(1)
+    p.z_step(1)
+
+
+def test_autotune_keeps_results_valid():
+    c = corpus("k1000")
+    say("autotune")
+    p = make_plan(c, seed=23)
+    p.init()
+    z0 = p.get_z()
+    p.phi_step(1)
+    sched = p.autotune(1, reps=1)
+    assert all(g in (16, 32, 64) for g in sched[1])
+    assert np.array_equal(p.get_z(), z0)
+    phi, wt = phi_from_gpu(p.get_phi(), c.K, c.V)
+    p.z_step(1)
+    r = oracle.replay(c.doc_off, c.words, z0, p.get_z(), 23, 1, phi, wt, c.K, c.V)
+    assert r["bad"] == 0
