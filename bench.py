@@ -1,0 +1,237 @@
+"""Benchmark: z-step tokens/s at K=1000 and fold-in serving, on one MI355X.
+
+One step = one sweep of Algorithm 2 over the whole synthetic corpus:
+Phi-step (Poisson Polya urn draws, per-word alias tables), z-step with the
+count rebuild, and the collapsed log joint.  Inputs are resident in HBM
+before the timed region.  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--config large]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, AMD's published figure
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(N, sum_J, sum_A):
+    """Bytes the doubly sparse z-step must touch per sweep (per token:
+    word id 4, z read 2 and write 2, the column's two offsets 8, sigma_a 4,
+    the count increment 8, plus 6 per b-term (u16 topic + fp32 phi) and 8
+    per a-part alias bucket)."""
+    return 28 * N + 6 * sum_J + 8 * sum_A
+
+
+def cpu_baseline(corpus, seed, budget_docs):
+    """The oracle (single-threaded C) on a bounded sample of the same corpus."""
+    import oracle
+    d = min(budget_docs, corpus.D)
+    off = corpus.doc_off[: d + 1].copy()
+    words = corpus.words[: off[-1]].copy()
+    n_tok = int(off[-1])
+    z = oracle.init_z(n_tok, corpus.K, seed)
+    alpha = np.full(corpus.K, corpus.alpha)
+    t0 = time.perf_counter()
+    n, _, _ = oracle.counts(off, words, z, corpus.K, corpus.V, with_m=False)
+    gam = oracle.phi_counts(n, corpus.beta, 100, seed, 1)
+    S, phi, _ = oracle.phi_normalise(gam)
+    wt = oracle.word_tables(alpha, phi)
+    t1 = time.perf_counter()
+    oracle.z_step(off, words, z, seed, 1, phi, wt, corpus.K, corpus.V)
+    t2 = time.perf_counter()
+    oracle.loglik(off, words, z, alpha, corpus.beta, corpus.K, corpus.V)
+    t3 = time.perf_counter()
+    return dict(value=n_tok / (t2 - t1), unit="tokens/s", cores=1, kind="oracle",
+                sample=f"first {d} documents ({n_tok} tokens) of the same corpus, one sweep from the "
+                       f"initial state; z-step {t2 - t1:.2f}s, Phi-step {t1 - t0:.2f}s, log joint {t3 - t2:.2f}s "
+                       f"(oracle is single-threaded)",
+                sweep_tokens_per_s=n_tok / (t3 - t0))
+
+
+def foldin_bench(args, torch, pulda, synth):
+    """Fold-in serving against a resident Phi (K=1000, V=141000)."""
+    cfg = synth.CONFIGS["large"]
+    K, V = cfg["K"], cfg["V"]
+    log("fold-in: drawing serving counts and Phi")
+    n = synth.topic_word_counts_draw("large")
+    model = pulda.Plan(K, V, 0, 0, alpha=synth.ALPHA, beta=synth.BETA, seed=args.seed)
+    model.set_counts(np.ascontiguousarray(n.T).reshape(-1))
+    del n
+    model.phi_step(1)
+    torch.cuda.synchronize()
+    reqs = synth.foldin_requests(args.foldin_requests + args.plain_requests, seed=170403581 + 5)
+    lens = np.array([len(r) for r in reqs])
+    server = pulda.FoldIn(model, sweeps=50, burn_in=25, max_slots=args.slots, arena_tokens=args.slots * 600,
+                          max_len=5000, group=64, seed=args.seed)
+
+    def run_batched(arrivals, reqs_):
+        """Continuous batching: admit whatever has arrived while slots and
+        arena tokens allow, advance every resident request by a quantum,
+        collect finished ones, repeat."""
+        t0 = time.perf_counter()
+        nxt, done = 0, 0
+        lat = np.zeros(len(reqs_))
+        pending = []
+        while done < len(reqs_):
+            now = time.perf_counter() - t0
+            while nxt < len(reqs_) and arrivals[nxt] <= now:
+                pending.append(nxt)
+                nxt += 1
+            while pending:
+                if not server.submit(pending[0], reqs_[pending[0]]):
+                    break
+                pending.pop(0)
+            occ = server.occupancy()
+            if occ["resident"] == 0:
+                if nxt < len(reqs_):
+                    time.sleep(max(0.0, min(arrivals[nxt] - now, 0.001)))
+                continue
+            server.step(args.quantum)
+            for r in server.poll(cap=args.slots):
+                lat[r["request_id"]] = time.perf_counter() - t0 - arrivals[r["request_id"]]
+                done += 1
+        return time.perf_counter() - t0, lat
+
+    nb = args.foldin_requests
+    batched_reqs = reqs[:nb]
+    log(f"fold-in: closed loop, {nb} requests")
+    wall, lat = run_batched(np.zeros(nb), batched_reqs)
+    xmax = nb / wall
+    out = dict(saturation_docs_per_s=xmax, requests=nb, mean_len=float(lens[:nb].mean()),
+               sweeps=50, burn_in=25, slots=args.slots, quantum=args.quantum, rates={})
+    rng = np.random.default_rng(170403581 + 5)
+    for frac in args.rates:
+        lam = frac * xmax
+        arr = np.cumsum(rng.exponential(1.0 / lam, size=nb))
+        wall, lat = run_batched(arr, batched_reqs)
+        out["rates"][f"{frac:.2f}"] = dict(offered_docs_per_s=lam, docs_per_s=nb / wall,
+                                           p50_ms=float(np.percentile(lat, 50) * 1e3),
+                                           p99_ms=float(np.percentile(lat, 99) * 1e3))
+        log(f"fold-in: rate {frac:.2f} x -> {out['rates'][f'{frac:.2f}']}")
+    # plain per-document sampler on the same kind of requests
+    plain = reqs[nb:nb + args.plain_requests]
+    t0 = time.perf_counter()
+    plain_res = [server.run_one(nb + j, r) for j, r in enumerate(plain)]
+    pw = time.perf_counter() - t0
+    out["plain_docs_per_s"] = len(plain) / pw
+    out["plain_mean_latency_ms"] = pw / len(plain) * 1e3
+    # the batched path gives the same result per request
+    mixed = {}
+    for j, r in enumerate(plain):
+        assert server.submit(nb + j, r)
+    while len(mixed) < len(plain):
+        server.step(args.quantum)
+        for r in server.poll(cap=args.slots):
+            mixed[r["request_id"]] = r
+    same = all(np.array_equal(mixed[nb + j]["theta"], plain_res[j]["theta"]) and
+               mixed[nb + j]["loglik"] == plain_res[j]["loglik"] for j in range(len(plain)))
+    out["batched_equals_plain"] = bool(same)
+    out["speedup_vs_plain"] = xmax / out["plain_docs_per_s"]
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="large", choices=["tiny", "small", "medium", "large"])
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--graph", action="store_true", help="replay a captured sweep (no per-phase events)")
+    ap.add_argument("--cpu-docs", type=int, default=20000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-foldin", action="store_true")
+    ap.add_argument("--foldin-requests", type=int, default=4000)
+    ap.add_argument("--plain-requests", type=int, default=60)
+    ap.add_argument("--slots", type=int, default=2048)
+    ap.add_argument("--quantum", type=int, default=10)
+    ap.add_argument("--rates", type=float, nargs="*", default=[0.5, 0.8, 0.95])
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    from paper_1704_03581_amd import synth
+    log(f"generating the {args.config} corpus")
+    t0 = time.perf_counter()
+    corpus = synth.generate(args.config, keep_true_z=False)
+    log(f"corpus: D={corpus.D} V={corpus.V} K={corpus.K} N={corpus.N} ({time.perf_counter() - t0:.1f}s)")
+
+    import torch
+    from paper_1704_03581_amd import pulda
+    dev = torch.device("cuda:0")
+    plan = pulda.Plan(corpus.K, corpus.V, corpus.D, corpus.N, alpha=corpus.alpha, beta=corpus.beta,
+                      seed=args.seed, device=dev)
+    plan.upload(corpus.doc_off, corpus.words)
+    plan.init()
+    plan.phi_step(1)
+    torch.cuda.synchronize()
+    if not args.no_autotune:
+        sched = plan.autotune(1, reps=1)
+        log(f"autotuned schedule: {sched}")
+    plan.set_graph(args.graph)
+    plan.set_timing(not args.graph)
+    t = 1
+    log(f"warmup {args.warmup} sweeps")
+    if args.warmup:
+        plan.sweep(t, args.warmup, want_ll=False)
+        t += args.warmup
+    torch.cuda.synchronize()
+    plan.stats()  # restart counters and event totals
+    log(f"timing {args.steps} sweeps")
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    plan.sweep(t, args.steps, want_ll=False)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    st = plan.stats()
+    ll = plan.loglik()
+    N = corpus.N
+    ms_step = wall * 1e3 / args.steps
+    tokens_per_s = N * args.steps / wall
+    res = dict(metric="z-step tokens/sec at K=1000 (% HBM roofline); fold-in docs/sec + p50/p99 latency",
+               value=tokens_per_s, unit="tokens/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+               ms_per_step=ms_step, higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64",
+               data="synthetic",
+               config=dict(workload=f"{args.config}: synthetic LDA corpus D={corpus.D} V={corpus.V} K={corpus.K} "
+                                    f"N={N}, alpha={corpus.alpha}, beta={corpus.beta}; one sweep = Phi-step + "
+                                    f"z-step + count rebuild + log joint",
+                           global_batch=N, parallelism="single GPU"))
+    if not args.graph and st["n_z"]:
+        z_ms = st["ms_z"] / st["n_z"]
+        bytes_launch = algorithmic_bytes(N, st["sum_J"] / st["z_steps"], st["sum_A"] / st["z_steps"])
+        achieved = bytes_launch / (z_ms * 1e-3) / 1e9
+        res["zstep"] = dict(tokens_per_s=N / (z_ms * 1e-3), kernel_ms=z_ms, phi_ms=st["ms_phi"] / st["n_phi"],
+                            loglik_ms=st["ms_ll"] / st["n_ll"],
+                            mean_J=st["sum_J"] / st["z_steps"] / N, a_fraction=st["sum_A"] / st["z_steps"] / N,
+                            degenerate_per_sweep=st["degenerate_tokens"] / st["z_steps"],
+                            nnz_phi=st["nnz_phi"], loglik=ll)
+        res["roofline"] = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                               frac=achieved / HBM_PEAK_GBS, traffic=None,
+                               kernel="z_step_kernel", algorithmic_bytes_per_launch=bytes_launch)
+    log(f"sweep {ms_step:.2f} ms, {tokens_per_s / 1e9:.3f} G tokens/s; {res.get('zstep')}")
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        res["cpu_baseline"] = cpu_baseline(corpus, args.seed, args.cpu_docs)
+    del plan
+    torch.cuda.empty_cache()
+    if not args.no_foldin:
+        res["foldin"] = foldin_bench(args, torch, pulda, synth)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -208,15 +208,30 @@ pulda_status pulda_set_phi(pulda_plan *plan, const pulda_phi_view *in, void *str
 /* Statistics, schedule, graph replay                                        */
 /* ------------------------------------------------------------------------ */
 typedef struct {
-    int64_t degenerate_tokens;  /* last z-step: tokens with an empty Phi column */
-    int64_t sum_J;              /* last z-step: sum over tokens of min(K_d^{-i}, K_v^Phi) */
-    int64_t sum_A;              /* last z-step: tokens drawn from the a-part */
-    int64_t nnz_phi;            /* last Phi-step */
-    int64_t empty_rows;         /* last Phi-step: topics with S_k = 0 */
+    /* z-step counters, summed over the z-steps since the previous
+     * pulda_stats call (which resets them) */
+    int64_t degenerate_tokens;  /* tokens with an empty Phi column (kept their topic) */
+    int64_t sum_J;              /* sum over tokens of min(K_d^{-i}, K_v^Phi): the work of the
+                                   doubly sparse b-sum (computational complexity, Section 3.6) */
+    int64_t sum_A;              /* tokens drawn from the a-part */
+    int64_t z_steps;            /* z-steps counted */
+    /* last Phi-step */
+    int64_t nnz_phi;
+    int64_t empty_rows;         /* topics with S_k = 0 */
+    /* with timing on (pulda_set_timing): milliseconds between hipEvents
+     * recorded on the caller's stream around each Phi-step, each z-step
+     * kernel and each log-joint evaluation since the previous call, and
+     * how many of each */
+    double ms_phi, ms_z, ms_ll;
+    int64_t n_phi, n_z, n_ll;
 } pulda_sweep_stats;
 
-/* Counters of the last Phi-step and z-step.  Synchronises. */
+/* Read (and restart) the counters above.  Synchronises. */
 pulda_status pulda_stats(pulda_plan *plan, pulda_sweep_stats *out, void *stream);
+
+/* Record hipEvents around every phase (1) or not (0).  While on, pulda_sweep
+ * runs eagerly (no graph replay). */
+pulda_status pulda_set_timing(pulda_plan *plan, int32_t enable);
 
 /* z-step schedule: documents are ordered by decreasing length and split
  * into n_buckets length buckets; bucket b holds documents with length >=

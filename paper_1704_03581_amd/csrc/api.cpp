@@ -162,7 +162,12 @@ struct pulda_plan {
     // graph replay
     bool graph_on = false;
     hipGraphExec_t gexec = nullptr;
-    hipStream_t gstream = nullptr;
+    hipStream_t cap_stream = nullptr;  // private stream the sweep is captured on
+    // phase timing (hipEvents on the caller's stream around each phase)
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<std::pair<size_t, size_t>> ev_phi, ev_z, ev_ll;
 };
 
 struct pulda_foldin {
@@ -333,7 +338,22 @@ void pulda_plan_destroy(pulda_plan *p)
 {
     if (!p) return;
     if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+    for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
     delete p;
+}
+
+// record a pair of events around a phase when timing is on
+static hipError_t phase_event(pulda_plan *p, hipStream_t s, size_t *idx)
+{
+    if (p->ev_used == p->ev_pool.size()) {
+        hipEvent_t e;
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return r;
+        p->ev_pool.push_back(e);
+    }
+    *idx = p->ev_used++;
+    return hipEventRecord(p->ev_pool[*idx], s);
 }
 
 // smallest group size whose lanes can own all K topics with <= 64 topics each
@@ -476,13 +496,34 @@ pulda_status pulda_set_counts(pulda_plan *p, const int32_t *n_dev, void *stream)
 
 static pulda_status enqueue_phi(pulda_plan *p, hipStream_t s)
 {
+    size_t a = 0, b = 0;
+    if (p->timing) HIP_TRY(phase_event(p, s, &a));
     HIP_TRY(launch_phi_step(p->m, p->stats, s));
+    if (p->timing) {
+        HIP_TRY(phase_event(p, s, &b));
+        p->ev_phi.push_back({a, b});
+    }
     return PULDA_OK;
 }
 
 static pulda_status enqueue_z(pulda_plan *p, hipStream_t s)
 {
-    HIP_TRY(launch_z_step(p->c, p->m, p->items, p->n_items, p->n_waves, p->queue, p->stats, s));
+    HIP_TRY(launch_z_step(p->c, p->m, p->items, p->n_items, p->n_waves, p->queue, p->stats, s,
+                          p->timing ? &p->ev_pool : nullptr, p->timing ? &p->ev_used : nullptr,
+                          p->timing ? &p->ev_z : nullptr));
+    return PULDA_OK;
+}
+
+static pulda_status enqueue_ll(pulda_plan *p, hipStream_t s, double *hist, const uint32_t *hist_idx)
+{
+    size_t a = 0, b = 0;
+    if (p->timing) HIP_TRY(phase_event(p, s, &a));
+    HIP_TRY(launch_loglik(p->c, p->m, p->A, p->ll_part, p->n_part_words, p->n_part_docs, p->ll_out, hist, hist_idx,
+                          s));
+    if (p->timing) {
+        HIP_TRY(phase_event(p, s, &b));
+        p->ev_ll.push_back({a, b});
+    }
     return PULDA_OK;
 }
 
@@ -518,8 +559,8 @@ static pulda_status enqueue_sweep_body(pulda_plan *p, hipStream_t s)
     if (st != PULDA_OK) return st;
     st = enqueue_z(p, s);
     if (st != PULDA_OK) return st;
-    HIP_TRY(launch_loglik(p->c, p->m, p->A, p->ll_part, p->n_part_words, p->n_part_docs, p->ll_out, p->ll_hist,
-                          p->hist_idx, s));
+    st = enqueue_ll(p, s, p->ll_hist, p->hist_idx);
+    if (st != PULDA_OK) return st;
     HIP_TRY(launch_advance(p->tptr, p->hist_idx, s));
     return PULDA_OK;
 }
@@ -535,22 +576,22 @@ pulda_status pulda_sweep(pulda_plan *p, uint32_t t_first, int32_t n_sweeps, doub
         const int32_t chunk = (int32_t)std::min<int64_t>(n_sweeps - done, p->hist_cap);
         HIP_TRY(launch_fill_u32(p->tptr, t_first + (uint32_t)done, 1, s));
         HIP_TRY(launch_fill_u32(p->hist_idx, 0u, 1, s));
-        if (p->graph_on) {
-            if (!p->gexec || p->gstream != s) {
-                if (p->gexec) {
-                    (void)hipGraphExecDestroy(p->gexec);
-                    p->gexec = nullptr;
-                }
+        if (p->graph_on && !p->timing) {
+            if (!p->gexec) {
+                // capture one sweep on a private stream (the caller's stream
+                // may be the legacy default stream, which cannot capture);
+                // nothing runs during capture, the graph is then replayed on
+                // the caller's stream
+                if (!p->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
                 hipGraph_t graph;
-                HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-                pulda_status st = enqueue_sweep_body(p, s);
-                hipError_t ec = hipStreamEndCapture(s, &graph);
+                HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+                pulda_status st = enqueue_sweep_body(p, p->cap_stream);
+                hipError_t ec = hipStreamEndCapture(p->cap_stream, &graph);
                 if (st != PULDA_OK) return st;
                 if (ec != hipSuccess) return fail(PULDA_ERR_DEVICE, "graph capture: %s", hipGetErrorString(ec));
                 ec = hipGraphInstantiate(&p->gexec, graph, nullptr, nullptr, 0);
                 (void)hipGraphDestroy(graph);
                 if (ec != hipSuccess) return fail(PULDA_ERR_DEVICE, "graph instantiate: %s", hipGetErrorString(ec));
-                p->gstream = s;
             }
             for (int32_t i = 0; i < chunk; ++i) HIP_TRY(hipGraphLaunch(p->gexec, s));
         } else {
@@ -574,8 +615,8 @@ pulda_status pulda_loglik(pulda_plan *p, double *ll_host, void *stream)
     if (!p || !ll_host) return fail(PULDA_ERR_INVALID_ARG, "null argument");
     if (!p->have_z) return fail(PULDA_ERR_STATE, "no state (call pulda_init)");
     hipStream_t s = (hipStream_t)stream;
-    HIP_TRY(launch_loglik(p->c, p->m, p->A, p->ll_part, p->n_part_words, p->n_part_docs, p->ll_out, nullptr,
-                          nullptr, s));
+    pulda_status st = enqueue_ll(p, s, nullptr, nullptr);
+    if (st != PULDA_OK) return st;
     HIP_TRY(hipMemcpyAsync(ll_host, p->ll_out, sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     return PULDA_OK;
@@ -708,8 +749,30 @@ pulda_status pulda_stats(pulda_plan *p, pulda_sweep_stats *out, void *stream)
     out->degenerate_tokens = (int64_t)st[ST_DEGENERATE];
     out->sum_J = (int64_t)st[ST_SUM_J];
     out->sum_A = (int64_t)st[ST_SUM_A];
+    out->z_steps = (int64_t)st[ST_TOKENS];
     out->nnz_phi = (int64_t)st[ST_NNZ_PHI];
     out->empty_rows = (int64_t)st[ST_EMPTY_ROWS];
+    auto total = [&](std::vector<std::pair<size_t, size_t>> &v, double *ms, int64_t *cnt) -> hipError_t {
+        double t = 0.0;
+        for (auto &pr : v) {
+            float x = 0.0f;
+            hipError_t e = hipEventElapsedTime(&x, p->ev_pool[pr.first], p->ev_pool[pr.second]);
+            if (e != hipSuccess) return e;
+            t += x;
+        }
+        *ms = t;
+        *cnt = (int64_t)v.size();
+        v.clear();
+        return hipSuccess;
+    };
+    HIP_TRY(total(p->ev_phi, &out->ms_phi, &out->n_phi));
+    HIP_TRY(total(p->ev_z, &out->ms_z, &out->n_z));
+    HIP_TRY(total(p->ev_ll, &out->ms_ll, &out->n_ll));
+    p->ev_used = 0;
+    // z-step counters restart from zero
+    HIP_TRY(launch_fill_u64(p->stats, 0ull, 3, s));
+    HIP_TRY(launch_fill_u64(p->stats + ST_TOKENS, 0ull, 1, s));
+    HIP_TRY(hipStreamSynchronize(s));
     return PULDA_OK;
 }
 
@@ -787,7 +850,8 @@ pulda_status pulda_autotune(pulda_plan *p, uint32_t t, int32_t reps, void *strea
             for (int r = 0; r <= reps; ++r) {
                 if (p->N) HIP_TRY(hipMemcpyAsync(p->c.z, p->zsave, p->N * 2, hipMemcpyDeviceToDevice, s));
                 HIP_TRY(hipEventRecord(e0, s));
-                HIP_TRY(launch_z_step(p->c, p->m, p->items, (int32_t)items.size(), p->n_waves, p->queue, nullptr, s));
+                HIP_TRY(launch_z_step(p->c, p->m, p->items, (int32_t)items.size(), p->n_waves, p->queue, nullptr, s,
+                                      nullptr, nullptr, nullptr));
                 HIP_TRY(hipEventRecord(e1, s));
                 HIP_TRY(hipEventSynchronize(e1));
                 float ms;
@@ -810,6 +874,17 @@ pulda_status pulda_autotune(pulda_plan *p, uint32_t t, int32_t reps, void *strea
     if (p->N) HIP_TRY(hipMemcpyAsync(p->c.z, p->zsave, p->N * 2, hipMemcpyDeviceToDevice, s));
     HIP_TRY(launch_count_rebuild(p->c, p->m, s));
     HIP_TRY(hipStreamSynchronize(s));
+    return PULDA_OK;
+}
+
+pulda_status pulda_set_timing(pulda_plan *p, int32_t enable)
+{
+    if (!p) return fail(PULDA_ERR_INVALID_ARG, "null argument");
+    p->timing = enable != 0;
+    p->ev_phi.clear();
+    p->ev_z.clear();
+    p->ev_ll.clear();
+    p->ev_used = 0;
     return PULDA_OK;
 }
 

@@ -3,6 +3,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <utility>
+#include <vector>
+
 namespace pulda {
 
 // device buffers of one model, carved from the caller's workspace
@@ -45,6 +48,7 @@ struct WorkItem {
     int32_t first, count, group, pad;
 };
 
+// ST_TOKENS counts z-step launches since the last statistics read
 enum StatIndex { ST_DEGENERATE = 0, ST_SUM_J = 1, ST_SUM_A = 2, ST_NNZ_PHI = 3, ST_EMPTY_ROWS = 4, ST_TOKENS = 5,
                  ST_COUNT = 8 };
 
@@ -56,8 +60,12 @@ hipError_t launch_init_z(const DevCorpus &c, int32_t K, uint32_t key0, uint32_t 
 hipError_t launch_count_rebuild(const DevCorpus &c, const DevModel &m, hipStream_t s);
 hipError_t launch_row_sums(const int32_t *dense, int32_t V, int32_t K, unsigned long long *out, hipStream_t s);
 hipError_t launch_phi_step(const DevModel &m, unsigned long long *stats, hipStream_t s);
+// with ev_pool non-null, records a pair of events around the z-step kernel
+// itself and appends their indices to ev_pairs
 hipError_t launch_z_step(const DevCorpus &c, const DevModel &m, const WorkItem *items, int32_t n_items,
-                         int32_t n_waves, int32_t *queue, unsigned long long *stats, hipStream_t s);
+                         int32_t n_waves, int32_t *queue, unsigned long long *stats, hipStream_t s,
+                         std::vector<hipEvent_t> *ev_pool, size_t *ev_used,
+                         std::vector<std::pair<size_t, size_t>> *ev_pairs);
 hipError_t launch_loglik(const DevCorpus &c, const DevModel &m, double A, double *partials, int32_t n_part_words,
                          int32_t n_part_docs, double *out, double *hist, const uint32_t *hist_idx, hipStream_t s);
 hipError_t launch_advance(uint32_t *tptr, uint32_t *hist_idx, hipStream_t s);

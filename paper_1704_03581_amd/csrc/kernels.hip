@@ -767,8 +767,27 @@ static int topics_per_lane_log2(int K, int G)
     return c;
 }
 
+__global__ void bump_kernel(unsigned long long *x)
+{
+    if (threadIdx.x == 0) *x += 1ull;
+}
+
+static hipError_t record(std::vector<hipEvent_t> *pool, size_t *used, hipStream_t s, size_t *idx)
+{
+    if (*used == pool->size()) {
+        hipEvent_t e;
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return r;
+        pool->push_back(e);
+    }
+    *idx = (*used)++;
+    return hipEventRecord((*pool)[*idx], s);
+}
+
 hipError_t launch_z_step(const DevCorpus &c, const DevModel &m, const WorkItem *items, int32_t n_items,
-                         int32_t n_waves, int32_t *queue, unsigned long long *stats, hipStream_t s)
+                         int32_t n_waves, int32_t *queue, unsigned long long *stats, hipStream_t s,
+                         std::vector<hipEvent_t> *ev_pool, size_t *ev_used,
+                         std::vector<std::pair<size_t, size_t>> *ev_pairs)
 {
     hipError_t e;
     if (m.n) {
@@ -776,7 +795,8 @@ hipError_t launch_z_step(const DevCorpus &c, const DevModel &m, const WorkItem *
         if (e != hipSuccess) return e;
     }
     if (stats) {
-        e = launch_fill_u64(stats, 0ull, 3, s);  // degenerate, sum_J, sum_A
+        bump_kernel<<<1, 64, 0, s>>>(&stats[ST_TOKENS]);
+        e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     e = launch_fill_u32((uint32_t *)queue, 0u, 1, s);
@@ -799,8 +819,20 @@ hipError_t launch_z_step(const DevCorpus &c, const DevModel &m, const WorkItem *
     if (a.log2c16 <= 6) per_wave = 64 << a.log2c16;
     a.lds_per_wave = per_wave;
     const int blocks = (n_waves + 3) / 4;
+    size_t ea = 0, eb = 0;
+    if (ev_pool) {
+        e = record(ev_pool, ev_used, s, &ea);
+        if (e != hipSuccess) return e;
+    }
     z_step_kernel<<<blocks, 256, 4 * per_wave * sizeof(uint16_t), s>>>(a);
-    return hipGetLastError();
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (ev_pool) {
+        e = record(ev_pool, ev_used, s, &eb);
+        if (e != hipSuccess) return e;
+        ev_pairs->push_back({ea, eb});
+    }
+    return hipSuccess;
 }
 
 // ---------------------------------------------------------------------------

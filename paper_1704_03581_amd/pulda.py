@@ -53,7 +53,9 @@ class PhiView(C.Structure):
 
 
 class SweepStats(C.Structure):
-    _fields_ = [("degenerate_tokens", i64), ("sum_J", i64), ("sum_A", i64), ("nnz_phi", i64), ("empty_rows", i64)]
+    _fields_ = [("degenerate_tokens", i64), ("sum_J", i64), ("sum_A", i64), ("z_steps", i64), ("nnz_phi", i64),
+                ("empty_rows", i64), ("ms_phi", f64), ("ms_z", f64), ("ms_ll", f64), ("n_phi", i64), ("n_z", i64),
+                ("n_ll", i64)]
 
 
 class FoldinDesc(C.Structure):
@@ -89,6 +91,7 @@ _SIGS = {
     "pulda_get_schedule": [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)],
     "pulda_autotune": [vp, u32, i32, vp],
     "pulda_set_graph": [vp, i32],
+    "pulda_set_timing": [vp, i32],
     "pulda_foldin_create": [vp, C.POINTER(FoldinDesc), C.POINTER(vp)],
     "pulda_foldin_workspace_bytes": [vp, C.POINTER(i64)],
     "pulda_foldin_bind": [vp, vp, i64],
@@ -317,6 +320,9 @@ class Plan:
 
     def set_graph(self, enable: bool):
         _check(_lib.pulda_set_graph(self._h, 1 if enable else 0))
+
+    def set_timing(self, enable: bool):
+        _check(_lib.pulda_set_timing(self._h, 1 if enable else 0))
 
 
 class FoldIn:
