@@ -158,6 +158,11 @@ def main():
     ap.add_argument("--slots", type=int, default=2048)
     ap.add_argument("--quantum", type=int, default=10)
     ap.add_argument("--rates", type=float, nargs="*", default=[0.5, 0.8, 0.95])
+    ap.add_argument("--corpus-cache", default=None,
+                    help=".npz file: load the corpus from it if present, else generate and save it there")
+    ap.add_argument("--generate-only", action="store_true", help="generate (and cache) the corpus, then exit")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="first copy 1 GiB device-to-device 3 times (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
@@ -165,14 +170,31 @@ def main():
         sys.exit(2)
 
     from paper_1704_03581_amd import synth
-    log(f"generating the {args.config} corpus")
     t0 = time.perf_counter()
-    corpus = synth.generate(args.config, keep_true_z=False)
+    if args.corpus_cache and os.path.exists(args.corpus_cache):
+        log(f"loading the {args.config} corpus from {args.corpus_cache}")
+        corpus = synth.load(args.corpus_cache)
+        assert corpus.name == args.config, (corpus.name, args.config)
+    else:
+        log(f"generating the {args.config} corpus")
+        corpus = synth.generate(args.config, keep_true_z=False)
+        if args.corpus_cache:
+            synth.save(corpus, args.corpus_cache)
+    if args.generate_only:
+        return
     log(f"corpus: D={corpus.D} V={corpus.V} K={corpus.K} N={corpus.N} ({time.perf_counter() - t0:.1f}s)")
 
     import torch
     from paper_1704_03581_amd import pulda
     dev = torch.device("cuda:0")
+    if args.calibrate:
+        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        log("calibration copies: 3 x 1 GiB device-to-device")
     plan = pulda.Plan(corpus.K, corpus.V, corpus.D, corpus.N, alpha=corpus.alpha, beta=corpus.beta,
                       seed=args.seed, device=dev)
     plan.upload(corpus.doc_off, corpus.words)

@@ -134,12 +134,14 @@ struct pulda_plan {
     struct {
         int64_t z, n, gam, phid, colcnt, colptr, ctopic, cphi, calias, sigma_a, S, nk, alpha, pois, pois_off,
             doc_order, items, queue, stats, ll_part, ll_out, ll_hist, tptr, err, scratch, cnt_a, ptr_a, cnt_b,
-            ptr_b, zsave;
+            ptr_b, zsave, lg_beta, lg_alpha, lg_A;
     } off;
     int64_t cap = 0, items_cap = 0, hist_cap = 4096;
     int32_t n_part_words = 1024, n_part_docs = 1024;
     std::vector<int32_t> pois_off_h;
     std::vector<uint64_t> pois_h;
+    std::vector<double> lg_beta_h, lg_alpha_h, lg_A_h;  // log-joint term tables
+    bool symmetric_alpha = true;
     uint32_t ztp[5];
     // device views
     DevModel m{};
@@ -222,6 +224,17 @@ pulda_status pulda_plan_create(const pulda_model_desc *desc, int64_t D, int64_t 
     p->N = N;
     poisson_tables(p->beta, p->L, p->pois_off_h, p->pois_h);
     ztp_thresholds(p->beta, p->ztp);
+    // log-joint terms of small integer counts, evaluated once
+    for (double a : alpha) p->symmetric_alpha = p->symmetric_alpha && a == alpha[0];
+    p->lg_beta_h.resize(LG_TABLE);
+    p->lg_alpha_h.resize(LG_TABLE);
+    p->lg_A_h.resize(LG_TABLE);
+    const double lgb = std::lgamma(p->beta), lga = std::lgamma(alpha[0]), lgA = std::lgamma(p->A);
+    for (int32_t x = 0; x < LG_TABLE; ++x) {
+        p->lg_beta_h[x] = std::lgamma((double)x + p->beta) - lgb;
+        p->lg_alpha_h[x] = std::lgamma((double)x + alpha[0]) - lga;
+        p->lg_A_h[x] = lgA - std::lgamma((double)x + p->A);
+    }
 
     const int64_t VK = (int64_t)p->V * p->K;
     p->cap = VK;
@@ -257,6 +270,9 @@ pulda_status pulda_plan_create(const pulda_model_desc *desc, int64_t D, int64_t 
     p->off.cnt_b = L.take((D + 2) * 8);
     p->off.ptr_b = L.take((D + 2) * 8);
     p->off.zsave = L.take(N * 2);
+    p->off.lg_beta = L.take((int64_t)LG_TABLE * 8);
+    p->off.lg_alpha = L.take((int64_t)LG_TABLE * 8);
+    p->off.lg_A = L.take((int64_t)LG_TABLE * 8);
     p->ws_need = L.total;
     *out = p;
     return PULDA_OK;
@@ -299,6 +315,9 @@ pulda_status pulda_plan_bind(pulda_plan *p, void *workspace_dev, int64_t bytes)
     m.pois = (const uint64_t *)(w + p->off.pois);
     m.pois_off = (const int32_t *)(w + p->off.pois_off);
     std::memcpy(m.ztp, p->ztp, sizeof(m.ztp));
+    m.lg_beta = (const double *)(w + p->off.lg_beta);
+    m.lg_alpha = p->symmetric_alpha ? (const double *)(w + p->off.lg_alpha) : nullptr;
+    m.lg_A = (const double *)(w + p->off.lg_A);
     p->tptr = (uint32_t *)(w + p->off.tptr);
     p->hist_idx = p->tptr + 1;
     m.tptr = p->tptr;
@@ -323,6 +342,9 @@ pulda_status pulda_plan_bind(pulda_plan *p, void *workspace_dev, int64_t bytes)
     HIP_TRY(hipMemcpy((void *)m.alpha, p->alpha.data(), p->K * sizeof(double), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy((void *)m.pois, p->pois_h.data(), p->pois_h.size() * 8, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy((void *)m.pois_off, p->pois_off_h.data(), p->pois_off_h.size() * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(w + p->off.lg_beta, p->lg_beta_h.data(), LG_TABLE * 8, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(w + p->off.lg_alpha, p->lg_alpha_h.data(), LG_TABLE * 8, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(w + p->off.lg_A, p->lg_A_h.data(), LG_TABLE * 8, hipMemcpyHostToDevice));
     HIP_TRY(hipMemset(p->stats, 0, ST_COUNT * 8));
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));

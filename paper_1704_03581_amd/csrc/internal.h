@@ -30,6 +30,11 @@ struct DevModel {
     const uint64_t *pois;         // Poisson alias tables, thr | x_alias << 32
     const int32_t *pois_off;      // [L+2]
     uint32_t ztp[5];              // zero-truncated Pois(beta) thresholds
+    // log-joint terms for integer counts x < LG_TABLE:
+    //   lg_beta[x] = lgamma(x + beta) - lgamma(beta),
+    //   lg_alpha[x] = lgamma(x + alpha) - lgamma(alpha) (symmetric alpha only, else null),
+    //   lg_A[x] = lgamma(A) - lgamma(x + A), A = sum_k alpha_k
+    const double *lg_beta, *lg_alpha, *lg_A;
     const uint32_t *tptr;         // sweep number t, read on the device
     long long *scratch;           // scan scratch: ceil(max(V, D) / 1024) + 2 entries
 };
@@ -49,6 +54,8 @@ struct WorkItem {
 };
 
 // ST_TOKENS counts z-step launches since the last statistics read
+constexpr int32_t LG_TABLE = 65536;
+
 enum StatIndex { ST_DEGENERATE = 0, ST_SUM_J = 1, ST_SUM_A = 2, ST_NNZ_PHI = 3, ST_EMPTY_ROWS = 4, ST_TOKENS = 5,
                  ST_COUNT = 8 };
 

@@ -512,27 +512,82 @@ struct ZArgs {
     DevCorpus c;
     const WorkItem *items;
     int32_t n_items;
-    int32_t lds_per_wave;   // u16 slots per wave
+    int32_t m_per_wave;     // u16 count slots per wave
     int32_t *queue;
     unsigned long long *stats;
     int32_t log2c64, log2c32, log2c16;  // log2 of topics per lane for each group size
 };
 
-struct TokenStats {
-    unsigned long long J, A, degenerate;
+// inputs of one token draw, staged in LDS so every lane of the group reads
+// them with one broadcast load
+struct alignas(16) TokenIn {
+    int32_t v;      // word
+    int32_t kold;   // topic before the draw
+    int32_t cb;     // first CSC entry of the word's Phi column
+    int32_t kv;     // nonzeros in the column (K_v^Phi)
+    uint32_t r0, r1, r2, pad;
+    double sa;      // sigma_a(v)
+    double pad2;
 };
 
-// draw one token (group-uniform control flow); returns the new topic
+struct ZCount {
+    uint32_t J, A, degenerate;
+};
+
+constexpr int KEEP = 4;  // b-terms per lane kept in registers for the walk
+
 template <int G>
-__device__ __forceinline__ int32_t draw_token(const DevModel &M, int32_t v, int32_t kold, uint32_t r0, uint32_t r1,
-                                              uint32_t r2, uint16_t *mt, int g, int log2c, uint64_t &mask,
-                                              int32_t &Kd, int32_t *n_out, TokenStats &st)
+constexpr int log2g()
 {
+    return G == 64 ? 6 : (G == 32 ? 5 : 4);
+}
+
+template <int G>
+__device__ __forceinline__ int32_t mslot(int32_t k, int log2c)
+{
+    return ((k & ((1 << log2c) - 1)) << log2g<G>()) + (k >> log2c);
+}
+
+// up to KEEP b-terms of this lane starting at entry `base` of its list:
+// topic, phi and m_d of each (zeros past the end); loads are issued together
+template <int G>
+__device__ __forceinline__ void lane_terms(const DevModel &M, const float *pcol, const uint16_t *mt, bool docside,
+                                           uint64_t &rest, int32_t cbe, int32_t base, int32_t nl, int g, int log2c,
+                                           int32_t (&kk)[KEEP], float (&fk)[KEEP], int32_t (&mk)[KEEP])
+{
+#pragma unroll
+    for (int u = 0; u < KEEP; ++u) {
+        const bool ok = base + u < nl;
+        int32_t k = 0;
+        float f = 0.0f;
+        if (docside) {
+            const int b = ok ? __builtin_ctzll(rest) : 0;
+            rest &= rest - 1;
+            k = (g << log2c) + b;
+            if (ok) f = pcol[k];
+        } else if (ok) {
+            k = M.ctopic[cbe + base + u];
+            f = M.cphi[cbe + base + u];
+        }
+        kk[u] = ok ? k : -1;
+        fk[u] = f;
+    }
+#pragma unroll
+    for (int u = 0; u < KEEP; ++u) mk[u] = kk[u] >= 0 ? (int32_t)mt[mslot<G>(kk[u], log2c)] : 0;
+}
+
+// draw one token (group-uniform control flow); returns the new topic, or
+// -1 - kold for a token whose word has an empty Phi column (it keeps kold)
+template <int G>
+__device__ __forceinline__ int32_t draw_token(const DevModel &M, const TokenIn &tk, uint16_t *mt, const int g,
+                                              const int log2c, uint64_t &mask, int32_t &Kd, ZCount &cnt)
+{
+    constexpr int LG = log2g<G>();
     const int32_t C = 1 << log2c;
-    const int32_t K = M.K;
-    // remove token i: m^{-i}
+    // m^{-i}: remove the token from its document's counts
+    const int32_t kold = tk.kold;
     const int32_t ob = kold & (C - 1), oo = kold >> log2c;
-    const int32_t oslot = ob * G + oo;
+    const int32_t oslot = (ob << LG) + oo;
     const int32_t mo = mt[oslot];
     __builtin_amdgcn_wave_barrier();
     if (g == oo) {
@@ -541,9 +596,7 @@ __device__ __forceinline__ int32_t draw_token(const DevModel &M, int32_t v, int3
     }
     if (mo == 1) --Kd;
     __builtin_amdgcn_wave_barrier();
-
-    const int32_t cb = M.colptr[v];
-    const int32_t Kv = M.colptr[v + 1] - cb;
+    const int32_t Kv = tk.kv;
     if (Kv == 0) {
         // 0/0 conditional: the token keeps its topic
         if (g == oo) {
@@ -552,101 +605,100 @@ __device__ __forceinline__ int32_t draw_token(const DevModel &M, int32_t v, int3
         }
         if (mo == 1) ++Kd;
         __builtin_amdgcn_wave_barrier();
-        if (g == 0) {
-            st.degenerate++;
-            if (n_out) atomicAdd(&n_out[(int64_t)v * K + kold], 1);
-        }
-        return kold;
+        cnt.degenerate++;
+        return -1 - kold;
     }
-    const double sa = M.sigma_a[v];
+    cnt.J += (uint32_t)(Kd < Kv ? Kd : Kv);
+    // b-terms over the smaller side: the document's nonzero topics (lane g
+    // owns topics [g*C, (g+1)*C)) or the word's Phi column (lane g takes a
+    // contiguous block of entries); ascending topic order either way
     const bool docside = Kd <= Kv;
-    const float *pcol = M.phid + (int64_t)v * K;
-    int32_t e0 = 0, e1 = 0;
-    double p = 0.0;
+    const float *pcol = M.phid + (uint32_t)tk.v * (uint32_t)M.K;
+    int32_t nl, cbe = 0;
+    uint64_t rest = mask;
     if (docside) {
-        uint64_t mm = mask;
-        while (mm) {
-            const int b = __builtin_ctzll(mm);
-            mm &= mm - 1;
-            p += (double)pcol[(g << log2c) + b] * (double)mt[b * G + g];
-        }
+        nl = __builtin_popcountll(mask);
     } else {
-        const int32_t q = (Kv + G - 1) / G;
-        e0 = g * q;
-        e1 = e0 + q < Kv ? e0 + q : Kv;
-        for (int32_t e = e0; e < e1; ++e) {
-            const int32_t k = M.ctopic[cb + e];
-            p += (double)M.cphi[cb + e] * (double)mt[(k & (C - 1)) * G + (k >> log2c)];
-        }
+        const int32_t q = (Kv + G - 1) >> LG;
+        const int32_t e0 = g * q;
+        nl = Kv - e0 < q ? Kv - e0 : q;
+        nl = nl > 0 ? nl : 0;
+        cbe = tk.cb + e0;
+    }
+    int32_t kk[KEEP], mk[KEEP];
+    float fk[KEEP];
+    lane_terms<G>(M, pcol, mt, docside, rest, cbe, 0, nl, g, log2c, kk, fk, mk);
+    double p = 0.0;
+#pragma unroll
+    for (int u = 0; u < KEEP; ++u) p += (double)fk[u] * (double)mk[u];
+    for (int32_t base = KEEP; base < nl; base += KEEP) {
+        int32_t k2[KEEP], m2[KEEP];
+        float f2[KEEP];
+        lane_terms<G>(M, pcol, mt, docside, rest, cbe, base, nl, g, log2c, k2, f2, m2);
+#pragma unroll
+        for (int u = 0; u < KEEP; ++u) p += (double)f2[u] * (double)m2[u];
     }
     const double incl = group_scan_incl<G>(p);
     const double T = group_bcast_f64<G>(incl, G - 1);
-    const double Z = sa + T;
-    const double x = unit24(r0) * Z;
-    int32_t knew;
-    if (x < sa) {
-        const uint32_t j = scale32(r1, (uint32_t)Kv);
-        const uint64_t a = M.calias[cb + j];
-        knew = (r2 < (uint32_t)a) ? (int32_t)((a >> 32) & 0xFFFFu) : (int32_t)(a >> 48);
-        if (g == 0) st.A++;
-    } else {
-        const double y = x - sa;
-        uint64_t bal = group_ballot<G>(incl > y);
-        int f;
+    const double Z = tk.sa + T;
+    const double x = unit24(tk.r0) * Z;
+    int32_t knew = -1;
+    if (!(x < tk.sa)) {
+        // b-part: the first lane whose running sum passes y walks its terms
+        const double y = x - tk.sa;
+        const uint64_t bal = group_ballot<G>(incl > y);
+        int f = -1;
         if (bal) {
             f = __builtin_ctzll(bal);
         } else {
             const uint64_t pos = group_ballot<G>(p > 0.0);
-            f = pos ? 63 - __builtin_clzll(pos) : 0;
+            if (pos) f = 63 - __builtin_clzll(pos);
         }
         int32_t kf = -1;
         if (g == f) {
             double c = incl - p;
             int32_t last = -1;
-            if (docside) {
-                uint64_t mm = mask;
-                while (mm) {
-                    const int b = __builtin_ctzll(mm);
-                    mm &= mm - 1;
-                    const int32_t k = (g << log2c) + b;
-                    const double bv = (double)pcol[k] * (double)mt[b * G + g];
+            if (nl <= KEEP) {
+#pragma unroll
+                for (int u = 0; u < KEEP; ++u) {
+                    const double bv = (double)fk[u] * (double)mk[u];
                     if (bv > 0.0) {
                         c += bv;
-                        last = k;
-                        if (c > y) {
-                            kf = k;
-                            break;
-                        }
+                        last = kk[u];
+                        if (kf < 0 && c > y) kf = kk[u];
                     }
                 }
             } else {
-                for (int32_t e = e0; e < e1; ++e) {
-                    const int32_t k = M.ctopic[cb + e];
-                    const double bv = (double)M.cphi[cb + e] * (double)mt[(k & (C - 1)) * G + (k >> log2c)];
-                    if (bv > 0.0) {
-                        c += bv;
-                        last = k;
-                        if (c > y) {
-                            kf = k;
-                            break;
+                uint64_t r2 = mask;
+                for (int32_t base = 0; base < nl && kf < 0; base += KEEP) {
+                    int32_t k2[KEEP], m2[KEEP];
+                    float f2[KEEP];
+                    lane_terms<G>(M, pcol, mt, docside, r2, cbe, base, nl, g, log2c, k2, f2, m2);
+#pragma unroll
+                    for (int u = 0; u < KEEP; ++u) {
+                        const double bv = (double)f2[u] * (double)m2[u];
+                        if (bv > 0.0) {
+                            c += bv;
+                            last = k2[u];
+                            if (kf < 0 && c > y) kf = k2[u];
                         }
                     }
                 }
             }
             if (kf < 0) kf = last;
         }
-        knew = group_bcast<G>(kf, f);
-        if (knew < 0) {
-            // no positive b-term survived rounding: the a-part is the whole law
-            const uint32_t j = scale32(r1, (uint32_t)Kv);
-            const uint64_t a = M.calias[cb + j];
-            knew = (r2 < (uint32_t)a) ? (int32_t)((a >> 32) & 0xFFFFu) : (int32_t)(a >> 48);
-        }
+        if (f >= 0) knew = group_bcast<G>(kf, f);
     }
-    if (g == 0) st.J += (unsigned long long)(Kd < Kv ? Kd : Kv);
-    // add token i back with its new topic
+    if (knew < 0) {
+        // a-part (or no positive b-term survived rounding): the word's alias table
+        const uint32_t j = scale32(tk.r1, (uint32_t)Kv);
+        const uint64_t a = M.calias[tk.cb + j];
+        knew = (tk.r2 < (uint32_t)a) ? (int32_t)((a >> 32) & 0xFFFFu) : (int32_t)(a >> 48);
+        cnt.A++;
+    }
+    // add the token back with its new topic
     const int32_t nb = knew & (C - 1), no = knew >> log2c;
-    const int32_t nslot = nb * G + no;
+    const int32_t nslot = (nb << LG) + no;
     const int32_t mn = mt[nslot];
     __builtin_amdgcn_wave_barrier();
     if (g == no) {
@@ -655,7 +707,6 @@ __device__ __forceinline__ int32_t draw_token(const DevModel &M, int32_t v, int3
     }
     if (mn == 0) ++Kd;
     __builtin_amdgcn_wave_barrier();
-    if (g == 0 && n_out) atomicAdd(&n_out[(int64_t)v * K + knew], 1);
     return knew;
 }
 
@@ -665,26 +716,42 @@ __device__ __forceinline__ void load_doc_counts(uint16_t *mt, const uint16_t *z,
                                                 int log2c, uint64_t &mask, int32_t &Kd)
 {
     const int32_t C = 1 << log2c;
-    for (int32_t i = g; i < C * G; i += G) mt[i] = 0;
+    uint32_t *w32 = (uint32_t *)mt;
+    for (int32_t i = g; i < C * G / 2; i += G) w32[i] = 0;
     __builtin_amdgcn_wave_barrier();
     for (int64_t i = s + g; i < e; i += G) {
-        const int32_t k = z[i];
-        const int32_t slot = (k & (C - 1)) * G + (k >> log2c);
-        uint32_t *word = (uint32_t *)(mt + (slot & ~1));
-        atomicAdd(word, (slot & 1) ? 65536u : 1u);
+        const int32_t slot = mslot<G>(z[i], log2c);
+        atomicAdd(w32 + (slot >> 1), (slot & 1) ? 65536u : 1u);
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     mask = 0;
     for (int32_t b = 0; b < C; ++b)
-        if (mt[b * G + g]) mask |= 1ull << b;
-    const int32_t cnt = __builtin_popcountll(mask);
-    const int32_t tot = group_scan_incl_i32<G>(cnt);
+        if (mt[(b << log2g<G>()) + g]) mask |= 1ull << b;
+    const int32_t tot = group_scan_incl_i32<G>(__builtin_popcountll(mask));
     Kd = group_bcast<G>(tot, G - 1);
 }
 
+// stage the inputs of tokens i0 + g (one per lane) for a block of draws
+__device__ __forceinline__ void stage_token(const DevModel &M, TokenIn *tok, int g, int32_t v, int32_t kold,
+                                            const r4 &r)
+{
+    TokenIn x;
+    x.v = v;
+    x.kold = kold;
+    x.cb = M.colptr[v];
+    x.kv = M.colptr[v + 1] - x.cb;
+    x.r0 = r.x;
+    x.r1 = r.y;
+    x.r2 = r.z;
+    x.pad = 0;
+    x.sa = M.sigma_a[v];
+    x.pad2 = 0.0;
+    tok[g] = x;
+}
+
 template <int G>
-__device__ void z_step_item(const ZArgs &a, const WorkItem &w, uint16_t *wave_lds, TokenStats &st)
+__device__ void z_step_item(const ZArgs &a, const WorkItem &w, uint16_t *wave_m, TokenIn *wave_tok, ZCount &cnt)
 {
     constexpr int NG = 64 / G;
     const int lane = __lane_id();
@@ -692,7 +759,8 @@ __device__ void z_step_item(const ZArgs &a, const WorkItem &w, uint16_t *wave_ld
     const int grp = lane / G;
     const int log2c = G == 64 ? a.log2c64 : (G == 32 ? a.log2c32 : a.log2c16);
     const int32_t C = 1 << log2c;
-    uint16_t *mt = wave_lds + grp * (C * G);
+    uint16_t *mt = wave_m + grp * (C * G);
+    TokenIn *tok = wave_tok + grp * G;
     const DevModel &M = a.m;
     const uint32_t t = *M.tptr;
     for (int32_t di = grp; di < w.count; di += NG) {
@@ -705,27 +773,24 @@ __device__ void z_step_item(const ZArgs &a, const WorkItem &w, uint16_t *wave_ld
         for (int64_t i0 = s; i0 < e; i0 += G) {
             const int64_t i = i0 + g;
             const bool valid = i < e;
-            int32_t wv = 0, zo = 0;
-            uint32_t r0 = 0, r1 = 0, r2 = 0;
+            int32_t zo = 0;
             if (valid) {
-                wv = a.c.words[i];
+                const int32_t wv = a.c.words[i];
                 zo = a.c.z[i];
                 const r4 r = philox((uint32_t)i, (uint32_t)((uint64_t)i >> 32), t, TAG_Z, M.key0, M.key1);
-                r0 = r.x;
-                r1 = r.y;
-                r2 = r.z;
+                stage_token(M, tok, g, wv, zo, r);
             }
+            __builtin_amdgcn_wave_barrier();
             int32_t znew = zo;
             const int nb = (int)((e - i0) < G ? (e - i0) : G);
             for (int jj = 0; jj < nb; ++jj) {
-                const int32_t v = group_bcast<G>(wv, jj);
-                const int32_t kold = group_bcast<G>(zo, jj);
-                const uint32_t q0 = (uint32_t)group_bcast<G>((int)r0, jj);
-                const uint32_t q1 = (uint32_t)group_bcast<G>((int)r1, jj);
-                const uint32_t q2 = (uint32_t)group_bcast<G>((int)r2, jj);
-                const int32_t k = draw_token<G>(M, v, kold, q0, q1, q2, mt, g, log2c, mask, Kd, M.n, st);
+                const TokenIn tk = tok[jj];
+                int32_t k = draw_token<G>(M, tk, mt, g, log2c, mask, Kd, cnt);
+                if (k < 0) k = -1 - k;
+                if (g == 0) atomicAdd(&M.n[(uint32_t)tk.v * (uint32_t)M.K + (uint32_t)k], 1);
                 if (g == jj) znew = k;
             }
+            __builtin_amdgcn_wave_barrier();
             if (valid) a.c.z[i] = (uint16_t)znew;
         }
     }
@@ -735,22 +800,31 @@ __global__ void __launch_bounds__(256) z_step_kernel(ZArgs a)
 {
     extern __shared__ uint16_t z_lds[];
     const int wave = threadIdx.x >> 6;
-    uint16_t *wave_lds = z_lds + wave * a.lds_per_wave;
-    TokenStats st = {0, 0, 0};
+    uint16_t *wave_m = z_lds + wave * a.m_per_wave;
+    TokenIn *wave_tok = (TokenIn *)(z_lds + 4 * a.m_per_wave) + wave * 64;
+    ZCount cnt = {0, 0, 0};
+    unsigned long long J = 0, A = 0, D = 0;
     while (true) {
         int item = 0;
         if (__lane_id() == 0) item = atomicAdd(a.queue, 1);
         item = __builtin_amdgcn_readlane(item, 0);
         if (item >= a.n_items) break;
         const WorkItem w = a.items[item];
-        if (w.group == 64) z_step_item<64>(a, w, wave_lds, st);
-        else if (w.group == 32) z_step_item<32>(a, w, wave_lds, st);
-        else z_step_item<16>(a, w, wave_lds, st);
+        if (w.group == 64) z_step_item<64>(a, w, wave_m, wave_tok, cnt);
+        else if (w.group == 32) z_step_item<32>(a, w, wave_m, wave_tok, cnt);
+        else z_step_item<16>(a, w, wave_m, wave_tok, cnt);
+        // every lane of a group counted the group's tokens; its first lane keeps them
+        if ((__lane_id() & (w.group - 1)) == 0) {
+            J += cnt.J;
+            A += cnt.A;
+            D += cnt.degenerate;
+        }
+        cnt = {0, 0, 0};
     }
-    if (a.stats && (__lane_id() & 15) == 0) {
-        if (st.J) atomicAdd(&a.stats[ST_SUM_J], st.J);
-        if (st.A) atomicAdd(&a.stats[ST_SUM_A], st.A);
-        if (st.degenerate) atomicAdd(&a.stats[ST_DEGENERATE], st.degenerate);
+    if (a.stats) {
+        if (J) atomicAdd(&a.stats[ST_SUM_J], J);
+        if (A) atomicAdd(&a.stats[ST_SUM_A], A);
+        if (D) atomicAdd(&a.stats[ST_DEGENERATE], D);
     }
 }
 
@@ -813,18 +887,20 @@ hipError_t launch_z_step(const DevCorpus &c, const DevModel &m, const WorkItem *
     a.log2c32 = topics_per_lane_log2(m.K, 32);
     a.log2c16 = topics_per_lane_log2(m.K, 16);
     // a wave holds 64/G tables of C*G slots: 64*C slots, largest for the
-    // smallest group size that is valid for K (C <= 64)
+    // smallest group size that is valid for K (C <= 64); then 64 staged
+    // token inputs per wave
     int per_wave = 64 << a.log2c64;
     if (a.log2c32 <= 6) per_wave = 64 << a.log2c32;
     if (a.log2c16 <= 6) per_wave = 64 << a.log2c16;
-    a.lds_per_wave = per_wave;
+    a.m_per_wave = per_wave;
+    const size_t lds = 4 * (per_wave * sizeof(uint16_t) + 64 * sizeof(TokenIn));
     const int blocks = (n_waves + 3) / 4;
     size_t ea = 0, eb = 0;
     if (ev_pool) {
         e = record(ev_pool, ev_used, s, &ea);
         if (e != hipSuccess) return e;
     }
-    z_step_kernel<<<blocks, 256, 4 * per_wave * sizeof(uint16_t), s>>>(a);
+    z_step_kernel<<<blocks, 256, lds, s>>>(a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (ev_pool) {
@@ -857,20 +933,21 @@ __device__ __forceinline__ double block_sum_f64(double x, double *red)
 }
 
 __global__ void __launch_bounds__(256) ll_words_kernel(const int32_t *n, int64_t cells, double beta, double lgb,
-                                                       double *partials)
+                                                       const double *lg_beta, double *partials)
 {
     __shared__ double red[4];
     double acc = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cells; i += (int64_t)gridDim.x * blockDim.x) {
         const int32_t c = n[i];
-        if (c > 0) acc += lgamma((double)c + beta) - lgb;
+        if (c > 0) acc += c < LG_TABLE ? lg_beta[c] : lgamma((double)c + beta) - lgb;
     }
     const double t = block_sum_f64(acc, red);
     if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
-__global__ void __launch_bounds__(256) ll_docs_kernel(DevCorpus c, int32_t K, const double *alpha, double A,
-                                                      double lgA, int32_t log2c, double *partials)
+__global__ void __launch_bounds__(256) ll_docs_kernel(DevCorpus c, int32_t K, const double *alpha,
+                                                      const double *lg_alpha, const double *lg_A, int32_t log2c,
+                                                      double *partials)
 {
     extern __shared__ uint16_t ll_lds[];
     __shared__ double red[4];
@@ -878,16 +955,17 @@ __global__ void __launch_bounds__(256) ll_docs_kernel(DevCorpus c, int32_t K, co
     const int wv = threadIdx.x >> 6;
     const int32_t C = 1 << log2c;
     uint16_t *mt = ll_lds + wv * (64 * C);
+    uint32_t *w32 = (uint32_t *)mt;
     double acc = 0.0;
     const int64_t nw = (int64_t)gridDim.x * 4;
     for (int64_t d = blockIdx.x * 4 + wv; d < c.D; d += nw) {
         const int64_t s = c.doc_off[d], e = c.doc_off[d + 1];
-        for (int32_t i = lane; i < 64 * C; i += 64) mt[i] = 0;
+        for (int32_t i = lane; i < 32 * C; i += 64) w32[i] = 0;
         __builtin_amdgcn_wave_barrier();
         for (int64_t i = s + lane; i < e; i += 64) {
             const int32_t k = c.z[i];
             const int32_t slot = (k & (C - 1)) * 64 + (k >> log2c);
-            atomicAdd((uint32_t *)(mt + (slot & ~1)), (slot & 1) ? 65536u : 1u);
+            atomicAdd(w32 + (slot >> 1), (slot & 1) ? 65536u : 1u);
         }
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -896,10 +974,10 @@ __global__ void __launch_bounds__(256) ll_docs_kernel(DevCorpus c, int32_t K, co
             const int32_t cnt = mt[b * 64 + lane];
             if (cnt) {
                 const int32_t k = lane * C + b;
-                part += lgamma((double)cnt + alpha[k]) - lgamma(alpha[k]);
+                part += lg_alpha ? lg_alpha[cnt] : lgamma((double)cnt + alpha[k]) - lgamma(alpha[k]);
             }
         }
-        if (lane == 0) part += lgA - lgamma((double)(e - s) + A);
+        if (lane == 0) part += lg_A[e - s];
         acc += part;
     }
     const double t = block_sum_f64(acc, red);
@@ -937,12 +1015,14 @@ hipError_t launch_loglik(const DevCorpus &c, const DevModel &m, double A, double
 {
     hipError_t e = launch_row_sums(m.n, m.V, m.K, m.nk, s);
     if (e != hipSuccess) return e;
-    ll_words_kernel<<<n_part_words, 256, 0, s>>>(m.n, (int64_t)m.V * m.K, m.beta, lgamma(m.beta), partials);
+    (void)A;
+    ll_words_kernel<<<n_part_words, 256, 0, s>>>(m.n, (int64_t)m.V * m.K, m.beta, lgamma(m.beta), m.lg_beta,
+                                                 partials);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int log2c = topics_per_lane_log2(m.K, 64);
     ll_docs_kernel<<<n_part_docs, 256, 4 * 64 * (1 << log2c) * sizeof(uint16_t), s>>>(
-        c, m.K, m.alpha, A, lgamma(A), log2c, partials + n_part_words);
+        c, m.K, m.alpha, m.lg_alpha, m.lg_A, log2c, partials + n_part_words);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     ll_final_kernel<<<1, 64, 0, s>>>(partials, n_part_words + n_part_docs, m.nk, m.K, (double)m.V * m.beta, out,
@@ -1125,7 +1205,8 @@ hipError_t launch_scan_i64(const int64_t *in, int64_t *out_excl, int64_t n, long
 // the log-likelihood of the final state.
 // ---------------------------------------------------------------------------
 template <int G>
-__device__ void foldin_slot(const DevModel &M, const DevFoldin &F, int32_t sid, uint16_t *mt, int log2c)
+__device__ void foldin_slot(const DevModel &M, const DevFoldin &F, int32_t sid, uint16_t *mt, TokenIn *tok,
+                            int log2c)
 {
     const int lane = __lane_id();
     const int g = lane & (G - 1);
@@ -1169,33 +1250,28 @@ __device__ void foldin_slot(const DevModel &M, const DevFoldin &F, int32_t sid, 
     uint64_t mask;
     int32_t Kd;
     load_doc_counts<G>(mt, zz, 0, kept, g, log2c, mask, Kd);
-    TokenStats st = {0, 0, 0};
+    ZCount st = {0, 0, 0};
     for (int32_t s = sl.done + 1; s <= sl.done + sl.todo; ++s) {
         for (int32_t q0 = 0; q0 < kept; q0 += G) {
             const int32_t q = q0 + g;
             const bool valid = q < kept;
-            int32_t wv = 0, zo = 0;
-            uint32_t r0 = 0, r1 = 0, r2 = 0;
+            int32_t zo = 0;
             if (valid) {
                 const int32_t p = pos[q];
-                wv = wds[p];
                 zo = zz[q];
                 const r4 r = philox((uint32_t)p, sl.req, (uint32_t)s, TAG_FOLDIN_Z, F.key0, F.key1);
-                r0 = r.x;
-                r1 = r.y;
-                r2 = r.z;
+                stage_token(M, tok, g, wds[p], zo, r);
             }
+            __builtin_amdgcn_wave_barrier();
             int32_t znew = zo;
             const int nb = (kept - q0) < G ? (kept - q0) : G;
             for (int jj = 0; jj < nb; ++jj) {
-                const int32_t v = group_bcast<G>(wv, jj);
-                const int32_t kold = group_bcast<G>(zo, jj);
-                const uint32_t a0 = (uint32_t)group_bcast<G>((int)r0, jj);
-                const uint32_t a1 = (uint32_t)group_bcast<G>((int)r1, jj);
-                const uint32_t a2 = (uint32_t)group_bcast<G>((int)r2, jj);
-                const int32_t k = draw_token<G>(M, v, kold, a0, a1, a2, mt, g, log2c, mask, Kd, nullptr, st);
+                const TokenIn tk = tok[jj];
+                int32_t k = draw_token<G>(M, tk, mt, g, log2c, mask, Kd, st);
+                if (k < 0) k = -1 - k;
                 if (g == jj) znew = k;
             }
+            __builtin_amdgcn_wave_barrier();
             if (valid) zz[q] = (uint16_t)znew;
         }
         if (s > F.burn_in) {
@@ -1235,11 +1311,12 @@ __global__ void __launch_bounds__(256) foldin_step_kernel(DevModel M, DevFoldin 
     const int ngw = 64 / gsz;
     const int64_t gid = ((int64_t)blockIdx.x * 4 + wave) * ngw + grp;
     uint16_t *mt = f_lds + (wave * ngw + grp) * per_group;
+    TokenIn *tok = (TokenIn *)(f_lds + 4 * ngw * per_group) + wave * 64 + grp * gsz;
     if (gid >= n_active) return;
     const int32_t sid = active[gid];
-    if (gsz == 64) foldin_slot<64>(M, F, sid, mt, log2c);
-    else if (gsz == 32) foldin_slot<32>(M, F, sid, mt, log2c);
-    else foldin_slot<16>(M, F, sid, mt, log2c);
+    if (gsz == 64) foldin_slot<64>(M, F, sid, mt, tok, log2c);
+    else if (gsz == 32) foldin_slot<32>(M, F, sid, mt, tok, log2c);
+    else foldin_slot<16>(M, F, sid, mt, tok, log2c);
 }
 
 hipError_t launch_foldin_step(const DevModel &m, const DevFoldin &f, const int32_t *active, int32_t n_active,
@@ -1251,8 +1328,8 @@ hipError_t launch_foldin_step(const DevModel &m, const DevFoldin &f, const int32
     const int ngw = 64 / f.group;
     const int64_t waves = (n_active + ngw - 1) / ngw;
     const unsigned blocks = (unsigned)((waves + 3) / 4);
-    foldin_step_kernel<<<blocks, 256, 4 * ngw * per_group * sizeof(uint16_t), s>>>(m, f, active, n_active, log2c,
-                                                                                   per_group);
+    const size_t lds = 4 * ngw * per_group * sizeof(uint16_t) + 4 * 64 * sizeof(TokenIn);
+    foldin_step_kernel<<<blocks, 256, lds, s>>>(m, f, active, n_active, log2c, per_group);
     return hipGetLastError();
 }
 

@@ -197,6 +197,19 @@ def generate(name: str, seed: Optional[int] = None, workers: Optional[int] = Non
     return Corpus(name, D, V, K, ALPHA, BETA, off, words, z)
 
 
+def save(c: Corpus, path: str) -> None:
+    """Write a corpus as a plain .npz (no pickled objects)."""
+    np.savez(path, name=np.array(c.name), shape=np.array([c.D, c.V, c.K], np.int64),
+             prior=np.array([c.alpha, c.beta]), doc_off=c.doc_off, words=c.words)
+
+
+def load(path: str) -> Corpus:
+    with np.load(path, allow_pickle=False) as f:
+        D, V, K = (int(x) for x in f["shape"])
+        alpha, beta = (float(x) for x in f["prior"])
+        return Corpus(str(f["name"]), D, V, K, alpha, beta, f["doc_off"], f["words"], None)
+
+
 def small_random(D: int, V: int, K: int, mean_len: float, seed: int, zipf: bool = True,
                  empty_docs: bool = True) -> Corpus:
     """A small corpus of arbitrary shape for tests (Poisson lengths)."""
