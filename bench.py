@@ -149,6 +149,11 @@ def main():
     ap.add_argument("--config", default="large", choices=["tiny", "small", "medium", "large"])
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--side-ratio", type=int, default=1, help="side ratio with --force-group")
+    ap.add_argument("--separate-loglik", action="store_true",
+                    help="recount document terms of the log joint in their own pass")
+    ap.add_argument("--force-group", type=int, default=0,
+                    help="one schedule bucket with this group size (16, 32, 64) instead of autotuning")
     ap.add_argument("--graph", action="store_true", help="replay a captured sweep (no per-phase events)")
     ap.add_argument("--cpu-docs", type=int, default=20000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -201,10 +206,14 @@ def main():
     plan.init()
     plan.phi_step(1)
     torch.cuda.synchronize()
-    if not args.no_autotune:
+    if args.force_group:
+        plan.set_schedule([0], [args.force_group], [64 // args.force_group * 16], [args.side_ratio])
+        log(f"schedule: one bucket, group {args.force_group}, side ratio {args.side_ratio}")
+    elif not args.no_autotune:
         sched = plan.autotune(1, reps=1)
         log(f"autotuned schedule: {sched}")
     plan.set_graph(args.graph)
+    plan.set_fused_loglik(not args.separate_loglik)
     plan.set_timing(not args.graph)
     t = 1
     log(f"warmup {args.warmup} sweeps")

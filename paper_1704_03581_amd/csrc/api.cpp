@@ -134,7 +134,7 @@ struct pulda_plan {
     struct {
         int64_t z, n, gam, phid, colcnt, colptr, ctopic, cphi, calias, sigma_a, S, nk, alpha, pois, pois_off,
             doc_order, items, queue, stats, ll_part, ll_out, ll_hist, tptr, err, scratch, cnt_a, ptr_a, cnt_b,
-            ptr_b, zsave, lg_beta, lg_alpha, lg_A;
+            ptr_b, zsave, lg_beta, lg_alpha, lg_A, ll_doc;
     } off;
     int64_t cap = 0, items_cap = 0, hist_cap = 4096;
     int32_t n_part_words = 1024, n_part_docs = 1024;
@@ -149,20 +149,26 @@ struct pulda_plan {
     WorkItem *items = nullptr;
     int32_t *queue = nullptr;
     unsigned long long *stats = nullptr;
-    double *ll_part = nullptr, *ll_out = nullptr, *ll_hist = nullptr;
+    double *ll_part = nullptr, *ll_out = nullptr, *ll_hist = nullptr, *ll_doc = nullptr;
     uint32_t *tptr = nullptr, *hist_idx = nullptr;
     int32_t *err = nullptr;
     int64_t *cnt_a = nullptr, *ptr_a = nullptr, *cnt_b = nullptr, *ptr_b = nullptr;
     uint16_t *zsave = nullptr;
     // schedule
     std::vector<int32_t> len_sorted;  // lengths in doc_order
-    std::vector<int32_t> min_len{1024, 256, 64, 0}, group{64, 64, 32, 16}, dpi{1, 2, 8, 32};
+    std::vector<int32_t> min_len{1024, 256, 64, 0}, group{64, 64, 32, 16}, dpi{1, 2, 8, 32}, side{1, 1, 1, 1};
     int32_t n_items = 0;
+    int32_t cls_first[3] = {0, 0, 0}, cls_count[3] = {0, 0, 0};  // items per group size 64, 32, 16
     int32_t n_waves = 0;
+    // internal streams: the three group-size kernels of a z-step run
+    // concurrently, forked from and joined back to the caller's stream
+    hipStream_t aux[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t fork_ev = nullptr, join_ev[3] = {nullptr, nullptr, nullptr};
     // state
     bool bound = false, uploaded = false, have_z = false, have_phi = false;
     // graph replay
     bool graph_on = false;
+    bool fused_ll = true;  // document terms of the log joint inside the z-step
     hipGraphExec_t gexec = nullptr;
     hipStream_t cap_stream = nullptr;  // private stream the sweep is captured on
     // phase timing (hipEvents on the caller's stream around each phase)
@@ -273,6 +279,7 @@ pulda_status pulda_plan_create(const pulda_model_desc *desc, int64_t D, int64_t 
     p->off.lg_beta = L.take((int64_t)LG_TABLE * 8);
     p->off.lg_alpha = L.take((int64_t)LG_TABLE * 8);
     p->off.lg_A = L.take((int64_t)LG_TABLE * 8);
+    p->off.ll_doc = L.take(D * 8);
     p->ws_need = L.total;
     *out = p;
     return PULDA_OK;
@@ -338,6 +345,7 @@ pulda_status pulda_plan_bind(pulda_plan *p, void *workspace_dev, int64_t bytes)
     p->cnt_b = (int64_t *)(w + p->off.cnt_b);
     p->ptr_b = (int64_t *)(w + p->off.ptr_b);
     p->zsave = (uint16_t *)(w + p->off.zsave);
+    p->ll_doc = (double *)(w + p->off.ll_doc);
     // constant tables (synchronous copies from host memory)
     HIP_TRY(hipMemcpy((void *)m.alpha, p->alpha.data(), p->K * sizeof(double), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy((void *)m.pois, p->pois_h.data(), p->pois_h.size() * 8, hipMemcpyHostToDevice));
@@ -351,6 +359,11 @@ pulda_status pulda_plan_bind(pulda_plan *p, void *workspace_dev, int64_t bytes)
     hipDeviceProp_t prop;
     HIP_TRY(hipGetDeviceProperties(&prop, dev));
     p->n_waves = prop.multiProcessorCount * 20;
+    for (int c = 0; c < 3; ++c) {
+        if (!p->aux[c]) HIP_TRY(hipStreamCreateWithFlags(&p->aux[c], hipStreamNonBlocking));
+        if (!p->join_ev[c]) HIP_TRY(hipEventCreateWithFlags(&p->join_ev[c], hipEventDisableTiming));
+    }
+    if (!p->fork_ev) HIP_TRY(hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming));
     p->bound = true;
     p->uploaded = p->have_z = p->have_phi = false;
     return PULDA_OK;
@@ -361,6 +374,11 @@ void pulda_plan_destroy(pulda_plan *p)
     if (!p) return;
     if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+    for (int c = 0; c < 3; ++c) {
+        if (p->aux[c]) (void)hipStreamDestroy(p->aux[c]);
+        if (p->join_ev[c]) (void)hipEventDestroy(p->join_ev[c]);
+    }
+    if (p->fork_ev) (void)hipEventDestroy(p->fork_ev);
     for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
     delete p;
 }
@@ -386,6 +404,8 @@ static int32_t min_group(int32_t K)
     return 64;
 }
 
+static int group_class(int32_t g) { return g == 64 ? 0 : (g == 32 ? 1 : 2); }
+
 static pulda_status build_items(pulda_plan *p)
 {
     const int32_t gmin = min_group(p->K);
@@ -396,7 +416,9 @@ static pulda_status build_items(pulda_plan *p)
             p->dpi[b] = std::max(1, per_group) * (64 / gmin);
         }
     }
-    std::vector<WorkItem> items;
+    // items grouped by group size (64, 32, 16); within a group size in
+    // decreasing document length (longest first)
+    std::vector<WorkItem> cls[3];
     const int32_t nb = (int32_t)p->min_len.size();
     int64_t pos = 0;
     for (int32_t b = 0; b < nb; ++b) {
@@ -408,9 +430,15 @@ static pulda_status build_items(pulda_plan *p)
             w.first = (int32_t)s;
             w.count = (int32_t)std::min<int64_t>(per, pos - s);
             w.group = p->group[b];
-            w.pad = b;
-            items.push_back(w);
+            w.side_ratio = p->side[b];
+            cls[group_class(w.group)].push_back(w);
         }
+    }
+    std::vector<WorkItem> items;
+    for (int c = 0; c < 3; ++c) {
+        p->cls_first[c] = (int32_t)items.size();
+        p->cls_count[c] = (int32_t)cls[c].size();
+        items.insert(items.end(), cls[c].begin(), cls[c].end());
     }
     if ((int64_t)items.size() > p->items_cap) return fail(PULDA_ERR_INVALID_ARG, "schedule yields too many work items");
     p->n_items = (int32_t)items.size();
@@ -528,20 +556,46 @@ static pulda_status enqueue_phi(pulda_plan *p, hipStream_t s)
     return PULDA_OK;
 }
 
-static pulda_status enqueue_z(pulda_plan *p, hipStream_t s)
+static pulda_status enqueue_z(pulda_plan *p, hipStream_t s, double *ll_doc = nullptr)
 {
-    HIP_TRY(launch_z_step(p->c, p->m, p->items, p->n_items, p->n_waves, p->queue, p->stats, s,
-                          p->timing ? &p->ev_pool : nullptr, p->timing ? &p->ev_used : nullptr,
-                          p->timing ? &p->ev_z : nullptr));
+    size_t ta = 0, tb = 0;
+    if (p->timing) HIP_TRY(phase_event(p, s, &ta));
+    HIP_TRY(launch_z_prepare(p->m, p->queue, p->stats, s));
+    int used = 0;
+    for (int c = 0; c < 3; ++c) used += p->cls_count[c] > 0;
+    static const int32_t gsz[3] = {64, 32, 16};
+    if (used <= 1) {
+        for (int c = 0; c < 3; ++c)
+            if (p->cls_count[c])
+                HIP_TRY(launch_z_class(p->c, p->m, gsz[c], p->items + p->cls_first[c], p->cls_count[c], p->n_waves,
+                                       p->queue + c, p->stats, ll_doc, s));
+    } else {
+        // group sizes run concurrently: long documents (large groups) next to
+        // the bulk of short ones
+        HIP_TRY(hipEventRecord(p->fork_ev, s));
+        for (int c = 0; c < 3; ++c) {
+            if (!p->cls_count[c]) continue;
+            HIP_TRY(hipStreamWaitEvent(p->aux[c], p->fork_ev, 0));
+            HIP_TRY(launch_z_class(p->c, p->m, gsz[c], p->items + p->cls_first[c], p->cls_count[c], p->n_waves,
+                                   p->queue + c, p->stats, ll_doc, p->aux[c]));
+            HIP_TRY(hipEventRecord(p->join_ev[c], p->aux[c]));
+            HIP_TRY(hipStreamWaitEvent(s, p->join_ev[c], 0));
+        }
+    }
+    if (p->timing) {
+        HIP_TRY(phase_event(p, s, &tb));
+        p->ev_z.push_back({ta, tb});
+    }
     return PULDA_OK;
 }
 
-static pulda_status enqueue_ll(pulda_plan *p, hipStream_t s, double *hist, const uint32_t *hist_idx)
+static pulda_status enqueue_ll(pulda_plan *p, hipStream_t s, double *hist, const uint32_t *hist_idx,
+                               const double *ll_doc = nullptr)
 {
     size_t a = 0, b = 0;
     if (p->timing) HIP_TRY(phase_event(p, s, &a));
-    HIP_TRY(launch_loglik(p->c, p->m, p->A, p->ll_part, p->n_part_words, p->n_part_docs, p->ll_out, hist, hist_idx,
-                          s));
+    HIP_TRY(launch_loglik(p->c, p->m, p->ll_part, p->n_part_words, p->n_part_docs, ll_doc, p->ll_out, hist,
+                          hist_idx, s));
     if (p->timing) {
         HIP_TRY(phase_event(p, s, &b));
         p->ev_ll.push_back({a, b});
@@ -579,9 +633,11 @@ static pulda_status enqueue_sweep_body(pulda_plan *p, hipStream_t s)
 {
     pulda_status st = enqueue_phi(p, s);
     if (st != PULDA_OK) return st;
-    st = enqueue_z(p, s);
+    // the z-step leaves each document's log-joint term behind (symmetric alpha)
+    double *ll_doc = (p->symmetric_alpha && p->fused_ll) ? p->ll_doc : nullptr;
+    st = enqueue_z(p, s, ll_doc);
     if (st != PULDA_OK) return st;
-    st = enqueue_ll(p, s, p->ll_hist, p->hist_idx);
+    st = enqueue_ll(p, s, p->ll_hist, p->hist_idx, ll_doc);
     if (st != PULDA_OK) return st;
     HIP_TRY(launch_advance(p->tptr, p->hist_idx, s));
     return PULDA_OK;
@@ -637,7 +693,7 @@ pulda_status pulda_loglik(pulda_plan *p, double *ll_host, void *stream)
     if (!p || !ll_host) return fail(PULDA_ERR_INVALID_ARG, "null argument");
     if (!p->have_z) return fail(PULDA_ERR_STATE, "no state (call pulda_init)");
     hipStream_t s = (hipStream_t)stream;
-    pulda_status st = enqueue_ll(p, s, nullptr, nullptr);
+    pulda_status st = enqueue_ll(p, s, nullptr, nullptr, nullptr);
     if (st != PULDA_OK) return st;
     HIP_TRY(hipMemcpyAsync(ll_host, p->ll_out, sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -799,7 +855,7 @@ pulda_status pulda_stats(pulda_plan *p, pulda_sweep_stats *out, void *stream)
 }
 
 pulda_status pulda_set_schedule(pulda_plan *p, int32_t nb, const int32_t *min_len, const int32_t *group,
-                                const int32_t *dpi)
+                                const int32_t *dpi, const int32_t *side_ratio)
 {
     if (!p || nb < 1 || !min_len || !group || !dpi) return fail(PULDA_ERR_INVALID_ARG, "bad schedule");
     for (int32_t b = 0; b < nb; ++b) {
@@ -807,6 +863,8 @@ pulda_status pulda_set_schedule(pulda_plan *p, int32_t nb, const int32_t *min_le
             return fail(PULDA_ERR_INVALID_ARG, "group size %d not in {16, 32, 64}", group[b]);
         if (dpi[b] < 1 || dpi[b] % (64 / group[b])) return fail(PULDA_ERR_INVALID_ARG, "docs per item %d", dpi[b]);
         if (b > 0 && min_len[b] >= min_len[b - 1]) return fail(PULDA_ERR_INVALID_ARG, "min_len must decrease");
+        if (side_ratio && (side_ratio[b] < 1 || side_ratio[b] > 1024))
+            return fail(PULDA_ERR_INVALID_ARG, "side ratio %d outside 1..1024", side_ratio[b]);
         if ((1 << (int)std::ceil(std::log2((double)((p->K + group[b] - 1) / group[b])))) > 64)
             return fail(PULDA_ERR_INVALID_ARG, "group %d too small for K=%d", group[b], p->K);
     }
@@ -814,12 +872,14 @@ pulda_status pulda_set_schedule(pulda_plan *p, int32_t nb, const int32_t *min_le
     p->min_len.assign(min_len, min_len + nb);
     p->group.assign(group, group + nb);
     p->dpi.assign(dpi, dpi + nb);
+    if (side_ratio) p->side.assign(side_ratio, side_ratio + nb);
+    else p->side.assign(nb, 1);
     if (p->uploaded) return build_items(p);
     return PULDA_OK;
 }
 
 pulda_status pulda_get_schedule(const pulda_plan *p, int32_t cap, int32_t *nb, int32_t *min_len, int32_t *group,
-                                int32_t *dpi)
+                                int32_t *dpi, int32_t *side_ratio)
 {
     if (!p || !nb) return fail(PULDA_ERR_INVALID_ARG, "null argument");
     *nb = (int32_t)p->min_len.size();
@@ -827,6 +887,7 @@ pulda_status pulda_get_schedule(const pulda_plan *p, int32_t cap, int32_t *nb, i
         if (min_len) min_len[b] = p->min_len[b];
         if (group) group[b] = p->group[b];
         if (dpi) dpi[b] = p->dpi[b];
+        if (side_ratio) side_ratio[b] = p->side[b];
     }
     return PULDA_OK;
 }
@@ -843,7 +904,7 @@ pulda_status pulda_autotune(pulda_plan *p, uint32_t t, int32_t reps, void *strea
     HIP_TRY(hipEventCreate(&e1));
     const std::vector<int32_t> keep_group = p->group, keep_dpi = p->dpi;
     const int32_t nb = (int32_t)p->min_len.size();
-    std::vector<int32_t> best_g(keep_group), best_d(keep_dpi);
+    std::vector<int32_t> best_g(keep_group), best_d(keep_dpi), best_r(p->side);
     for (int32_t b = 0; b < nb; ++b) {
         // documents of bucket b
         int64_t lo = 0, hi = 0;
@@ -862,28 +923,33 @@ pulda_status pulda_autotune(pulda_plan *p, uint32_t t, int32_t reps, void *strea
         float best_ms = 1e30f;
         for (int gsz : {64, 32, 16}) {
             if ((1 << (int)std::ceil(std::log2((double)((p->K + gsz - 1) / gsz)))) > 64) continue;
-            const int ng = 64 / gsz;
-            int per = (int)std::max(1.0, std::round(4096.0 / std::max(1.0, mean_len) / ng)) * ng;
-            std::vector<WorkItem> items;
-            for (int64_t q = lo; q < hi; q += per)
-                items.push_back({(int32_t)q, (int32_t)std::min<int64_t>(per, hi - q), gsz, b});
-            HIP_TRY(hipMemcpyAsync(p->items, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice, s));
-            float total = 0;
-            for (int r = 0; r <= reps; ++r) {
-                if (p->N) HIP_TRY(hipMemcpyAsync(p->c.z, p->zsave, p->N * 2, hipMemcpyDeviceToDevice, s));
-                HIP_TRY(hipEventRecord(e0, s));
-                HIP_TRY(launch_z_step(p->c, p->m, p->items, (int32_t)items.size(), p->n_waves, p->queue, nullptr, s,
-                                      nullptr, nullptr, nullptr));
-                HIP_TRY(hipEventRecord(e1, s));
-                HIP_TRY(hipEventSynchronize(e1));
-                float ms;
-                HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-                if (r > 0) total += ms;  // first run warms up
-            }
-            if (total < best_ms) {
-                best_ms = total;
-                best_g[b] = gsz;
-                best_d[b] = per;
+            for (int ratio : {1, 4, 16}) {
+                const int ng = 64 / gsz;
+                int per = (int)std::max(1.0, std::round(4096.0 / std::max(1.0, mean_len) / ng)) * ng;
+                std::vector<WorkItem> items;
+                for (int64_t q = lo; q < hi; q += per)
+                    items.push_back({(int32_t)q, (int32_t)std::min<int64_t>(per, hi - q), gsz, ratio});
+                HIP_TRY(hipMemcpyAsync(p->items, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice,
+                                       s));
+                float total = 0;
+                for (int r = 0; r <= reps; ++r) {
+                    if (p->N) HIP_TRY(hipMemcpyAsync(p->c.z, p->zsave, p->N * 2, hipMemcpyDeviceToDevice, s));
+                    HIP_TRY(hipEventRecord(e0, s));
+                    HIP_TRY(launch_z_prepare(p->m, p->queue, nullptr, s));
+                    HIP_TRY(launch_z_class(p->c, p->m, gsz, p->items, (int32_t)items.size(), p->n_waves, p->queue,
+                                           nullptr, nullptr, s));
+                    HIP_TRY(hipEventRecord(e1, s));
+                    HIP_TRY(hipEventSynchronize(e1));
+                    float ms;
+                    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                    if (r > 0) total += ms;  // first run warms up
+                }
+                if (total < best_ms) {
+                    best_ms = total;
+                    best_g[b] = gsz;
+                    best_d[b] = per;
+                    best_r[b] = ratio;
+                }
             }
         }
     }
@@ -891,6 +957,7 @@ pulda_status pulda_autotune(pulda_plan *p, uint32_t t, int32_t reps, void *strea
     (void)hipEventDestroy(e1);
     p->group = best_g;
     p->dpi = best_d;
+    p->side = best_r;
     pulda_status st = build_items(p);
     if (st != PULDA_OK) return st;
     if (p->N) HIP_TRY(hipMemcpyAsync(p->c.z, p->zsave, p->N * 2, hipMemcpyDeviceToDevice, s));
@@ -907,6 +974,17 @@ pulda_status pulda_set_timing(pulda_plan *p, int32_t enable)
     p->ev_z.clear();
     p->ev_ll.clear();
     p->ev_used = 0;
+    return PULDA_OK;
+}
+
+pulda_status pulda_set_fused_loglik(pulda_plan *p, int32_t enable)
+{
+    if (!p) return fail(PULDA_ERR_INVALID_ARG, "null argument");
+    p->fused_ll = enable != 0;
+    if (p->gexec) {
+        (void)hipGraphExecDestroy(p->gexec);
+        p->gexec = nullptr;
+    }
     return PULDA_OK;
 }
 

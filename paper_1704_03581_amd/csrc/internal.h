@@ -48,9 +48,11 @@ struct DevCorpus {
 };
 
 // a unit of z-step work: `count` documents of doc_order starting at `first`,
-// processed by groups of `group` lanes
+// processed by groups of `group` lanes; the b-terms of a token are taken
+// from the word's Phi column when K_v <= side_ratio * K_d, else from the
+// document's topics (which side is walked changes cost, not the result)
 struct WorkItem {
-    int32_t first, count, group, pad;
+    int32_t first, count, group, side_ratio;
 };
 
 // ST_TOKENS counts z-step launches since the last statistics read
@@ -67,14 +69,19 @@ hipError_t launch_init_z(const DevCorpus &c, int32_t K, uint32_t key0, uint32_t 
 hipError_t launch_count_rebuild(const DevCorpus &c, const DevModel &m, hipStream_t s);
 hipError_t launch_row_sums(const int32_t *dense, int32_t V, int32_t K, unsigned long long *out, hipStream_t s);
 hipError_t launch_phi_step(const DevModel &m, unsigned long long *stats, hipStream_t s);
-// with ev_pool non-null, records a pair of events around the z-step kernel
-// itself and appends their indices to ev_pairs
-hipError_t launch_z_step(const DevCorpus &c, const DevModel &m, const WorkItem *items, int32_t n_items,
-                         int32_t n_waves, int32_t *queue, unsigned long long *stats, hipStream_t s,
-                         std::vector<hipEvent_t> *ev_pool, size_t *ev_used,
-                         std::vector<std::pair<size_t, size_t>> *ev_pairs);
-hipError_t launch_loglik(const DevCorpus &c, const DevModel &m, double A, double *partials, int32_t n_part_words,
-                         int32_t n_part_docs, double *out, double *hist, const uint32_t *hist_idx, hipStream_t s);
+// z-step: launch_z_prepare clears n and the three work queues; then one
+// persistent kernel per group size (16, 32, 64) over that size's work items.
+// With ll_doc non-null (symmetric alpha) the z-step also writes each
+// document's term of the log joint for the state it leaves.
+hipError_t launch_z_prepare(const DevModel &m, int32_t *queues, unsigned long long *stats, hipStream_t s);
+hipError_t launch_z_class(const DevCorpus &c, const DevModel &m, int32_t group, const WorkItem *items,
+                          int32_t n_items, int32_t n_waves, int32_t *queue, unsigned long long *stats,
+                          double *ll_doc, hipStream_t s);
+// log joint of the current state; with ll_doc non-null the document terms
+// are taken from it (written by the z-step) instead of recounted from z
+hipError_t launch_loglik(const DevCorpus &c, const DevModel &m, double *partials, int32_t n_part_words,
+                         int32_t n_part_docs, const double *ll_doc, double *out, double *hist,
+                         const uint32_t *hist_idx, hipStream_t s);
 hipError_t launch_advance(uint32_t *tptr, uint32_t *hist_idx, hipStream_t s);
 hipError_t launch_n_colcount(const DevModel &m, int64_t *cnt, hipStream_t s);
 hipError_t launch_export_phi(const DevModel &m, int64_t *colptr64, uint16_t *topic, int32_t *gam_e, float *phi_e,

@@ -515,6 +515,7 @@ struct ZArgs {
     int32_t m_per_wave;     // u16 count slots per wave
     int32_t *queue;
     unsigned long long *stats;
+    double *ll_doc;         // per-document log-joint terms (or null)
     int32_t log2c64, log2c32, log2c16;  // log2 of topics per lane for each group size
 };
 
@@ -531,7 +532,7 @@ struct alignas(16) TokenIn {
 };
 
 struct ZCount {
-    uint32_t J, A, degenerate;
+    unsigned long long J, A, degenerate;
 };
 
 constexpr int KEEP = 4;  // b-terms per lane kept in registers for the walk
@@ -549,38 +550,144 @@ __device__ __forceinline__ int32_t mslot(int32_t k, int log2c)
 }
 
 // up to KEEP b-terms of this lane starting at entry `base` of its list:
-// topic, phi and m_d of each (zeros past the end); loads are issued together
-template <int G>
-__device__ __forceinline__ void lane_terms(const DevModel &M, const float *pcol, const uint16_t *mt, bool docside,
-                                           uint64_t &rest, int32_t cbe, int32_t base, int32_t nl, int g, int log2c,
+// topic, phi and m_d of each (zeros past the end); loads are issued together.
+// DOC: the lane's list is its set mask bits (document side); otherwise a
+// contiguous block of the word's CSC entries starting at cbe (column side).
+template <int G, bool DOC>
+__device__ __forceinline__ void lane_terms(const DevModel &M, const float *pcol, const uint16_t *mt, uint64_t &rest,
+                                           int32_t cb, int32_t cbe, int32_t base, int32_t nl, int g, int log2c,
                                            int32_t (&kk)[KEEP], float (&fk)[KEEP], int32_t (&mk)[KEEP])
 {
+    // Branch-free: every slot loads from a valid address (slots past the
+    // lane's end read the column's first element) and is zeroed afterwards,
+    // so the loads of all slots are in flight together.
+    int32_t kidx[KEEP];
+    bool ok[KEEP];
 #pragma unroll
     for (int u = 0; u < KEEP; ++u) {
-        const bool ok = base + u < nl;
-        int32_t k = 0;
-        float f = 0.0f;
-        if (docside) {
-            const int b = ok ? __builtin_ctzll(rest) : 0;
+        ok[u] = base + u < nl;
+        if constexpr (DOC) {
+            const int b = ok[u] ? __builtin_ctzll(rest) : 0;
             rest &= rest - 1;
-            k = (g << log2c) + b;
-            if (ok) f = pcol[k];
-        } else if (ok) {
-            k = M.ctopic[cbe + base + u];
-            f = M.cphi[cbe + base + u];
+            kidx[u] = ok[u] ? (g << log2c) + b : 0;
+        } else {
+            kidx[u] = ok[u] ? cbe + base + u : cb;
         }
-        kk[u] = ok ? k : -1;
-        fk[u] = f;
+    }
+    float fr[KEEP];
+    int32_t kr[KEEP];
+#pragma unroll
+    for (int u = 0; u < KEEP; ++u) {
+        if constexpr (DOC) {
+            fr[u] = pcol[kidx[u]];
+            kr[u] = kidx[u];
+        } else {
+            fr[u] = M.cphi[kidx[u]];
+            kr[u] = M.ctopic[kidx[u]];
+        }
     }
 #pragma unroll
-    for (int u = 0; u < KEEP; ++u) mk[u] = kk[u] >= 0 ? (int32_t)mt[mslot<G>(kk[u], log2c)] : 0;
+    for (int u = 0; u < KEEP; ++u) {
+        const int32_t m = mt[mslot<G>(kr[u], log2c)];
+        kk[u] = ok[u] ? kr[u] : -1;
+        fk[u] = ok[u] ? fr[u] : 0.0f;
+        mk[u] = ok[u] ? m : 0;
+    }
+}
+
+// sigma_b = sum of the b-terms phi_kv m_k over one side, the a/b decision,
+// and for the b-part the topic whose running sum first exceeds
+// y = u_sigma - sigma_a (Section 3.5).  Returns the topic, or -1 for the
+// a-part (the caller draws from the word's alias table).
+template <int G, bool DOC>
+__device__ __forceinline__ int32_t b_part(const DevModel &M, const TokenIn &tk, const uint16_t *mt, const int g,
+                                          const int log2c, const uint64_t mask)
+{
+    constexpr int LG = log2g<G>();
+    const int32_t Kv = tk.kv;
+    const float *pcol = M.phid + (uint32_t)tk.v * (uint32_t)M.K;
+    int32_t nl, cbe = 0;
+    if constexpr (DOC) {
+        nl = __builtin_popcountll(mask);
+    } else {
+        const int32_t q = (Kv + G - 1) >> LG;
+        const int32_t e0 = g * q;
+        nl = Kv - e0 < q ? Kv - e0 : q;
+        nl = nl > 0 ? nl : 0;
+        cbe = tk.cb + e0;
+    }
+    uint64_t rest = mask;
+    int32_t kk[KEEP], mk[KEEP];
+    float fk[KEEP];
+    lane_terms<G, DOC>(M, pcol, mt, rest, tk.cb, cbe, 0, nl, g, log2c, kk, fk, mk);
+    double p = 0.0;
+#pragma unroll
+    for (int u = 0; u < KEEP; ++u) p += (double)fk[u] * (double)mk[u];
+    for (int32_t base = KEEP; base < nl; base += KEEP) {
+        int32_t k2[KEEP], m2[KEEP];
+        float f2[KEEP];
+        lane_terms<G, DOC>(M, pcol, mt, rest, tk.cb, cbe, base, nl, g, log2c, k2, f2, m2);
+#pragma unroll
+        for (int u = 0; u < KEEP; ++u) p += (double)f2[u] * (double)m2[u];
+    }
+    const double incl = group_scan_incl<G>(p);
+    const double T = group_bcast_f64<G>(incl, G - 1);
+    const double Z = tk.sa + T;
+    const double x = unit24(tk.r0) * Z;
+    if (x < tk.sa) return -1;
+    // b-part: the first lane whose running sum passes y walks its terms
+    const double y = x - tk.sa;
+    const uint64_t bal = group_ballot<G>(incl > y);
+    int f = -1;
+    if (bal) {
+        f = __builtin_ctzll(bal);
+    } else {
+        const uint64_t pos = group_ballot<G>(p > 0.0);
+        if (pos) f = 63 - __builtin_clzll(pos);
+    }
+    if (f < 0) return -1;  // no positive b-term survived rounding: the a-part is the whole law
+    int32_t kf = -1;
+    if (g == f) {
+        double c = incl - p;
+        int32_t last = -1;
+        if (nl <= KEEP) {
+#pragma unroll
+            for (int u = 0; u < KEEP; ++u) {
+                const double bv = (double)fk[u] * (double)mk[u];
+                if (bv > 0.0) {
+                    c += bv;
+                    last = kk[u];
+                    if (kf < 0 && c > y) kf = kk[u];
+                }
+            }
+        } else {
+            uint64_t r2 = mask;
+            for (int32_t base = 0; base < nl && kf < 0; base += KEEP) {
+                int32_t k2[KEEP], m2[KEEP];
+                float f2[KEEP];
+                lane_terms<G, DOC>(M, pcol, mt, r2, tk.cb, cbe, base, nl, g, log2c, k2, f2, m2);
+#pragma unroll
+                for (int u = 0; u < KEEP; ++u) {
+                    const double bv = (double)f2[u] * (double)m2[u];
+                    if (bv > 0.0) {
+                        c += bv;
+                        last = k2[u];
+                        if (kf < 0 && c > y) kf = k2[u];
+                    }
+                }
+            }
+        }
+        if (kf < 0) kf = last;
+    }
+    return group_bcast<G>(kf, f);
 }
 
 // draw one token (group-uniform control flow); returns the new topic, or
 // -1 - kold for a token whose word has an empty Phi column (it keeps kold)
 template <int G>
 __device__ __forceinline__ int32_t draw_token(const DevModel &M, const TokenIn &tk, uint16_t *mt, const int g,
-                                              const int log2c, uint64_t &mask, int32_t &Kd, ZCount &cnt)
+                                              const int log2c, const int32_t side_ratio, uint64_t &mask,
+                                              int32_t &Kd, ZCount &cnt)
 {
     constexpr int LG = log2g<G>();
     const int32_t C = 1 << log2c;
@@ -608,89 +715,18 @@ __device__ __forceinline__ int32_t draw_token(const DevModel &M, const TokenIn &
         cnt.degenerate++;
         return -1 - kold;
     }
-    cnt.J += (uint32_t)(Kd < Kv ? Kd : Kv);
-    // b-terms over the smaller side: the document's nonzero topics (lane g
-    // owns topics [g*C, (g+1)*C)) or the word's Phi column (lane g takes a
-    // contiguous block of entries); ascending topic order either way
-    const bool docside = Kd <= Kv;
-    const float *pcol = M.phid + (uint32_t)tk.v * (uint32_t)M.K;
-    int32_t nl, cbe = 0;
-    uint64_t rest = mask;
-    if (docside) {
-        nl = __builtin_popcountll(mask);
-    } else {
-        const int32_t q = (Kv + G - 1) >> LG;
-        const int32_t e0 = g * q;
-        nl = Kv - e0 < q ? Kv - e0 : q;
-        nl = nl > 0 ? nl : 0;
-        cbe = tk.cb + e0;
-    }
-    int32_t kk[KEEP], mk[KEEP];
-    float fk[KEEP];
-    lane_terms<G>(M, pcol, mt, docside, rest, cbe, 0, nl, g, log2c, kk, fk, mk);
-    double p = 0.0;
-#pragma unroll
-    for (int u = 0; u < KEEP; ++u) p += (double)fk[u] * (double)mk[u];
-    for (int32_t base = KEEP; base < nl; base += KEEP) {
-        int32_t k2[KEEP], m2[KEEP];
-        float f2[KEEP];
-        lane_terms<G>(M, pcol, mt, docside, rest, cbe, base, nl, g, log2c, k2, f2, m2);
-#pragma unroll
-        for (int u = 0; u < KEEP; ++u) p += (double)f2[u] * (double)m2[u];
-    }
-    const double incl = group_scan_incl<G>(p);
-    const double T = group_bcast_f64<G>(incl, G - 1);
-    const double Z = tk.sa + T;
-    const double x = unit24(tk.r0) * Z;
-    int32_t knew = -1;
-    if (!(x < tk.sa)) {
-        // b-part: the first lane whose running sum passes y walks its terms
-        const double y = x - tk.sa;
-        const uint64_t bal = group_ballot<G>(incl > y);
-        int f = -1;
-        if (bal) {
-            f = __builtin_ctzll(bal);
-        } else {
-            const uint64_t pos = group_ballot<G>(p > 0.0);
-            if (pos) f = 63 - __builtin_clzll(pos);
-        }
-        int32_t kf = -1;
-        if (g == f) {
-            double c = incl - p;
-            int32_t last = -1;
-            if (nl <= KEEP) {
-#pragma unroll
-                for (int u = 0; u < KEEP; ++u) {
-                    const double bv = (double)fk[u] * (double)mk[u];
-                    if (bv > 0.0) {
-                        c += bv;
-                        last = kk[u];
-                        if (kf < 0 && c > y) kf = kk[u];
-                    }
-                }
-            } else {
-                uint64_t r2 = mask;
-                for (int32_t base = 0; base < nl && kf < 0; base += KEEP) {
-                    int32_t k2[KEEP], m2[KEEP];
-                    float f2[KEEP];
-                    lane_terms<G>(M, pcol, mt, docside, r2, cbe, base, nl, g, log2c, k2, f2, m2);
-#pragma unroll
-                    for (int u = 0; u < KEEP; ++u) {
-                        const double bv = (double)f2[u] * (double)m2[u];
-                        if (bv > 0.0) {
-                            c += bv;
-                            last = k2[u];
-                            if (kf < 0 && c > y) kf = k2[u];
-                        }
-                    }
-                }
-            }
-            if (kf < 0) kf = last;
-        }
-        if (f >= 0) knew = group_bcast<G>(kf, f);
-    }
+    cnt.J += (unsigned long long)(Kd < Kv ? Kd : Kv);
+    // b-terms over one side: the document's nonzero topics (lane g owns
+    // topics [g*C, (g+1)*C)) or the word's Phi column (lane g takes a
+    // contiguous block of entries); ascending topic order either way.  The
+    // column is read contiguously while the document side gathers single
+    // phi values from the dense column, so the column side is preferred up
+    // to side_ratio times the document's topic count.
+    int32_t knew;
+    if (Kd == 0 || Kv > side_ratio * Kd) knew = b_part<G, true>(M, tk, mt, g, log2c, mask);
+    else knew = b_part<G, false>(M, tk, mt, g, log2c, mask);
     if (knew < 0) {
-        // a-part (or no positive b-term survived rounding): the word's alias table
+        // a-part: the word's alias table over alpha_k phi_kv
         const uint32_t j = scale32(tk.r1, (uint32_t)Kv);
         const uint64_t a = M.calias[tk.cb + j];
         knew = (tk.r2 < (uint32_t)a) ? (int32_t)((a >> 32) & 0xFFFFu) : (int32_t)(a >> 48);
@@ -766,7 +802,10 @@ __device__ void z_step_item(const ZArgs &a, const WorkItem &w, uint16_t *wave_m,
     for (int32_t di = grp; di < w.count; di += NG) {
         const int32_t d = a.c.doc_order[w.first + di];
         const int64_t s = a.c.doc_off[d], e = a.c.doc_off[d + 1];
-        if (s == e) continue;
+        if (s == e) {
+            if (a.ll_doc && g == 0) a.ll_doc[d] = 0.0;
+            continue;
+        }
         uint64_t mask;
         int32_t Kd;
         load_doc_counts<G>(mt, a.c.z, s, e, g, log2c, mask, Kd);
@@ -785,7 +824,7 @@ __device__ void z_step_item(const ZArgs &a, const WorkItem &w, uint16_t *wave_m,
             const int nb = (int)((e - i0) < G ? (e - i0) : G);
             for (int jj = 0; jj < nb; ++jj) {
                 const TokenIn tk = tok[jj];
-                int32_t k = draw_token<G>(M, tk, mt, g, log2c, mask, Kd, cnt);
+                int32_t k = draw_token<G>(M, tk, mt, g, log2c, w.side_ratio, mask, Kd, cnt);
                 if (k < 0) k = -1 - k;
                 if (g == 0) atomicAdd(&M.n[(uint32_t)tk.v * (uint32_t)M.K + (uint32_t)k], 1);
                 if (g == jj) znew = k;
@@ -793,9 +832,32 @@ __device__ void z_step_item(const ZArgs &a, const WorkItem &w, uint16_t *wave_m,
             __builtin_amdgcn_wave_barrier();
             if (valid) a.c.z[i] = (uint16_t)znew;
         }
+        if (a.ll_doc) {
+            // the document's term of log p(z | alpha) for its final counts:
+            // lgamma(A) - lgamma(N_d + A) + sum_k [lgamma(m_k + alpha) - lgamma(alpha)]
+            double part = 0.0;
+            uint64_t mm = mask;
+            while (mm) {
+                double v4[KEEP];
+#pragma unroll
+                for (int u = 0; u < KEEP; ++u) {
+                    const bool ok = mm != 0;
+                    const int b = ok ? __builtin_ctzll(mm) : 0;
+                    mm &= mm - 1;
+                    v4[u] = ok ? M.lg_alpha[mt[(b << log2g<G>()) + g]] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < KEEP; ++u) part += v4[u];
+            }
+            const double tot = group_bcast_f64<G>(group_scan_incl<G>(part), G - 1);
+            if (g == 0) a.ll_doc[d] = tot + M.lg_A[e - s];
+        }
     }
 }
 
+// one persistent kernel per group size: waves take work items from this
+// group size's queue until it is empty
+template <int G>
 __global__ void __launch_bounds__(256) z_step_kernel(ZArgs a)
 {
     extern __shared__ uint16_t z_lds[];
@@ -803,28 +865,21 @@ __global__ void __launch_bounds__(256) z_step_kernel(ZArgs a)
     uint16_t *wave_m = z_lds + wave * a.m_per_wave;
     TokenIn *wave_tok = (TokenIn *)(z_lds + 4 * a.m_per_wave) + wave * 64;
     ZCount cnt = {0, 0, 0};
-    unsigned long long J = 0, A = 0, D = 0;
     while (true) {
         int item = 0;
         if (__lane_id() == 0) item = atomicAdd(a.queue, 1);
         item = __builtin_amdgcn_readlane(item, 0);
         if (item >= a.n_items) break;
+        // a private copy: a reference into global memory would be reloaded
+        // after every store of the item (stores may alias it)
         const WorkItem w = a.items[item];
-        if (w.group == 64) z_step_item<64>(a, w, wave_m, wave_tok, cnt);
-        else if (w.group == 32) z_step_item<32>(a, w, wave_m, wave_tok, cnt);
-        else z_step_item<16>(a, w, wave_m, wave_tok, cnt);
-        // every lane of a group counted the group's tokens; its first lane keeps them
-        if ((__lane_id() & (w.group - 1)) == 0) {
-            J += cnt.J;
-            A += cnt.A;
-            D += cnt.degenerate;
-        }
-        cnt = {0, 0, 0};
+        z_step_item<G>(a, w, wave_m, wave_tok, cnt);
     }
-    if (a.stats) {
-        if (J) atomicAdd(&a.stats[ST_SUM_J], J);
-        if (A) atomicAdd(&a.stats[ST_SUM_A], A);
-        if (D) atomicAdd(&a.stats[ST_DEGENERATE], D);
+    // every lane of a group counted the group's tokens; its first lane reports
+    if (a.stats && (__lane_id() & (G - 1)) == 0) {
+        if (cnt.J) atomicAdd(&a.stats[ST_SUM_J], (unsigned long long)cnt.J);
+        if (cnt.A) atomicAdd(&a.stats[ST_SUM_A], (unsigned long long)cnt.A);
+        if (cnt.degenerate) atomicAdd(&a.stats[ST_DEGENERATE], (unsigned long long)cnt.degenerate);
     }
 }
 
@@ -846,22 +901,7 @@ __global__ void bump_kernel(unsigned long long *x)
     if (threadIdx.x == 0) *x += 1ull;
 }
 
-static hipError_t record(std::vector<hipEvent_t> *pool, size_t *used, hipStream_t s, size_t *idx)
-{
-    if (*used == pool->size()) {
-        hipEvent_t e;
-        hipError_t r = hipEventCreate(&e);
-        if (r != hipSuccess) return r;
-        pool->push_back(e);
-    }
-    *idx = (*used)++;
-    return hipEventRecord((*pool)[*idx], s);
-}
-
-hipError_t launch_z_step(const DevCorpus &c, const DevModel &m, const WorkItem *items, int32_t n_items,
-                         int32_t n_waves, int32_t *queue, unsigned long long *stats, hipStream_t s,
-                         std::vector<hipEvent_t> *ev_pool, size_t *ev_used,
-                         std::vector<std::pair<size_t, size_t>> *ev_pairs)
+hipError_t launch_z_prepare(const DevModel &m, int32_t *queues, unsigned long long *stats, hipStream_t s)
 {
     hipError_t e;
     if (m.n) {
@@ -873,8 +913,13 @@ hipError_t launch_z_step(const DevCorpus &c, const DevModel &m, const WorkItem *
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    e = launch_fill_u32((uint32_t *)queue, 0u, 1, s);
-    if (e != hipSuccess) return e;
+    return launch_fill_u32((uint32_t *)queues, 0u, 3, s);
+}
+
+hipError_t launch_z_class(const DevCorpus &c, const DevModel &m, int32_t group, const WorkItem *items,
+                          int32_t n_items, int32_t n_waves, int32_t *queue, unsigned long long *stats,
+                          double *ll_doc, hipStream_t s)
+{
     if (n_items == 0) return hipSuccess;
     ZArgs a;
     a.m = m;
@@ -883,32 +928,19 @@ hipError_t launch_z_step(const DevCorpus &c, const DevModel &m, const WorkItem *
     a.n_items = n_items;
     a.queue = queue;
     a.stats = stats;
+    a.ll_doc = m.lg_alpha ? ll_doc : nullptr;
     a.log2c64 = topics_per_lane_log2(m.K, 64);
     a.log2c32 = topics_per_lane_log2(m.K, 32);
     a.log2c16 = topics_per_lane_log2(m.K, 16);
-    // a wave holds 64/G tables of C*G slots: 64*C slots, largest for the
-    // smallest group size that is valid for K (C <= 64); then 64 staged
-    // token inputs per wave
-    int per_wave = 64 << a.log2c64;
-    if (a.log2c32 <= 6) per_wave = 64 << a.log2c32;
-    if (a.log2c16 <= 6) per_wave = 64 << a.log2c16;
-    a.m_per_wave = per_wave;
-    const size_t lds = 4 * (per_wave * sizeof(uint16_t) + 64 * sizeof(TokenIn));
+    // a wave holds 64/G tables of C*G slots (64*C slots), then 64 staged token inputs
+    const int log2c = group == 64 ? a.log2c64 : (group == 32 ? a.log2c32 : a.log2c16);
+    a.m_per_wave = 64 << log2c;
+    const size_t lds = 4 * (a.m_per_wave * sizeof(uint16_t) + 64 * sizeof(TokenIn));
     const int blocks = (n_waves + 3) / 4;
-    size_t ea = 0, eb = 0;
-    if (ev_pool) {
-        e = record(ev_pool, ev_used, s, &ea);
-        if (e != hipSuccess) return e;
-    }
-    z_step_kernel<<<blocks, 256, lds, s>>>(a);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    if (ev_pool) {
-        e = record(ev_pool, ev_used, s, &eb);
-        if (e != hipSuccess) return e;
-        ev_pairs->push_back({ea, eb});
-    }
-    return hipSuccess;
+    if (group == 64) z_step_kernel<64><<<blocks, 256, lds, s>>>(a);
+    else if (group == 32) z_step_kernel<32><<<blocks, 256, lds, s>>>(a);
+    else z_step_kernel<16><<<blocks, 256, lds, s>>>(a);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -945,6 +977,7 @@ __global__ void __launch_bounds__(256) ll_words_kernel(const int32_t *n, int64_t
     if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
+template <bool SYM>
 __global__ void __launch_bounds__(256) ll_docs_kernel(DevCorpus c, int32_t K, const double *alpha,
                                                       const double *lg_alpha, const double *lg_A, int32_t log2c,
                                                       double *partials)
@@ -974,12 +1007,25 @@ __global__ void __launch_bounds__(256) ll_docs_kernel(DevCorpus c, int32_t K, co
             const int32_t cnt = mt[b * 64 + lane];
             if (cnt) {
                 const int32_t k = lane * C + b;
-                part += lg_alpha ? lg_alpha[cnt] : lgamma((double)cnt + alpha[k]) - lgamma(alpha[k]);
+                if constexpr (SYM) part += lg_alpha[cnt];
+                else part += lgamma((double)cnt + alpha[k]) - lgamma(alpha[k]);
             }
         }
         if (lane == 0) part += lg_A[e - s];
         acc += part;
     }
+    const double t = block_sum_f64(acc, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+// fixed-order partial sums of the per-document terms written by the z-step
+__global__ void __launch_bounds__(256) ll_docsum_kernel(const double *ll_doc, int64_t D, double *partials)
+{
+    __shared__ double red[4];
+    const int64_t per = (D + gridDim.x - 1) / gridDim.x;
+    const int64_t a = blockIdx.x * per, b = a + per < D ? a + per : D;
+    double acc = 0.0;
+    for (int64_t d = a + threadIdx.x; d < b; d += blockDim.x) acc += ll_doc[d];
     const double t = block_sum_f64(acc, red);
     if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
@@ -1010,19 +1056,28 @@ hipError_t launch_advance(uint32_t *tptr, uint32_t *hist_idx, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_loglik(const DevCorpus &c, const DevModel &m, double A, double *partials, int32_t n_part_words,
-                         int32_t n_part_docs, double *out, double *hist, const uint32_t *hist_idx, hipStream_t s)
+hipError_t launch_loglik(const DevCorpus &c, const DevModel &m, double *partials, int32_t n_part_words,
+                         int32_t n_part_docs, const double *ll_doc, double *out, double *hist,
+                         const uint32_t *hist_idx, hipStream_t s)
 {
     hipError_t e = launch_row_sums(m.n, m.V, m.K, m.nk, s);
     if (e != hipSuccess) return e;
-    (void)A;
     ll_words_kernel<<<n_part_words, 256, 0, s>>>(m.n, (int64_t)m.V * m.K, m.beta, lgamma(m.beta), m.lg_beta,
                                                  partials);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int log2c = topics_per_lane_log2(m.K, 64);
-    ll_docs_kernel<<<n_part_docs, 256, 4 * 64 * (1 << log2c) * sizeof(uint16_t), s>>>(
-        c, m.K, m.alpha, m.lg_alpha, m.lg_A, log2c, partials + n_part_words);
+    if (ll_doc) {
+        ll_docsum_kernel<<<n_part_docs, 256, 0, s>>>(ll_doc, c.D, partials + n_part_words);
+    } else {
+        const int log2c = topics_per_lane_log2(m.K, 64);
+        const size_t lds = 4 * 64 * (1 << log2c) * sizeof(uint16_t);
+        if (m.lg_alpha)
+            ll_docs_kernel<true><<<n_part_docs, 256, lds, s>>>(c, m.K, m.alpha, m.lg_alpha, m.lg_A, log2c,
+                                                               partials + n_part_words);
+        else
+            ll_docs_kernel<false><<<n_part_docs, 256, lds, s>>>(c, m.K, m.alpha, m.lg_alpha, m.lg_A, log2c,
+                                                                partials + n_part_words);
+    }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     ll_final_kernel<<<1, 64, 0, s>>>(partials, n_part_words + n_part_docs, m.nk, m.K, (double)m.V * m.beta, out,
@@ -1204,7 +1259,7 @@ hipError_t launch_scan_i64(const int64_t *in, int64_t *out_excl, int64_t n, long
 // the topic counts after the burn-in, and the last sweep writes theta and
 // the log-likelihood of the final state.
 // ---------------------------------------------------------------------------
-template <int G>
+template <int G, bool SYM>
 __device__ void foldin_slot(const DevModel &M, const DevFoldin &F, int32_t sid, uint16_t *mt, TokenIn *tok,
                             int log2c)
 {
@@ -1267,7 +1322,7 @@ __device__ void foldin_slot(const DevModel &M, const DevFoldin &F, int32_t sid, 
             const int nb = (kept - q0) < G ? (kept - q0) : G;
             for (int jj = 0; jj < nb; ++jj) {
                 const TokenIn tk = tok[jj];
-                int32_t k = draw_token<G>(M, tk, mt, g, log2c, mask, Kd, st);
+                int32_t k = draw_token<G>(M, tk, mt, g, log2c, 1, mask, Kd, st);
                 if (k < 0) k = -1 - k;
                 if (g == jj) znew = k;
             }
@@ -1293,20 +1348,24 @@ __device__ void foldin_slot(const DevModel &M, const DevFoldin &F, int32_t sid, 
         for (int32_t b = 0; b < C; ++b) {
             const int32_t k = (g << log2c) + b;
             const int32_t c = mt[b * G + g];
-            if (k < K && c > 0) part += lgamma((double)c + M.alpha[k]) - lgamma(M.alpha[k]);
+            if (k < K && c > 0) {
+                if constexpr (SYM) part += M.lg_alpha[c];
+                else part += lgamma((double)c + M.alpha[k]) - lgamma(M.alpha[k]);
+            }
         }
         const double tot = group_bcast_f64<G>(group_scan_incl<G>(part), G - 1);
-        if (g == 0) F.ll[sid] = tot + lgamma(F.A) - lgamma(denom);
+        if (g == 0) F.ll[sid] = tot + M.lg_A[kept];
     }
 }
 
+template <int G, bool SYM>
 __global__ void __launch_bounds__(256) foldin_step_kernel(DevModel M, DevFoldin F, const int32_t *active,
                                                           int32_t n_active, int32_t log2c, int32_t per_group)
 {
     extern __shared__ uint16_t f_lds[];
     const int lane = __lane_id();
     const int wave = threadIdx.x >> 6;
-    const int gsz = F.group;
+    constexpr int gsz = G;
     const int grp = lane / gsz;
     const int ngw = 64 / gsz;
     const int64_t gid = ((int64_t)blockIdx.x * 4 + wave) * ngw + grp;
@@ -1314,9 +1373,7 @@ __global__ void __launch_bounds__(256) foldin_step_kernel(DevModel M, DevFoldin 
     TokenIn *tok = (TokenIn *)(f_lds + 4 * ngw * per_group) + wave * 64 + grp * gsz;
     if (gid >= n_active) return;
     const int32_t sid = active[gid];
-    if (gsz == 64) foldin_slot<64>(M, F, sid, mt, tok, log2c);
-    else if (gsz == 32) foldin_slot<32>(M, F, sid, mt, tok, log2c);
-    else foldin_slot<16>(M, F, sid, mt, tok, log2c);
+    foldin_slot<G, SYM>(M, F, sid, mt, tok, log2c);
 }
 
 hipError_t launch_foldin_step(const DevModel &m, const DevFoldin &f, const int32_t *active, int32_t n_active,
@@ -1329,7 +1386,17 @@ hipError_t launch_foldin_step(const DevModel &m, const DevFoldin &f, const int32
     const int64_t waves = (n_active + ngw - 1) / ngw;
     const unsigned blocks = (unsigned)((waves + 3) / 4);
     const size_t lds = 4 * ngw * per_group * sizeof(uint16_t) + 4 * 64 * sizeof(TokenIn);
-    foldin_step_kernel<<<blocks, 256, lds, s>>>(m, f, active, n_active, log2c, per_group);
+#define PULDA_FOLDIN(G_, S_) foldin_step_kernel<G_, S_><<<blocks, 256, lds, s>>>(m, f, active, n_active, log2c, per_group)
+    if (m.lg_alpha) {
+        if (f.group == 64) PULDA_FOLDIN(64, true);
+        else if (f.group == 32) PULDA_FOLDIN(32, true);
+        else PULDA_FOLDIN(16, true);
+    } else {
+        if (f.group == 64) PULDA_FOLDIN(64, false);
+        else if (f.group == 32) PULDA_FOLDIN(32, false);
+        else PULDA_FOLDIN(16, false);
+    }
+#undef PULDA_FOLDIN
     return hipGetLastError();
 }
 

@@ -87,11 +87,13 @@ _SIGS = {
     "pulda_get_phi": [vp, C.POINTER(PhiView), vp],
     "pulda_set_phi": [vp, C.POINTER(PhiView), vp],
     "pulda_stats": [vp, C.POINTER(SweepStats), vp],
-    "pulda_set_schedule": [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)],
-    "pulda_get_schedule": [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)],
+    "pulda_set_schedule": [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)],
+    "pulda_get_schedule": [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32),
+                           C.POINTER(i32)],
     "pulda_autotune": [vp, u32, i32, vp],
     "pulda_set_graph": [vp, i32],
     "pulda_set_timing": [vp, i32],
+    "pulda_set_fused_loglik": [vp, i32],
     "pulda_foldin_create": [vp, C.POINTER(FoldinDesc), C.POINTER(vp)],
     "pulda_foldin_workspace_bytes": [vp, C.POINTER(i64)],
     "pulda_foldin_bind": [vp, vp, i64],
@@ -173,7 +175,7 @@ class Plan:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
+        if h and _lib is not None:
             _lib.pulda_plan_destroy(h)
             self._h = None
 
@@ -300,19 +302,20 @@ class Plan:
         return {k: getattr(s, k) for k, _ in SweepStats._fields_}
 
     # schedule ------------------------------------------------------------------
-    def set_schedule(self, min_len, group, docs_per_item):
+    def set_schedule(self, min_len, group, docs_per_item, side_ratio=None):
         nb = len(min_len)
         a = (i32 * nb)(*min_len)
         b = (i32 * nb)(*group)
         c = (i32 * nb)(*docs_per_item)
-        _check(_lib.pulda_set_schedule(self._h, nb, a, b, c))
+        d = None if side_ratio is None else (i32 * nb)(*side_ratio)
+        _check(_lib.pulda_set_schedule(self._h, nb, a, b, c, d))
 
     def get_schedule(self):
         nb = i32()
-        a, b, c = (i32 * 64)(), (i32 * 64)(), (i32 * 64)()
-        _check(_lib.pulda_get_schedule(self._h, 64, C.byref(nb), a, b, c))
+        a, b, c, d = (i32 * 64)(), (i32 * 64)(), (i32 * 64)(), (i32 * 64)()
+        _check(_lib.pulda_get_schedule(self._h, 64, C.byref(nb), a, b, c, d))
         n = nb.value
-        return list(a[:n]), list(b[:n]), list(c[:n])
+        return list(a[:n]), list(b[:n]), list(c[:n]), list(d[:n])
 
     def autotune(self, t: int, reps: int = 2, stream=None):
         _check(_lib.pulda_autotune(self._h, t, reps, _stream(stream)))
@@ -320,6 +323,9 @@ class Plan:
 
     def set_graph(self, enable: bool):
         _check(_lib.pulda_set_graph(self._h, 1 if enable else 0))
+
+    def set_fused_loglik(self, enable: bool):
+        _check(_lib.pulda_set_fused_loglik(self._h, 1 if enable else 0))
 
     def set_timing(self, enable: bool):
         _check(_lib.pulda_set_timing(self._h, 1 if enable else 0))
@@ -347,7 +353,7 @@ class FoldIn:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
+        if h and _lib is not None:
             _lib.pulda_foldin_destroy(h)
             self._h = None
 
