@@ -158,12 +158,15 @@ struct pulda_plan {
     std::vector<int32_t> len_sorted;  // lengths in doc_order
     std::vector<int32_t> min_len{1024, 256, 64, 0}, group{64, 64, 32, 16}, dpi{1, 2, 8, 32}, side{1, 1, 1, 1};
     int32_t n_items = 0;
-    int32_t cls_first[3] = {0, 0, 0}, cls_count[3] = {0, 0, 0};  // items per group size 64, 32, 16
+    // work-item classes: (group size, count width) = (64, 16-bit), (32, 16),
+    // (32, 8), (16, 16), (16, 8); 8-bit counts serve documents under 256 tokens
+    static constexpr int NCLS = 5;
+    int32_t cls_first[NCLS] = {}, cls_count[NCLS] = {};
     int32_t n_waves = 0;
     // internal streams: the three group-size kernels of a z-step run
     // concurrently, forked from and joined back to the caller's stream
-    hipStream_t aux[3] = {nullptr, nullptr, nullptr};
-    hipEvent_t fork_ev = nullptr, join_ev[3] = {nullptr, nullptr, nullptr};
+    hipStream_t aux[NCLS] = {};
+    hipEvent_t fork_ev = nullptr, join_ev[NCLS] = {};
     // state
     bool bound = false, uploaded = false, have_z = false, have_phi = false;
     // graph replay
@@ -263,7 +266,7 @@ pulda_status pulda_plan_create(const pulda_model_desc *desc, int64_t D, int64_t 
     p->off.pois_off = L.take((int64_t)p->pois_off_h.size() * 4);
     p->off.doc_order = L.take(D * 4);
     p->off.items = L.take(p->items_cap * (int64_t)sizeof(WorkItem));
-    p->off.queue = L.take(16);
+    p->off.queue = L.take(32);
     p->off.stats = L.take(ST_COUNT * 8);
     p->off.ll_part = L.take((int64_t)(p->n_part_words + p->n_part_docs) * 8);
     p->off.ll_out = L.take(8);
@@ -359,7 +362,7 @@ pulda_status pulda_plan_bind(pulda_plan *p, void *workspace_dev, int64_t bytes)
     hipDeviceProp_t prop;
     HIP_TRY(hipGetDeviceProperties(&prop, dev));
     p->n_waves = prop.multiProcessorCount * 20;
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < pulda_plan::NCLS; ++c) {
         if (!p->aux[c]) HIP_TRY(hipStreamCreateWithFlags(&p->aux[c], hipStreamNonBlocking));
         if (!p->join_ev[c]) HIP_TRY(hipEventCreateWithFlags(&p->join_ev[c], hipEventDisableTiming));
     }
@@ -374,7 +377,7 @@ void pulda_plan_destroy(pulda_plan *p)
     if (!p) return;
     if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < pulda_plan::NCLS; ++c) {
         if (p->aux[c]) (void)hipStreamDestroy(p->aux[c]);
         if (p->join_ev[c]) (void)hipEventDestroy(p->join_ev[c]);
     }
@@ -404,7 +407,15 @@ static int32_t min_group(int32_t K)
     return 64;
 }
 
-static int group_class(int32_t g) { return g == 64 ? 0 : (g == 32 ? 1 : 2); }
+static const int32_t kClassGroup[5] = {64, 32, 32, 16, 16};
+static const bool kClassNarrow[5] = {false, false, true, false, true};
+
+static int item_class(int32_t g, bool narrow)
+{
+    if (g == 64) return 0;
+    if (g == 32) return narrow ? 2 : 1;
+    return narrow ? 4 : 3;
+}
 
 static pulda_status build_items(pulda_plan *p)
 {
@@ -418,7 +429,7 @@ static pulda_status build_items(pulda_plan *p)
     }
     // items grouped by group size (64, 32, 16); within a group size in
     // decreasing document length (longest first)
-    std::vector<WorkItem> cls[3];
+    std::vector<WorkItem> cls[pulda_plan::NCLS];
     const int32_t nb = (int32_t)p->min_len.size();
     int64_t pos = 0;
     for (int32_t b = 0; b < nb; ++b) {
@@ -431,11 +442,13 @@ static pulda_status build_items(pulda_plan *p)
             w.count = (int32_t)std::min<int64_t>(per, pos - s);
             w.group = p->group[b];
             w.side_ratio = p->side[b];
-            cls[group_class(w.group)].push_back(w);
+            // documents are in decreasing length: the first is the longest
+            const bool narrow = p->len_sorted[s] < 256;
+            cls[item_class(w.group, narrow)].push_back(w);
         }
     }
     std::vector<WorkItem> items;
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < pulda_plan::NCLS; ++c) {
         p->cls_first[c] = (int32_t)items.size();
         p->cls_count[c] = (int32_t)cls[c].size();
         items.insert(items.end(), cls[c].begin(), cls[c].end());
@@ -562,22 +575,21 @@ static pulda_status enqueue_z(pulda_plan *p, hipStream_t s, double *ll_doc = nul
     if (p->timing) HIP_TRY(phase_event(p, s, &ta));
     HIP_TRY(launch_z_prepare(p->m, p->queue, p->stats, s));
     int used = 0;
-    for (int c = 0; c < 3; ++c) used += p->cls_count[c] > 0;
-    static const int32_t gsz[3] = {64, 32, 16};
+    for (int c = 0; c < pulda_plan::NCLS; ++c) used += p->cls_count[c] > 0;
     if (used <= 1) {
-        for (int c = 0; c < 3; ++c)
+        for (int c = 0; c < pulda_plan::NCLS; ++c)
             if (p->cls_count[c])
-                HIP_TRY(launch_z_class(p->c, p->m, gsz[c], p->items + p->cls_first[c], p->cls_count[c], p->n_waves,
-                                       p->queue + c, p->stats, ll_doc, s));
+                HIP_TRY(launch_z_class(p->c, p->m, kClassGroup[c], kClassNarrow[c], p->items + p->cls_first[c],
+                                       p->cls_count[c], p->n_waves, p->queue + c, p->stats, ll_doc, s));
     } else {
-        // group sizes run concurrently: long documents (large groups) next to
+        // classes run concurrently: long documents (large groups) next to
         // the bulk of short ones
         HIP_TRY(hipEventRecord(p->fork_ev, s));
-        for (int c = 0; c < 3; ++c) {
+        for (int c = 0; c < pulda_plan::NCLS; ++c) {
             if (!p->cls_count[c]) continue;
             HIP_TRY(hipStreamWaitEvent(p->aux[c], p->fork_ev, 0));
-            HIP_TRY(launch_z_class(p->c, p->m, gsz[c], p->items + p->cls_first[c], p->cls_count[c], p->n_waves,
-                                   p->queue + c, p->stats, ll_doc, p->aux[c]));
+            HIP_TRY(launch_z_class(p->c, p->m, kClassGroup[c], kClassNarrow[c], p->items + p->cls_first[c],
+                                   p->cls_count[c], p->n_waves, p->queue + c, p->stats, ll_doc, p->aux[c]));
             HIP_TRY(hipEventRecord(p->join_ev[c], p->aux[c]));
             HIP_TRY(hipStreamWaitEvent(s, p->join_ev[c], 0));
         }
@@ -936,8 +948,8 @@ pulda_status pulda_autotune(pulda_plan *p, uint32_t t, int32_t reps, void *strea
                     if (p->N) HIP_TRY(hipMemcpyAsync(p->c.z, p->zsave, p->N * 2, hipMemcpyDeviceToDevice, s));
                     HIP_TRY(hipEventRecord(e0, s));
                     HIP_TRY(launch_z_prepare(p->m, p->queue, nullptr, s));
-                    HIP_TRY(launch_z_class(p->c, p->m, gsz, p->items, (int32_t)items.size(), p->n_waves, p->queue,
-                                           nullptr, nullptr, s));
+                    HIP_TRY(launch_z_class(p->c, p->m, gsz, gsz < 64 && p->len_sorted[lo] < 256, p->items,
+                                           (int32_t)items.size(), p->n_waves, p->queue, nullptr, nullptr, s));
                     HIP_TRY(hipEventRecord(e1, s));
                     HIP_TRY(hipEventSynchronize(e1));
                     float ms;

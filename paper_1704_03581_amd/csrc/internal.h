@@ -74,7 +74,9 @@ hipError_t launch_phi_step(const DevModel &m, unsigned long long *stats, hipStre
 // With ll_doc non-null (symmetric alpha) the z-step also writes each
 // document's term of the log joint for the state it leaves.
 hipError_t launch_z_prepare(const DevModel &m, int32_t *queues, unsigned long long *stats, hipStream_t s);
-hipError_t launch_z_class(const DevCorpus &c, const DevModel &m, int32_t group, const WorkItem *items,
+// narrow: 8-bit document-topic counts (every document of the items is
+// shorter than 256 tokens; group 16 or 32)
+hipError_t launch_z_class(const DevCorpus &c, const DevModel &m, int32_t group, bool narrow, const WorkItem *items,
                           int32_t n_items, int32_t n_waves, int32_t *queue, unsigned long long *stats,
                           double *ll_doc, hipStream_t s);
 // log joint of the current state; with ll_doc non-null the document terms

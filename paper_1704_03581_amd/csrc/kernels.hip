@@ -512,7 +512,7 @@ struct ZArgs {
     DevCorpus c;
     const WorkItem *items;
     int32_t n_items;
-    int32_t m_per_wave;     // u16 count slots per wave
+    int32_t m_bytes_per_wave;  // bytes of count tables per wave
     int32_t *queue;
     unsigned long long *stats;
     double *ll_doc;         // per-document log-joint terms (or null)
@@ -522,13 +522,12 @@ struct ZArgs {
 // inputs of one token draw, staged in LDS so every lane of the group reads
 // them with one broadcast load
 struct alignas(16) TokenIn {
-    int32_t v;      // word
-    int32_t kold;   // topic before the draw
-    int32_t cb;     // first CSC entry of the word's Phi column
-    int32_t kv;     // nonzeros in the column (K_v^Phi)
-    uint32_t r0, r1, r2, pad;
-    double sa;      // sigma_a(v)
-    double pad2;
+    int32_t v;       // word
+    int32_t cb;      // first CSC entry of the word's Phi column
+    uint16_t kold;   // topic before the draw
+    uint16_t kv;     // nonzeros in the column (K_v^Phi <= K <= 4096)
+    uint32_t r0, r1, r2;
+    double sa;       // sigma_a(v)
 };
 
 struct ZCount {
@@ -553,8 +552,8 @@ __device__ __forceinline__ int32_t mslot(int32_t k, int log2c)
 // topic, phi and m_d of each (zeros past the end); loads are issued together.
 // DOC: the lane's list is its set mask bits (document side); otherwise a
 // contiguous block of the word's CSC entries starting at cbe (column side).
-template <int G, bool DOC>
-__device__ __forceinline__ void lane_terms(const DevModel &M, const float *pcol, const uint16_t *mt, uint64_t &rest,
+template <int G, bool DOC, typename CT>
+__device__ __forceinline__ void lane_terms(const DevModel &M, const float *pcol, const CT *mt, uint64_t &rest,
                                            int32_t cb, int32_t cbe, int32_t base, int32_t nl, int g, int log2c,
                                            int32_t (&kk)[KEEP], float (&fk)[KEEP], int32_t (&mk)[KEEP])
 {
@@ -599,8 +598,8 @@ __device__ __forceinline__ void lane_terms(const DevModel &M, const float *pcol,
 // and for the b-part the topic whose running sum first exceeds
 // y = u_sigma - sigma_a (Section 3.5).  Returns the topic, or -1 for the
 // a-part (the caller draws from the word's alias table).
-template <int G, bool DOC>
-__device__ __forceinline__ int32_t b_part(const DevModel &M, const TokenIn &tk, const uint16_t *mt, const int g,
+template <int G, bool DOC, typename CT>
+__device__ __forceinline__ int32_t b_part(const DevModel &M, const TokenIn &tk, const CT *mt, const int g,
                                           const int log2c, const uint64_t mask)
 {
     constexpr int LG = log2g<G>();
@@ -619,14 +618,14 @@ __device__ __forceinline__ int32_t b_part(const DevModel &M, const TokenIn &tk, 
     uint64_t rest = mask;
     int32_t kk[KEEP], mk[KEEP];
     float fk[KEEP];
-    lane_terms<G, DOC>(M, pcol, mt, rest, tk.cb, cbe, 0, nl, g, log2c, kk, fk, mk);
+    lane_terms<G, DOC, CT>(M, pcol, mt, rest, tk.cb, cbe, 0, nl, g, log2c, kk, fk, mk);
     double p = 0.0;
 #pragma unroll
     for (int u = 0; u < KEEP; ++u) p += (double)fk[u] * (double)mk[u];
     for (int32_t base = KEEP; base < nl; base += KEEP) {
         int32_t k2[KEEP], m2[KEEP];
         float f2[KEEP];
-        lane_terms<G, DOC>(M, pcol, mt, rest, tk.cb, cbe, base, nl, g, log2c, k2, f2, m2);
+        lane_terms<G, DOC, CT>(M, pcol, mt, rest, tk.cb, cbe, base, nl, g, log2c, k2, f2, m2);
 #pragma unroll
         for (int u = 0; u < KEEP; ++u) p += (double)f2[u] * (double)m2[u];
     }
@@ -665,7 +664,7 @@ __device__ __forceinline__ int32_t b_part(const DevModel &M, const TokenIn &tk, 
             for (int32_t base = 0; base < nl && kf < 0; base += KEEP) {
                 int32_t k2[KEEP], m2[KEEP];
                 float f2[KEEP];
-                lane_terms<G, DOC>(M, pcol, mt, r2, tk.cb, cbe, base, nl, g, log2c, k2, f2, m2);
+                lane_terms<G, DOC, CT>(M, pcol, mt, r2, tk.cb, cbe, base, nl, g, log2c, k2, f2, m2);
 #pragma unroll
                 for (int u = 0; u < KEEP; ++u) {
                     const double bv = (double)f2[u] * (double)m2[u];
@@ -684,8 +683,8 @@ __device__ __forceinline__ int32_t b_part(const DevModel &M, const TokenIn &tk, 
 
 // draw one token (group-uniform control flow); returns the new topic, or
 // -1 - kold for a token whose word has an empty Phi column (it keeps kold)
-template <int G>
-__device__ __forceinline__ int32_t draw_token(const DevModel &M, const TokenIn &tk, uint16_t *mt, const int g,
+template <int G, typename CT>
+__device__ __forceinline__ int32_t draw_token(const DevModel &M, const TokenIn &tk, CT *mt, const int g,
                                               const int log2c, const int32_t side_ratio, uint64_t &mask,
                                               int32_t &Kd, ZCount &cnt)
 {
@@ -698,7 +697,7 @@ __device__ __forceinline__ int32_t draw_token(const DevModel &M, const TokenIn &
     const int32_t mo = mt[oslot];
     __builtin_amdgcn_wave_barrier();
     if (g == oo) {
-        mt[oslot] = (uint16_t)(mo - 1);
+        mt[oslot] = (CT)(mo - 1);
         if (mo == 1) mask &= ~(1ull << ob);
     }
     if (mo == 1) --Kd;
@@ -707,7 +706,7 @@ __device__ __forceinline__ int32_t draw_token(const DevModel &M, const TokenIn &
     if (Kv == 0) {
         // 0/0 conditional: the token keeps its topic
         if (g == oo) {
-            mt[oslot] = (uint16_t)mo;
+            mt[oslot] = (CT)mo;
             if (mo == 1) mask |= 1ull << ob;
         }
         if (mo == 1) ++Kd;
@@ -723,8 +722,8 @@ __device__ __forceinline__ int32_t draw_token(const DevModel &M, const TokenIn &
     // phi values from the dense column, so the column side is preferred up
     // to side_ratio times the document's topic count.
     int32_t knew;
-    if (Kd == 0 || Kv > side_ratio * Kd) knew = b_part<G, true>(M, tk, mt, g, log2c, mask);
-    else knew = b_part<G, false>(M, tk, mt, g, log2c, mask);
+    if (Kd == 0 || Kv > side_ratio * Kd) knew = b_part<G, true, CT>(M, tk, mt, g, log2c, mask);
+    else knew = b_part<G, false, CT>(M, tk, mt, g, log2c, mask);
     if (knew < 0) {
         // a-part: the word's alias table over alpha_k phi_kv
         const uint32_t j = scale32(tk.r1, (uint32_t)Kv);
@@ -738,7 +737,7 @@ __device__ __forceinline__ int32_t draw_token(const DevModel &M, const TokenIn &
     const int32_t mn = mt[nslot];
     __builtin_amdgcn_wave_barrier();
     if (g == no) {
-        mt[nslot] = (uint16_t)(mn + 1);
+        mt[nslot] = (CT)(mn + 1);
         if (mn == 0) mask |= 1ull << nb;
     }
     if (mn == 0) ++Kd;
@@ -747,17 +746,20 @@ __device__ __forceinline__ int32_t draw_token(const DevModel &M, const TokenIn &
 }
 
 // load a document's topic counts into the group's LDS table and masks
-template <int G>
-__device__ __forceinline__ void load_doc_counts(uint16_t *mt, const uint16_t *z, int64_t s, int64_t e, int g,
-                                                int log2c, uint64_t &mask, int32_t &Kd)
+// (CT: 8-bit counts for documents shorter than 256 tokens, else 16-bit)
+template <int G, typename CT>
+__device__ __forceinline__ void load_doc_counts(CT *mt, const uint16_t *z, int64_t s, int64_t e, int g, int log2c,
+                                                uint64_t &mask, int32_t &Kd)
 {
+    constexpr int PER_WORD = 4 / sizeof(CT);   // counters per 32-bit word
+    constexpr int SHIFT = 8 * sizeof(CT);
     const int32_t C = 1 << log2c;
     uint32_t *w32 = (uint32_t *)mt;
-    for (int32_t i = g; i < C * G / 2; i += G) w32[i] = 0;
+    for (int32_t i = g; i < C * G / PER_WORD; i += G) w32[i] = 0;
     __builtin_amdgcn_wave_barrier();
     for (int64_t i = s + g; i < e; i += G) {
         const int32_t slot = mslot<G>(z[i], log2c);
-        atomicAdd(w32 + (slot >> 1), (slot & 1) ? 65536u : 1u);
+        atomicAdd(w32 + slot / PER_WORD, 1u << (SHIFT * (slot % PER_WORD)));
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -774,20 +776,18 @@ __device__ __forceinline__ void stage_token(const DevModel &M, TokenIn *tok, int
 {
     TokenIn x;
     x.v = v;
-    x.kold = kold;
     x.cb = M.colptr[v];
-    x.kv = M.colptr[v + 1] - x.cb;
+    x.kold = (uint16_t)kold;
+    x.kv = (uint16_t)(M.colptr[v + 1] - x.cb);
     x.r0 = r.x;
     x.r1 = r.y;
     x.r2 = r.z;
-    x.pad = 0;
     x.sa = M.sigma_a[v];
-    x.pad2 = 0.0;
     tok[g] = x;
 }
 
-template <int G>
-__device__ void z_step_item(const ZArgs &a, const WorkItem &w, uint16_t *wave_m, TokenIn *wave_tok, ZCount &cnt)
+template <int G, typename CT>
+__device__ void z_step_item(const ZArgs &a, const WorkItem &w, CT *wave_m, TokenIn *wave_tok, ZCount &cnt)
 {
     constexpr int NG = 64 / G;
     const int lane = __lane_id();
@@ -795,7 +795,7 @@ __device__ void z_step_item(const ZArgs &a, const WorkItem &w, uint16_t *wave_m,
     const int grp = lane / G;
     const int log2c = G == 64 ? a.log2c64 : (G == 32 ? a.log2c32 : a.log2c16);
     const int32_t C = 1 << log2c;
-    uint16_t *mt = wave_m + grp * (C * G);
+    CT *mt = wave_m + grp * (C * G);
     TokenIn *tok = wave_tok + grp * G;
     const DevModel &M = a.m;
     const uint32_t t = *M.tptr;
@@ -808,7 +808,7 @@ __device__ void z_step_item(const ZArgs &a, const WorkItem &w, uint16_t *wave_m,
         }
         uint64_t mask;
         int32_t Kd;
-        load_doc_counts<G>(mt, a.c.z, s, e, g, log2c, mask, Kd);
+        load_doc_counts<G, CT>(mt, a.c.z, s, e, g, log2c, mask, Kd);
         for (int64_t i0 = s; i0 < e; i0 += G) {
             const int64_t i = i0 + g;
             const bool valid = i < e;
@@ -824,7 +824,7 @@ __device__ void z_step_item(const ZArgs &a, const WorkItem &w, uint16_t *wave_m,
             const int nb = (int)((e - i0) < G ? (e - i0) : G);
             for (int jj = 0; jj < nb; ++jj) {
                 const TokenIn tk = tok[jj];
-                int32_t k = draw_token<G>(M, tk, mt, g, log2c, w.side_ratio, mask, Kd, cnt);
+                int32_t k = draw_token<G, CT>(M, tk, mt, g, log2c, w.side_ratio, mask, Kd, cnt);
                 if (k < 0) k = -1 - k;
                 if (g == 0) atomicAdd(&M.n[(uint32_t)tk.v * (uint32_t)M.K + (uint32_t)k], 1);
                 if (g == jj) znew = k;
@@ -855,15 +855,15 @@ __device__ void z_step_item(const ZArgs &a, const WorkItem &w, uint16_t *wave_m,
     }
 }
 
-// one persistent kernel per group size: waves take work items from this
-// group size's queue until it is empty
-template <int G>
+// one persistent kernel per group size and count width: waves take work
+// items from this class's queue until it is empty
+template <int G, typename CT>
 __global__ void __launch_bounds__(256) z_step_kernel(ZArgs a)
 {
-    extern __shared__ uint16_t z_lds[];
+    extern __shared__ __align__(16) uint8_t z_lds[];
     const int wave = threadIdx.x >> 6;
-    uint16_t *wave_m = z_lds + wave * a.m_per_wave;
-    TokenIn *wave_tok = (TokenIn *)(z_lds + 4 * a.m_per_wave) + wave * 64;
+    CT *wave_m = (CT *)(z_lds + wave * a.m_bytes_per_wave);
+    TokenIn *wave_tok = (TokenIn *)(z_lds + 4 * a.m_bytes_per_wave) + wave * 64;
     ZCount cnt = {0, 0, 0};
     while (true) {
         int item = 0;
@@ -873,7 +873,7 @@ __global__ void __launch_bounds__(256) z_step_kernel(ZArgs a)
         // a private copy: a reference into global memory would be reloaded
         // after every store of the item (stores may alias it)
         const WorkItem w = a.items[item];
-        z_step_item<G>(a, w, wave_m, wave_tok, cnt);
+        z_step_item<G, CT>(a, w, wave_m, wave_tok, cnt);
     }
     // every lane of a group counted the group's tokens; its first lane reports
     if (a.stats && (__lane_id() & (G - 1)) == 0) {
@@ -913,10 +913,10 @@ hipError_t launch_z_prepare(const DevModel &m, int32_t *queues, unsigned long lo
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    return launch_fill_u32((uint32_t *)queues, 0u, 3, s);
+    return launch_fill_u32((uint32_t *)queues, 0u, 8, s);
 }
 
-hipError_t launch_z_class(const DevCorpus &c, const DevModel &m, int32_t group, const WorkItem *items,
+hipError_t launch_z_class(const DevCorpus &c, const DevModel &m, int32_t group, bool narrow, const WorkItem *items,
                           int32_t n_items, int32_t n_waves, int32_t *queue, unsigned long long *stats,
                           double *ll_doc, hipStream_t s)
 {
@@ -932,14 +932,19 @@ hipError_t launch_z_class(const DevCorpus &c, const DevModel &m, int32_t group, 
     a.log2c64 = topics_per_lane_log2(m.K, 64);
     a.log2c32 = topics_per_lane_log2(m.K, 32);
     a.log2c16 = topics_per_lane_log2(m.K, 16);
-    // a wave holds 64/G tables of C*G slots (64*C slots), then 64 staged token inputs
+    // a wave holds 64/G tables of C*G counters (64*C), then 64 staged token inputs
     const int log2c = group == 64 ? a.log2c64 : (group == 32 ? a.log2c32 : a.log2c16);
-    a.m_per_wave = 64 << log2c;
-    const size_t lds = 4 * (a.m_per_wave * sizeof(uint16_t) + 64 * sizeof(TokenIn));
+    a.m_bytes_per_wave = (64 << log2c) * (narrow ? 1 : 2);
+    const size_t lds = 4 * ((size_t)a.m_bytes_per_wave + 64 * sizeof(TokenIn));
     const int blocks = (n_waves + 3) / 4;
-    if (group == 64) z_step_kernel<64><<<blocks, 256, lds, s>>>(a);
-    else if (group == 32) z_step_kernel<32><<<blocks, 256, lds, s>>>(a);
-    else z_step_kernel<16><<<blocks, 256, lds, s>>>(a);
+    if (narrow) {
+        if (group == 32) z_step_kernel<32, uint8_t><<<blocks, 256, lds, s>>>(a);
+        else z_step_kernel<16, uint8_t><<<blocks, 256, lds, s>>>(a);
+    } else {
+        if (group == 64) z_step_kernel<64, uint16_t><<<blocks, 256, lds, s>>>(a);
+        else if (group == 32) z_step_kernel<32, uint16_t><<<blocks, 256, lds, s>>>(a);
+        else z_step_kernel<16, uint16_t><<<blocks, 256, lds, s>>>(a);
+    }
     return hipGetLastError();
 }
 
@@ -1304,7 +1309,7 @@ __device__ void foldin_slot(const DevModel &M, const DevFoldin &F, int32_t sid, 
     }
     uint64_t mask;
     int32_t Kd;
-    load_doc_counts<G>(mt, zz, 0, kept, g, log2c, mask, Kd);
+    load_doc_counts<G, uint16_t>(mt, zz, 0, kept, g, log2c, mask, Kd);
     ZCount st = {0, 0, 0};
     for (int32_t s = sl.done + 1; s <= sl.done + sl.todo; ++s) {
         for (int32_t q0 = 0; q0 < kept; q0 += G) {
@@ -1322,7 +1327,7 @@ __device__ void foldin_slot(const DevModel &M, const DevFoldin &F, int32_t sid, 
             const int nb = (kept - q0) < G ? (kept - q0) : G;
             for (int jj = 0; jj < nb; ++jj) {
                 const TokenIn tk = tok[jj];
-                int32_t k = draw_token<G>(M, tk, mt, g, log2c, 1, mask, Kd, st);
+                int32_t k = draw_token<G, uint16_t>(M, tk, mt, g, log2c, 1, mask, Kd, st);
                 if (k < 0) k = -1 - k;
                 if (g == jj) znew = k;
             }
@@ -1362,7 +1367,7 @@ template <int G, bool SYM>
 __global__ void __launch_bounds__(256) foldin_step_kernel(DevModel M, DevFoldin F, const int32_t *active,
                                                           int32_t n_active, int32_t log2c, int32_t per_group)
 {
-    extern __shared__ uint16_t f_lds[];
+    extern __shared__ __align__(16) uint16_t f_lds[];
     const int lane = __lane_id();
     const int wave = threadIdx.x >> 6;
     constexpr int gsz = G;
