@@ -60,7 +60,10 @@ def cpu_baseline(corpus, seed, budget_docs):
 
 
 def foldin_bench(args, torch, pulda, synth):
-    """Fold-in serving against a resident Phi (K=1000, V=141000)."""
+    """Fold-in serving against a resident Phi (K=1000, V=141000): continuous
+    batching (closed loop, then open-loop Poisson arrivals) and the plain
+    per-document sampler on the same requests."""
+    from paper_1704_03581_amd import server
     cfg = synth.CONFIGS["large"]
     K, V = cfg["K"], cfg["V"]
     log("fold-in: drawing serving counts and Phi")
@@ -72,71 +75,33 @@ def foldin_bench(args, torch, pulda, synth):
     torch.cuda.synchronize()
     reqs = synth.foldin_requests(args.foldin_requests + args.plain_requests, seed=170403581 + 5)
     lens = np.array([len(r) for r in reqs])
-    server = pulda.FoldIn(model, sweeps=50, burn_in=25, max_slots=args.slots, arena_tokens=args.slots * 600,
-                          max_len=5000, group=64, seed=args.seed)
-
-    def run_batched(arrivals, reqs_):
-        """Continuous batching: admit whatever has arrived while slots and
-        arena tokens allow, advance every resident request by a quantum,
-        collect finished ones, repeat."""
-        t0 = time.perf_counter()
-        nxt, done = 0, 0
-        lat = np.zeros(len(reqs_))
-        pending = []
-        while done < len(reqs_):
-            now = time.perf_counter() - t0
-            while nxt < len(reqs_) and arrivals[nxt] <= now:
-                pending.append(nxt)
-                nxt += 1
-            while pending:
-                if not server.submit(pending[0], reqs_[pending[0]]):
-                    break
-                pending.pop(0)
-            occ = server.occupancy()
-            if occ["resident"] == 0:
-                if nxt < len(reqs_):
-                    time.sleep(max(0.0, min(arrivals[nxt] - now, 0.001)))
-                continue
-            server.step(args.quantum)
-            for r in server.poll(cap=args.slots):
-                lat[r["request_id"]] = time.perf_counter() - t0 - arrivals[r["request_id"]]
-                done += 1
-        return time.perf_counter() - t0, lat
-
+    fi = pulda.FoldIn(model, sweeps=50, burn_in=25, max_slots=args.slots, arena_tokens=args.slots * 600,
+                      max_len=5000, group=64, seed=args.seed)
     nb = args.foldin_requests
-    batched_reqs = reqs[:nb]
+    batched = reqs[:nb]
     log(f"fold-in: closed loop, {nb} requests")
-    wall, lat = run_batched(np.zeros(nb), batched_reqs)
-    xmax = nb / wall
-    out = dict(saturation_docs_per_s=xmax, requests=nb, mean_len=float(lens[:nb].mean()),
+    rep = server.serve(fi, batched, quantum=args.quantum)
+    xmax = rep.docs_per_s
+    out = dict(saturation_docs_per_s=xmax, saturation_p50_ms=rep.percentile_ms(50),
+               saturation_p99_ms=rep.percentile_ms(99), requests=nb, mean_len=float(lens[:nb].mean()),
                sweeps=50, burn_in=25, slots=args.slots, quantum=args.quantum, rates={})
-    rng = np.random.default_rng(170403581 + 5)
-    for frac in args.rates:
-        lam = frac * xmax
-        arr = np.cumsum(rng.exponential(1.0 / lam, size=nb))
-        wall, lat = run_batched(arr, batched_reqs)
-        out["rates"][f"{frac:.2f}"] = dict(offered_docs_per_s=lam, docs_per_s=nb / wall,
-                                           p50_ms=float(np.percentile(lat, 50) * 1e3),
-                                           p99_ms=float(np.percentile(lat, 99) * 1e3))
+    for i, frac in enumerate(args.rates):
+        arr = server.poisson_arrivals(nb, frac * xmax, seed=170403581 + 5 + i)
+        rep = server.serve(fi, batched, arrivals=arr, quantum=args.quantum)
+        out["rates"][f"{frac:.2f}"] = dict(offered_docs_per_s=frac * xmax, docs_per_s=rep.docs_per_s,
+                                           p50_ms=rep.percentile_ms(50), p99_ms=rep.percentile_ms(99),
+                                           max_resident=rep.max_resident)
         log(f"fold-in: rate {frac:.2f} x -> {out['rates'][f'{frac:.2f}']}")
-    # plain per-document sampler on the same kind of requests
     plain = reqs[nb:nb + args.plain_requests]
-    t0 = time.perf_counter()
-    plain_res = [server.run_one(nb + j, r) for j, r in enumerate(plain)]
-    pw = time.perf_counter() - t0
-    out["plain_docs_per_s"] = len(plain) / pw
-    out["plain_mean_latency_ms"] = pw / len(plain) * 1e3
-    # the batched path gives the same result per request
-    mixed = {}
-    for j, r in enumerate(plain):
-        assert server.submit(nb + j, r)
-    while len(mixed) < len(plain):
-        server.step(args.quantum)
-        for r in server.poll(cap=args.slots):
-            mixed[r["request_id"]] = r
-    same = all(np.array_equal(mixed[nb + j]["theta"], plain_res[j]["theta"]) and
-               mixed[nb + j]["loglik"] == plain_res[j]["loglik"] for j in range(len(plain)))
-    out["batched_equals_plain"] = bool(same)
+    rep_p = server.serve_plain(fi, plain)
+    out["plain_docs_per_s"] = rep_p.docs_per_s
+    out["plain_p50_ms"] = rep_p.percentile_ms(50)
+    out["plain_p99_ms"] = rep_p.percentile_ms(99)
+    # the same requests through the batched path give the same results
+    rep_b = server.serve(fi, plain, quantum=args.quantum)
+    out["batched_equals_plain"] = bool(all(
+        np.array_equal(rep_b.results[j]["theta"], rep_p.results[j]["theta"]) and
+        rep_b.results[j]["loglik"] == rep_p.results[j]["loglik"] for j in range(len(plain))))
     out["speedup_vs_plain"] = xmax / out["plain_docs_per_s"]
     return out
 
@@ -152,6 +117,8 @@ def main():
     ap.add_argument("--side-ratio", type=int, default=1, help="side ratio with --force-group")
     ap.add_argument("--separate-loglik", action="store_true",
                     help="recount document terms of the log joint in their own pass")
+    ap.add_argument("--schedule", default=None,
+                    help="explicit schedule as JSON [min_len, group, docs_per_item, side_ratio] (no autotuning)")
     ap.add_argument("--force-group", type=int, default=0,
                     help="one schedule bucket with this group size (16, 32, 64) instead of autotuning")
     ap.add_argument("--graph", action="store_true", help="replay a captured sweep (no per-phase events)")
@@ -204,22 +171,26 @@ def main():
                       seed=args.seed, device=dev)
     plan.upload(corpus.doc_off, corpus.words)
     plan.init()
-    plan.phi_step(1)
-    torch.cuda.synchronize()
-    if args.force_group:
-        plan.set_schedule([0], [args.force_group], [64 // args.force_group * 16], [args.side_ratio])
-        log(f"schedule: one bucket, group {args.force_group}, side ratio {args.side_ratio}")
-    elif not args.no_autotune:
-        sched = plan.autotune(1, reps=1)
-        log(f"autotuned schedule: {sched}")
-    plan.set_graph(args.graph)
     plan.set_fused_loglik(not args.separate_loglik)
-    plan.set_timing(not args.graph)
     t = 1
     log(f"warmup {args.warmup} sweeps")
     if args.warmup:
         plan.sweep(t, args.warmup, want_ll=False)
         t += args.warmup
+    torch.cuda.synchronize()
+    # the schedule is tuned on the state the timed sweeps start from
+    if args.schedule:
+        plan.set_schedule(*json.loads(args.schedule))
+        log(f"schedule: {plan.get_schedule()}")
+    elif args.force_group:
+        plan.set_schedule([0], [args.force_group], [64 // args.force_group * 16], [args.side_ratio])
+        log(f"schedule: one bucket, group {args.force_group}, side ratio {args.side_ratio}")
+    elif not args.no_autotune:
+        plan.phi_step(t)
+        sched = plan.autotune(t, reps=1)
+        log(f"autotuned schedule: {sched}")
+    plan.set_graph(args.graph)
+    plan.set_timing(not args.graph)
     torch.cuda.synchronize()
     plan.stats()  # restart counters and event totals
     log(f"timing {args.steps} sweeps")
@@ -240,7 +211,7 @@ def main():
                config=dict(workload=f"{args.config}: synthetic LDA corpus D={corpus.D} V={corpus.V} K={corpus.K} "
                                     f"N={N}, alpha={corpus.alpha}, beta={corpus.beta}; one sweep = Phi-step + "
                                     f"z-step + count rebuild + log joint",
-                           global_batch=N, parallelism="single GPU"))
+                           global_batch=N, parallelism="single GPU", schedule=plan.get_schedule()))
     if not args.graph and st["n_z"]:
         z_ms = st["ms_z"] / st["n_z"]
         bytes_launch = algorithmic_bytes(N, st["sum_J"] / st["z_steps"], st["sum_A"] / st["z_steps"])

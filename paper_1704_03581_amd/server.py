@@ -1,0 +1,112 @@
+"""Continuous-batching fold-in server loop.
+
+Requests are new documents whose topic proportions theta are inferred
+against a fixed, device-resident Phi (fold-in).  The loop admits every
+request that has arrived as soon as a slot and enough arena tokens are free
+(admission by device memory), advances all resident requests together by a
+quantum of sweeps in one launch, collects the finished ones and admits more:
+requests that arrive while others are on the GPU join the running batch.
+
+The loop drives any backend with the FoldIn interface (submit / step / poll /
+occupancy), so its bookkeeping is testable without a GPU.
+"""
+from __future__ import annotations
+
+import time
+from collections import deque
+from dataclasses import dataclass, field
+from typing import Callable, Dict, List, Optional, Sequence
+
+import numpy as np
+
+
+@dataclass
+class ServeReport:
+    results: Dict[int, dict]                 # request id -> result
+    latency_s: np.ndarray                    # completion - arrival, per request
+    wall_s: float
+    steps: int = 0
+    max_resident: int = 0
+    admission_waits: int = 0                 # submits refused for capacity
+    order_admitted: List[int] = field(default_factory=list)
+
+    @property
+    def docs_per_s(self) -> float:
+        return len(self.results) / self.wall_s if self.wall_s > 0 else float("inf")
+
+    def percentile_ms(self, q: float) -> float:
+        return float(np.percentile(self.latency_s, q) * 1e3) if len(self.latency_s) else 0.0
+
+
+def serve(backend, requests: Sequence[np.ndarray], arrivals: Optional[Sequence[float]] = None,
+          quantum: int = 10, clock: Callable[[], float] = time.perf_counter,
+          sleep: Callable[[float], None] = time.sleep, max_poll: int = 4096) -> ServeReport:
+    """Serve requests[i] arriving at arrivals[i] seconds (None: all at 0).
+
+    Request ids are the indices into `requests`.  Admission is first come,
+    first served: a request that does not fit waits (and blocks those behind
+    it) until a poll frees a slot and arena space.
+    """
+    n = len(requests)
+    arr = np.zeros(n) if arrivals is None else np.asarray(arrivals, dtype=np.float64)
+    if n and np.any(np.diff(arr) < 0):
+        raise ValueError("arrivals must be non-decreasing")
+    t0 = clock()
+    lat = np.zeros(n)
+    results: Dict[int, dict] = {}
+    pending: deque = deque()
+    nxt = 0
+    rep = ServeReport(results, lat, 0.0)
+    while len(results) < n:
+        now = clock() - t0
+        while nxt < n and arr[nxt] <= now:
+            pending.append(nxt)
+            nxt += 1
+        while pending:
+            rid = pending[0]
+            if not backend.submit(rid, requests[rid]):
+                rep.admission_waits += 1
+                break
+            rep.order_admitted.append(rid)
+            pending.popleft()
+        occ = backend.occupancy()
+        rep.max_resident = max(rep.max_resident, occ["resident"])
+        if occ["resident"] == 0:
+            if pending:
+                raise RuntimeError(f"request {pending[0]} can never be admitted (larger than the arena?)")
+            if nxt < n:
+                sleep(max(0.0, min(arr[nxt] - (clock() - t0), 0.001)))
+            continue
+        backend.step(quantum)
+        rep.steps += 1
+        for r in backend.poll(cap=max_poll):
+            rid = r["request_id"]
+            lat[rid] = clock() - t0 - arr[rid]
+            results[rid] = r
+    rep.wall_s = clock() - t0
+    return rep
+
+
+def serve_plain(backend, requests: Sequence[np.ndarray], arrivals: Optional[Sequence[float]] = None,
+                clock: Callable[[], float] = time.perf_counter,
+                sleep: Callable[[float], None] = time.sleep) -> ServeReport:
+    """The plain per-document sampler: one request at a time, all sweeps in
+    one launch, in arrival order."""
+    n = len(requests)
+    arr = np.zeros(n) if arrivals is None else np.asarray(arrivals, dtype=np.float64)
+    t0 = clock()
+    lat = np.zeros(n)
+    results: Dict[int, dict] = {}
+    for rid in range(n):
+        now = clock() - t0
+        if arr[rid] > now:
+            sleep(arr[rid] - now)
+        results[rid] = backend.run_one(rid, requests[rid])
+        lat[rid] = clock() - t0 - arr[rid]
+    return ServeReport(results, lat, clock() - t0, steps=n)
+
+
+def poisson_arrivals(n: int, rate: float, seed: int) -> np.ndarray:
+    """Open-loop arrival times of a Poisson process with the given rate (1/s)."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, size=n))
