@@ -33,6 +33,35 @@ def algorithmic_bytes(N, sum_J, sum_A):
     return 28 * N + 6 * sum_J + 8 * sum_A
 
 
+def kernel_source_hash():
+    """sha256 prefix of the z-step kernel sources; a recorded counter reading
+    applies only to the kernel it was taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("kernels.hip", "device.h"):
+        with open(os.path.join(ROOT, "paper_1704_03581_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(config):
+    """HBM bytes per z-step launch from the committed FETCH_SIZE/WRITE_SIZE
+    counter summary (already scaled by the 1 GiB copy calibration), or None
+    when the summary is for another workload or an older kernel."""
+    path = os.path.join(ROOT, "profiles", f"zstep_{config}_counters.txt")
+    if not os.path.exists(path):
+        return None, None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if "=" in line and not line.startswith("#"):
+                k, v = line.strip().split("=", 1)
+                kv[k] = v
+    if kv.get("kernel_source_hash") != kernel_source_hash():
+        return None, path
+    return float(kv["traffic_bytes_per_launch"]), path
+
+
 def cpu_baseline(corpus, seed, budget_docs):
     """The oracle (single-threaded C) on a bounded sample of the same corpus."""
     import oracle
@@ -221,9 +250,12 @@ def main():
                             mean_J=st["sum_J"] / st["z_steps"] / N, a_fraction=st["sum_A"] / st["z_steps"] / N,
                             degenerate_per_sweep=st["degenerate_tokens"] / st["z_steps"],
                             nnz_phi=st["nnz_phi"], loglik=ll)
+        traffic, tsrc = recorded_traffic(args.config)
         res["roofline"] = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                               frac=achieved / HBM_PEAK_GBS, traffic=None,
-                               kernel="z_step_kernel", algorithmic_bytes_per_launch=bytes_launch)
+                               frac=achieved / HBM_PEAK_GBS, traffic=traffic,
+                               kernel="z_step_kernel", algorithmic_bytes_per_launch=bytes_launch,
+                               traffic_unit="bytes per launch (FETCH_SIZE x2.0 + WRITE_SIZE x1.0, calibrated)",
+                               traffic_source=os.path.relpath(tsrc, ROOT) if tsrc else None)
     log(f"sweep {ms_step:.2f} ms, {tokens_per_s / 1e9:.3f} G tokens/s; {res.get('zstep')}")
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
