@@ -162,7 +162,7 @@ struct pulda_plan {
     // (32, 8), (16, 16), (16, 8); 8-bit counts serve documents under 256 tokens
     static constexpr int NCLS = 5;
     int32_t cls_first[NCLS] = {}, cls_count[NCLS] = {};
-    int32_t n_waves = 0;
+    int32_t n_cu = 0;                 // compute units of the device
     // internal streams: the three group-size kernels of a z-step run
     // concurrently, forked from and joined back to the caller's stream
     hipStream_t aux[NCLS] = {};
@@ -361,7 +361,7 @@ pulda_status pulda_plan_bind(pulda_plan *p, void *workspace_dev, int64_t bytes)
     HIP_TRY(hipGetDevice(&dev));
     hipDeviceProp_t prop;
     HIP_TRY(hipGetDeviceProperties(&prop, dev));
-    p->n_waves = prop.multiProcessorCount * 20;
+    p->n_cu = prop.multiProcessorCount;
     for (int c = 0; c < pulda_plan::NCLS; ++c) {
         if (!p->aux[c]) HIP_TRY(hipStreamCreateWithFlags(&p->aux[c], hipStreamNonBlocking));
         if (!p->join_ev[c]) HIP_TRY(hipEventCreateWithFlags(&p->join_ev[c], hipEventDisableTiming));
@@ -580,7 +580,7 @@ static pulda_status enqueue_z(pulda_plan *p, hipStream_t s, double *ll_doc = nul
         for (int c = 0; c < pulda_plan::NCLS; ++c)
             if (p->cls_count[c])
                 HIP_TRY(launch_z_class(p->c, p->m, kClassGroup[c], kClassNarrow[c], p->items + p->cls_first[c],
-                                       p->cls_count[c], p->n_waves, p->queue + c, p->stats, ll_doc, s));
+                                       p->cls_count[c], p->n_cu, p->queue + c, p->stats, ll_doc, s));
     } else {
         // classes run concurrently: long documents (large groups) next to
         // the bulk of short ones
@@ -589,7 +589,7 @@ static pulda_status enqueue_z(pulda_plan *p, hipStream_t s, double *ll_doc = nul
             if (!p->cls_count[c]) continue;
             HIP_TRY(hipStreamWaitEvent(p->aux[c], p->fork_ev, 0));
             HIP_TRY(launch_z_class(p->c, p->m, kClassGroup[c], kClassNarrow[c], p->items + p->cls_first[c],
-                                   p->cls_count[c], p->n_waves, p->queue + c, p->stats, ll_doc, p->aux[c]));
+                                   p->cls_count[c], p->n_cu, p->queue + c, p->stats, ll_doc, p->aux[c]));
             HIP_TRY(hipEventRecord(p->join_ev[c], p->aux[c]));
             HIP_TRY(hipStreamWaitEvent(s, p->join_ev[c], 0));
         }
@@ -949,7 +949,7 @@ pulda_status pulda_autotune(pulda_plan *p, uint32_t t, int32_t reps, void *strea
                     HIP_TRY(hipEventRecord(e0, s));
                     HIP_TRY(launch_z_prepare(p->m, p->queue, nullptr, s));
                     HIP_TRY(launch_z_class(p->c, p->m, gsz, gsz < 64 && p->len_sorted[lo] < 256, p->items,
-                                           (int32_t)items.size(), p->n_waves, p->queue, nullptr, nullptr, s));
+                                           (int32_t)items.size(), p->n_cu, p->queue, nullptr, nullptr, s));
                     HIP_TRY(hipEventRecord(e1, s));
                     HIP_TRY(hipEventSynchronize(e1));
                     float ms;

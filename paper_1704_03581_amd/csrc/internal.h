@@ -75,9 +75,10 @@ hipError_t launch_phi_step(const DevModel &m, unsigned long long *stats, hipStre
 // document's term of the log joint for the state it leaves.
 hipError_t launch_z_prepare(const DevModel &m, int32_t *queues, unsigned long long *stats, hipStream_t s);
 // narrow: 8-bit document-topic counts (every document of the items is
-// shorter than 256 tokens; group 16 or 32)
+// shorter than 256 tokens; group 16 or 32).  The grid is as many blocks as
+// n_cu compute units hold at once.
 hipError_t launch_z_class(const DevCorpus &c, const DevModel &m, int32_t group, bool narrow, const WorkItem *items,
-                          int32_t n_items, int32_t n_waves, int32_t *queue, unsigned long long *stats,
+                          int32_t n_items, int32_t n_cu, int32_t *queue, unsigned long long *stats,
                           double *ll_doc, hipStream_t s);
 // log joint of the current state; with ll_doc non-null the document terms
 // are taken from it (written by the z-step) instead of recounted from z

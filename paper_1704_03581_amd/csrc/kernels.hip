@@ -526,9 +526,16 @@ struct alignas(16) TokenIn {
     int32_t cb;      // first CSC entry of the word's Phi column
     uint16_t kold;   // topic before the draw
     uint16_t kv;     // nonzeros in the column (K_v^Phi <= K <= 4096)
-    uint32_t r0, r1, r2;
+    uint32_t r0;     // uniform of the a/b decision and the b-walk
+    uint16_t ka;     // the a-part's topic: the alias draw depends only on the
+                     // word and the token's random numbers, so it is taken at
+                     // staging time, off the draw's critical path
+    uint16_t pad0;
+    uint32_t pad1;
     double sa;       // sigma_a(v)
 };
+
+static_assert(sizeof(TokenIn) == 32, "TokenIn is staged as 32-byte records");
 
 struct ZCount {
     unsigned long long J, A, degenerate;
@@ -725,10 +732,9 @@ __device__ __forceinline__ int32_t draw_token(const DevModel &M, const TokenIn &
     if (Kd == 0 || Kv > side_ratio * Kd) knew = b_part<G, true, CT>(M, tk, mt, g, log2c, mask);
     else knew = b_part<G, false, CT>(M, tk, mt, g, log2c, mask);
     if (knew < 0) {
-        // a-part: the word's alias table over alpha_k phi_kv
-        const uint32_t j = scale32(tk.r1, (uint32_t)Kv);
-        const uint64_t a = M.calias[tk.cb + j];
-        knew = (tk.r2 < (uint32_t)a) ? (int32_t)((a >> 32) & 0xFFFFu) : (int32_t)(a >> 48);
+        // a-part: the word's alias table over alpha_k phi_kv (drawn when the
+        // token was staged)
+        knew = tk.ka;
         cnt.A++;
     }
     // add the token back with its new topic
@@ -778,11 +784,22 @@ __device__ __forceinline__ void stage_token(const DevModel &M, TokenIn *tok, int
     x.v = v;
     x.cb = M.colptr[v];
     x.kold = (uint16_t)kold;
-    x.kv = (uint16_t)(M.colptr[v + 1] - x.cb);
+    const int32_t kv = M.colptr[v + 1] - x.cb;
+    x.kv = (uint16_t)kv;
     x.r0 = r.x;
-    x.r1 = r.y;
-    x.r2 = r.z;
     x.sa = M.sigma_a[v];
+    // the a-part's draw from the word's alias table over alpha_k phi_kv:
+    // slot j = floor(r1 * K_v / 2^32), kept when r2 < its threshold, else
+    // its alias (Section 3.5)
+    uint32_t ka = 0;
+    if (kv > 0) {
+        const uint32_t j = scale32(r.y, (uint32_t)kv);
+        const uint64_t a = M.calias[x.cb + j];
+        ka = (r.z < (uint32_t)a) ? (uint32_t)((a >> 32) & 0xFFFFu) : (uint32_t)(a >> 48);
+    }
+    x.ka = (uint16_t)ka;
+    x.pad0 = 0;
+    x.pad1 = 0;
     tok[g] = x;
 }
 
@@ -857,8 +874,10 @@ __device__ void z_step_item(const ZArgs &a, const WorkItem &w, CT *wave_m, Token
 
 // one persistent kernel per group size and count width: waves take work
 // items from this class's queue until it is empty
+// 6 waves per SIMD (80 VGPRs): the draws are latency-bound chains, and more
+// resident groups beat the few registers spilled to reach it
 template <int G, typename CT>
-__global__ void __launch_bounds__(256) z_step_kernel(ZArgs a)
+__global__ void __launch_bounds__(256, 6) z_step_kernel(ZArgs a)
 {
     extern __shared__ __align__(16) uint8_t z_lds[];
     const int wave = threadIdx.x >> 6;
@@ -917,7 +936,7 @@ hipError_t launch_z_prepare(const DevModel &m, int32_t *queues, unsigned long lo
 }
 
 hipError_t launch_z_class(const DevCorpus &c, const DevModel &m, int32_t group, bool narrow, const WorkItem *items,
-                          int32_t n_items, int32_t n_waves, int32_t *queue, unsigned long long *stats,
+                          int32_t n_items, int32_t n_cu, int32_t *queue, unsigned long long *stats,
                           double *ll_doc, hipStream_t s)
 {
     if (n_items == 0) return hipSuccess;
@@ -936,16 +955,25 @@ hipError_t launch_z_class(const DevCorpus &c, const DevModel &m, int32_t group, 
     const int log2c = group == 64 ? a.log2c64 : (group == 32 ? a.log2c32 : a.log2c16);
     a.m_bytes_per_wave = (64 << log2c) * (narrow ? 1 : 2);
     const size_t lds = 4 * ((size_t)a.m_bytes_per_wave + 64 * sizeof(TokenIn));
-    const int blocks = (n_waves + 3) / 4;
+    auto launch = [&](auto kernel) -> hipError_t {
+        // persistent: exactly the blocks the device holds at once, and no
+        // more waves than work items (a wave takes one item at a time)
+        int per_cu = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, lds);
+        if (e != hipSuccess) return e;
+        int64_t blocks = (int64_t)(per_cu > 0 ? per_cu : 1) * (n_cu > 0 ? n_cu : 1);
+        const int64_t need = ((int64_t)n_items + 3) / 4;
+        if (blocks > need) blocks = need;
+        kernel<<<(unsigned)blocks, 256, lds, s>>>(a);
+        return hipGetLastError();
+    };
     if (narrow) {
-        if (group == 32) z_step_kernel<32, uint8_t><<<blocks, 256, lds, s>>>(a);
-        else z_step_kernel<16, uint8_t><<<blocks, 256, lds, s>>>(a);
-    } else {
-        if (group == 64) z_step_kernel<64, uint16_t><<<blocks, 256, lds, s>>>(a);
-        else if (group == 32) z_step_kernel<32, uint16_t><<<blocks, 256, lds, s>>>(a);
-        else z_step_kernel<16, uint16_t><<<blocks, 256, lds, s>>>(a);
+        if (group == 32) return launch(z_step_kernel<32, uint8_t>);
+        return launch(z_step_kernel<16, uint8_t>);
     }
-    return hipGetLastError();
+    if (group == 64) return launch(z_step_kernel<64, uint16_t>);
+    if (group == 32) return launch(z_step_kernel<32, uint16_t>);
+    return launch(z_step_kernel<16, uint16_t>);
 }
 
 // ---------------------------------------------------------------------------
