@@ -513,6 +513,8 @@ struct ZArgs {
     const WorkItem *items;
     int32_t n_items;
     int32_t m_bytes_per_wave;  // bytes of count tables per wave
+    int32_t lcap;              // topic-list entries per group
+    int32_t wave_bytes;        // count tables and topic lists of one wave
     int32_t *queue;
     unsigned long long *stats;
     double *ll_doc;         // per-document log-joint terms (or null)
@@ -555,42 +557,75 @@ __device__ __forceinline__ int32_t mslot(int32_t k, int log2c)
     return ((k & ((1 << log2c) - 1)) << log2g<G>()) + (k >> log2c);
 }
 
-// up to KEEP b-terms of this lane starting at entry `base` of its list:
-// topic, phi and m_d of each (zeros past the end); loads are issued together.
-// DOC: the lane's list is its set mask bits (document side); otherwise a
-// contiguous block of the word's CSC entries starting at cbe (column side).
+// The state of the document a group is working on.  m_d lives in LDS as
+// the interleaved table mt (lane g owns topics [g*C, (g+1)*C), topic
+// g*C + b at slot b*G + g); nz holds a bit per owned topic with a nonzero
+// count.  For the document side of the b-sum the group also keeps lst, the
+// document's topics in ascending order as of the last rebuild; lane g walks
+// the contiguous block [g*q, (g+1)*q) of it, q = ceil(L / G), so every lane
+// has the same share.  A topic whose count falls to zero stays in lst (its
+// b-term is zero) until the next rebuild; a topic that enters the document
+// marks lst stale and the next document-side draw rebuilds it from nz.
+template <typename CT>
+struct DocState {
+    CT *mt;
+    uint16_t *lst;
+    uint64_t nz;     // this lane's topics with a nonzero count
+    uint64_t inl;    // this lane's topics present in lst
+    int32_t Kd;      // topics of the document with a nonzero count (group-uniform)
+    int32_t L;       // entries of lst (group-uniform)
+    bool stale;      // lst lacks a topic of the document (group-uniform)
+};
+
+// lst <- the lane's nonzero topics at its offset in ascending order
+template <int G, typename CT>
+__device__ __forceinline__ void rebuild_list(DocState<CT> &S, int g, int log2c)
+{
+    S.inl = S.nz;
+    const int32_t c = __builtin_popcountll(S.inl);
+    const int32_t incl = group_scan_incl_i32<G>(c);
+    int32_t o = incl - c;
+    S.L = group_bcast<G>(incl, G - 1);
+    uint64_t r = S.inl;
+    while (r) {
+        const int b = __builtin_ctzll(r);
+        r &= r - 1;
+        S.lst[o++] = (uint16_t)((g << log2c) + b);
+    }
+    S.stale = false;
+    __builtin_amdgcn_wave_barrier();
+}
+
+// up to KEEP b-terms of this lane: entries first + base + u (u < KEEP) of its
+// block, which has nl entries: topic, phi and m_d of each (zeros past the
+// end).  DOC: the block is in lst and phi comes from the word's dense
+// column; otherwise the block is of the word's CSC entries.
 template <int G, bool DOC, typename CT>
-__device__ __forceinline__ void lane_terms(const DevModel &M, const float *pcol, const CT *mt, uint64_t &rest,
-                                           int32_t cb, int32_t cbe, int32_t base, int32_t nl, int g, int log2c,
+__device__ __forceinline__ void lane_terms(const DevModel &M, const float *pcol, const CT *mt, const uint16_t *lst,
+                                           int32_t cb, int32_t first, int32_t base, int32_t nl, int log2c,
                                            int32_t (&kk)[KEEP], float (&fk)[KEEP], int32_t (&mk)[KEEP])
 {
     // Branch-free: every slot loads from a valid address (slots past the
-    // lane's end read the column's first element) and is zeroed afterwards,
-    // so the loads of all slots are in flight together.
-    int32_t kidx[KEEP];
+    // lane's end read entry 0 of the list or the column's first entry) and
+    // is zeroed afterwards, so the loads of all slots are in flight together.
     bool ok[KEEP];
-#pragma unroll
-    for (int u = 0; u < KEEP; ++u) {
-        ok[u] = base + u < nl;
-        if constexpr (DOC) {
-            const int b = ok[u] ? __builtin_ctzll(rest) : 0;
-            rest &= rest - 1;
-            kidx[u] = ok[u] ? (g << log2c) + b : 0;
-        } else {
-            kidx[u] = ok[u] ? cbe + base + u : cb;
-        }
-    }
     float fr[KEEP];
     int32_t kr[KEEP];
 #pragma unroll
     for (int u = 0; u < KEEP; ++u) {
+        ok[u] = base + u < nl;
         if constexpr (DOC) {
-            fr[u] = pcol[kidx[u]];
-            kr[u] = kidx[u];
+            const int32_t k = lst[ok[u] ? first + base + u : 0];
+            kr[u] = ok[u] ? k : 0;
         } else {
-            fr[u] = M.cphi[kidx[u]];
-            kr[u] = M.ctopic[kidx[u]];
+            const int32_t e = ok[u] ? first + base + u : cb;
+            fr[u] = M.cphi[e];
+            kr[u] = M.ctopic[e];
         }
+    }
+    if constexpr (DOC) {
+#pragma unroll
+        for (int u = 0; u < KEEP; ++u) fr[u] = pcol[kr[u]];
     }
 #pragma unroll
     for (int u = 0; u < KEEP; ++u) {
@@ -604,35 +639,36 @@ __device__ __forceinline__ void lane_terms(const DevModel &M, const float *pcol,
 // sigma_b = sum of the b-terms phi_kv m_k over one side, the a/b decision,
 // and for the b-part the topic whose running sum first exceeds
 // y = u_sigma - sigma_a (Section 3.5).  Returns the topic, or -1 for the
-// a-part (the caller draws from the word's alias table).
+// a-part (the caller takes the word's alias draw).
 template <int G, bool DOC, typename CT>
-__device__ __forceinline__ int32_t b_part(const DevModel &M, const TokenIn &tk, const CT *mt, const int g,
-                                          const int log2c, const uint64_t mask)
+__device__ __forceinline__ int32_t b_part(const DevModel &M, const TokenIn &tk, DocState<CT> &S, const int g,
+                                          const int log2c)
 {
     constexpr int LG = log2g<G>();
-    const int32_t Kv = tk.kv;
     const float *pcol = M.phid + (uint32_t)tk.v * (uint32_t)M.K;
-    int32_t nl, cbe = 0;
+    int32_t nl, first;
     if constexpr (DOC) {
-        nl = __builtin_popcountll(mask);
+        if (S.stale) rebuild_list<G, CT>(S, g, log2c);
+        const int32_t q = (S.L + G - 1) >> LG;
+        first = g * q;
+        nl = S.L - first < q ? S.L - first : q;
     } else {
+        const int32_t Kv = tk.kv;
         const int32_t q = (Kv + G - 1) >> LG;
-        const int32_t e0 = g * q;
-        nl = Kv - e0 < q ? Kv - e0 : q;
-        nl = nl > 0 ? nl : 0;
-        cbe = tk.cb + e0;
+        first = tk.cb + g * q;
+        nl = Kv - g * q < q ? Kv - g * q : q;
     }
-    uint64_t rest = mask;
+    nl = nl > 0 ? nl : 0;
     int32_t kk[KEEP], mk[KEEP];
     float fk[KEEP];
-    lane_terms<G, DOC, CT>(M, pcol, mt, rest, tk.cb, cbe, 0, nl, g, log2c, kk, fk, mk);
+    lane_terms<G, DOC, CT>(M, pcol, S.mt, S.lst, tk.cb, first, 0, nl, log2c, kk, fk, mk);
     double p = 0.0;
 #pragma unroll
     for (int u = 0; u < KEEP; ++u) p += (double)fk[u] * (double)mk[u];
     for (int32_t base = KEEP; base < nl; base += KEEP) {
         int32_t k2[KEEP], m2[KEEP];
         float f2[KEEP];
-        lane_terms<G, DOC, CT>(M, pcol, mt, rest, tk.cb, cbe, base, nl, g, log2c, k2, f2, m2);
+        lane_terms<G, DOC, CT>(M, pcol, S.mt, S.lst, tk.cb, first, base, nl, log2c, k2, f2, m2);
 #pragma unroll
         for (int u = 0; u < KEEP; ++u) p += (double)f2[u] * (double)m2[u];
     }
@@ -667,11 +703,10 @@ __device__ __forceinline__ int32_t b_part(const DevModel &M, const TokenIn &tk, 
                 }
             }
         } else {
-            uint64_t r2 = mask;
             for (int32_t base = 0; base < nl && kf < 0; base += KEEP) {
                 int32_t k2[KEEP], m2[KEEP];
                 float f2[KEEP];
-                lane_terms<G, DOC, CT>(M, pcol, mt, r2, tk.cb, cbe, base, nl, g, log2c, k2, f2, m2);
+                lane_terms<G, DOC, CT>(M, pcol, S.mt, S.lst, tk.cb, first, base, nl, log2c, k2, f2, m2);
 #pragma unroll
                 for (int u = 0; u < KEEP; ++u) {
                     const double bv = (double)f2[u] * (double)m2[u];
@@ -691,12 +726,12 @@ __device__ __forceinline__ int32_t b_part(const DevModel &M, const TokenIn &tk, 
 // draw one token (group-uniform control flow); returns the new topic, or
 // -1 - kold for a token whose word has an empty Phi column (it keeps kold)
 template <int G, typename CT>
-__device__ __forceinline__ int32_t draw_token(const DevModel &M, const TokenIn &tk, CT *mt, const int g,
-                                              const int log2c, const int32_t side_ratio, uint64_t &mask,
-                                              int32_t &Kd, ZCount &cnt)
+__device__ __forceinline__ int32_t draw_token(const DevModel &M, const TokenIn &tk, DocState<CT> &S, const int g,
+                                              const int log2c, const int32_t side_ratio, ZCount &cnt)
 {
     constexpr int LG = log2g<G>();
     const int32_t C = 1 << log2c;
+    CT *mt = S.mt;
     // m^{-i}: remove the token from its document's counts
     const int32_t kold = tk.kold;
     const int32_t ob = kold & (C - 1), oo = kold >> log2c;
@@ -705,32 +740,32 @@ __device__ __forceinline__ int32_t draw_token(const DevModel &M, const TokenIn &
     __builtin_amdgcn_wave_barrier();
     if (g == oo) {
         mt[oslot] = (CT)(mo - 1);
-        if (mo == 1) mask &= ~(1ull << ob);
+        if (mo == 1) S.nz &= ~(1ull << ob);
     }
-    if (mo == 1) --Kd;
+    if (mo == 1) --S.Kd;
     __builtin_amdgcn_wave_barrier();
     const int32_t Kv = tk.kv;
     if (Kv == 0) {
         // 0/0 conditional: the token keeps its topic
         if (g == oo) {
             mt[oslot] = (CT)mo;
-            if (mo == 1) mask |= 1ull << ob;
+            if (mo == 1) S.nz |= 1ull << ob;
         }
-        if (mo == 1) ++Kd;
+        if (mo == 1) ++S.Kd;
         __builtin_amdgcn_wave_barrier();
         cnt.degenerate++;
         return -1 - kold;
     }
+    const int32_t Kd = S.Kd;
     cnt.J += (unsigned long long)(Kd < Kv ? Kd : Kv);
-    // b-terms over one side: the document's nonzero topics (lane g owns
-    // topics [g*C, (g+1)*C)) or the word's Phi column (lane g takes a
-    // contiguous block of entries); ascending topic order either way.  The
-    // column is read contiguously while the document side gathers single
-    // phi values from the dense column, so the column side is preferred up
-    // to side_ratio times the document's topic count.
+    // b-terms over one side: the document's topics (lst) or the word's Phi
+    // column, ascending topic order either way.  The column is read
+    // contiguously while the document side gathers single phi values from
+    // the dense column, so the column side is preferred up to side_ratio
+    // times the document's topic count.
     int32_t knew;
-    if (Kd == 0 || Kv > side_ratio * Kd) knew = b_part<G, true, CT>(M, tk, mt, g, log2c, mask);
-    else knew = b_part<G, false, CT>(M, tk, mt, g, log2c, mask);
+    if (Kd == 0 || Kv > side_ratio * Kd) knew = b_part<G, true, CT>(M, tk, S, g, log2c);
+    else knew = b_part<G, false, CT>(M, tk, S, g, log2c);
     if (knew < 0) {
         // a-part: the word's alias table over alpha_k phi_kv (drawn when the
         // token was staged)
@@ -742,25 +777,33 @@ __device__ __forceinline__ int32_t draw_token(const DevModel &M, const TokenIn &
     const int32_t nslot = (nb << LG) + no;
     const int32_t mn = mt[nslot];
     __builtin_amdgcn_wave_barrier();
+    bool fresh = false;
     if (g == no) {
         mt[nslot] = (CT)(mn + 1);
-        if (mn == 0) mask |= 1ull << nb;
+        if (mn == 0) {
+            S.nz |= 1ull << nb;
+            fresh = !((S.inl >> nb) & 1ull);
+        }
     }
-    if (mn == 0) ++Kd;
+    if (mn == 0) {
+        ++S.Kd;
+        if (group_ballot<G>(fresh)) S.stale = true;
+    }
     __builtin_amdgcn_wave_barrier();
     return knew;
 }
 
 // load a document's topic counts into the group's LDS table and masks
-// (CT: 8-bit counts for documents shorter than 256 tokens, else 16-bit)
+// (CT: 8-bit counts for documents shorter than 256 tokens, else 16-bit);
+// lst is built by the first document-side draw
 template <int G, typename CT>
-__device__ __forceinline__ void load_doc_counts(CT *mt, const uint16_t *z, int64_t s, int64_t e, int g, int log2c,
-                                                uint64_t &mask, int32_t &Kd)
+__device__ __forceinline__ void load_doc_counts(DocState<CT> &S, const uint16_t *z, int64_t s, int64_t e, int g,
+                                                int log2c)
 {
     constexpr int PER_WORD = 4 / sizeof(CT);   // counters per 32-bit word
     constexpr int SHIFT = 8 * sizeof(CT);
     const int32_t C = 1 << log2c;
-    uint32_t *w32 = (uint32_t *)mt;
+    uint32_t *w32 = (uint32_t *)S.mt;
     for (int32_t i = g; i < C * G / PER_WORD; i += G) w32[i] = 0;
     __builtin_amdgcn_wave_barrier();
     for (int64_t i = s + g; i < e; i += G) {
@@ -769,11 +812,15 @@ __device__ __forceinline__ void load_doc_counts(CT *mt, const uint16_t *z, int64
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    mask = 0;
+    uint64_t mask = 0;
     for (int32_t b = 0; b < C; ++b)
-        if (mt[(b << log2g<G>()) + g]) mask |= 1ull << b;
+        if (S.mt[(b << log2g<G>()) + g]) mask |= 1ull << b;
+    S.nz = mask;
     const int32_t tot = group_scan_incl_i32<G>(__builtin_popcountll(mask));
-    Kd = group_bcast<G>(tot, G - 1);
+    S.Kd = group_bcast<G>(tot, G - 1);
+    S.inl = 0;
+    S.L = 0;
+    S.stale = true;
 }
 
 // stage the inputs of tokens i0 + g (one per lane) for a block of draws
@@ -804,7 +851,8 @@ __device__ __forceinline__ void stage_token(const DevModel &M, TokenIn *tok, int
 }
 
 template <int G, typename CT>
-__device__ void z_step_item(const ZArgs &a, const WorkItem &w, CT *wave_m, TokenIn *wave_tok, ZCount &cnt)
+__device__ void z_step_item(const ZArgs &a, const WorkItem &w, CT *wave_m, uint16_t *wave_lst, TokenIn *wave_tok,
+                            ZCount &cnt)
 {
     constexpr int NG = 64 / G;
     const int lane = __lane_id();
@@ -812,7 +860,10 @@ __device__ void z_step_item(const ZArgs &a, const WorkItem &w, CT *wave_m, Token
     const int grp = lane / G;
     const int log2c = G == 64 ? a.log2c64 : (G == 32 ? a.log2c32 : a.log2c16);
     const int32_t C = 1 << log2c;
-    CT *mt = wave_m + grp * (C * G);
+    DocState<CT> S;
+    S.mt = wave_m + grp * (C * G);
+    S.lst = wave_lst + grp * a.lcap;
+    CT *mt = S.mt;
     TokenIn *tok = wave_tok + grp * G;
     const DevModel &M = a.m;
     const uint32_t t = *M.tptr;
@@ -823,9 +874,7 @@ __device__ void z_step_item(const ZArgs &a, const WorkItem &w, CT *wave_m, Token
             if (a.ll_doc && g == 0) a.ll_doc[d] = 0.0;
             continue;
         }
-        uint64_t mask;
-        int32_t Kd;
-        load_doc_counts<G, CT>(mt, a.c.z, s, e, g, log2c, mask, Kd);
+        load_doc_counts<G, CT>(S, a.c.z, s, e, g, log2c);
         for (int64_t i0 = s; i0 < e; i0 += G) {
             const int64_t i = i0 + g;
             const bool valid = i < e;
@@ -841,7 +890,7 @@ __device__ void z_step_item(const ZArgs &a, const WorkItem &w, CT *wave_m, Token
             const int nb = (int)((e - i0) < G ? (e - i0) : G);
             for (int jj = 0; jj < nb; ++jj) {
                 const TokenIn tk = tok[jj];
-                int32_t k = draw_token<G, CT>(M, tk, mt, g, log2c, w.side_ratio, mask, Kd, cnt);
+                int32_t k = draw_token<G, CT>(M, tk, S, g, log2c, w.side_ratio, cnt);
                 if (k < 0) k = -1 - k;
                 if (g == 0) atomicAdd(&M.n[(uint32_t)tk.v * (uint32_t)M.K + (uint32_t)k], 1);
                 if (g == jj) znew = k;
@@ -853,7 +902,7 @@ __device__ void z_step_item(const ZArgs &a, const WorkItem &w, CT *wave_m, Token
             // the document's term of log p(z | alpha) for its final counts:
             // lgamma(A) - lgamma(N_d + A) + sum_k [lgamma(m_k + alpha) - lgamma(alpha)]
             double part = 0.0;
-            uint64_t mm = mask;
+            uint64_t mm = S.nz;
             while (mm) {
                 double v4[KEEP];
 #pragma unroll
@@ -881,8 +930,10 @@ __global__ void __launch_bounds__(256, 6) z_step_kernel(ZArgs a)
 {
     extern __shared__ __align__(16) uint8_t z_lds[];
     const int wave = threadIdx.x >> 6;
-    CT *wave_m = (CT *)(z_lds + wave * a.m_bytes_per_wave);
-    TokenIn *wave_tok = (TokenIn *)(z_lds + 4 * a.m_bytes_per_wave) + wave * 64;
+    uint8_t *wave_base = z_lds + wave * a.wave_bytes;
+    CT *wave_m = (CT *)wave_base;
+    uint16_t *wave_lst = (uint16_t *)(wave_base + a.m_bytes_per_wave);
+    TokenIn *wave_tok = (TokenIn *)(z_lds + 4 * a.wave_bytes) + wave * 64;
     ZCount cnt = {0, 0, 0};
     while (true) {
         int item = 0;
@@ -892,7 +943,7 @@ __global__ void __launch_bounds__(256, 6) z_step_kernel(ZArgs a)
         // a private copy: a reference into global memory would be reloaded
         // after every store of the item (stores may alias it)
         const WorkItem w = a.items[item];
-        z_step_item<G, CT>(a, w, wave_m, wave_tok, cnt);
+        z_step_item<G, CT>(a, w, wave_m, wave_lst, wave_tok, cnt);
     }
     // every lane of a group counted the group's tokens; its first lane reports
     if (a.stats && (__lane_id() & (G - 1)) == 0) {
@@ -954,14 +1005,18 @@ hipError_t launch_z_class(const DevCorpus &c, const DevModel &m, int32_t group, 
     // a wave holds 64/G tables of C*G counters (64*C), then 64 staged token inputs
     const int log2c = group == 64 ? a.log2c64 : (group == 32 ? a.log2c32 : a.log2c16);
     a.m_bytes_per_wave = (64 << log2c) * (narrow ? 1 : 2);
-    const size_t lds = 4 * ((size_t)a.m_bytes_per_wave + 64 * sizeof(TokenIn));
+    // a document's topic list holds at most min(K, its length - 1) topics
+    a.lcap = narrow ? (m.K < 255 ? m.K : 255) : m.K;
+    a.wave_bytes = (a.m_bytes_per_wave + (64 / group) * a.lcap * 2 + 15) / 16 * 16;
+    const size_t lds = 4 * ((size_t)a.wave_bytes + 64 * sizeof(TokenIn));
     auto launch = [&](auto kernel) -> hipError_t {
         // persistent: exactly the blocks the device holds at once, and no
         // more waves than work items (a wave takes one item at a time)
         int per_cu = 0;
         hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, lds);
         if (e != hipSuccess) return e;
-        int64_t blocks = (int64_t)(per_cu > 0 ? per_cu : 1) * (n_cu > 0 ? n_cu : 1);
+        if (per_cu <= 0) return hipErrorInvalidConfiguration;  // the block's LDS exceeds the CU's
+        int64_t blocks = (int64_t)per_cu * (n_cu > 0 ? n_cu : 1);
         const int64_t need = ((int64_t)n_items + 3) / 4;
         if (blocks > need) blocks = need;
         kernel<<<(unsigned)blocks, 256, lds, s>>>(a);
@@ -1296,6 +1351,9 @@ template <int G, bool SYM>
 __device__ void foldin_slot(const DevModel &M, const DevFoldin &F, int32_t sid, uint16_t *mt, TokenIn *tok,
                             int log2c)
 {
+    DocState<uint16_t> S;
+    S.mt = mt;
+    S.lst = mt + (G << log2c);
     const int lane = __lane_id();
     const int g = lane & (G - 1);
     const int32_t C = 1 << log2c;
@@ -1335,9 +1393,7 @@ __device__ void foldin_slot(const DevModel &M, const DevFoldin &F, int32_t sid, 
     } else {
         kept = F.kept[2 * sid];
     }
-    uint64_t mask;
-    int32_t Kd;
-    load_doc_counts<G, uint16_t>(mt, zz, 0, kept, g, log2c, mask, Kd);
+    load_doc_counts<G, uint16_t>(S, zz, 0, kept, g, log2c);
     ZCount st = {0, 0, 0};
     for (int32_t s = sl.done + 1; s <= sl.done + sl.todo; ++s) {
         for (int32_t q0 = 0; q0 < kept; q0 += G) {
@@ -1355,7 +1411,7 @@ __device__ void foldin_slot(const DevModel &M, const DevFoldin &F, int32_t sid, 
             const int nb = (kept - q0) < G ? (kept - q0) : G;
             for (int jj = 0; jj < nb; ++jj) {
                 const TokenIn tk = tok[jj];
-                int32_t k = draw_token<G, uint16_t>(M, tk, mt, g, log2c, 1, mask, Kd, st);
+                int32_t k = draw_token<G, uint16_t>(M, tk, S, g, log2c, 1, st);
                 if (k < 0) k = -1 - k;
                 if (g == jj) znew = k;
             }
@@ -1414,11 +1470,17 @@ hipError_t launch_foldin_step(const DevModel &m, const DevFoldin &f, const int32
 {
     if (n_active == 0) return hipSuccess;
     const int log2c = topics_per_lane_log2(m.K, f.group);
-    const int per_group = f.group << log2c;
+    // per group: the count table, then the topic list (K entries, rounded
+    // to keep the next table 4-byte aligned)
+    const int per_group = (f.group << log2c) + ((m.K + 1) & ~1);
     const int ngw = 64 / f.group;
     const int64_t waves = (n_active + ngw - 1) / ngw;
     const unsigned blocks = (unsigned)((waves + 3) / 4);
     const size_t lds = 4 * ngw * per_group * sizeof(uint16_t) + 4 * 64 * sizeof(TokenIn);
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, foldin_step_kernel<64, true>, 256, lds);
+    if (e != hipSuccess) return e;
+    if (per_cu <= 0) return hipErrorInvalidConfiguration;  // the block's LDS exceeds the CU's
 #define PULDA_FOLDIN(G_, S_) foldin_step_kernel<G_, S_><<<blocks, 256, lds, s>>>(m, f, active, n_active, log2c, per_group)
     if (m.lg_alpha) {
         if (f.group == 64) PULDA_FOLDIN(64, true);
