@@ -492,20 +492,18 @@ hipError_t launch_phi_step(const DevModel &m, unsigned long long *stats, hipStre
 // ---------------------------------------------------------------------------
 // z-step (Section 3.5).  A group of G lanes (G = 16, 32, 64) owns one
 // document at a time and walks its tokens in stored order (sequential Gibbs
-// within the document).  The document-topic counts m_d live in LDS; lane g
-// owns topics [g*C, (g+1)*C) (C a power of two, C*G >= K) and keeps a C-bit
-// mask of which of them are nonzero.  For each token:
+// within the document).  The document-topic counts m_d live in LDS, indexed
+// by topic; lane g owns topics [g*C, (g+1)*C) (C a power of two, C*G >= K)
+// for the bookkeeping of which topics are nonzero.  For each token:
 //   sigma_b = sum_k phi_kv m_k is taken over the smaller of the document's
-//   nonzero topics (lanes walk their own mask bits, phi from the dense
-//   column) and the word's Phi column (lanes walk a contiguous block of its
-//   CSC entries, m from LDS); either way each lane's entries are in
-//   ascending topic order and a group prefix sum orders the lanes, so the
-//   running sums are ascending in k as the definition requires;
-//   u_sigma = u (sigma_a + sigma_b) < sigma_a draws from the word's alias
-//   table, otherwise the crossing lane (first with prefix > u_sigma -
-//   sigma_a) re-walks its entries to find the topic.
-// m_d is stored interleaved (topic g*C + b at LDS slot b*G + g) so the lanes
-// of a group touch consecutive slots.
+//   topics (a list in LDS, phi gathered from the word's dense column) and
+//   the word's Phi column (its CSC entries, m from LDS); either way lane g
+//   takes a contiguous block of entries in ascending topic order and a
+//   group prefix sum orders the lanes, so the running sums are ascending in
+//   k as the definition requires;
+//   u_sigma = u (sigma_a + sigma_b) < sigma_a takes the word's alias draw,
+//   otherwise the crossing lane (first with prefix > u_sigma - sigma_a)
+//   walks its entries to find the topic.
 // ---------------------------------------------------------------------------
 struct ZArgs {
     DevModel m;
@@ -551,33 +549,26 @@ constexpr int log2g()
     return G == 64 ? 6 : (G == 32 ? 5 : 4);
 }
 
-template <int G>
-__device__ __forceinline__ int32_t mslot(int32_t k, int log2c)
-{
-    return ((k & ((1 << log2c) - 1)) << log2g<G>()) + (k >> log2c);
-}
-
-// The state of the document a group is working on.  m_d lives in LDS as
-// the interleaved table mt (lane g owns topics [g*C, (g+1)*C), topic
-// g*C + b at slot b*G + g); nz holds a bit per owned topic with a nonzero
-// count.  For the document side of the b-sum the group also keeps lst, the
-// document's topics in ascending order as of the last rebuild; lane g walks
-// the contiguous block [g*q, (g+1)*q) of it, q = ceil(L / G), so every lane
-// has the same share.  A topic whose count falls to zero stays in lst (its
-// b-term is zero) until the next rebuild; a topic that enters the document
-// marks lst stale and the next document-side draw rebuilds it from nz.
+// The state of the document a group is working on.  m_d is the table mt
+// (indexed by topic); nz holds a bit per topic of this lane's range with a
+// nonzero count.  For the document side of the b-sum the group also keeps
+// lst, the document's topics in ascending order as of the last rebuild.  A
+// topic whose count falls to zero stays in lst (its b-term is zero) until
+// the next rebuild; a topic that enters the document marks lst stale and the
+// next document-side draw rebuilds it from nz.  lst[0] always holds a valid
+// topic, so padding slots can read it.
 template <typename CT>
 struct DocState {
     CT *mt;
     uint16_t *lst;
-    uint64_t nz;     // this lane's topics with a nonzero count
-    uint64_t inl;    // this lane's topics present in lst
+    uint64_t nz;     // topics of this lane's range with a nonzero count
+    uint64_t inl;    // topics of this lane's range present in lst
     int32_t Kd;      // topics of the document with a nonzero count (group-uniform)
     int32_t L;       // entries of lst (group-uniform)
     bool stale;      // lst lacks a topic of the document (group-uniform)
 };
 
-// lst <- the lane's nonzero topics at its offset in ascending order
+// lst <- each lane's nonzero topics at its offset, ascending
 template <int G, typename CT>
 __device__ __forceinline__ void rebuild_list(DocState<CT> &S, int g, int log2c)
 {
@@ -593,85 +584,74 @@ __device__ __forceinline__ void rebuild_list(DocState<CT> &S, int g, int log2c)
         S.lst[o++] = (uint16_t)((g << log2c) + b);
     }
     S.stale = false;
+    // the list is read back through generic (flat) loads by other lanes:
+    // complete the LDS writes first
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
-}
-
-// up to KEEP b-terms of this lane: entries first + base + u (u < KEEP) of its
-// block, which has nl entries: topic, phi and m_d of each (zeros past the
-// end).  DOC: the block is in lst and phi comes from the word's dense
-// column; otherwise the block is of the word's CSC entries.
-template <int G, bool DOC, typename CT>
-__device__ __forceinline__ void lane_terms(const DevModel &M, const float *pcol, const CT *mt, const uint16_t *lst,
-                                           int32_t cb, int32_t first, int32_t base, int32_t nl, int log2c,
-                                           int32_t (&kk)[KEEP], float (&fk)[KEEP], int32_t (&mk)[KEEP])
-{
-    // Branch-free: every slot loads from a valid address (slots past the
-    // lane's end read entry 0 of the list or the column's first entry) and
-    // is zeroed afterwards, so the loads of all slots are in flight together.
-    bool ok[KEEP];
-    float fr[KEEP];
-    int32_t kr[KEEP];
-#pragma unroll
-    for (int u = 0; u < KEEP; ++u) {
-        ok[u] = base + u < nl;
-        if constexpr (DOC) {
-            const int32_t k = lst[ok[u] ? first + base + u : 0];
-            kr[u] = ok[u] ? k : 0;
-        } else {
-            const int32_t e = ok[u] ? first + base + u : cb;
-            fr[u] = M.cphi[e];
-            kr[u] = M.ctopic[e];
-        }
-    }
-    if constexpr (DOC) {
-#pragma unroll
-        for (int u = 0; u < KEEP; ++u) fr[u] = pcol[kr[u]];
-    }
-#pragma unroll
-    for (int u = 0; u < KEEP; ++u) {
-        const int32_t m = mt[mslot<G>(kr[u], log2c)];
-        kk[u] = ok[u] ? kr[u] : -1;
-        fk[u] = ok[u] ? fr[u] : 0.0f;
-        mk[u] = ok[u] ? m : 0;
-    }
 }
 
 // sigma_b = sum of the b-terms phi_kv m_k over one side, the a/b decision,
 // and for the b-part the topic whose running sum first exceeds
 // y = u_sigma - sigma_a (Section 3.5).  Returns the topic, or -1 for the
 // a-part (the caller takes the word's alias draw).
-template <int G, bool DOC, typename CT>
-__device__ __forceinline__ int32_t b_part(const DevModel &M, const TokenIn &tk, DocState<CT> &S, const int g,
-                                          const int log2c)
+//
+// Both sides run the same instructions (groups of one wave that chose
+// different sides do not diverge): entry e of the lane's block gives the
+// topic k = ksrc[e] (the LDS list through a generic pointer, or the CSC
+// topics) and phi = fsrc[by_k ? k : e] (the word's dense column, or the CSC
+// values).  Every slot loads from a valid address (padding slots read entry
+// `pad`) and its count is zeroed, so all loads of a round are in flight
+// together.
+template <int G, typename CT>
+__device__ __forceinline__ void lane_terms(const uint16_t *ksrc, const float *fsrc, const bool by_k, const CT *mt,
+                                           const int32_t pad, const int32_t first, const int32_t base,
+                                           const int32_t nl, int32_t (&kk)[KEEP], float (&fk)[KEEP],
+                                           int32_t (&mk)[KEEP])
+{
+    int32_t e[KEEP];
+    bool ok[KEEP];
+#pragma unroll
+    for (int u = 0; u < KEEP; ++u) {
+        ok[u] = base + u < nl;
+        e[u] = ok[u] ? first + base + u : pad;
+        kk[u] = ksrc[e[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < KEEP; ++u) {
+        fk[u] = fsrc[by_k ? kk[u] : e[u]];
+        const int32_t m = mt[kk[u]];
+        mk[u] = ok[u] ? m : 0;
+    }
+}
+
+template <int G, typename CT>
+__device__ __forceinline__ int32_t b_part(const DevModel &M, const TokenIn &tk, DocState<CT> &S, const bool doc,
+                                          const int g, const int log2c)
 {
     constexpr int LG = log2g<G>();
-    const float *pcol = M.phid + (uint32_t)tk.v * (uint32_t)M.K;
-    int32_t nl, first;
-    if constexpr (DOC) {
-        if (S.stale) rebuild_list<G, CT>(S, g, log2c);
-        const int32_t q = (S.L + G - 1) >> LG;
-        first = g * q;
-        nl = S.L - first < q ? S.L - first : q;
-    } else {
-        const int32_t Kv = tk.kv;
-        const int32_t q = (Kv + G - 1) >> LG;
-        first = tk.cb + g * q;
-        nl = Kv - g * q < q ? Kv - g * q : q;
-    }
+    const int32_t J = doc ? S.L : (int32_t)tk.kv;
+    const int32_t q = (J + G - 1) >> LG;
+    int32_t nl = J - g * q < q ? J - g * q : q;
     nl = nl > 0 ? nl : 0;
+    const uint16_t *ksrc = doc ? (const uint16_t *)S.lst : M.ctopic;
+    const float *fsrc = doc ? M.phid + (uint32_t)tk.v * (uint32_t)M.K : M.cphi;
+    const int32_t pad = doc ? 0 : tk.cb;
+    const int32_t first = pad + g * q;
     int32_t kk[KEEP], mk[KEEP];
     float fk[KEEP];
-    lane_terms<G, DOC, CT>(M, pcol, S.mt, S.lst, tk.cb, first, 0, nl, log2c, kk, fk, mk);
+    lane_terms<G, CT>(ksrc, fsrc, doc, S.mt, pad, first, 0, nl, kk, fk, mk);
     double p = 0.0;
 #pragma unroll
-    for (int u = 0; u < KEEP; ++u) p += (double)fk[u] * (double)mk[u];
+    for (int u = 0; u < KEEP; ++u) p = __builtin_fma((double)fk[u], (double)mk[u], p);
     for (int32_t base = KEEP; base < nl; base += KEEP) {
         int32_t k2[KEEP], m2[KEEP];
         float f2[KEEP];
-        lane_terms<G, DOC, CT>(M, pcol, S.mt, S.lst, tk.cb, first, base, nl, log2c, k2, f2, m2);
+        lane_terms<G, CT>(ksrc, fsrc, doc, S.mt, pad, first, base, nl, k2, f2, m2);
 #pragma unroll
-        for (int u = 0; u < KEEP; ++u) p += (double)f2[u] * (double)m2[u];
+        for (int u = 0; u < KEEP; ++u) p = __builtin_fma((double)f2[u], (double)m2[u], p);
     }
+    // the products phi * m are exact in fp64, so each fma rounds exactly
+    // like the sum of the product
     const double incl = group_scan_incl<G>(p);
     const double T = group_bcast_f64<G>(incl, G - 1);
     const double Z = tk.sa + T;
@@ -706,7 +686,7 @@ __device__ __forceinline__ int32_t b_part(const DevModel &M, const TokenIn &tk, 
             for (int32_t base = 0; base < nl && kf < 0; base += KEEP) {
                 int32_t k2[KEEP], m2[KEEP];
                 float f2[KEEP];
-                lane_terms<G, DOC, CT>(M, pcol, S.mt, S.lst, tk.cb, first, base, nl, log2c, k2, f2, m2);
+                lane_terms<G, CT>(ksrc, fsrc, doc, S.mt, pad, first, base, nl, k2, f2, m2);
 #pragma unroll
                 for (int u = 0; u < KEEP; ++u) {
                     const double bv = (double)f2[u] * (double)m2[u];
@@ -729,17 +709,15 @@ template <int G, typename CT>
 __device__ __forceinline__ int32_t draw_token(const DevModel &M, const TokenIn &tk, DocState<CT> &S, const int g,
                                               const int log2c, const int32_t side_ratio, ZCount &cnt)
 {
-    constexpr int LG = log2g<G>();
     const int32_t C = 1 << log2c;
     CT *mt = S.mt;
     // m^{-i}: remove the token from its document's counts
     const int32_t kold = tk.kold;
     const int32_t ob = kold & (C - 1), oo = kold >> log2c;
-    const int32_t oslot = (ob << LG) + oo;
-    const int32_t mo = mt[oslot];
+    const int32_t mo = mt[kold];
     __builtin_amdgcn_wave_barrier();
     if (g == oo) {
-        mt[oslot] = (CT)(mo - 1);
+        mt[kold] = (CT)(mo - 1);
         if (mo == 1) S.nz &= ~(1ull << ob);
     }
     if (mo == 1) --S.Kd;
@@ -748,7 +726,7 @@ __device__ __forceinline__ int32_t draw_token(const DevModel &M, const TokenIn &
     if (Kv == 0) {
         // 0/0 conditional: the token keeps its topic
         if (g == oo) {
-            mt[oslot] = (CT)mo;
+            mt[kold] = (CT)mo;
             if (mo == 1) S.nz |= 1ull << ob;
         }
         if (mo == 1) ++S.Kd;
@@ -763,9 +741,9 @@ __device__ __forceinline__ int32_t draw_token(const DevModel &M, const TokenIn &
     // contiguously while the document side gathers single phi values from
     // the dense column, so the column side is preferred up to side_ratio
     // times the document's topic count.
-    int32_t knew;
-    if (Kd == 0 || Kv > side_ratio * Kd) knew = b_part<G, true, CT>(M, tk, S, g, log2c);
-    else knew = b_part<G, false, CT>(M, tk, S, g, log2c);
+    const bool doc = Kd == 0 || Kv > side_ratio * Kd;
+    if (doc && S.stale) rebuild_list<G, CT>(S, g, log2c);
+    int32_t knew = b_part<G, CT>(M, tk, S, doc, g, log2c);
     if (knew < 0) {
         // a-part: the word's alias table over alpha_k phi_kv (drawn when the
         // token was staged)
@@ -774,12 +752,11 @@ __device__ __forceinline__ int32_t draw_token(const DevModel &M, const TokenIn &
     }
     // add the token back with its new topic
     const int32_t nb = knew & (C - 1), no = knew >> log2c;
-    const int32_t nslot = (nb << LG) + no;
-    const int32_t mn = mt[nslot];
+    const int32_t mn = mt[knew];
     __builtin_amdgcn_wave_barrier();
     bool fresh = false;
     if (g == no) {
-        mt[nslot] = (CT)(mn + 1);
+        mt[knew] = (CT)(mn + 1);
         if (mn == 0) {
             S.nz |= 1ull << nb;
             fresh = !((S.inl >> nb) & 1ull);
@@ -805,16 +782,29 @@ __device__ __forceinline__ void load_doc_counts(DocState<CT> &S, const uint16_t 
     const int32_t C = 1 << log2c;
     uint32_t *w32 = (uint32_t *)S.mt;
     for (int32_t i = g; i < C * G / PER_WORD; i += G) w32[i] = 0;
+    if (g == 0) S.lst[0] = 0;
     __builtin_amdgcn_wave_barrier();
     for (int64_t i = s + g; i < e; i += G) {
-        const int32_t slot = mslot<G>(z[i], log2c);
-        atomicAdd(w32 + slot / PER_WORD, 1u << (SHIFT * (slot % PER_WORD)));
+        const int32_t k = z[i];
+        atomicAdd(w32 + k / PER_WORD, 1u << (SHIFT * (k % PER_WORD)));
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    // this lane's range: PER_WORD counters per read when the range covers
+    // whole words, else one counter at a time
     uint64_t mask = 0;
-    for (int32_t b = 0; b < C; ++b)
-        if (S.mt[(b << log2g<G>()) + g]) mask |= 1ull << b;
+    if (C >= PER_WORD) {
+        const uint32_t *own = w32 + ((g << log2c) / PER_WORD);
+        for (int32_t wd = 0; wd < C / PER_WORD; ++wd) {
+            const uint32_t x = own[wd];
+#pragma unroll
+            for (int j = 0; j < PER_WORD; ++j)
+                if ((x >> (SHIFT * j)) & ((1u << SHIFT) - 1u)) mask |= 1ull << (wd * PER_WORD + j);
+        }
+    } else {
+        for (int32_t b = 0; b < C; ++b)
+            if (S.mt[(g << log2c) + b]) mask |= 1ull << b;
+    }
     S.nz = mask;
     const int32_t tot = group_scan_incl_i32<G>(__builtin_popcountll(mask));
     S.Kd = group_bcast<G>(tot, G - 1);
@@ -910,7 +900,7 @@ __device__ void z_step_item(const ZArgs &a, const WorkItem &w, CT *wave_m, uint1
                     const bool ok = mm != 0;
                     const int b = ok ? __builtin_ctzll(mm) : 0;
                     mm &= mm - 1;
-                    v4[u] = ok ? M.lg_alpha[mt[(b << log2g<G>()) + g]] : 0.0;
+                    v4[u] = ok ? M.lg_alpha[mt[(g << log2c) + b]] : 0.0;
                 }
 #pragma unroll
                 for (int u = 0; u < KEEP; ++u) part += v4[u];
@@ -923,10 +913,10 @@ __device__ void z_step_item(const ZArgs &a, const WorkItem &w, CT *wave_m, uint1
 
 // one persistent kernel per group size and count width: waves take work
 // items from this class's queue until it is empty
-// 6 waves per SIMD (80 VGPRs): the draws are latency-bound chains, and more
-// resident groups beat the few registers spilled to reach it
+// 5 waves per SIMD (96 VGPRs): more resident groups hide the chains'
+// latency, more than 96 registers would spill in the draw loop
 template <int G, typename CT>
-__global__ void __launch_bounds__(256, 6) z_step_kernel(ZArgs a)
+__global__ void __launch_bounds__(256, 5) z_step_kernel(ZArgs a)
 {
     extern __shared__ __align__(16) uint8_t z_lds[];
     const int wave = threadIdx.x >> 6;
@@ -1421,7 +1411,7 @@ __device__ void foldin_slot(const DevModel &M, const DevFoldin &F, int32_t sid, 
         if (s > F.burn_in) {
             for (int32_t b = 0; b < C; ++b) {
                 const int32_t k = (g << log2c) + b;
-                if (k < K) acc[k] += mt[b * G + g];
+                if (k < K) acc[k] += mt[k];
             }
         }
     }
@@ -1436,7 +1426,7 @@ __device__ void foldin_slot(const DevModel &M, const DevFoldin &F, int32_t sid, 
         for (int32_t q = g; q < kept; q += G) part += log((double)M.phid[(int64_t)wds[pos[q]] * K + zz[q]]);
         for (int32_t b = 0; b < C; ++b) {
             const int32_t k = (g << log2c) + b;
-            const int32_t c = mt[b * G + g];
+            const int32_t c = mt[k];
             if (k < K && c > 0) {
                 if constexpr (SYM) part += M.lg_alpha[c];
                 else part += lgamma((double)c + M.alpha[k]) - lgamma(M.alpha[k]);
