@@ -132,11 +132,12 @@ struct pulda_plan {
     uint8_t *ws = nullptr;
     int64_t ws_need = 0;
     struct {
-        int64_t z, n, gam, phid, colcnt, colptr, ctopic, cphi, calias, sigma_a, S, nk, alpha, pois, pois_off,
+        int64_t z, n, gam, phid, g16, Rd, ckg, colcnt, colptr, ctopic, cphi, calias, sigma_a, S, nk, alpha, pois, pois_off,
             doc_order, items, queue, stats, ll_part, ll_out, ll_hist, tptr, err, scratch, cnt_a, ptr_a, cnt_b,
             ptr_b, zsave, lg_beta, lg_alpha, lg_A, ll_doc;
     } off;
     int64_t cap = 0, items_cap = 0, hist_cap = 4096;
+    int32_t ks16 = 0;                 // row stride of the 16-bit draw table
     int32_t n_part_words = 1024, n_part_docs = 1024;
     std::vector<int32_t> pois_off_h;
     std::vector<uint64_t> pois_h;
@@ -253,10 +254,14 @@ pulda_status pulda_plan_create(const pulda_model_desc *desc, int64_t D, int64_t 
     p->off.n = L.take(VK * 4);
     p->off.gam = L.take(VK * 4);
     p->off.phid = L.take(VK * 4);
+    p->ks16 = (p->K + 63) / 64 * 64;
+    p->off.g16 = L.take((int64_t)p->V * p->ks16 * 2);
+    p->off.Rd = L.take((int64_t)p->K * 8);
     p->off.colcnt = L.take((int64_t)p->V * 4);
     p->off.colptr = L.take(((int64_t)p->V + 1) * 4);
     p->off.ctopic = L.take(p->cap * 2);
     p->off.cphi = L.take(p->cap * 4);
+    p->off.ckg = L.take(p->cap * 4);
     p->off.calias = L.take(p->cap * 8);
     p->off.sigma_a = L.take((int64_t)p->V * 8);
     p->off.S = L.take((int64_t)p->K * 8);
@@ -316,6 +321,10 @@ pulda_status pulda_plan_bind(pulda_plan *p, void *workspace_dev, int64_t bytes)
     m.gam = (int32_t *)(w + p->off.gam);
     m.S = (unsigned long long *)(w + p->off.S);
     m.phid = (float *)(w + p->off.phid);
+    m.g16 = (uint16_t *)(w + p->off.g16);
+    m.ks16 = p->ks16;
+    m.Rd = (double *)(w + p->off.Rd);
+    m.ckg = (uint32_t *)(w + p->off.ckg);
     m.colcnt = (int32_t *)(w + p->off.colcnt);
     m.colptr = (int32_t *)(w + p->off.colptr);
     m.ctopic = (uint16_t *)(w + p->off.ctopic);
@@ -821,6 +830,9 @@ pulda_status pulda_set_phi(pulda_plan *p, const pulda_phi_view *in, void *stream
     HIP_TRY(launch_import_phi(p->m, in->colptr_dev, in->topic_dev, in->phi_dev, in->alias_thr_dev,
                               in->alias_topic_dev, s));
     HIP_TRY(hipMemcpyAsync(p->m.sigma_a, in->sigma_a_dev, p->V * 8, hipMemcpyDeviceToDevice, s));
+    // values without draws behind them: R_k = 0 keeps 0 * R_k finite for the
+    // zero cells (every nonzero cell is read from phid)
+    HIP_TRY(launch_fill_u64((unsigned long long *)p->m.Rd, 0ull, p->K, s));
     p->have_phi = true;
     return PULDA_OK;
 }

@@ -21,10 +21,21 @@ struct DevModel {
     int32_t *gam;                 // [V*K] Poisson draws, word-major dense
     unsigned long long *S;        // [K] row sums
     float *phid;                  // [V*K] dense phi, word-major
+    // 16-bit copy of gam for the z-step's document-side gathers, word-major
+    // with row stride ks16 (K rounded up to 64: 128-byte aligned rows).
+    // phi_kv is recovered as fp32(gam_kv * R_k) with R_k = RN64(1 / S_k):
+    // for gam < 2^16 and S_k < 2^27 no fp32 rounding midpoint lies within
+    // the product's error of gam / S_k, so this equals fp32(RN64(gam / S_k))
+    // bit for bit.  Every other nonzero cell (gam >= 0xFFFF, S_k >= 2^27, or
+    // a Phi loaded from values) holds 0xFFFF and is read from phid.
+    uint16_t *g16;
+    int32_t ks16;
+    double *Rd;                   // [K] RN64(1 / S_k) (0 for an empty row)
     int32_t *colcnt;              // [V]
     int32_t *colptr;              // [V+1]
     uint16_t *ctopic;             // [cap] CSC by word, ascending topic
     float *cphi;                  // [cap]
+    uint32_t *ckg;                // [cap] topic | 16-bit draw << 16 (as g16)
     uint64_t *calias;             // [cap] thr | topic << 32 | alias_topic << 48
     double *sigma_a;              // [V]
     const uint64_t *pois;         // Poisson alias tables, thr | x_alias << 32

@@ -370,18 +370,23 @@ __global__ void __launch_bounds__(64) phi_fill_kernel(DevModel m, int32_t kpad)
     const int32_t cb = m.colptr[v];
     const int32_t *gcol = m.gam + (int64_t)v * K;
     float *pcol = m.phid + (int64_t)v * K;
+    uint16_t *g16col = m.g16 + (int64_t)v * m.ks16;
     int32_t run = 0;
-    for (int32_t k0 = 0; k0 < K; k0 += 64) {
+    for (int32_t k0 = 0; k0 < m.ks16; k0 += 64) {
         const int32_t k = k0 + lane;
         int32_t x = k < K ? gcol[k] : 0;
         float f = 0.0f;
         if (x > 0) f = (float)((double)x / (double)m.S[k]);
         if (k < K) pcol[k] = f;
+        const bool exact = x < 0xFFFF && (k >= K || m.S[k] < (1ull << 27));
+        const uint32_t x16 = exact ? (uint32_t)x : 0xFFFFu;
+        g16col[k] = (uint16_t)x16;
         const uint64_t bal = __builtin_amdgcn_ballot_w64(x > 0);
         if (x > 0) {
             const int32_t e = run + __builtin_popcountll(bal & ((1ull << lane) - 1ull));
             m.ctopic[cb + e] = (uint16_t)k;
             m.cphi[cb + e] = f;
+            m.ckg[cb + e] = (uint32_t)k | (x16 << 16);
             tk[e] = (uint16_t)k;
             w[e] = m.alpha[k] * (double)f;
         }
@@ -456,13 +461,16 @@ __global__ void __launch_bounds__(64) phi_fill_kernel(DevModel m, int32_t kpad)
 }
 
 __global__ void colptr_finish_kernel(const unsigned long long *S, int32_t K, const long long *total,
-                                     unsigned long long *stats)
+                                     unsigned long long *stats, double *Rd)
 {
     if (threadIdx.x == 0 && stats) {
         stats[ST_NNZ_PHI] = (unsigned long long)*total;
     }
     unsigned long long empty = 0;
-    for (int32_t k = threadIdx.x; k < K; k += blockDim.x) empty += S[k] == 0;
+    for (int32_t k = threadIdx.x; k < K; k += blockDim.x) {
+        empty += S[k] == 0;
+        Rd[k] = S[k] ? 1.0 / (double)S[k] : 0.0;
+    }
     for (int o = 32; o > 0; o >>= 1) empty += __shfl_down(empty, o, 64);
     if ((threadIdx.x & 63) == 0 && empty && stats) atomicAdd(&stats[ST_EMPTY_ROWS], empty);
 }
@@ -482,8 +490,8 @@ hipError_t launch_phi_step(const DevModel &m, unsigned long long *stats, hipStre
     if (stats) {
         e = launch_fill_u64(&stats[ST_EMPTY_ROWS], 0ull, 1, s);
         if (e != hipSuccess) return e;
-        colptr_finish_kernel<<<1, 256, 0, s>>>(m.S, m.K, total, stats);
     }
+    colptr_finish_kernel<<<1, 256, 0, s>>>(m.S, m.K, total, stats, m.Rd);
     const size_t lds = (size_t)kpad * (sizeof(double) + 4 * sizeof(uint16_t) + sizeof(uint32_t));
     phi_fill_kernel<<<m.V, 64, lds, s>>>(m, kpad);
     return hipGetLastError();
@@ -513,6 +521,7 @@ struct ZArgs {
     int32_t m_bytes_per_wave;  // bytes of count tables per wave
     int32_t lcap;              // topic-list entries per group
     int32_t wave_bytes;        // count tables and topic lists of one wave
+    int32_t r_bytes;           // the block's copy of R_k, at the start of LDS
     int32_t *queue;
     unsigned long long *stats;
     double *ll_doc;         // per-document log-joint terms (or null)
@@ -590,63 +599,84 @@ __device__ __forceinline__ void rebuild_list(DocState<CT> &S, int g, int log2c)
     __builtin_amdgcn_wave_barrier();
 }
 
+// up to KEEP b-terms of this lane: entries first + base + u (u < KEEP) of its
+// block, which has nl entries: topic, phi and m_d of each (count zeroed
+// past the end).  DOC: the block is in the document's topic list (LDS) and
+// the draw is gathered from the word's dense 16-bit column; otherwise the
+// block is of the word's packed CSC entries (topic | draw << 16), read
+// contiguously.  R (LDS) holds R_k.  Every slot loads from a valid address
+// (padding slots read entry `pad`), so all loads of a round are in flight
+// together.
+template <int G, bool DOC, typename CT>
+__device__ __forceinline__ void lane_terms(const DevModel &M, const uint16_t *lst, const uint16_t *g16col,
+                                           const float *pcol, const double *R, const CT *mt, const int32_t pad,
+                                           const int32_t first, const int32_t base, const int32_t nl,
+                                           int32_t (&kk)[KEEP], float (&fk)[KEEP], int32_t (&mk)[KEEP])
+{
+    bool ok[KEEP];
+    uint32_t x[KEEP];
+#pragma unroll
+    for (int u = 0; u < KEEP; ++u) {
+        ok[u] = base + u < nl;
+        const uint32_t e = (uint32_t)(ok[u] ? first + base + u : pad);
+        if constexpr (DOC) {
+            kk[u] = lst[e];
+        } else {
+            const uint32_t kg = M.ckg[e];
+            kk[u] = (int32_t)(kg & 0xFFFFu);
+            x[u] = kg >> 16;
+        }
+    }
+    if constexpr (DOC) {
+#pragma unroll
+        for (int u = 0; u < KEEP; ++u) x[u] = g16col[(uint32_t)kk[u]];
+    }
+    // phi_kv = fp32(x * R_k) == fp32(RN64(x / S_k)) for x < 2^16 and
+    // S_k < 2^27; every other nonzero cell carries 0xFFFF and its phi is
+    // read from the dense table (rare: one wave-uniform test per round)
+    bool esc = false;
+#pragma unroll
+    for (int u = 0; u < KEEP; ++u) {
+        const double r = R[kk[u]];
+        const int32_t m = mt[kk[u]];
+        fk[u] = (float)((double)x[u] * r);
+        esc |= x[u] == 0xFFFFu;
+        mk[u] = ok[u] ? m : 0;
+    }
+    if (__builtin_amdgcn_ballot_w64(esc)) {
+#pragma unroll
+        for (int u = 0; u < KEEP; ++u)
+            if (x[u] == 0xFFFFu) fk[u] = pcol[kk[u]];
+    }
+}
+
 // sigma_b = sum of the b-terms phi_kv m_k over one side, the a/b decision,
 // and for the b-part the topic whose running sum first exceeds
 // y = u_sigma - sigma_a (Section 3.5).  Returns the topic, or -1 for the
 // a-part (the caller takes the word's alias draw).
-//
-// Both sides run the same instructions (groups of one wave that chose
-// different sides do not diverge): entry e of the lane's block gives the
-// topic k = ksrc[e] (the LDS list through a generic pointer, or the CSC
-// topics) and phi = fsrc[by_k ? k : e] (the word's dense column, or the CSC
-// values).  Every slot loads from a valid address (padding slots read entry
-// `pad`) and its count is zeroed, so all loads of a round are in flight
-// together.
-template <int G, typename CT>
-__device__ __forceinline__ void lane_terms(const uint16_t *ksrc, const float *fsrc, const bool by_k, const CT *mt,
-                                           const int32_t pad, const int32_t first, const int32_t base,
-                                           const int32_t nl, int32_t (&kk)[KEEP], float (&fk)[KEEP],
-                                           int32_t (&mk)[KEEP])
-{
-    int32_t e[KEEP];
-    bool ok[KEEP];
-#pragma unroll
-    for (int u = 0; u < KEEP; ++u) {
-        ok[u] = base + u < nl;
-        e[u] = ok[u] ? first + base + u : pad;
-        kk[u] = ksrc[e[u]];
-    }
-#pragma unroll
-    for (int u = 0; u < KEEP; ++u) {
-        fk[u] = fsrc[by_k ? kk[u] : e[u]];
-        const int32_t m = mt[kk[u]];
-        mk[u] = ok[u] ? m : 0;
-    }
-}
-
-template <int G, typename CT>
-__device__ __forceinline__ int32_t b_part(const DevModel &M, const TokenIn &tk, DocState<CT> &S, const bool doc,
-                                          const int g, const int log2c)
+template <int G, bool DOC, typename CT>
+__device__ __forceinline__ int32_t b_part(const DevModel &M, const TokenIn &tk, DocState<CT> &S, const double *R,
+                                          const int g)
 {
     constexpr int LG = log2g<G>();
-    const int32_t J = doc ? S.L : (int32_t)tk.kv;
+    const int32_t J = DOC ? S.L : (int32_t)tk.kv;
     const int32_t q = (J + G - 1) >> LG;
     int32_t nl = J - g * q < q ? J - g * q : q;
     nl = nl > 0 ? nl : 0;
-    const uint16_t *ksrc = doc ? (const uint16_t *)S.lst : M.ctopic;
-    const float *fsrc = doc ? M.phid + (uint32_t)tk.v * (uint32_t)M.K : M.cphi;
-    const int32_t pad = doc ? 0 : tk.cb;
+    const uint16_t *g16col = M.g16 + (uint32_t)tk.v * (uint32_t)M.ks16;
+    const float *pcol = M.phid + (uint32_t)tk.v * (uint32_t)M.K;
+    const int32_t pad = DOC ? 0 : tk.cb;
     const int32_t first = pad + g * q;
     int32_t kk[KEEP], mk[KEEP];
     float fk[KEEP];
-    lane_terms<G, CT>(ksrc, fsrc, doc, S.mt, pad, first, 0, nl, kk, fk, mk);
+    lane_terms<G, DOC, CT>(M, S.lst, g16col, pcol, R, S.mt, pad, first, 0, nl, kk, fk, mk);
     double p = 0.0;
 #pragma unroll
     for (int u = 0; u < KEEP; ++u) p = __builtin_fma((double)fk[u], (double)mk[u], p);
     for (int32_t base = KEEP; base < nl; base += KEEP) {
         int32_t k2[KEEP], m2[KEEP];
         float f2[KEEP];
-        lane_terms<G, CT>(ksrc, fsrc, doc, S.mt, pad, first, base, nl, k2, f2, m2);
+        lane_terms<G, DOC, CT>(M, S.lst, g16col, pcol, R, S.mt, pad, first, base, nl, k2, f2, m2);
 #pragma unroll
         for (int u = 0; u < KEEP; ++u) p = __builtin_fma((double)f2[u], (double)m2[u], p);
     }
@@ -686,7 +716,7 @@ __device__ __forceinline__ int32_t b_part(const DevModel &M, const TokenIn &tk, 
             for (int32_t base = 0; base < nl && kf < 0; base += KEEP) {
                 int32_t k2[KEEP], m2[KEEP];
                 float f2[KEEP];
-                lane_terms<G, CT>(ksrc, fsrc, doc, S.mt, pad, first, base, nl, k2, f2, m2);
+                lane_terms<G, DOC, CT>(M, S.lst, g16col, pcol, R, S.mt, pad, first, base, nl, k2, f2, m2);
 #pragma unroll
                 for (int u = 0; u < KEEP; ++u) {
                     const double bv = (double)f2[u] * (double)m2[u];
@@ -706,8 +736,8 @@ __device__ __forceinline__ int32_t b_part(const DevModel &M, const TokenIn &tk, 
 // draw one token (group-uniform control flow); returns the new topic, or
 // -1 - kold for a token whose word has an empty Phi column (it keeps kold)
 template <int G, typename CT>
-__device__ __forceinline__ int32_t draw_token(const DevModel &M, const TokenIn &tk, DocState<CT> &S, const int g,
-                                              const int log2c, const int32_t side_ratio, ZCount &cnt)
+__device__ __forceinline__ int32_t draw_token(const DevModel &M, const TokenIn &tk, DocState<CT> &S, const double *R,
+                                              const int g, const int log2c, const int32_t side_ratio, ZCount &cnt)
 {
     const int32_t C = 1 << log2c;
     CT *mt = S.mt;
@@ -738,12 +768,21 @@ __device__ __forceinline__ int32_t draw_token(const DevModel &M, const TokenIn &
     cnt.J += (unsigned long long)(Kd < Kv ? Kd : Kv);
     // b-terms over one side: the document's topics (lst) or the word's Phi
     // column, ascending topic order either way.  The column is read
-    // contiguously while the document side gathers single phi values from
-    // the dense column, so the column side is preferred up to side_ratio
-    // times the document's topic count.
-    const bool doc = Kd == 0 || Kv > side_ratio * Kd;
-    if (doc && S.stale) rebuild_list<G, CT>(S, g, log2c);
-    int32_t knew = b_part<G, CT>(M, tk, S, doc, g, log2c);
+    // contiguously while the document side gathers single draws from the
+    // dense column, so a group prefers the column side up to side_ratio
+    // times the document's topic count.  The side is taken for the whole
+    // wave (the document side if any of its groups prefers it: a frequent
+    // word's column is long, a document's topic list is not), so the
+    // wave's groups do not diverge; the side changes cost, not the law.
+    const bool prefer_doc = Kd == 0 || Kv > side_ratio * Kd;
+    const bool doc = __builtin_amdgcn_ballot_w64(prefer_doc) != 0;
+    int32_t knew;
+    if (doc) {
+        if (S.stale) rebuild_list<G, CT>(S, g, log2c);
+        knew = b_part<G, true, CT>(M, tk, S, R, g);
+    } else {
+        knew = b_part<G, false, CT>(M, tk, S, R, g);
+    }
     if (knew < 0) {
         // a-part: the word's alias table over alpha_k phi_kv (drawn when the
         // token was staged)
@@ -841,8 +880,8 @@ __device__ __forceinline__ void stage_token(const DevModel &M, TokenIn *tok, int
 }
 
 template <int G, typename CT>
-__device__ void z_step_item(const ZArgs &a, const WorkItem &w, CT *wave_m, uint16_t *wave_lst, TokenIn *wave_tok,
-                            ZCount &cnt)
+__device__ void z_step_item(const ZArgs &a, const WorkItem &w, const double *R, CT *wave_m, uint16_t *wave_lst,
+                            TokenIn *wave_tok, ZCount &cnt)
 {
     constexpr int NG = 64 / G;
     const int lane = __lane_id();
@@ -880,7 +919,7 @@ __device__ void z_step_item(const ZArgs &a, const WorkItem &w, CT *wave_m, uint1
             const int nb = (int)((e - i0) < G ? (e - i0) : G);
             for (int jj = 0; jj < nb; ++jj) {
                 const TokenIn tk = tok[jj];
-                int32_t k = draw_token<G, CT>(M, tk, S, g, log2c, w.side_ratio, cnt);
+                int32_t k = draw_token<G, CT>(M, tk, S, R, g, log2c, w.side_ratio, cnt);
                 if (k < 0) k = -1 - k;
                 if (g == 0) atomicAdd(&M.n[(uint32_t)tk.v * (uint32_t)M.K + (uint32_t)k], 1);
                 if (g == jj) znew = k;
@@ -919,11 +958,15 @@ template <int G, typename CT>
 __global__ void __launch_bounds__(256, 5) z_step_kernel(ZArgs a)
 {
     extern __shared__ __align__(16) uint8_t z_lds[];
+    double *R = (double *)z_lds;
+    for (int32_t k = threadIdx.x; k < a.m.K; k += blockDim.x) R[k] = a.m.Rd[k];
+    __syncthreads();
     const int wave = threadIdx.x >> 6;
-    uint8_t *wave_base = z_lds + wave * a.wave_bytes;
+    uint8_t *blk = z_lds + a.r_bytes;
+    uint8_t *wave_base = blk + wave * a.wave_bytes;
     CT *wave_m = (CT *)wave_base;
     uint16_t *wave_lst = (uint16_t *)(wave_base + a.m_bytes_per_wave);
-    TokenIn *wave_tok = (TokenIn *)(z_lds + 4 * a.wave_bytes) + wave * 64;
+    TokenIn *wave_tok = (TokenIn *)(blk + 4 * a.wave_bytes) + wave * 64;
     ZCount cnt = {0, 0, 0};
     while (true) {
         int item = 0;
@@ -933,7 +976,7 @@ __global__ void __launch_bounds__(256, 5) z_step_kernel(ZArgs a)
         // a private copy: a reference into global memory would be reloaded
         // after every store of the item (stores may alias it)
         const WorkItem w = a.items[item];
-        z_step_item<G, CT>(a, w, wave_m, wave_lst, wave_tok, cnt);
+        z_step_item<G, CT>(a, w, R, wave_m, wave_lst, wave_tok, cnt);
     }
     // every lane of a group counted the group's tokens; its first lane reports
     if (a.stats && (__lane_id() & (G - 1)) == 0) {
@@ -998,7 +1041,8 @@ hipError_t launch_z_class(const DevCorpus &c, const DevModel &m, int32_t group, 
     // a document's topic list holds at most min(K, its length - 1) topics
     a.lcap = narrow ? (m.K < 255 ? m.K : 255) : m.K;
     a.wave_bytes = (a.m_bytes_per_wave + (64 / group) * a.lcap * 2 + 15) / 16 * 16;
-    const size_t lds = 4 * ((size_t)a.wave_bytes + 64 * sizeof(TokenIn));
+    a.r_bytes = (m.K * 8 + 15) / 16 * 16;
+    const size_t lds = (size_t)a.r_bytes + 4 * ((size_t)a.wave_bytes + 64 * sizeof(TokenIn));
     auto launch = [&](auto kernel) -> hipError_t {
         // persistent: exactly the blocks the device holds at once, and no
         // more waves than work items (a wave takes one item at a time)
@@ -1207,14 +1251,19 @@ __global__ void import_phi_kernel(DevModel m, const int64_t *colptr64, const uin
         if (v == m.V - 1) m.colptr[m.V] = (int32_t)b;
     }
     float *pcol = m.phid + (int64_t)v * m.K;
+    uint16_t *g16col = m.g16 + (int64_t)v * m.ks16;
     for (int32_t k = lane; k < m.K; k += 64) pcol[k] = 0.0f;
+    for (int32_t k = lane; k < m.ks16; k += 64) g16col[k] = 0;
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    // values without draws behind them: every nonzero cell is read from phid
     for (int64_t e = a + lane; e < b; e += 64) {
         const int32_t k = topic[e];
         m.ctopic[e] = (uint16_t)k;
         m.cphi[e] = phi_e[e];
+        m.ckg[e] = (uint32_t)k | (0xFFFFu << 16);
         pcol[k] = phi_e[e];
+        g16col[k] = 0xFFFF;
         m.calias[e] = (uint64_t)thr[e] | ((uint64_t)k << 32) | ((uint64_t)alias_topic[e] << 48);
     }
 }
@@ -1338,8 +1387,8 @@ hipError_t launch_scan_i64(const int64_t *in, int64_t *out_excl, int64_t n, long
 // the log-likelihood of the final state.
 // ---------------------------------------------------------------------------
 template <int G, bool SYM>
-__device__ void foldin_slot(const DevModel &M, const DevFoldin &F, int32_t sid, uint16_t *mt, TokenIn *tok,
-                            int log2c)
+__device__ void foldin_slot(const DevModel &M, const DevFoldin &F, int32_t sid, const double *R, uint16_t *mt,
+                            TokenIn *tok, int log2c)
 {
     DocState<uint16_t> S;
     S.mt = mt;
@@ -1401,7 +1450,7 @@ __device__ void foldin_slot(const DevModel &M, const DevFoldin &F, int32_t sid, 
             const int nb = (kept - q0) < G ? (kept - q0) : G;
             for (int jj = 0; jj < nb; ++jj) {
                 const TokenIn tk = tok[jj];
-                int32_t k = draw_token<G, uint16_t>(M, tk, S, g, log2c, 1, st);
+                int32_t k = draw_token<G, uint16_t>(M, tk, S, R, g, log2c, 1, st);
                 if (k < 0) k = -1 - k;
                 if (g == jj) znew = k;
             }
@@ -1442,17 +1491,22 @@ __global__ void __launch_bounds__(256) foldin_step_kernel(DevModel M, DevFoldin 
                                                           int32_t n_active, int32_t log2c, int32_t per_group)
 {
     extern __shared__ __align__(16) uint16_t f_lds[];
+    // the block's copy of R_k, then the groups' tables, then staged tokens
+    double *R = (double *)f_lds;
+    for (int32_t k = threadIdx.x; k < M.K; k += blockDim.x) R[k] = M.Rd[k];
+    __syncthreads();
+    uint16_t *blk = f_lds + (M.K * 8 + 15) / 16 * 8;
     const int lane = __lane_id();
     const int wave = threadIdx.x >> 6;
     constexpr int gsz = G;
     const int grp = lane / gsz;
     const int ngw = 64 / gsz;
     const int64_t gid = ((int64_t)blockIdx.x * 4 + wave) * ngw + grp;
-    uint16_t *mt = f_lds + (wave * ngw + grp) * per_group;
-    TokenIn *tok = (TokenIn *)(f_lds + 4 * ngw * per_group) + wave * 64 + grp * gsz;
+    uint16_t *mt = blk + (wave * ngw + grp) * per_group;
+    TokenIn *tok = (TokenIn *)(blk + 4 * ngw * per_group) + wave * 64 + grp * gsz;
     if (gid >= n_active) return;
     const int32_t sid = active[gid];
-    foldin_slot<G, SYM>(M, F, sid, mt, tok, log2c);
+    foldin_slot<G, SYM>(M, F, sid, R, mt, tok, log2c);
 }
 
 hipError_t launch_foldin_step(const DevModel &m, const DevFoldin &f, const int32_t *active, int32_t n_active,
@@ -1466,7 +1520,8 @@ hipError_t launch_foldin_step(const DevModel &m, const DevFoldin &f, const int32
     const int ngw = 64 / f.group;
     const int64_t waves = (n_active + ngw - 1) / ngw;
     const unsigned blocks = (unsigned)((waves + 3) / 4);
-    const size_t lds = 4 * ngw * per_group * sizeof(uint16_t) + 4 * 64 * sizeof(TokenIn);
+    const size_t lds = (size_t)(m.K * 8 + 15) / 16 * 16 + 4 * ngw * per_group * sizeof(uint16_t) +
+                       4 * 64 * sizeof(TokenIn);
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, foldin_step_kernel<64, true>, 256, lds);
     if (e != hipSuccess) return e;
