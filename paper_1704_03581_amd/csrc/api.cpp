@@ -161,7 +161,7 @@ struct pulda_plan {
     int32_t n_items = 0;
     // work-item classes: (group size, count width) = (64, 16-bit), (32, 16),
     // (32, 8), (16, 16), (16, 8); 8-bit counts serve documents under 256 tokens
-    static constexpr int NCLS = 5;
+    static constexpr int NCLS = 6;
     int32_t cls_first[NCLS] = {}, cls_count[NCLS] = {};
     int32_t n_cu = 0;                 // compute units of the device
     // internal streams: the three group-size kernels of a z-step run
@@ -408,34 +408,28 @@ static hipError_t phase_event(pulda_plan *p, hipStream_t s, size_t *idx)
     return hipEventRecord(p->ev_pool[*idx], s);
 }
 
-// smallest group size whose lanes can own all K topics with <= 64 topics each
-static int32_t min_group(int32_t K)
+// a z-step class fits when one wave's count tables, topic lists and staged
+// tokens take at most 32 KB of LDS (groups of 8 only for documents shorter
+// than 256 tokens)
+static bool class_fits(int32_t g, bool narrow, int32_t K)
 {
-    for (int32_t g : {16, 32, 64})
-        if ((int64_t)g * 64 >= K) return g;
-    return 64;
+    if (g == 8 && !narrow) return false;
+    return z_layout(g, narrow, K).wave_bytes + 64 * 32 <= 32 * 1024;
 }
 
-static const int32_t kClassGroup[5] = {64, 32, 32, 16, 16};
-static const bool kClassNarrow[5] = {false, false, true, false, true};
+static const int32_t kClassGroup[pulda_plan::NCLS] = {64, 32, 32, 16, 16, 8};
+static const bool kClassNarrow[pulda_plan::NCLS] = {false, false, true, false, true, true};
 
 static int item_class(int32_t g, bool narrow)
 {
     if (g == 64) return 0;
     if (g == 32) return narrow ? 2 : 1;
-    return narrow ? 4 : 3;
+    if (g == 16) return narrow ? 4 : 3;
+    return 5;
 }
 
 static pulda_status build_items(pulda_plan *p)
 {
-    const int32_t gmin = min_group(p->K);
-    for (size_t b = 0; b < p->group.size(); ++b) {
-        if (p->group[b] < gmin) {
-            const int32_t per_group = p->dpi[b] / (64 / p->group[b]);
-            p->group[b] = gmin;
-            p->dpi[b] = std::max(1, per_group) * (64 / gmin);
-        }
-    }
     // items grouped by group size (64, 32, 16); within a group size in
     // decreasing document length (longest first)
     std::vector<WorkItem> cls[pulda_plan::NCLS];
@@ -449,10 +443,13 @@ static pulda_status build_items(pulda_plan *p)
             WorkItem w;
             w.first = (int32_t)s;
             w.count = (int32_t)std::min<int64_t>(per, pos - s);
-            w.group = p->group[b];
             w.side_ratio = p->side[b];
             // documents are in decreasing length: the first is the longest
             const bool narrow = p->len_sorted[s] < 256;
+            // the bucket's group size, or the next larger one that fits
+            int32_t g = p->group[b];
+            while (g < 64 && !class_fits(g, narrow, p->K)) g *= 2;
+            w.group = g;
             cls[item_class(w.group, narrow)].push_back(w);
         }
     }
@@ -883,14 +880,12 @@ pulda_status pulda_set_schedule(pulda_plan *p, int32_t nb, const int32_t *min_le
 {
     if (!p || nb < 1 || !min_len || !group || !dpi) return fail(PULDA_ERR_INVALID_ARG, "bad schedule");
     for (int32_t b = 0; b < nb; ++b) {
-        if (group[b] != 16 && group[b] != 32 && group[b] != 64)
-            return fail(PULDA_ERR_INVALID_ARG, "group size %d not in {16, 32, 64}", group[b]);
+        if (group[b] != 8 && group[b] != 16 && group[b] != 32 && group[b] != 64)
+            return fail(PULDA_ERR_INVALID_ARG, "group size %d not in {8, 16, 32, 64}", group[b]);
         if (dpi[b] < 1 || dpi[b] % (64 / group[b])) return fail(PULDA_ERR_INVALID_ARG, "docs per item %d", dpi[b]);
         if (b > 0 && min_len[b] >= min_len[b - 1]) return fail(PULDA_ERR_INVALID_ARG, "min_len must decrease");
         if (side_ratio && (side_ratio[b] < 1 || side_ratio[b] > 1024))
             return fail(PULDA_ERR_INVALID_ARG, "side ratio %d outside 1..1024", side_ratio[b]);
-        if ((1 << (int)std::ceil(std::log2((double)((p->K + group[b] - 1) / group[b])))) > 64)
-            return fail(PULDA_ERR_INVALID_ARG, "group %d too small for K=%d", group[b], p->K);
     }
     if (min_len[nb - 1] != 0) return fail(PULDA_ERR_INVALID_ARG, "last bucket must start at length 0");
     p->min_len.assign(min_len, min_len + nb);
@@ -945,8 +940,9 @@ pulda_status pulda_autotune(pulda_plan *p, uint32_t t, int32_t reps, void *strea
         for (int64_t i = lo; i < hi; ++i) mean_len += p->len_sorted[i];
         mean_len /= (double)(hi - lo);
         float best_ms = 1e30f;
-        for (int gsz : {64, 32, 16}) {
-            if ((1 << (int)std::ceil(std::log2((double)((p->K + gsz - 1) / gsz)))) > 64) continue;
+        const bool narrow = p->len_sorted[lo] < 256;
+        for (int gsz : {64, 32, 16, 8}) {
+            if (!class_fits(gsz, narrow, p->K)) continue;
             for (int ratio : {1, 4, 16}) {
                 const int ng = 64 / gsz;
                 int per = (int)std::max(1.0, std::round(4096.0 / std::max(1.0, mean_len) / ng)) * ng;
@@ -960,7 +956,7 @@ pulda_status pulda_autotune(pulda_plan *p, uint32_t t, int32_t reps, void *strea
                     if (p->N) HIP_TRY(hipMemcpyAsync(p->c.z, p->zsave, p->N * 2, hipMemcpyDeviceToDevice, s));
                     HIP_TRY(hipEventRecord(e0, s));
                     HIP_TRY(launch_z_prepare(p->m, p->queue, nullptr, s));
-                    HIP_TRY(launch_z_class(p->c, p->m, gsz, gsz < 64 && p->len_sorted[lo] < 256, p->items,
+                    HIP_TRY(launch_z_class(p->c, p->m, gsz, gsz < 64 && narrow, p->items,
                                            (int32_t)items.size(), p->n_cu, p->queue, nullptr, nullptr, s));
                     HIP_TRY(hipEventRecord(e1, s));
                     HIP_TRY(hipEventSynchronize(e1));

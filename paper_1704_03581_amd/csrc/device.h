@@ -57,7 +57,7 @@ __device__ __forceinline__ double unit53(uint32_t ra, uint32_t rb)
 }
 
 // ---------------------------------------------------------------------------
-// Cross-lane helpers for groups of G lanes (G = 16, 32 or 64) inside a wave.
+// Cross-lane helpers for groups of G lanes (G = 8, 16, 32 or 64) inside a wave.
 // Scans use DPP row shifts within 16-lane rows and row broadcasts across
 // rows (GFX9 DPP), so a group's scan never reads another group's lanes.
 // ---------------------------------------------------------------------------
@@ -76,10 +76,22 @@ __device__ __forceinline__ double dpp_f64(double x)
     return __hiloint2double(hi, lo);
 }
 
-// inclusive prefix sum over the lanes of a group (ascending lane order)
+// inclusive prefix sum over the lanes of a group (ascending lane order);
+// a group of 8 is half a row, so its shifted-in values are dropped below
+// the shift distance
 template <int G>
 __device__ __forceinline__ double group_scan_incl(double x)
 {
+    if constexpr (G == 8) {
+        const int gi = __lane_id() & 7;
+        double y = dpp_f64<0x111, 0xF>(x);
+        x += gi >= 1 ? y : 0.0;
+        y = dpp_f64<0x112, 0xF>(x);
+        x += gi >= 2 ? y : 0.0;
+        y = dpp_f64<0x114, 0xF>(x);
+        x += gi >= 4 ? y : 0.0;
+        return x;
+    }
     x += dpp_f64<0x111, 0xF>(x);  // row_shr:1
     x += dpp_f64<0x112, 0xF>(x);  // row_shr:2
     x += dpp_f64<0x114, 0xF>(x);  // row_shr:4
@@ -92,6 +104,16 @@ __device__ __forceinline__ double group_scan_incl(double x)
 template <int G>
 __device__ __forceinline__ int group_scan_incl_i32(int x)
 {
+    if constexpr (G == 8) {
+        const int gi = __lane_id() & 7;
+        int y = dpp_i32<0x111, 0xF>(x);
+        x += gi >= 1 ? y : 0;
+        y = dpp_i32<0x112, 0xF>(x);
+        x += gi >= 2 ? y : 0;
+        y = dpp_i32<0x114, 0xF>(x);
+        x += gi >= 4 ? y : 0;
+        return x;
+    }
     x += dpp_i32<0x111, 0xF>(x);
     x += dpp_i32<0x112, 0xF>(x);
     x += dpp_i32<0x114, 0xF>(x);

@@ -66,6 +66,26 @@ struct WorkItem {
     int32_t first, count, group, side_ratio;
 };
 
+// LDS layout of one z-step class (group size, count width): per group a
+// count table (K counters of 1 or 2 bytes, rounded to 4 bytes) and the
+// document's topic list (u16; min(K, 255) entries for documents shorter
+// than 256 tokens, else K), 64/G groups per wave, and the block's copy of
+// R_k (K doubles) first
+struct ZLayout {
+    int32_t m_bytes, group_bytes, wave_bytes, r_bytes;
+};
+
+inline ZLayout z_layout(int32_t group, bool narrow, int32_t K)
+{
+    ZLayout L;
+    L.m_bytes = (K * (narrow ? 1 : 2) + 3) / 4 * 4;
+    const int32_t lcap = narrow ? (K < 255 ? K : 255) : K;
+    L.group_bytes = L.m_bytes + (lcap * 2 + 3) / 4 * 4;
+    L.wave_bytes = ((64 / group) * L.group_bytes + 15) / 16 * 16;
+    L.r_bytes = (K * 8 + 15) / 16 * 16;
+    return L;
+}
+
 // ST_TOKENS counts z-step launches since the last statistics read
 constexpr int32_t LG_TABLE = 65536;
 
@@ -86,8 +106,8 @@ hipError_t launch_phi_step(const DevModel &m, unsigned long long *stats, hipStre
 // document's term of the log joint for the state it leaves.
 hipError_t launch_z_prepare(const DevModel &m, int32_t *queues, unsigned long long *stats, hipStream_t s);
 // narrow: 8-bit document-topic counts (every document of the items is
-// shorter than 256 tokens; group 16 or 32).  The grid is as many blocks as
-// n_cu compute units hold at once.
+// shorter than 256 tokens; group 8, 16 or 32).  The grid is as many blocks
+// as n_cu compute units hold at once.
 hipError_t launch_z_class(const DevCorpus &c, const DevModel &m, int32_t group, bool narrow, const WorkItem *items,
                           int32_t n_items, int32_t n_cu, int32_t *queue, unsigned long long *stats,
                           double *ll_doc, hipStream_t s);

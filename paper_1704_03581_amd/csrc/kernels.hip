@@ -498,34 +498,35 @@ hipError_t launch_phi_step(const DevModel &m, unsigned long long *stats, hipStre
 }
 
 // ---------------------------------------------------------------------------
-// z-step (Section 3.5).  A group of G lanes (G = 16, 32, 64) owns one
+// z-step (Section 3.5).  A group of G lanes (G = 8, 16, 32, 64) owns one
 // document at a time and walks its tokens in stored order (sequential Gibbs
 // within the document).  The document-topic counts m_d live in LDS, indexed
-// by topic; lane g owns topics [g*C, (g+1)*C) (C a power of two, C*G >= K)
-// for the bookkeeping of which topics are nonzero.  For each token:
-//   sigma_b = sum_k phi_kv m_k is taken over the smaller of the document's
-//   topics (a list in LDS, phi gathered from the word's dense column) and
-//   the word's Phi column (its CSC entries, m from LDS); either way lane g
-//   takes a contiguous block of entries in ascending topic order and a
-//   group prefix sum orders the lanes, so the running sums are ascending in
-//   k as the definition requires;
+// by topic, beside lst, the document's topics with a nonzero count in
+// ascending order.  For each token:
+//   sigma_b = sum_k phi_kv m_k is taken over the document's topics (lst,
+//   phi from the word's dense column of draws) or the word's Phi column
+//   (its CSC entries, m from LDS); either way lane g takes a contiguous
+//   block of entries in ascending topic order and a group prefix sum orders
+//   the lanes, so the running sums are ascending in k as the definition
+//   requires;
 //   u_sigma = u (sigma_a + sigma_b) < sigma_a takes the word's alias draw,
 //   otherwise the crossing lane (first with prefix > u_sigma - sigma_a)
-//   walks its entries to find the topic.
+//   walks its entries to find the topic;
+//   the counts and lst are updated: a topic that leaves or enters the
+//   document moves the entries above it by one place.
 // ---------------------------------------------------------------------------
 struct ZArgs {
     DevModel m;
     DevCorpus c;
     const WorkItem *items;
     int32_t n_items;
-    int32_t m_bytes_per_wave;  // bytes of count tables per wave
-    int32_t lcap;              // topic-list entries per group
-    int32_t wave_bytes;        // count tables and topic lists of one wave
+    int32_t m_bytes;           // count table of one group
+    int32_t group_bytes;       // count table and topic list of one group
+    int32_t wave_bytes;        // the groups of one wave
     int32_t r_bytes;           // the block's copy of R_k, at the start of LDS
     int32_t *queue;
     unsigned long long *stats;
     double *ll_doc;         // per-document log-joint terms (or null)
-    int32_t log2c64, log2c32, log2c16;  // log2 of topics per lane for each group size
 };
 
 // inputs of one token draw, staged in LDS so every lane of the group reads
@@ -550,56 +551,102 @@ struct ZCount {
     unsigned long long J, A, degenerate;
 };
 
-constexpr int KEEP = 4;  // b-terms per lane kept in registers for the walk
+// b-terms per lane kept in registers for the walk: one gather round covers
+// G * keep entries
+template <int G>
+constexpr int keep_of()
+{
+    return G <= 8 ? 8 : 4;
+}
 
 template <int G>
 constexpr int log2g()
 {
-    return G == 64 ? 6 : (G == 32 ? 5 : 4);
+    return G == 64 ? 6 : (G == 32 ? 5 : (G == 16 ? 4 : 3));
 }
 
-// The state of the document a group is working on.  m_d is the table mt
-// (indexed by topic); nz holds a bit per topic of this lane's range with a
-// nonzero count.  For the document side of the b-sum the group also keeps
-// lst, the document's topics in ascending order as of the last rebuild.  A
-// topic whose count falls to zero stays in lst (its b-term is zero) until
-// the next rebuild; a topic that enters the document marks lst stale and the
-// next document-side draw rebuilds it from nz.  lst[0] always holds a valid
-// topic, so padding slots can read it.
+// The state of the document a group is working on: m_d by topic (mt) and
+// lst, its topics with a nonzero count in ascending order (during a draw it
+// also holds the token's old topic, whose count may be zero: that b-term is
+// zero).  lst[0] always holds a valid topic, so padding slots can read it.
 template <typename CT>
 struct DocState {
     CT *mt;
     uint16_t *lst;
-    uint64_t nz;     // topics of this lane's range with a nonzero count
-    uint64_t inl;    // topics of this lane's range present in lst
-    int32_t Kd;      // topics of the document with a nonzero count (group-uniform)
     int32_t L;       // entries of lst (group-uniform)
-    bool stale;      // lst lacks a topic of the document (group-uniform)
 };
 
-// lst <- each lane's nonzero topics at its offset, ascending
+// lst <- the topics with a nonzero count; lane g scans topics [g*R, g*R + R)
 template <int G, typename CT>
-__device__ __forceinline__ void rebuild_list(DocState<CT> &S, int g, int log2c)
+__device__ __forceinline__ void build_list(DocState<CT> &S, int g, int32_t K)
 {
-    S.inl = S.nz;
-    const int32_t c = __builtin_popcountll(S.inl);
+    const int32_t R = (K + G - 1) / G;
+    const int32_t t0 = g * R;
+    const int32_t t1 = t0 + R < K ? t0 + R : K;
+    int32_t c = 0;
+    for (int32_t t = t0; t < t1; ++t) c += S.mt[t] != 0;
     const int32_t incl = group_scan_incl_i32<G>(c);
     int32_t o = incl - c;
     S.L = group_bcast<G>(incl, G - 1);
-    uint64_t r = S.inl;
-    while (r) {
-        const int b = __builtin_ctzll(r);
-        r &= r - 1;
-        S.lst[o++] = (uint16_t)((g << log2c) + b);
-    }
-    S.stale = false;
-    // the list is read back through generic (flat) loads by other lanes:
-    // complete the LDS writes first
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    for (int32_t t = t0; t < t1; ++t)
+        if (S.mt[t]) S.lst[o++] = (uint16_t)t;
     __builtin_amdgcn_wave_barrier();
 }
 
-// up to KEEP b-terms of this lane: entries first + base + u (u < KEEP) of its
+// lane g's block of lst: entries [base, base + n), q = ceil(L / G) per lane
+template <int G>
+__device__ __forceinline__ int32_t list_block(int32_t L, int g, int32_t &base)
+{
+    const int32_t q = (L + G - 1) / G;
+    base = g * q;
+    const int32_t n = L - base < q ? L - base : q;
+    return n > 0 ? n : 0;
+}
+
+// insert topic k (not in lst): the entries above it move up one place
+template <int G, typename CT>
+__device__ __forceinline__ void list_insert(DocState<CT> &S, int32_t k, int g)
+{
+    int32_t base;
+    const int32_t n = list_block<G>(S.L, g, base);
+    // the block's first entry is overwritten by the lane below: read it first
+    const int32_t first = n > 0 ? S.lst[base] : 0;
+    __builtin_amdgcn_wave_barrier();
+    int32_t below = 0;
+    for (int32_t j = n - 1; j >= 1; --j) {
+        const int32_t v = S.lst[base + j];
+        if (v > k) S.lst[base + j + 1] = (uint16_t)v;
+        else ++below;
+    }
+    if (n > 0) {
+        if (first > k) S.lst[base + 1] = (uint16_t)first;
+        else ++below;
+    }
+    const int32_t pos = group_bcast<G>(group_scan_incl_i32<G>(below), G - 1);
+    __builtin_amdgcn_wave_barrier();
+    if (g == 0) S.lst[pos] = (uint16_t)k;
+    S.L += 1;
+    __builtin_amdgcn_wave_barrier();
+}
+
+// remove topic k (in lst): the entries above it move down one place
+template <int G, typename CT>
+__device__ __forceinline__ void list_remove(DocState<CT> &S, int32_t k, int g)
+{
+    int32_t base;
+    const int32_t n = list_block<G>(S.L, g, base);
+    // the block's last entry is overwritten by the lane above: read it first
+    const int32_t last = n > 0 ? S.lst[base + n - 1] : 0;
+    __builtin_amdgcn_wave_barrier();
+    for (int32_t j = 0; j < n; ++j) {
+        const int32_t v = j == n - 1 ? last : S.lst[base + j];
+        if (v > k) S.lst[base + j - 1] = (uint16_t)v;
+    }
+    S.L -= 1;
+    __builtin_amdgcn_wave_barrier();
+}
+
+// up to KP b-terms of this lane: entries first + base + u (u < KP) of its
 // block, which has nl entries: topic, phi and m_d of each (count zeroed
 // past the end).  DOC: the block is in the document's topic list (LDS) and
 // the draw is gathered from the word's dense 16-bit column; otherwise the
@@ -607,16 +654,16 @@ __device__ __forceinline__ void rebuild_list(DocState<CT> &S, int g, int log2c)
 // contiguously.  R (LDS) holds R_k.  Every slot loads from a valid address
 // (padding slots read entry `pad`), so all loads of a round are in flight
 // together.
-template <int G, bool DOC, typename CT>
+template <int KP, bool DOC, typename CT>
 __device__ __forceinline__ void lane_terms(const DevModel &M, const uint16_t *lst, const uint16_t *g16col,
                                            const float *pcol, const double *R, const CT *mt, const int32_t pad,
                                            const int32_t first, const int32_t base, const int32_t nl,
-                                           int32_t (&kk)[KEEP], float (&fk)[KEEP], int32_t (&mk)[KEEP])
+                                           int32_t (&kk)[KP], float (&fk)[KP], int32_t (&mk)[KP])
 {
-    bool ok[KEEP];
-    uint32_t x[KEEP];
+    bool ok[KP];
+    uint32_t x[KP];
 #pragma unroll
-    for (int u = 0; u < KEEP; ++u) {
+    for (int u = 0; u < KP; ++u) {
         ok[u] = base + u < nl;
         const uint32_t e = (uint32_t)(ok[u] ? first + base + u : pad);
         if constexpr (DOC) {
@@ -629,14 +676,14 @@ __device__ __forceinline__ void lane_terms(const DevModel &M, const uint16_t *ls
     }
     if constexpr (DOC) {
 #pragma unroll
-        for (int u = 0; u < KEEP; ++u) x[u] = g16col[(uint32_t)kk[u]];
+        for (int u = 0; u < KP; ++u) x[u] = g16col[(uint32_t)kk[u]];
     }
     // phi_kv = fp32(x * R_k) == fp32(RN64(x / S_k)) for x < 2^16 and
     // S_k < 2^27; every other nonzero cell carries 0xFFFF and its phi is
     // read from the dense table (rare: one wave-uniform test per round)
     bool esc = false;
 #pragma unroll
-    for (int u = 0; u < KEEP; ++u) {
+    for (int u = 0; u < KP; ++u) {
         const double r = R[kk[u]];
         const int32_t m = mt[kk[u]];
         fk[u] = (float)((double)x[u] * r);
@@ -645,7 +692,7 @@ __device__ __forceinline__ void lane_terms(const DevModel &M, const uint16_t *ls
     }
     if (__builtin_amdgcn_ballot_w64(esc)) {
 #pragma unroll
-        for (int u = 0; u < KEEP; ++u)
+        for (int u = 0; u < KP; ++u)
             if (x[u] == 0xFFFFu) fk[u] = pcol[kk[u]];
     }
 }
@@ -659,6 +706,7 @@ __device__ __forceinline__ int32_t b_part(const DevModel &M, const TokenIn &tk, 
                                           const int g)
 {
     constexpr int LG = log2g<G>();
+    constexpr int KP = keep_of<G>();
     const int32_t J = DOC ? S.L : (int32_t)tk.kv;
     const int32_t q = (J + G - 1) >> LG;
     int32_t nl = J - g * q < q ? J - g * q : q;
@@ -667,18 +715,18 @@ __device__ __forceinline__ int32_t b_part(const DevModel &M, const TokenIn &tk, 
     const float *pcol = M.phid + (uint32_t)tk.v * (uint32_t)M.K;
     const int32_t pad = DOC ? 0 : tk.cb;
     const int32_t first = pad + g * q;
-    int32_t kk[KEEP], mk[KEEP];
-    float fk[KEEP];
-    lane_terms<G, DOC, CT>(M, S.lst, g16col, pcol, R, S.mt, pad, first, 0, nl, kk, fk, mk);
+    int32_t kk[KP], mk[KP];
+    float fk[KP];
+    lane_terms<KP, DOC, CT>(M, S.lst, g16col, pcol, R, S.mt, pad, first, 0, nl, kk, fk, mk);
     double p = 0.0;
 #pragma unroll
-    for (int u = 0; u < KEEP; ++u) p = __builtin_fma((double)fk[u], (double)mk[u], p);
-    for (int32_t base = KEEP; base < nl; base += KEEP) {
-        int32_t k2[KEEP], m2[KEEP];
-        float f2[KEEP];
-        lane_terms<G, DOC, CT>(M, S.lst, g16col, pcol, R, S.mt, pad, first, base, nl, k2, f2, m2);
+    for (int u = 0; u < KP; ++u) p = __builtin_fma((double)fk[u], (double)mk[u], p);
+    for (int32_t base = KP; base < nl; base += KP) {
+        int32_t k2[KP], m2[KP];
+        float f2[KP];
+        lane_terms<KP, DOC, CT>(M, S.lst, g16col, pcol, R, S.mt, pad, first, base, nl, k2, f2, m2);
 #pragma unroll
-        for (int u = 0; u < KEEP; ++u) p = __builtin_fma((double)f2[u], (double)m2[u], p);
+        for (int u = 0; u < KP; ++u) p = __builtin_fma((double)f2[u], (double)m2[u], p);
     }
     // the products phi * m are exact in fp64, so each fma rounds exactly
     // like the sum of the product
@@ -702,9 +750,9 @@ __device__ __forceinline__ int32_t b_part(const DevModel &M, const TokenIn &tk, 
     if (g == f) {
         double c = incl - p;
         int32_t last = -1;
-        if (nl <= KEEP) {
+        if (nl <= KP) {
 #pragma unroll
-            for (int u = 0; u < KEEP; ++u) {
+            for (int u = 0; u < KP; ++u) {
                 const double bv = (double)fk[u] * (double)mk[u];
                 if (bv > 0.0) {
                     c += bv;
@@ -713,12 +761,12 @@ __device__ __forceinline__ int32_t b_part(const DevModel &M, const TokenIn &tk, 
                 }
             }
         } else {
-            for (int32_t base = 0; base < nl && kf < 0; base += KEEP) {
-                int32_t k2[KEEP], m2[KEEP];
-                float f2[KEEP];
-                lane_terms<G, DOC, CT>(M, S.lst, g16col, pcol, R, S.mt, pad, first, base, nl, k2, f2, m2);
+            for (int32_t base = 0; base < nl && kf < 0; base += KP) {
+                int32_t k2[KP], m2[KP];
+                float f2[KP];
+                lane_terms<KP, DOC, CT>(M, S.lst, g16col, pcol, R, S.mt, pad, first, base, nl, k2, f2, m2);
 #pragma unroll
-                for (int u = 0; u < KEEP; ++u) {
+                for (int u = 0; u < KP; ++u) {
                     const double bv = (double)f2[u] * (double)m2[u];
                     if (bv > 0.0) {
                         c += bv;
@@ -737,34 +785,25 @@ __device__ __forceinline__ int32_t b_part(const DevModel &M, const TokenIn &tk, 
 // -1 - kold for a token whose word has an empty Phi column (it keeps kold)
 template <int G, typename CT>
 __device__ __forceinline__ int32_t draw_token(const DevModel &M, const TokenIn &tk, DocState<CT> &S, const double *R,
-                                              const int g, const int log2c, const int32_t side_ratio, ZCount &cnt)
+                                              const int g, const int32_t side_ratio, ZCount &cnt)
 {
-    const int32_t C = 1 << log2c;
     CT *mt = S.mt;
     // m^{-i}: remove the token from its document's counts
     const int32_t kold = tk.kold;
-    const int32_t ob = kold & (C - 1), oo = kold >> log2c;
     const int32_t mo = mt[kold];
     __builtin_amdgcn_wave_barrier();
-    if (g == oo) {
-        mt[kold] = (CT)(mo - 1);
-        if (mo == 1) S.nz &= ~(1ull << ob);
-    }
-    if (mo == 1) --S.Kd;
+    if (g == 0) mt[kold] = (CT)(mo - 1);
     __builtin_amdgcn_wave_barrier();
     const int32_t Kv = tk.kv;
     if (Kv == 0) {
         // 0/0 conditional: the token keeps its topic
-        if (g == oo) {
-            mt[kold] = (CT)mo;
-            if (mo == 1) S.nz |= 1ull << ob;
-        }
-        if (mo == 1) ++S.Kd;
+        if (g == 0) mt[kold] = (CT)mo;
         __builtin_amdgcn_wave_barrier();
         cnt.degenerate++;
         return -1 - kold;
     }
-    const int32_t Kd = S.Kd;
+    // the document's topics with a nonzero count besides the token
+    const int32_t Kd = S.L - (mo == 1 ? 1 : 0);
     cnt.J += (unsigned long long)(Kd < Kv ? Kd : Kv);
     // b-terms over one side: the document's topics (lst) or the word's Phi
     // column, ascending topic order either way.  The column is read
@@ -776,13 +815,7 @@ __device__ __forceinline__ int32_t draw_token(const DevModel &M, const TokenIn &
     // wave's groups do not diverge; the side changes cost, not the law.
     const bool prefer_doc = Kd == 0 || Kv > side_ratio * Kd;
     const bool doc = __builtin_amdgcn_ballot_w64(prefer_doc) != 0;
-    int32_t knew;
-    if (doc) {
-        if (S.stale) rebuild_list<G, CT>(S, g, log2c);
-        knew = b_part<G, true, CT>(M, tk, S, R, g);
-    } else {
-        knew = b_part<G, false, CT>(M, tk, S, R, g);
-    }
+    int32_t knew = doc ? b_part<G, true, CT>(M, tk, S, R, g) : b_part<G, false, CT>(M, tk, S, R, g);
     if (knew < 0) {
         // a-part: the word's alias table over alpha_k phi_kv (drawn when the
         // token was staged)
@@ -790,38 +823,27 @@ __device__ __forceinline__ int32_t draw_token(const DevModel &M, const TokenIn &
         cnt.A++;
     }
     // add the token back with its new topic
-    const int32_t nb = knew & (C - 1), no = knew >> log2c;
     const int32_t mn = mt[knew];
     __builtin_amdgcn_wave_barrier();
-    bool fresh = false;
-    if (g == no) {
-        mt[knew] = (CT)(mn + 1);
-        if (mn == 0) {
-            S.nz |= 1ull << nb;
-            fresh = !((S.inl >> nb) & 1ull);
-        }
-    }
-    if (mn == 0) {
-        ++S.Kd;
-        if (group_ballot<G>(fresh)) S.stale = true;
-    }
+    if (g == 0) mt[knew] = (CT)(mn + 1);
     __builtin_amdgcn_wave_barrier();
+    if (knew != kold) {
+        if (mo == 1) list_remove<G, CT>(S, kold, g);
+        if (mn == 0) list_insert<G, CT>(S, knew, g);
+    }
     return knew;
 }
 
-// load a document's topic counts into the group's LDS table and masks
-// (CT: 8-bit counts for documents shorter than 256 tokens, else 16-bit);
-// lst is built by the first document-side draw
+// load a document's topic counts into the group's LDS table (CT: 8-bit
+// counts for documents shorter than 256 tokens, else 16-bit) and list them
 template <int G, typename CT>
 __device__ __forceinline__ void load_doc_counts(DocState<CT> &S, const uint16_t *z, int64_t s, int64_t e, int g,
-                                                int log2c)
+                                                int32_t K, int32_t m_words)
 {
     constexpr int PER_WORD = 4 / sizeof(CT);   // counters per 32-bit word
     constexpr int SHIFT = 8 * sizeof(CT);
-    const int32_t C = 1 << log2c;
     uint32_t *w32 = (uint32_t *)S.mt;
-    for (int32_t i = g; i < C * G / PER_WORD; i += G) w32[i] = 0;
-    if (g == 0) S.lst[0] = 0;
+    for (int32_t i = g; i < m_words; i += G) w32[i] = 0;
     __builtin_amdgcn_wave_barrier();
     for (int64_t i = s + g; i < e; i += G) {
         const int32_t k = z[i];
@@ -829,27 +851,7 @@ __device__ __forceinline__ void load_doc_counts(DocState<CT> &S, const uint16_t 
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    // this lane's range: PER_WORD counters per read when the range covers
-    // whole words, else one counter at a time
-    uint64_t mask = 0;
-    if (C >= PER_WORD) {
-        const uint32_t *own = w32 + ((g << log2c) / PER_WORD);
-        for (int32_t wd = 0; wd < C / PER_WORD; ++wd) {
-            const uint32_t x = own[wd];
-#pragma unroll
-            for (int j = 0; j < PER_WORD; ++j)
-                if ((x >> (SHIFT * j)) & ((1u << SHIFT) - 1u)) mask |= 1ull << (wd * PER_WORD + j);
-        }
-    } else {
-        for (int32_t b = 0; b < C; ++b)
-            if (S.mt[(g << log2c) + b]) mask |= 1ull << b;
-    }
-    S.nz = mask;
-    const int32_t tot = group_scan_incl_i32<G>(__builtin_popcountll(mask));
-    S.Kd = group_bcast<G>(tot, G - 1);
-    S.inl = 0;
-    S.L = 0;
-    S.stale = true;
+    build_list<G, CT>(S, g, K);
 }
 
 // stage the inputs of tokens i0 + g (one per lane) for a block of draws
@@ -880,19 +882,16 @@ __device__ __forceinline__ void stage_token(const DevModel &M, TokenIn *tok, int
 }
 
 template <int G, typename CT>
-__device__ void z_step_item(const ZArgs &a, const WorkItem &w, const double *R, CT *wave_m, uint16_t *wave_lst,
+__device__ void z_step_item(const ZArgs &a, const WorkItem &w, const double *R, uint8_t *wave_base,
                             TokenIn *wave_tok, ZCount &cnt)
 {
     constexpr int NG = 64 / G;
     const int lane = __lane_id();
     const int g = lane & (G - 1);
     const int grp = lane / G;
-    const int log2c = G == 64 ? a.log2c64 : (G == 32 ? a.log2c32 : a.log2c16);
-    const int32_t C = 1 << log2c;
     DocState<CT> S;
-    S.mt = wave_m + grp * (C * G);
-    S.lst = wave_lst + grp * a.lcap;
-    CT *mt = S.mt;
+    S.mt = (CT *)(wave_base + grp * a.group_bytes);
+    S.lst = (uint16_t *)(wave_base + grp * a.group_bytes + a.m_bytes);
     TokenIn *tok = wave_tok + grp * G;
     const DevModel &M = a.m;
     const uint32_t t = *M.tptr;
@@ -903,7 +902,7 @@ __device__ void z_step_item(const ZArgs &a, const WorkItem &w, const double *R, 
             if (a.ll_doc && g == 0) a.ll_doc[d] = 0.0;
             continue;
         }
-        load_doc_counts<G, CT>(S, a.c.z, s, e, g, log2c);
+        load_doc_counts<G, CT>(S, a.c.z, s, e, g, M.K, a.m_bytes / 4);
         for (int64_t i0 = s; i0 < e; i0 += G) {
             const int64_t i = i0 + g;
             const bool valid = i < e;
@@ -919,7 +918,7 @@ __device__ void z_step_item(const ZArgs &a, const WorkItem &w, const double *R, 
             const int nb = (int)((e - i0) < G ? (e - i0) : G);
             for (int jj = 0; jj < nb; ++jj) {
                 const TokenIn tk = tok[jj];
-                int32_t k = draw_token<G, CT>(M, tk, S, R, g, log2c, w.side_ratio, cnt);
+                int32_t k = draw_token<G, CT>(M, tk, S, R, g, w.side_ratio, cnt);
                 if (k < 0) k = -1 - k;
                 if (g == 0) atomicAdd(&M.n[(uint32_t)tk.v * (uint32_t)M.K + (uint32_t)k], 1);
                 if (g == jj) znew = k;
@@ -930,20 +929,10 @@ __device__ void z_step_item(const ZArgs &a, const WorkItem &w, const double *R, 
         if (a.ll_doc) {
             // the document's term of log p(z | alpha) for its final counts:
             // lgamma(A) - lgamma(N_d + A) + sum_k [lgamma(m_k + alpha) - lgamma(alpha)]
+            int32_t base;
+            const int32_t n = list_block<G>(S.L, g, base);
             double part = 0.0;
-            uint64_t mm = S.nz;
-            while (mm) {
-                double v4[KEEP];
-#pragma unroll
-                for (int u = 0; u < KEEP; ++u) {
-                    const bool ok = mm != 0;
-                    const int b = ok ? __builtin_ctzll(mm) : 0;
-                    mm &= mm - 1;
-                    v4[u] = ok ? M.lg_alpha[mt[(g << log2c) + b]] : 0.0;
-                }
-#pragma unroll
-                for (int u = 0; u < KEEP; ++u) part += v4[u];
-            }
+            for (int32_t j = 0; j < n; ++j) part += M.lg_alpha[S.mt[S.lst[base + j]]];
             const double tot = group_bcast_f64<G>(group_scan_incl<G>(part), G - 1);
             if (g == 0) a.ll_doc[d] = tot + M.lg_A[e - s];
         }
@@ -953,9 +942,11 @@ __device__ void z_step_item(const ZArgs &a, const WorkItem &w, const double *R, 
 // one persistent kernel per group size and count width: waves take work
 // items from this class's queue until it is empty
 // 5 waves per SIMD (96 VGPRs): more resident groups hide the chains'
-// latency, more than 96 registers would spill in the draw loop
+// latency, more than 96 registers would spill in the draw loop.  Groups of
+// 8 keep 8 b-terms per lane and their LDS allows 2 waves per SIMD, so they
+// take the registers instead.
 template <int G, typename CT>
-__global__ void __launch_bounds__(256, 5) z_step_kernel(ZArgs a)
+__global__ void __launch_bounds__(256, (G == 8 ? 2 : 5)) z_step_kernel(ZArgs a)
 {
     extern __shared__ __align__(16) uint8_t z_lds[];
     double *R = (double *)z_lds;
@@ -964,8 +955,6 @@ __global__ void __launch_bounds__(256, 5) z_step_kernel(ZArgs a)
     const int wave = threadIdx.x >> 6;
     uint8_t *blk = z_lds + a.r_bytes;
     uint8_t *wave_base = blk + wave * a.wave_bytes;
-    CT *wave_m = (CT *)wave_base;
-    uint16_t *wave_lst = (uint16_t *)(wave_base + a.m_bytes_per_wave);
     TokenIn *wave_tok = (TokenIn *)(blk + 4 * a.wave_bytes) + wave * 64;
     ZCount cnt = {0, 0, 0};
     while (true) {
@@ -976,7 +965,7 @@ __global__ void __launch_bounds__(256, 5) z_step_kernel(ZArgs a)
         // a private copy: a reference into global memory would be reloaded
         // after every store of the item (stores may alias it)
         const WorkItem w = a.items[item];
-        z_step_item<G, CT>(a, w, R, wave_m, wave_lst, wave_tok, cnt);
+        z_step_item<G, CT>(a, w, R, wave_base, wave_tok, cnt);
     }
     // every lane of a group counted the group's tokens; its first lane reports
     if (a.stats && (__lane_id() & (G - 1)) == 0) {
@@ -1024,6 +1013,7 @@ hipError_t launch_z_class(const DevCorpus &c, const DevModel &m, int32_t group, 
                           double *ll_doc, hipStream_t s)
 {
     if (n_items == 0) return hipSuccess;
+    if (group == 8 && !narrow) return hipErrorInvalidValue;
     ZArgs a;
     a.m = m;
     a.c = c;
@@ -1032,16 +1022,11 @@ hipError_t launch_z_class(const DevCorpus &c, const DevModel &m, int32_t group, 
     a.queue = queue;
     a.stats = stats;
     a.ll_doc = m.lg_alpha ? ll_doc : nullptr;
-    a.log2c64 = topics_per_lane_log2(m.K, 64);
-    a.log2c32 = topics_per_lane_log2(m.K, 32);
-    a.log2c16 = topics_per_lane_log2(m.K, 16);
-    // a wave holds 64/G tables of C*G counters (64*C), then 64 staged token inputs
-    const int log2c = group == 64 ? a.log2c64 : (group == 32 ? a.log2c32 : a.log2c16);
-    a.m_bytes_per_wave = (64 << log2c) * (narrow ? 1 : 2);
-    // a document's topic list holds at most min(K, its length - 1) topics
-    a.lcap = narrow ? (m.K < 255 ? m.K : 255) : m.K;
-    a.wave_bytes = (a.m_bytes_per_wave + (64 / group) * a.lcap * 2 + 15) / 16 * 16;
-    a.r_bytes = (m.K * 8 + 15) / 16 * 16;
+    const ZLayout L = z_layout(group, narrow, m.K);
+    a.m_bytes = L.m_bytes;
+    a.group_bytes = L.group_bytes;
+    a.wave_bytes = L.wave_bytes;
+    a.r_bytes = L.r_bytes;
     const size_t lds = (size_t)a.r_bytes + 4 * ((size_t)a.wave_bytes + 64 * sizeof(TokenIn));
     auto launch = [&](auto kernel) -> hipError_t {
         // persistent: exactly the blocks the device holds at once, and no
@@ -1058,7 +1043,8 @@ hipError_t launch_z_class(const DevCorpus &c, const DevModel &m, int32_t group, 
     };
     if (narrow) {
         if (group == 32) return launch(z_step_kernel<32, uint8_t>);
-        return launch(z_step_kernel<16, uint8_t>);
+        if (group == 16) return launch(z_step_kernel<16, uint8_t>);
+        return launch(z_step_kernel<8, uint8_t>);
     }
     if (group == 64) return launch(z_step_kernel<64, uint16_t>);
     if (group == 32) return launch(z_step_kernel<32, uint16_t>);
@@ -1388,14 +1374,14 @@ hipError_t launch_scan_i64(const int64_t *in, int64_t *out_excl, int64_t n, long
 // ---------------------------------------------------------------------------
 template <int G, bool SYM>
 __device__ void foldin_slot(const DevModel &M, const DevFoldin &F, int32_t sid, const double *R, uint16_t *mt,
-                            TokenIn *tok, int log2c)
+                            TokenIn *tok)
 {
+    const int32_t Kp = (M.K + 1) & ~1;
     DocState<uint16_t> S;
     S.mt = mt;
-    S.lst = mt + (G << log2c);
+    S.lst = mt + Kp;
     const int lane = __lane_id();
     const int g = lane & (G - 1);
-    const int32_t C = 1 << log2c;
     const int32_t K = M.K;
     const FoldSlot sl = F.slots[sid];
     int32_t *wds = F.words + sl.arena_off;
@@ -1432,7 +1418,7 @@ __device__ void foldin_slot(const DevModel &M, const DevFoldin &F, int32_t sid, 
     } else {
         kept = F.kept[2 * sid];
     }
-    load_doc_counts<G, uint16_t>(S, zz, 0, kept, g, log2c);
+    load_doc_counts<G, uint16_t>(S, zz, 0, kept, g, K, Kp / 2);
     ZCount st = {0, 0, 0};
     for (int32_t s = sl.done + 1; s <= sl.done + sl.todo; ++s) {
         for (int32_t q0 = 0; q0 < kept; q0 += G) {
@@ -1450,7 +1436,7 @@ __device__ void foldin_slot(const DevModel &M, const DevFoldin &F, int32_t sid, 
             const int nb = (kept - q0) < G ? (kept - q0) : G;
             for (int jj = 0; jj < nb; ++jj) {
                 const TokenIn tk = tok[jj];
-                int32_t k = draw_token<G, uint16_t>(M, tk, S, R, g, log2c, 1, st);
+                int32_t k = draw_token<G, uint16_t>(M, tk, S, R, g, 1, st);
                 if (k < 0) k = -1 - k;
                 if (g == jj) znew = k;
             }
@@ -1458,10 +1444,7 @@ __device__ void foldin_slot(const DevModel &M, const DevFoldin &F, int32_t sid, 
             if (valid) zz[q] = (uint16_t)znew;
         }
         if (s > F.burn_in) {
-            for (int32_t b = 0; b < C; ++b) {
-                const int32_t k = (g << log2c) + b;
-                if (k < K) acc[k] += mt[k];
-            }
+            for (int32_t k = g; k < K; k += G) acc[k] += mt[k];
         }
     }
     const int32_t done = sl.done + sl.todo;
@@ -1473,10 +1456,9 @@ __device__ void foldin_slot(const DevModel &M, const DevFoldin &F, int32_t sid, 
             F.theta[(int64_t)sid * K + k] = (float)(((double)acc[k] / ns + M.alpha[k]) / denom);
         double part = 0.0;
         for (int32_t q = g; q < kept; q += G) part += log((double)M.phid[(int64_t)wds[pos[q]] * K + zz[q]]);
-        for (int32_t b = 0; b < C; ++b) {
-            const int32_t k = (g << log2c) + b;
+        for (int32_t k = g; k < K; k += G) {
             const int32_t c = mt[k];
-            if (k < K && c > 0) {
+            if (c > 0) {
                 if constexpr (SYM) part += M.lg_alpha[c];
                 else part += lgamma((double)c + M.alpha[k]) - lgamma(M.alpha[k]);
             }
@@ -1488,7 +1470,7 @@ __device__ void foldin_slot(const DevModel &M, const DevFoldin &F, int32_t sid, 
 
 template <int G, bool SYM>
 __global__ void __launch_bounds__(256) foldin_step_kernel(DevModel M, DevFoldin F, const int32_t *active,
-                                                          int32_t n_active, int32_t log2c, int32_t per_group)
+                                                          int32_t n_active, int32_t per_group)
 {
     extern __shared__ __align__(16) uint16_t f_lds[];
     // the block's copy of R_k, then the groups' tables, then staged tokens
@@ -1506,17 +1488,16 @@ __global__ void __launch_bounds__(256) foldin_step_kernel(DevModel M, DevFoldin 
     TokenIn *tok = (TokenIn *)(blk + 4 * ngw * per_group) + wave * 64 + grp * gsz;
     if (gid >= n_active) return;
     const int32_t sid = active[gid];
-    foldin_slot<G, SYM>(M, F, sid, R, mt, tok, log2c);
+    foldin_slot<G, SYM>(M, F, sid, R, mt, tok);
 }
 
 hipError_t launch_foldin_step(const DevModel &m, const DevFoldin &f, const int32_t *active, int32_t n_active,
                               hipStream_t s)
 {
     if (n_active == 0) return hipSuccess;
-    const int log2c = topics_per_lane_log2(m.K, f.group);
-    // per group: the count table, then the topic list (K entries, rounded
-    // to keep the next table 4-byte aligned)
-    const int per_group = (f.group << log2c) + ((m.K + 1) & ~1);
+    // per group (u16 units): the count table, then the topic list, K
+    // entries each (rounded to keep the next table 4-byte aligned)
+    const int per_group = 2 * ((m.K + 1) & ~1);
     const int ngw = 64 / f.group;
     const int64_t waves = (n_active + ngw - 1) / ngw;
     const unsigned blocks = (unsigned)((waves + 3) / 4);
@@ -1526,7 +1507,7 @@ hipError_t launch_foldin_step(const DevModel &m, const DevFoldin &f, const int32
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, foldin_step_kernel<64, true>, 256, lds);
     if (e != hipSuccess) return e;
     if (per_cu <= 0) return hipErrorInvalidConfiguration;  // the block's LDS exceeds the CU's
-#define PULDA_FOLDIN(G_, S_) foldin_step_kernel<G_, S_><<<blocks, 256, lds, s>>>(m, f, active, n_active, log2c, per_group)
+#define PULDA_FOLDIN(G_, S_) foldin_step_kernel<G_, S_><<<blocks, 256, lds, s>>>(m, f, active, n_active, per_group)
     if (m.lg_alpha) {
         if (f.group == 64) PULDA_FOLDIN(64, true);
         else if (f.group == 32) PULDA_FOLDIN(32, true);
