@@ -109,14 +109,17 @@ def foldin_bench(args, torch, pulda, synth):
     nb = args.foldin_requests
     batched = reqs[:nb]
     log(f"fold-in: closed loop, {nb} requests")
-    rep = server.serve(fi, batched, quantum=args.quantum)
-    xmax = rep.docs_per_s
-    out = dict(saturation_docs_per_s=xmax, saturation_p50_ms=rep.percentile_ms(50),
+    rep = server.serve(fi, batched, draws=args.draws)
+    # the service rate: completions between the 10% and 90% marks (the run's
+    # end waits for its longest requests, 50 sweeps of up to 5000 tokens)
+    xmax = rep.steady_docs_per_s()
+    out = dict(saturation_docs_per_s=xmax, closed_loop_docs_per_s=rep.docs_per_s,
+               saturation_p50_ms=rep.percentile_ms(50),
                saturation_p99_ms=rep.percentile_ms(99), requests=nb, mean_len=float(lens[:nb].mean()),
-               sweeps=50, burn_in=25, slots=args.slots, quantum=args.quantum, rates={})
+               sweeps=50, burn_in=25, slots=args.slots, draws_per_step=args.draws, rates={})
     for i, frac in enumerate(args.rates):
         arr = server.poisson_arrivals(nb, frac * xmax, seed=170403581 + 5 + i)
-        rep = server.serve(fi, batched, arrivals=arr, quantum=args.quantum)
+        rep = server.serve(fi, batched, arrivals=arr, draws=args.draws)
         out["rates"][f"{frac:.2f}"] = dict(offered_docs_per_s=frac * xmax, docs_per_s=rep.docs_per_s,
                                            p50_ms=rep.percentile_ms(50), p99_ms=rep.percentile_ms(99),
                                            max_resident=rep.max_resident)
@@ -127,7 +130,7 @@ def foldin_bench(args, torch, pulda, synth):
     out["plain_p50_ms"] = rep_p.percentile_ms(50)
     out["plain_p99_ms"] = rep_p.percentile_ms(99)
     # the same requests through the batched path give the same results
-    rep_b = server.serve(fi, plain, quantum=args.quantum)
+    rep_b = server.serve(fi, plain, draws=args.draws)
     out["batched_equals_plain"] = bool(all(
         np.array_equal(rep_b.results[j]["theta"], rep_p.results[j]["theta"]) and
         rep_b.results[j]["loglik"] == rep_p.results[j]["loglik"] for j in range(len(plain))))
@@ -154,10 +157,10 @@ def main():
     ap.add_argument("--cpu-docs", type=int, default=20000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-foldin", action="store_true")
-    ap.add_argument("--foldin-requests", type=int, default=4000)
+    ap.add_argument("--foldin-requests", type=int, default=12000)
     ap.add_argument("--plain-requests", type=int, default=60)
-    ap.add_argument("--slots", type=int, default=2048)
-    ap.add_argument("--quantum", type=int, default=10)
+    ap.add_argument("--slots", type=int, default=4096)
+    ap.add_argument("--draws", type=int, default=2048, help="fold-in token draws per request per step")
     ap.add_argument("--rates", type=float, nargs="*", default=[0.5, 0.8, 0.95])
     ap.add_argument("--corpus-cache", default=None,
                     help=".npz file: load the corpus from it if present, else generate and save it there")

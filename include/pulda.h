@@ -315,12 +315,16 @@ void pulda_foldin_destroy(pulda_foldin *f);
 pulda_status pulda_foldin_submit(pulda_foldin *f, uint32_t request_id, const int32_t *words_host, int32_t len,
                                  void *stream);
 
-/* Advance every resident request by up to `quantum` sweeps in one launch
- * (asynchronous). */
-pulda_status pulda_foldin_step(pulda_foldin *f, int32_t quantum, void *stream);
+/* Advance every resident request by up to `draws` token draws in one launch
+ * (asynchronous).  A request resumes where its previous step stopped (sweep
+ * and token within it; the progress is kept on the device), so a step takes
+ * about the same time for long and short requests.  Results do not depend
+ * on how a request's draws are split into steps. */
+pulda_status pulda_foldin_step(pulda_foldin *f, int32_t draws, void *stream);
 
 /* Collect finished requests (at most cap): results into out[], theta into
- * theta_host[cap * K] (row j for out[j]); frees their slots.  Synchronises. */
+ * theta_host[cap * K] (row j for out[j]); frees their slots.  Reads the
+ * requests' progress from the device.  Synchronises. */
 pulda_status pulda_foldin_poll(pulda_foldin *f, pulda_foldin_result *out, float *theta_host, int32_t cap,
                                int32_t *n_done, void *stream);
 

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -187,7 +188,7 @@ struct pulda_foldin {
     pulda_foldin_desc desc{};
     int64_t ws_need = 0;
     struct {
-        int64_t slots, kept, words, pos, z, acc, theta, ll, active;
+        int64_t slots, kept, prog, words, pos, z, acc, theta, ll, active;
     } off;
     uint8_t *ws = nullptr;
     DevFoldin f{};
@@ -196,6 +197,7 @@ struct pulda_foldin {
     // host bookkeeping
     std::vector<FoldSlot> slots;      // control mirror
     std::vector<int32_t> resident;    // 1 if the slot holds a request
+    std::vector<int32_t> finished;    // 1 if its last sweep is known done (not yet collected)
     std::vector<std::pair<int32_t, int32_t>> free_blocks;  // arena [off, len), by offset
     int32_t free_tokens = 0;
 };
@@ -1032,8 +1034,6 @@ pulda_status pulda_foldin_create(const pulda_plan *model, const pulda_foldin_des
         d->max_len > 65535)
         return fail(PULDA_ERR_INVALID_ARG, "bad capacity");
     if (d->group != 16 && d->group != 32 && d->group != 64) return fail(PULDA_ERR_INVALID_ARG, "bad group");
-    if ((1 << (int)std::ceil(std::log2((double)((model->K + d->group - 1) / d->group)))) > 64)
-        return fail(PULDA_ERR_INVALID_ARG, "group %d too small for K=%d", d->group, model->K);
     pulda_foldin *f = new pulda_foldin();
     f->model = model;
     f->desc = *d;
@@ -1041,6 +1041,7 @@ pulda_status pulda_foldin_create(const pulda_plan *model, const pulda_foldin_des
     const int64_t S = d->max_slots, T = d->arena_tokens, K = model->K;
     f->off.slots = L.take(S * (int64_t)sizeof(FoldSlot));
     f->off.kept = L.take(S * 8);
+    f->off.prog = L.take(S * 8);
     f->off.words = L.take(T * 4);
     f->off.pos = L.take(T * 4);
     f->off.z = L.take(T * 2);
@@ -1051,6 +1052,7 @@ pulda_status pulda_foldin_create(const pulda_plan *model, const pulda_foldin_des
     f->ws_need = L.total;
     f->slots.assign(S, FoldSlot{});
     f->resident.assign(S, 0);
+    f->finished.assign(S, 0);
     f->free_blocks = {{0, (int32_t)T}};
     f->free_tokens = (int32_t)T;
     *out = f;
@@ -1083,6 +1085,7 @@ pulda_status pulda_foldin_bind(pulda_foldin *f, void *ws, int64_t bytes)
     F.A = f->model->A;
     F.slots = f->slots_dev;
     F.kept = (int32_t *)(w + f->off.kept);
+    F.prog = (int32_t *)(w + f->off.prog);
     F.words = (int32_t *)(w + f->off.words);
     F.pos = (int32_t *)(w + f->off.pos);
     F.z = (uint16_t *)(w + f->off.z);
@@ -1156,25 +1159,26 @@ pulda_status pulda_foldin_submit(pulda_foldin *f, uint32_t req, const int32_t *w
     sl.arena_off = at;
     sl.len = len;
     sl.req = req;
-    sl.done = 0;
-    sl.todo = 0;
+    sl.fresh = 1;
+    sl.budget = 0;
     f->resident[sid] = 1;
+    f->finished[sid] = 0;
     return PULDA_OK;
 }
 
-pulda_status pulda_foldin_step(pulda_foldin *f, int32_t quantum, void *stream)
+pulda_status pulda_foldin_step(pulda_foldin *f, int32_t draws, void *stream)
 {
-    if (!f || quantum < 1) return fail(PULDA_ERR_INVALID_ARG, "bad argument");
+    if (!f || draws < 1) return fail(PULDA_ERR_INVALID_ARG, "bad argument");
     if (!f->ws) return fail(PULDA_ERR_STATE, "no workspace bound");
     hipStream_t s = (hipStream_t)stream;
     std::vector<int32_t> active;
     for (int32_t i = 0; i < f->desc.max_slots; ++i) {
         FoldSlot &sl = f->slots[i];
-        if (f->resident[i] && sl.done < f->desc.sweeps) {
-            sl.todo = std::min(quantum, f->desc.sweeps - sl.done);
+        if (f->resident[i] && !f->finished[i]) {
+            sl.budget = draws;
             active.push_back(i);
         } else {
-            sl.todo = 0;
+            sl.budget = 0;
         }
     }
     if (active.empty()) return PULDA_OK;
@@ -1183,8 +1187,8 @@ pulda_status pulda_foldin_step(pulda_foldin *f, int32_t quantum, void *stream)
     HIP_TRY(hipMemcpyAsync(f->active_dev, active.data(), active.size() * 4, hipMemcpyHostToDevice, s));
     HIP_TRY(launch_foldin_step(f->model->m, f->f, f->active_dev, (int32_t)active.size(), s));
     for (int32_t i : active) {
-        f->slots[i].done += f->slots[i].todo;
-        f->slots[i].todo = 0;
+        f->slots[i].fresh = 0;
+        f->slots[i].budget = 0;
     }
     return PULDA_OK;
 }
@@ -1195,16 +1199,25 @@ pulda_status pulda_foldin_poll(pulda_foldin *f, pulda_foldin_result *out, float 
     if (!f || !n_done || (cap > 0 && (!out || !theta))) return fail(PULDA_ERR_INVALID_ARG, "null argument");
     if (!f->ws) return fail(PULDA_ERR_STATE, "no workspace bound");
     hipStream_t s = (hipStream_t)stream;
-    const int32_t K = f->model->K;
-    std::vector<int32_t> fin;
-    for (int32_t i = 0; i < f->desc.max_slots && (int32_t)fin.size() < cap; ++i)
-        if (f->resident[i] && f->slots[i].done >= f->desc.sweeps) fin.push_back(i);
+    const int32_t K = f->model->K, S = f->desc.max_slots;
     *n_done = 0;
-    if (fin.empty()) return PULDA_OK;
-    std::vector<int32_t> kept(2 * f->desc.max_slots);
-    std::vector<double> ll(f->desc.max_slots);
+    bool any = false;
+    for (int32_t i = 0; i < S; ++i) any |= f->resident[i] && !f->slots[i].fresh;
+    if (!any) return PULDA_OK;
+    // progress is kept on the device: read it with the results
+    std::vector<int32_t> prog(2 * S), kept(2 * S);
+    std::vector<double> ll(S);
+    HIP_TRY(hipMemcpyAsync(prog.data(), f->f.prog, prog.size() * 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(kept.data(), f->f.kept, kept.size() * 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(ll.data(), f->f.ll, ll.size() * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    std::vector<int32_t> fin;
+    for (int32_t i = 0; i < S; ++i) {
+        if (!f->resident[i] || f->slots[i].fresh || prog[2 * i] < f->desc.sweeps) continue;
+        f->finished[i] = 1;
+        if ((int32_t)fin.size() < cap) fin.push_back(i);
+    }
+    if (fin.empty()) return PULDA_OK;
     for (size_t j = 0; j < fin.size(); ++j)
         HIP_TRY(hipMemcpyAsync(theta + j * K, f->f.theta + (int64_t)fin[j] * K, K * 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -1216,6 +1229,7 @@ pulda_status pulda_foldin_poll(pulda_foldin *f, pulda_foldin_result *out, float 
         out[j].pad = 0;
         out[j].loglik = ll[i];
         f->resident[i] = 0;
+        f->finished[i] = 0;
         arena_free(f, f->slots[i].arena_off, f->slots[i].len);
     }
     *n_done = (int32_t)fin.size();
@@ -1243,7 +1257,7 @@ pulda_status pulda_foldin_run_one(pulda_foldin *f, uint32_t req, const int32_t *
     if (r) return fail(PULDA_ERR_STATE, "the server holds %d requests", r);
     pulda_status st = pulda_foldin_submit(f, req, words, len, stream);
     if (st != PULDA_OK) return st;
-    st = pulda_foldin_step(f, f->desc.sweeps, stream);
+    st = pulda_foldin_step(f, INT32_MAX, stream);
     if (st != PULDA_OK) return st;
     int32_t n = 0;
     st = pulda_foldin_poll(f, out, theta, 1, &n, stream);

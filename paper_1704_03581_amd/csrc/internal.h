@@ -137,8 +137,8 @@ struct FoldSlot {
     int32_t arena_off;  // first token of the slot's region in the arena
     int32_t len;        // request length
     uint32_t req;       // request id
-    int32_t done;       // sweeps completed before this step
-    int32_t todo;       // sweeps to run in this step
+    int32_t fresh;      // 1 on the request's first step (drop tokens, draw initial topics)
+    int32_t budget;     // token draws to run in this step
     int32_t pad[3];
 };
 
@@ -148,6 +148,7 @@ struct DevFoldin {
     double A;
     const FoldSlot *slots;  // [max_slots] control, written by the host
     int32_t *kept;          // [2*max_slots] kept, dropped: written by the device
+    int32_t *prog;          // [2*max_slots] sweeps done, next token of the current sweep: device-written
     int32_t *words;         // arena [arena_tokens]
     int32_t *pos;           // arena: kept positions
     uint16_t *z;            // arena

@@ -1367,10 +1367,13 @@ hipError_t launch_scan_i64(const int64_t *in, int64_t *out_excl, int64_t n, long
 // ---------------------------------------------------------------------------
 // Fold-in (Phi fixed, no count rebuild): each group owns one request slot.
 // On its first step a slot drops tokens whose word is out of range or has an
-// empty Phi column, and draws initial topics; every step then runs `todo`
-// sweeps of the token draw with counters (p, request, sweep), accumulating
-// the topic counts after the burn-in, and the last sweep writes theta and
-// the log-likelihood of the final state.
+// empty Phi column, and draws initial topics.  Every step then runs up to
+// `budget` token draws, resuming where the previous step stopped (sweep and
+// token within it, kept on the device), with counters (p, request, sweep):
+// the draws do not depend on how a request's work is cut into steps.  The
+// topic counts are accumulated after each sweep past the burn-in, and the
+// step that ends the last sweep writes theta and the log-likelihood of the
+// final state.
 // ---------------------------------------------------------------------------
 template <int G, bool SYM>
 __device__ void foldin_slot(const DevModel &M, const DevFoldin &F, int32_t sid, const double *R, uint16_t *mt,
@@ -1388,8 +1391,8 @@ __device__ void foldin_slot(const DevModel &M, const DevFoldin &F, int32_t sid, 
     int32_t *pos = F.pos + sl.arena_off;
     uint16_t *zz = F.z + sl.arena_off;
     uint32_t *acc = F.acc + (int64_t)sid * K;
-    int32_t kept = 0;
-    if (sl.done == 0) {
+    int32_t kept = 0, done = 0, next = 0;
+    if (sl.fresh) {
         // drop tokens, compact the kept positions, draw initial topics
         int32_t run = 0;
         for (int32_t p0 = 0; p0 < sl.len; p0 += G) {
@@ -1417,13 +1420,18 @@ __device__ void foldin_slot(const DevModel &M, const DevFoldin &F, int32_t sid, 
         __threadfence();
     } else {
         kept = F.kept[2 * sid];
+        done = F.prog[2 * sid];
+        next = F.prog[2 * sid + 1];
     }
     load_doc_counts<G, uint16_t>(S, zz, 0, kept, g, K, Kp / 2);
     ZCount st = {0, 0, 0};
-    for (int32_t s = sl.done + 1; s <= sl.done + sl.todo; ++s) {
-        for (int32_t q0 = 0; q0 < kept; q0 += G) {
+    int32_t budget = sl.budget;
+    while (budget > 0 && done < F.sweeps) {
+        const int32_t s = done + 1;
+        const int32_t t1 = kept - next < budget ? kept : next + budget;
+        for (int32_t q0 = next; q0 < t1; q0 += G) {
             const int32_t q = q0 + g;
-            const bool valid = q < kept;
+            const bool valid = q < t1;
             int32_t zo = 0;
             if (valid) {
                 const int32_t p = pos[q];
@@ -1433,7 +1441,7 @@ __device__ void foldin_slot(const DevModel &M, const DevFoldin &F, int32_t sid, 
             }
             __builtin_amdgcn_wave_barrier();
             int32_t znew = zo;
-            const int nb = (kept - q0) < G ? (kept - q0) : G;
+            const int nb = (t1 - q0) < G ? (t1 - q0) : G;
             for (int jj = 0; jj < nb; ++jj) {
                 const TokenIn tk = tok[jj];
                 int32_t k = draw_token<G, uint16_t>(M, tk, S, R, g, 1, st);
@@ -1443,11 +1451,21 @@ __device__ void foldin_slot(const DevModel &M, const DevFoldin &F, int32_t sid, 
             __builtin_amdgcn_wave_barrier();
             if (valid) zz[q] = (uint16_t)znew;
         }
-        if (s > F.burn_in) {
-            for (int32_t k = g; k < K; k += G) acc[k] += mt[k];
+        budget -= t1 - next;
+        next = t1;
+        if (next == kept) {
+            // the sweep is complete
+            if (s > F.burn_in) {
+                for (int32_t k = g; k < K; k += G) acc[k] += mt[k];
+            }
+            done = s;
+            next = 0;
         }
     }
-    const int32_t done = sl.done + sl.todo;
+    if (g == 0) {
+        F.prog[2 * sid] = done;
+        F.prog[2 * sid + 1] = next;
+    }
     __threadfence();
     if (done == F.sweeps) {
         const double denom = (double)kept + F.A;

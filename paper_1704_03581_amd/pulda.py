@@ -366,12 +366,17 @@ class FoldIn:
         _check(st)
         return True
 
-    def step(self, quantum: int, stream=None):
-        _check(_lib.pulda_foldin_step(self._h, quantum, _stream(stream)))
+    def step(self, draws: int, stream=None):
+        """Advance every resident request by up to `draws` token draws."""
+        _check(_lib.pulda_foldin_step(self._h, draws, _stream(stream)))
 
     def poll(self, cap: int = 4096, stream=None):
-        res = (FoldinResult * cap)()
-        theta = np.zeros((cap, self.K), np.float32)
+        # result buffers are reused across polls
+        if getattr(self, "_poll_cap", 0) < cap:
+            self._poll_res = (FoldinResult * cap)()
+            self._poll_theta = np.empty((cap, self.K), np.float32)
+            self._poll_cap = cap
+        res, theta = self._poll_res, self._poll_theta
         n = i32()
         _check(_lib.pulda_foldin_poll(self._h, res, theta.ctypes.data_as(vp), cap, C.byref(n), _stream(stream)))
         out = []

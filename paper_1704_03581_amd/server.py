@@ -3,9 +3,11 @@
 Requests are new documents whose topic proportions theta are inferred
 against a fixed, device-resident Phi (fold-in).  The loop admits every
 request that has arrived as soon as a slot and enough arena tokens are free
-(admission by device memory), advances all resident requests together by a
-quantum of sweeps in one launch, collects the finished ones and admits more:
-requests that arrive while others are on the GPU join the running batch.
+(admission by device memory), advances all resident requests together by the
+same budget of token draws in one launch (a request resumes mid-sweep where
+the previous step stopped, so long and short requests take the same time per
+step), collects the finished ones and admits more: requests that arrive
+while others are on the GPU join the running batch.
 
 The loop drives any backend with the FoldIn interface (submit / step / poll /
 occupancy), so its bookkeeping is testable without a GPU.
@@ -29,6 +31,7 @@ class ServeReport:
     max_resident: int = 0
     admission_waits: int = 0                 # submits refused for capacity
     order_admitted: List[int] = field(default_factory=list)
+    completion_s: np.ndarray = field(default_factory=lambda: np.zeros(0))  # completion time, per request
 
     @property
     def docs_per_s(self) -> float:
@@ -37,9 +40,20 @@ class ServeReport:
     def percentile_ms(self, q: float) -> float:
         return float(np.percentile(self.latency_s, q) * 1e3) if len(self.latency_s) else 0.0
 
+    def steady_docs_per_s(self, lo: float = 0.1, hi: float = 0.9) -> float:
+        """Completions per second between the lo and hi quantiles of the
+        completion times: the service rate with the start-up and the drain
+        of the last (longest) requests left out."""
+        done = np.sort(self.completion_s)
+        if len(done) < 10:
+            return self.docs_per_s
+        a, b = int(lo * len(done)), int(hi * len(done)) - 1
+        span = done[b] - done[a]
+        return (b - a) / span if span > 0 else float("inf")
+
 
 def serve(backend, requests: Sequence[np.ndarray], arrivals: Optional[Sequence[float]] = None,
-          quantum: int = 10, clock: Callable[[], float] = time.perf_counter,
+          draws: int = 2048, clock: Callable[[], float] = time.perf_counter,
           sleep: Callable[[float], None] = time.sleep, max_poll: int = 4096) -> ServeReport:
     """Serve requests[i] arriving at arrivals[i] seconds (None: all at 0).
 
@@ -56,7 +70,7 @@ def serve(backend, requests: Sequence[np.ndarray], arrivals: Optional[Sequence[f
     results: Dict[int, dict] = {}
     pending: deque = deque()
     nxt = 0
-    rep = ServeReport(results, lat, 0.0)
+    rep = ServeReport(results, lat, 0.0, completion_s=np.zeros(n))
     while len(results) < n:
         now = clock() - t0
         while nxt < n and arr[nxt] <= now:
@@ -77,11 +91,13 @@ def serve(backend, requests: Sequence[np.ndarray], arrivals: Optional[Sequence[f
             if nxt < n:
                 sleep(max(0.0, min(arr[nxt] - (clock() - t0), 0.001)))
             continue
-        backend.step(quantum)
+        backend.step(draws)
         rep.steps += 1
         for r in backend.poll(cap=max_poll):
             rid = r["request_id"]
-            lat[rid] = clock() - t0 - arr[rid]
+            now = clock() - t0
+            rep.completion_s[rid] = now
+            lat[rid] = now - arr[rid]
             results[rid] = r
     rep.wall_s = clock() - t0
     return rep

@@ -58,7 +58,7 @@ def test_foldin_batched_matches_oracle(model, group):
     say(f"fold-in batched group={group}")
     f = pulda.FoldIn(p, sweeps=12, burn_in=6, max_slots=16, arena_tokens=4000, max_len=400, group=group, seed=21)
     reqs = _requests(c.V, 40, 5)
-    rep = server.serve(f, reqs, quantum=5)
+    rep = server.serve(f, reqs, draws=300)
     assert sorted(rep.results) == list(range(len(reqs)))
     for rid, r in rep.results.items():
         _check(r, phi, wt, np.full(c.K, c.alpha), 21, rid, reqs[rid], 12, 6)
@@ -66,14 +66,15 @@ def test_foldin_batched_matches_oracle(model, group):
 
 def test_foldin_alone_equals_in_the_mix(model):
     """Each request's result is the same alone (plain sampler) and among
-    others with any quantum."""
+    others with any budget of draws per step (steps that stop mid-sweep
+    included)."""
     p, phi, wt, c = model
     say("fold-in alone vs mix")
     f = pulda.FoldIn(p, sweeps=10, burn_in=5, max_slots=8, arena_tokens=2000, max_len=400, group=64, seed=33)
     reqs = _requests(c.V, 20, 8)
     alone = {rid: f.run_one(rid, w) for rid, w in enumerate(reqs)}
-    for q in (1, 3, 10):
-        rep = server.serve(f, reqs, quantum=q)
+    for q in (7, 100, 1000):
+        rep = server.serve(f, reqs, draws=q)
         for rid, r in rep.results.items():
             assert np.array_equal(r["theta"], alone[rid]["theta"]) and r["loglik"] == alone[rid]["loglik"]
     _check(alone[0], phi, wt, np.full(c.K, c.alpha), 33, 0, reqs[0], 10, 5)
@@ -87,7 +88,7 @@ def test_foldin_admission_under_memory_cap(model):
     reqs = _requests(c.V, 25, 9)
     with pytest.raises(pulda.PuldaError):
         f.submit(999, np.zeros(301, np.int32))                          # longer than max_len
-    rep = server.serve(f, reqs, quantum=2)
+    rep = server.serve(f, reqs, draws=150)
     assert rep.admission_waits > 0 and sorted(rep.results) == list(range(len(reqs)))
     occ = f.occupancy()
     assert occ["resident"] == 0 and occ["free_tokens"] == 500 and occ["free_slots"] == 32

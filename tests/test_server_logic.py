@@ -19,15 +19,15 @@ class FakeClock:
 
 
 class FakeFoldIn:
-    """FoldIn's interface with the oracle's arithmetic; one step costs 1 ms
-    of fake time."""
+    """FoldIn's interface with the oracle's arithmetic; one step (up to
+    `draws` token draws per resident request) costs 1 ms of fake time."""
 
     def __init__(self, phi, wt, alpha, seed, clock, sweeps=8, burn_in=4, max_slots=4, arena_tokens=200):
         self.phi, self.wt, self.alpha, self.seed = phi, wt, alpha, seed
         self.clock = clock
         self.sweeps, self.burn_in = sweeps, burn_in
         self.max_slots, self.arena_tokens = max_slots, arena_tokens
-        self.res = {}          # rid -> [words, done]
+        self.res = {}          # rid -> [words, draws done]
         self.used = 0
         self.submits = []
 
@@ -43,9 +43,9 @@ class FakeFoldIn:
         return dict(resident=len(self.res), free_slots=self.max_slots - len(self.res),
                     free_tokens=self.arena_tokens - self.used)
 
-    def step(self, quantum):
+    def step(self, draws):
         for r in self.res.values():
-            r[1] = min(self.sweeps, r[1] + quantum)
+            r[1] = min(self.sweeps * len(r[0]), r[1] + draws)
         self.clock.t += 1e-3
 
     def _result(self, rid, words):
@@ -54,7 +54,7 @@ class FakeFoldIn:
         return dict(request_id=rid, theta=theta, loglik=ll, kept=kept, dropped=dropped)
 
     def poll(self, cap=4096):
-        done = [rid for rid, r in self.res.items() if r[1] >= self.sweeps][:cap]
+        done = [rid for rid, r in self.res.items() if r[1] >= self.sweeps * len(r[0])][:cap]
         out = []
         for rid in done:
             words, _ = self.res.pop(rid)
@@ -86,7 +86,7 @@ def test_all_served_fifo_and_identical_to_alone(model):
     reqs = _requests(30, phi.shape[1], 1)
     clk = FakeClock()
     be = FakeFoldIn(phi, wt, alpha, 9, clk)
-    rep = server.serve(be, reqs, arrivals=None, quantum=3, clock=clk, sleep=clk.sleep)
+    rep = server.serve(be, reqs, arrivals=None, draws=100, clock=clk, sleep=clk.sleep)
     assert sorted(rep.results) == list(range(30))
     assert rep.order_admitted == sorted(rep.order_admitted)          # first come, first served
     assert rep.max_resident <= be.max_slots and rep.admission_waits > 0
@@ -103,7 +103,7 @@ def test_admission_by_arena_tokens(model):
     reqs = [np.zeros(150, np.int32), np.zeros(150, np.int32), np.zeros(10, np.int32)]
     clk = FakeClock()
     be = FakeFoldIn(phi, wt, alpha, 9, clk, max_slots=8, arena_tokens=200)
-    rep = server.serve(be, reqs, quantum=8, clock=clk, sleep=clk.sleep)
+    rep = server.serve(be, reqs, draws=8 * 150, clock=clk, sleep=clk.sleep)
     assert rep.admission_waits >= 1
     assert rep.order_admitted == [0, 1, 2]
     # 150 + 150 never fit together; 150 + 10 do
@@ -125,10 +125,11 @@ def test_open_loop_latency_arithmetic(model):
     arr = server.poisson_arrivals(20, rate=200.0, seed=5)
     clk = FakeClock()
     be = FakeFoldIn(phi, wt, alpha, 9, clk, max_slots=16, arena_tokens=10000)
-    rep = server.serve(be, reqs, arrivals=arr, quantum=4, clock=clk, sleep=clk.sleep)
+    rep = server.serve(be, reqs, arrivals=arr, draws=60, clock=clk, sleep=clk.sleep)
     assert np.all(rep.latency_s > 0)
-    # each request needs sweeps/quantum = 2 steps of 1 ms after admission
-    assert np.all(rep.latency_s >= 2e-3 - 1e-12)
+    # a request of n tokens needs ceil(8 n / 60) steps of 1 ms after admission
+    need = np.array([max(1, -(-8 * len(r) // 60)) for r in reqs]) * 1e-3
+    assert np.all(rep.latency_s >= need - 1e-12)
     assert rep.percentile_ms(50) <= rep.percentile_ms(99)
     assert abs(rep.percentile_ms(50) - np.percentile(rep.latency_s, 50) * 1e3) < 1e-9
 
@@ -138,7 +139,16 @@ def test_plain_sampler_same_results(model):
     reqs = _requests(10, phi.shape[1], 4)
     clk = FakeClock()
     be = FakeFoldIn(phi, wt, alpha, 9, clk)
-    rep_b = server.serve(be, reqs, quantum=2, clock=clk, sleep=clk.sleep)
+    rep_b = server.serve(be, reqs, draws=37, clock=clk, sleep=clk.sleep)
     rep_p = server.serve_plain(be, reqs, clock=clk, sleep=clk.sleep)
     for rid in range(10):
         assert np.array_equal(rep_b.results[rid]["theta"], rep_p.results[rid]["theta"])
+
+
+def test_steady_rate_leaves_out_the_tail():
+    """Completions at 1 per ms for 100 requests, then one straggler at 1 s:
+    the steady rate is 1000/s, the plain rate is about 100/s."""
+    comp = np.concatenate([np.arange(1, 101) * 1e-3, [1.0]])
+    rep = server.ServeReport({i: {} for i in range(len(comp))}, comp.copy(), 1.0, completion_s=comp)
+    assert abs(rep.steady_docs_per_s() - 1000.0) < 1e-6
+    assert rep.docs_per_s < 110
