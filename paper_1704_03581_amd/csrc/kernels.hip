@@ -700,13 +700,13 @@ __device__ __forceinline__ void lane_terms(const DevModel &M, const uint16_t *ls
 // sigma_b = sum of the b-terms phi_kv m_k over one side, the a/b decision,
 // and for the b-part the topic whose running sum first exceeds
 // y = u_sigma - sigma_a (Section 3.5).  Returns the topic, or -1 for the
-// a-part (the caller takes the word's alias draw).
-template <int G, bool DOC, typename CT>
+// a-part (the caller takes the word's alias draw).  KP terms per lane and
+// round; the first round's terms stay in registers for the walk.
+template <int G, bool DOC, typename CT, int KP>
 __device__ __forceinline__ int32_t b_part(const DevModel &M, const TokenIn &tk, DocState<CT> &S, const double *R,
                                           const int g)
 {
     constexpr int LG = log2g<G>();
-    constexpr int KP = keep_of<G>();
     const int32_t J = DOC ? S.L : (int32_t)tk.kv;
     const int32_t q = (J + G - 1) >> LG;
     int32_t nl = J - g * q < q ? J - g * q : q;
@@ -718,9 +718,15 @@ __device__ __forceinline__ int32_t b_part(const DevModel &M, const TokenIn &tk, 
     int32_t kk[KP], mk[KP];
     float fk[KP];
     lane_terms<KP, DOC, CT>(M, S.lst, g16col, pcol, R, S.mt, pad, first, 0, nl, kk, fk, mk);
+    // the products phi * m are exact in fp64, so adding them (or an fma)
+    // rounds exactly like the sum of the products
+    double bk[KP];
     double p = 0.0;
 #pragma unroll
-    for (int u = 0; u < KP; ++u) p = __builtin_fma((double)fk[u], (double)mk[u], p);
+    for (int u = 0; u < KP; ++u) {
+        bk[u] = (double)fk[u] * (double)mk[u];
+        p += bk[u];
+    }
     for (int32_t base = KP; base < nl; base += KP) {
         int32_t k2[KP], m2[KP];
         float f2[KP];
@@ -728,8 +734,6 @@ __device__ __forceinline__ int32_t b_part(const DevModel &M, const TokenIn &tk, 
 #pragma unroll
         for (int u = 0; u < KP; ++u) p = __builtin_fma((double)f2[u], (double)m2[u], p);
     }
-    // the products phi * m are exact in fp64, so each fma rounds exactly
-    // like the sum of the product
     const double incl = group_scan_incl<G>(p);
     const double T = group_bcast_f64<G>(incl, G - 1);
     const double Z = tk.sa + T;
@@ -753,9 +757,8 @@ __device__ __forceinline__ int32_t b_part(const DevModel &M, const TokenIn &tk, 
         if (nl <= KP) {
 #pragma unroll
             for (int u = 0; u < KP; ++u) {
-                const double bv = (double)fk[u] * (double)mk[u];
-                if (bv > 0.0) {
-                    c += bv;
+                if (bk[u] > 0.0) {
+                    c += bk[u];
                     last = kk[u];
                     if (kf < 0 && c > y) kf = kk[u];
                 }
@@ -815,7 +818,14 @@ __device__ __forceinline__ int32_t draw_token(const DevModel &M, const TokenIn &
     // wave's groups do not diverge; the side changes cost, not the law.
     const bool prefer_doc = Kd == 0 || Kv > side_ratio * Kd;
     const bool doc = __builtin_amdgcn_ballot_w64(prefer_doc) != 0;
-    int32_t knew = doc ? b_part<G, true, CT>(M, tk, S, R, g) : b_part<G, false, CT>(M, tk, S, R, g);
+    // terms per lane and round: half the registers' worth when no group of
+    // the wave has more than that many per lane (one round either way)
+    constexpr int KP = keep_of<G>();
+    const int32_t J = doc ? S.L : Kv;
+    const bool full = __builtin_amdgcn_ballot_w64(J > (KP / 2) * G) != 0;
+    int32_t knew;
+    if (doc) knew = full ? b_part<G, true, CT, KP>(M, tk, S, R, g) : b_part<G, true, CT, KP / 2>(M, tk, S, R, g);
+    else knew = full ? b_part<G, false, CT, KP>(M, tk, S, R, g) : b_part<G, false, CT, KP / 2>(M, tk, S, R, g);
     if (knew < 0) {
         // a-part: the word's alias table over alpha_k phi_kv (drawn when the
         // token was staged)
