@@ -236,10 +236,11 @@ pulda_status pulda_set_timing(pulda_plan *plan, int32_t enable);
 /* z-step schedule: documents are ordered by decreasing length and split
  * into n_buckets length buckets; bucket b holds documents with length >=
  * min_len[b] (min_len decreasing, last 0) and is processed by groups of
- * group[b] lanes (8, 16, 32 or 64) with docs_per_item[b] documents per work
- * item (a multiple of 64 / group).  A work item whose group would not fit
- * in LDS (groups of 8 take only documents shorter than 256 tokens) runs on
- * the next larger group size.  A token's b-terms (Section 3.5) are summed
+ * group[b] lanes (1, 8, 16, 32 or 64) with docs_per_item[b] documents per
+ * work item (a multiple of 64 / group).  Group 1 runs one document per lane
+ * (its b-sum is the sequential ascending sum) and takes documents shorter
+ * than 128 tokens; groups of 8 take documents shorter than 256 tokens; a
+ * work item whose group would not fit runs on a larger group size.  A token's b-terms (Section 3.5) are summed
  * over the word's Phi column or over the document's topics; a group prefers
  * the column when K_v <= side_ratio[b] * K_d (side_ratio NULL: all 1, the
  * smaller side) and a wave takes the document side when any of its groups
@@ -251,7 +252,7 @@ pulda_status pulda_set_schedule(pulda_plan *plan, int32_t n_buckets, const int32
 pulda_status pulda_get_schedule(const pulda_plan *plan, int32_t cap, int32_t *n_buckets, int32_t *min_len_host,
                                 int32_t *group_host, int32_t *docs_per_item_host, int32_t *side_ratio_host);
 
-/* Time each candidate group size (8, 16, 32, 64) and side ratio (1, 4, 16) on
+/* Time each candidate group size (1, 8, 16, 32, 64) and side ratio (1, 4, 16) on
  * each bucket (z-step at sweep t, reps repetitions, current Phi) and keep the
  * fastest.  Restores z and n.  Synchronises. */
 pulda_status pulda_autotune(pulda_plan *plan, uint32_t t, int32_t reps, void *stream);

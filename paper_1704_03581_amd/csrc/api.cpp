@@ -162,7 +162,7 @@ struct pulda_plan {
     int32_t n_items = 0;
     // work-item classes: (group size, count width) = (64, 16-bit), (32, 16),
     // (32, 8), (16, 16), (16, 8); 8-bit counts serve documents under 256 tokens
-    static constexpr int NCLS = 6;
+    static constexpr int NCLS = 7;
     int32_t cls_first[NCLS] = {}, cls_count[NCLS] = {};
     int32_t n_cu = 0;                 // compute units of the device
     // internal streams: the three group-size kernels of a z-step run
@@ -412,22 +412,25 @@ static hipError_t phase_event(pulda_plan *p, hipStream_t s, size_t *idx)
 
 // a z-step class fits when one wave's count tables, topic lists and staged
 // tokens take at most 32 KB of LDS (groups of 8 only for documents shorter
-// than 256 tokens)
-static bool class_fits(int32_t g, bool narrow, int32_t K)
+// than 256 tokens); one document per lane (group 1) takes documents shorter
+// than 128 tokens (longest is the work item's longest document)
+static bool class_fits(int32_t g, bool narrow, int32_t K, int32_t longest)
 {
+    if (g == 1) return longest < 128;
     if (g == 8 && !narrow) return false;
     return z_layout(g, narrow, K).wave_bytes + 64 * 32 <= 32 * 1024;
 }
 
-static const int32_t kClassGroup[pulda_plan::NCLS] = {64, 32, 32, 16, 16, 8};
-static const bool kClassNarrow[pulda_plan::NCLS] = {false, false, true, false, true, true};
+static const int32_t kClassGroup[pulda_plan::NCLS] = {64, 32, 32, 16, 16, 8, 1};
+static const bool kClassNarrow[pulda_plan::NCLS] = {false, false, true, false, true, true, true};
 
 static int item_class(int32_t g, bool narrow)
 {
     if (g == 64) return 0;
     if (g == 32) return narrow ? 2 : 1;
     if (g == 16) return narrow ? 4 : 3;
-    return 5;
+    if (g == 8) return 5;
+    return 6;
 }
 
 static pulda_status build_items(pulda_plan *p)
@@ -450,7 +453,8 @@ static pulda_status build_items(pulda_plan *p)
             const bool narrow = p->len_sorted[s] < 256;
             // the bucket's group size, or the next larger one that fits
             int32_t g = p->group[b];
-            while (g < 64 && !class_fits(g, narrow, p->K)) g *= 2;
+            if (g == 1 && !class_fits(1, narrow, p->K, p->len_sorted[s])) g = 16;
+            while (g < 64 && !class_fits(g, narrow, p->K, p->len_sorted[s])) g *= 2;
             w.group = g;
             cls[item_class(w.group, narrow)].push_back(w);
         }
@@ -882,8 +886,8 @@ pulda_status pulda_set_schedule(pulda_plan *p, int32_t nb, const int32_t *min_le
 {
     if (!p || nb < 1 || !min_len || !group || !dpi) return fail(PULDA_ERR_INVALID_ARG, "bad schedule");
     for (int32_t b = 0; b < nb; ++b) {
-        if (group[b] != 8 && group[b] != 16 && group[b] != 32 && group[b] != 64)
-            return fail(PULDA_ERR_INVALID_ARG, "group size %d not in {8, 16, 32, 64}", group[b]);
+        if (group[b] != 1 && group[b] != 8 && group[b] != 16 && group[b] != 32 && group[b] != 64)
+            return fail(PULDA_ERR_INVALID_ARG, "group size %d not in {1, 8, 16, 32, 64}", group[b]);
         if (dpi[b] < 1 || dpi[b] % (64 / group[b])) return fail(PULDA_ERR_INVALID_ARG, "docs per item %d", dpi[b]);
         if (b > 0 && min_len[b] >= min_len[b - 1]) return fail(PULDA_ERR_INVALID_ARG, "min_len must decrease");
         if (side_ratio && (side_ratio[b] < 1 || side_ratio[b] > 1024))
@@ -943,8 +947,8 @@ pulda_status pulda_autotune(pulda_plan *p, uint32_t t, int32_t reps, void *strea
         mean_len /= (double)(hi - lo);
         float best_ms = 1e30f;
         const bool narrow = p->len_sorted[lo] < 256;
-        for (int gsz : {64, 32, 16, 8}) {
-            if (!class_fits(gsz, narrow, p->K)) continue;
+        for (int gsz : {64, 32, 16, 8, 1}) {
+            if (!class_fits(gsz, narrow, p->K, p->len_sorted[lo])) continue;
             for (int ratio : {1, 4, 16}) {
                 const int ng = 64 / gsz;
                 int per = (int)std::max(1.0, std::round(4096.0 / std::max(1.0, mean_len) / ng)) * ng;

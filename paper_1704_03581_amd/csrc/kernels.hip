@@ -985,6 +985,220 @@ __global__ void __launch_bounds__(256, (G == 8 ? 2 : 5)) z_step_kernel(ZArgs a)
     }
 }
 
+// ---------------------------------------------------------------------------
+// z-step, one document per lane (documents shorter than 128 tokens).  Lane l
+// keeps its document's topics with a nonzero count as an ascending list of
+// (topic, count) in LDS, entry j at j*64 + l so that the lanes' j-th entries
+// are adjacent.  A token's b-terms are summed over the whole list in
+// ascending topic order, one after the other in the lane (a listed topic
+// the word's column lacks adds a zero term), so the running sums are those
+// of the definition term by term.  The running sum after every block of 8
+// entries stays in registers; the b-part walk re-reads one block.
+// ---------------------------------------------------------------------------
+constexpr int LANE_CAP = 127;                                      // list capacity
+constexpr int LANE_BLK = 8;                                        // entries per gather batch
+constexpr int LANE_NBLK = (LANE_CAP + LANE_BLK - 1) / LANE_BLK;    // 16
+
+// first index j of the lane's list with topic >= key
+__device__ __forceinline__ int32_t lane_lower_bound(const uint16_t *kl, int32_t L, int32_t key)
+{
+    int32_t lo = 0, hi = L;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if ((int32_t)kl[mid * 64] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// one block of the lane's list: b-terms of entries [j0, j0 + 8) (zero past L)
+__device__ __forceinline__ void lane_block_terms(const uint16_t *kl, const uint8_t *ml, int32_t L, int32_t j0,
+                                                 const uint16_t *g16col, const float *pcol, const double *Rd,
+                                                 int32_t (&kk)[LANE_BLK], double (&bb)[LANE_BLK])
+{
+    uint32_t mm[LANE_BLK], xx[LANE_BLK];
+    double rr[LANE_BLK];
+#pragma unroll
+    for (int u = 0; u < LANE_BLK; ++u) {
+        const bool ok = j0 + u < L;
+        const int32_t j = ok ? j0 + u : 0;
+        const int32_t k = kl[j * 64];
+        const uint32_t m = ml[j * 64];
+        kk[u] = ok ? k : 0;
+        mm[u] = ok ? m : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < LANE_BLK; ++u) {
+        xx[u] = g16col[(uint32_t)kk[u]];
+        rr[u] = Rd[kk[u]];
+    }
+    // phi_kv = fp32(x * R_k) == fp32(RN64(x / S_k)); escapes (0xFFFF) read
+    // the fp32 table
+    float fk[LANE_BLK];
+    bool esc = false;
+#pragma unroll
+    for (int u = 0; u < LANE_BLK; ++u) {
+        fk[u] = (float)((double)xx[u] * rr[u]);
+        esc |= xx[u] == 0xFFFFu;
+    }
+    if (__builtin_amdgcn_ballot_w64(esc)) {
+#pragma unroll
+        for (int u = 0; u < LANE_BLK; ++u)
+            if (xx[u] == 0xFFFFu) fk[u] = pcol[kk[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < LANE_BLK; ++u) bb[u] = (double)fk[u] * (double)mm[u];
+}
+
+__global__ void __launch_bounds__(64) z_lane_kernel(ZArgs a)
+{
+    extern __shared__ __align__(16) uint8_t l_lds[];
+    const int lane = __lane_id();
+    uint16_t *kl = (uint16_t *)l_lds + lane;                            // entry j at kl[j * 64]
+    uint8_t *ml = l_lds + LANE_CAP * 64 * sizeof(uint16_t) + lane;      // entry j at ml[j * 64]
+    const DevModel &M = a.m;
+    const uint32_t t = *M.tptr;
+    ZCount cnt = {0, 0, 0};
+    while (true) {
+        int item = 0;
+        if (lane == 0) item = atomicAdd(a.queue, 1);
+        item = __builtin_amdgcn_readlane(item, 0);
+        if (item >= a.n_items) break;
+        const WorkItem w = a.items[item];
+        for (int32_t di = lane; di < w.count; di += 64) {
+            const int32_t d = a.c.doc_order[w.first + di];
+            const int64_t s = a.c.doc_off[d], e = a.c.doc_off[d + 1];
+            // the document's counts as an ascending (topic, count) list
+            int32_t L = 0;
+            for (int64_t i = s; i < e; ++i) {
+                const int32_t k = a.c.z[i];
+                const int32_t pos = lane_lower_bound(kl, L, k);
+                if (pos < L && kl[pos * 64] == k) {
+                    ml[pos * 64] += 1;
+                } else {
+                    for (int32_t j = L - 1; j >= pos; --j) {
+                        kl[(j + 1) * 64] = kl[j * 64];
+                        ml[(j + 1) * 64] = ml[j * 64];
+                    }
+                    kl[pos * 64] = (uint16_t)k;
+                    ml[pos * 64] = 1;
+                    ++L;
+                }
+            }
+            for (int64_t i = s; i < e; ++i) {
+                const int32_t v = a.c.words[i];
+                const int32_t kold = a.c.z[i];
+                const int32_t cb = M.colptr[v];
+                const int32_t Kv = M.colptr[v + 1] - cb;
+                int32_t knew = kold;
+                if (Kv == 0) {
+                    // 0/0 conditional: the token keeps its topic
+                    cnt.degenerate++;
+                } else {
+                    const r4 r = philox((uint32_t)i, (uint32_t)((uint64_t)i >> 32), t, TAG_Z, M.key0, M.key1);
+                    const double sa = M.sigma_a[v];
+                    const uint64_t al = M.calias[cb + scale32(r.y, (uint32_t)Kv)];
+                    const int32_t ka = (r.z < (uint32_t)al) ? (int32_t)((al >> 32) & 0xFFFFu) : (int32_t)(al >> 48);
+                    // m^{-i}
+                    const int32_t po = lane_lower_bound(kl, L, kold);
+                    const int32_t mo = ml[po * 64];
+                    ml[po * 64] = (uint8_t)(mo - 1);
+                    const int32_t Kd = L - (mo == 1 ? 1 : 0);
+                    cnt.J += (unsigned long long)(Kd < Kv ? Kd : Kv);
+                    const uint16_t *g16col = M.g16 + (uint32_t)v * (uint32_t)M.ks16;
+                    const float *pcol = M.phid + (uint32_t)v * (uint32_t)M.K;
+                    // sigma_b over the list, ascending, with the running sum after each block
+                    double bs[LANE_NBLK];
+                    double sb = 0.0;
+                    int32_t last = -1;
+    #pragma unroll
+                    for (int blk = 0; blk < LANE_NBLK; ++blk) {
+                        bs[blk] = sb;
+                        if (!__builtin_amdgcn_ballot_w64(blk * LANE_BLK < L)) continue;
+                        int32_t kk[LANE_BLK];
+                        double bb[LANE_BLK];
+                        lane_block_terms(kl, ml, L, blk * LANE_BLK, g16col, pcol, M.Rd, kk, bb);
+    #pragma unroll
+                        for (int u = 0; u < LANE_BLK; ++u) {
+                            sb += bb[u];
+                            if (bb[u] > 0.0) last = blk * LANE_BLK + u;
+                        }
+                        bs[blk] = sb;
+                    }
+                    const double x = unit24(r.x) * (sa + sb);
+                    if (x < sa) {
+                        knew = ka;
+                        cnt.A++;
+                    } else {
+                        // b-part: the block whose running sum first passes y, then its entries
+                        const double y = x - sa;
+                        int32_t blk = -1;
+                        double c0 = 0.0;
+    #pragma unroll
+                        for (int b = LANE_NBLK - 1; b >= 0; --b) {
+                            if (bs[b] > y) {
+                                blk = b;
+                                c0 = b > 0 ? bs[b - 1] : 0.0;
+                            }
+                        }
+                        knew = -1;
+                        if (blk >= 0) {
+                            int32_t kk[LANE_BLK];
+                            double bb[LANE_BLK];
+                            lane_block_terms(kl, ml, L, blk * LANE_BLK, g16col, pcol, M.Rd, kk, bb);
+                            double c = c0;
+    #pragma unroll
+                            for (int u = 0; u < LANE_BLK; ++u) {
+                                c += bb[u];
+                                if (knew < 0 && bb[u] > 0.0 && c > y) knew = kk[u];
+                            }
+                        }
+                        // no running sum passed y (rounding): the last positive term
+                        if (knew < 0) knew = kl[last * 64];
+                    }
+                    // counts and list
+                    if (knew == kold) {
+                        ml[po * 64] = (uint8_t)mo;
+                    } else {
+                        if (mo == 1) {
+                            for (int32_t j = po; j < L - 1; ++j) {
+                                kl[j * 64] = kl[(j + 1) * 64];
+                                ml[j * 64] = ml[(j + 1) * 64];
+                            }
+                            --L;
+                        }
+                        const int32_t pn = lane_lower_bound(kl, L, knew);
+                        if (pn < L && kl[pn * 64] == knew) {
+                            ml[pn * 64] += 1;
+                        } else {
+                            for (int32_t j = L - 1; j >= pn; --j) {
+                                kl[(j + 1) * 64] = kl[j * 64];
+                                ml[(j + 1) * 64] = ml[j * 64];
+                            }
+                            kl[pn * 64] = (uint16_t)knew;
+                            ml[pn * 64] = 1;
+                            ++L;
+                        }
+                    }
+                    a.c.z[i] = (uint16_t)knew;
+                }
+                atomicAdd(&M.n[(uint32_t)v * (uint32_t)M.K + (uint32_t)knew], 1);
+            }
+            if (a.ll_doc) {
+                // lgamma(A) - lgamma(N_d + A) + sum_k [lgamma(m_k + alpha) - lgamma(alpha)]
+                double part = 0.0;
+                for (int32_t j = 0; j < L; ++j) part += M.lg_alpha[ml[j * 64]];
+                a.ll_doc[d] = part + M.lg_A[e - s];
+            }
+        }
+    }
+    if (a.stats) {
+        if (cnt.J) atomicAdd(&a.stats[ST_SUM_J], (unsigned long long)cnt.J);
+        if (cnt.A) atomicAdd(&a.stats[ST_SUM_A], (unsigned long long)cnt.A);
+        if (cnt.degenerate) atomicAdd(&a.stats[ST_DEGENERATE], (unsigned long long)cnt.degenerate);
+    }
+}
+
 static int ilog2(int x)
 {
     int r = 0;
@@ -1023,7 +1237,7 @@ hipError_t launch_z_class(const DevCorpus &c, const DevModel &m, int32_t group, 
                           double *ll_doc, hipStream_t s)
 {
     if (n_items == 0) return hipSuccess;
-    if (group == 8 && !narrow) return hipErrorInvalidValue;
+    if ((group == 8 || group == 1) && !narrow) return hipErrorInvalidValue;
     ZArgs a;
     a.m = m;
     a.c = c;
@@ -1051,6 +1265,18 @@ hipError_t launch_z_class(const DevCorpus &c, const DevModel &m, int32_t group, 
         kernel<<<(unsigned)blocks, 256, lds, s>>>(a);
         return hipGetLastError();
     };
+    if (group == 1) {
+        // one document per lane: 64-thread blocks, the lanes' topic lists
+        const size_t llds = (size_t)LANE_CAP * 64 * 3;
+        int per_cu = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, z_lane_kernel, 64, llds);
+        if (e != hipSuccess) return e;
+        if (per_cu <= 0) return hipErrorInvalidConfiguration;
+        int64_t blocks = (int64_t)per_cu * (n_cu > 0 ? n_cu : 1);
+        if (blocks > n_items) blocks = n_items;
+        z_lane_kernel<<<(unsigned)blocks, 64, llds, s>>>(a);
+        return hipGetLastError();
+    }
     if (narrow) {
         if (group == 32) return launch(z_step_kernel<32, uint8_t>);
         if (group == 16) return launch(z_step_kernel<16, uint8_t>);

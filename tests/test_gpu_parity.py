@@ -106,7 +106,7 @@ def test_phi_step_bit_exact(name):
 
 
 @pytest.mark.parametrize("side", [1, 16])
-@pytest.mark.parametrize("group", [64, 32, 16, 8])
+@pytest.mark.parametrize("group", [64, 32, 16, 8, 1])
 @pytest.mark.parametrize("name", list(CASES))
 def test_z_step_replay(name, group, side):
     """Every group size, and both sides of the b-sum (side ratio 1: the
@@ -115,7 +115,7 @@ def test_z_step_replay(name, group, side):
     say(f"z-step {name} group={group} side={side}")
     p = make_plan(c, seed=13)
     try:
-        p.set_schedule([0], [group], [64 // group * 4], [side])
+        p.set_schedule([0], [group], [max(64 // group * 4, 64) if group == 1 else 64 // group * 4], [side])
     except pulda.PuldaError:
         pytest.skip(f"group {group} too small for K={c.K}")
     p.init()
@@ -274,7 +274,7 @@ def test_autotune_keeps_results_valid():
     z0 = p.get_z()
     p.phi_step(1)
     sched = p.autotune(1, reps=1)
-    assert all(g in (8, 16, 32, 64) for g in sched[1]) and all(r in (1, 4, 16) for r in sched[3])
+    assert all(g in (1, 8, 16, 32, 64) for g in sched[1]) and all(r in (1, 4, 16) for r in sched[3])
     assert np.array_equal(p.get_z(), z0)
     phi, wt = phi_from_gpu(p.get_phi(), c.K, c.V)
     p.z_step(1)
