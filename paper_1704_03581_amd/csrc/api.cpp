@@ -214,6 +214,8 @@ pulda_status pulda_plan_create(const pulda_model_desc *desc, int64_t D, int64_t 
     if (desc->K < 1 || desc->K > 4096) return fail(PULDA_ERR_INVALID_ARG, "K=%d outside 1..4096", desc->K);
     if (desc->V < 1) return fail(PULDA_ERR_INVALID_ARG, "V=%d must be >= 1", desc->V);
     if ((int64_t)desc->K * desc->V >= (1ll << 31)) return fail(PULDA_ERR_INVALID_ARG, "K*V must be < 2^31");
+    if ((int64_t)desc->V * ((desc->K + 63) / 64 * 64) >= (1ll << 32))
+        return fail(PULDA_ERR_INVALID_ARG, "V * (K rounded up to 64) must be < 2^32");
     if (!(desc->beta > 0.0) || !std::isfinite(desc->beta)) return fail(PULDA_ERR_INVALID_ARG, "beta must be > 0");
     if (desc->L < 1 || desc->L > 1000) return fail(PULDA_ERR_INVALID_ARG, "L=%d outside 1..1000", desc->L);
     if (D < 0 || N < 0 || N >= (1ll << 40) || D >= (1ll << 31))

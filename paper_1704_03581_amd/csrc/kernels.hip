@@ -532,7 +532,7 @@ struct ZArgs {
 // inputs of one token draw, staged in LDS so every lane of the group reads
 // them with one broadcast load
 struct alignas(16) TokenIn {
-    int32_t v;       // word
+    uint32_t vk;     // v * K: the word's row of n and of the dense phi
     int32_t cb;      // first CSC entry of the word's Phi column
     uint16_t kold;   // topic before the draw
     uint16_t kv;     // nonzeros in the column (K_v^Phi <= K <= 4096)
@@ -541,7 +541,8 @@ struct alignas(16) TokenIn {
                      // word and the token's random numbers, so it is taken at
                      // staging time, off the draw's critical path
     uint16_t pad0;
-    uint32_t pad1;
+    uint32_t vs;     // v * ks16: the word's row of the 16-bit draws (the
+                     // products are taken once, at staging)
     double sa;       // sigma_a(v)
 };
 
@@ -598,7 +599,7 @@ template <int G>
 __device__ __forceinline__ int32_t list_block(int32_t L, int g, int32_t &base)
 {
     const int32_t q = (L + G - 1) / G;
-    base = g * q;
+    base = (int32_t)__umul24((uint32_t)g, (uint32_t)q);
     const int32_t n = L - base < q ? L - base : q;
     return n > 0 ? n : 0;
 }
@@ -711,10 +712,10 @@ __device__ __forceinline__ int32_t b_part(const DevModel &M, const TokenIn &tk, 
     const int32_t q = (J + G - 1) >> LG;
     int32_t nl = J - g * q < q ? J - g * q : q;
     nl = nl > 0 ? nl : 0;
-    const uint16_t *g16col = M.g16 + (uint32_t)tk.v * (uint32_t)M.ks16;
-    const float *pcol = M.phid + (uint32_t)tk.v * (uint32_t)M.K;
+    const uint16_t *g16col = M.g16 + tk.vs;
+    const float *pcol = M.phid + tk.vk;
     const int32_t pad = DOC ? 0 : tk.cb;
-    const int32_t first = pad + g * q;
+    const int32_t first = pad + (int32_t)__umul24((uint32_t)g, (uint32_t)q);
     int32_t kk[KP], mk[KP];
     float fk[KP];
     lane_terms<KP, DOC, CT>(M, S.lst, g16col, pcol, R, S.mt, pad, first, 0, nl, kk, fk, mk);
@@ -816,7 +817,7 @@ __device__ __forceinline__ int32_t draw_token(const DevModel &M, const TokenIn &
     // wave (the document side if any of its groups prefers it: a frequent
     // word's column is long, a document's topic list is not), so the
     // wave's groups do not diverge; the side changes cost, not the law.
-    const bool prefer_doc = Kd == 0 || Kv > side_ratio * Kd;
+    const bool prefer_doc = Kd == 0 || (uint32_t)Kv > __umul24((uint32_t)side_ratio, (uint32_t)Kd);
     const bool doc = __builtin_amdgcn_ballot_w64(prefer_doc) != 0;
     // terms per lane and round: half the registers' worth when no group of
     // the wave has more than that many per lane (one round either way)
@@ -869,7 +870,8 @@ __device__ __forceinline__ void stage_token(const DevModel &M, TokenIn *tok, int
                                             const r4 &r)
 {
     TokenIn x;
-    x.v = v;
+    x.vk = (uint32_t)v * (uint32_t)M.K;
+    x.vs = (uint32_t)v * (uint32_t)M.ks16;
     x.cb = M.colptr[v];
     x.kold = (uint16_t)kold;
     const int32_t kv = M.colptr[v + 1] - x.cb;
@@ -887,7 +889,6 @@ __device__ __forceinline__ void stage_token(const DevModel &M, TokenIn *tok, int
     }
     x.ka = (uint16_t)ka;
     x.pad0 = 0;
-    x.pad1 = 0;
     tok[g] = x;
 }
 
@@ -930,7 +931,7 @@ __device__ void z_step_item(const ZArgs &a, const WorkItem &w, const double *R, 
                 const TokenIn tk = tok[jj];
                 int32_t k = draw_token<G, CT>(M, tk, S, R, g, w.side_ratio, cnt);
                 if (k < 0) k = -1 - k;
-                if (g == 0) atomicAdd(&M.n[(uint32_t)tk.v * (uint32_t)M.K + (uint32_t)k], 1);
+                if (g == 0) atomicAdd(&M.n[tk.vk + (uint32_t)k], 1);
                 if (g == jj) znew = k;
             }
             __builtin_amdgcn_wave_barrier();
