@@ -22,7 +22,7 @@ _SRC = os.path.join(_HERE, "pulda_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
-TAG_INIT, TAG_PHI_CELL, TAG_PHI_PRIOR, TAG_Z, TAG_FOLDIN_INIT, TAG_FOLDIN_Z = range(6)
+TAG_INIT, TAG_PHI_CELL, TAG_PHI_PRIOR, TAG_Z, TAG_FOLDIN_INIT, TAG_FOLDIN_Z, TAG_PHI_GAMMA = range(7)
 
 
 def build() -> str:
@@ -64,6 +64,10 @@ def _declare(L):
     L.or_phi_counts.argtypes = [C.c_int32, C.c_int32, C.c_double, C.c_int32, C.c_uint64, C.c_uint32, i32p, i32p]
     L.or_phi_normalise.argtypes = [C.c_int32, C.c_int32, i32p, i64p, f32p]
     L.or_phi_normalise.restype = C.c_int32
+    L.or_gamma_draw.argtypes = [C.c_double, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32]
+    L.or_gamma_draw.restype = C.c_double
+    L.or_phi_dirichlet.argtypes = [C.c_int32, C.c_int32, C.c_double, C.c_uint64, C.c_uint32, i32p, f64p, f64p, f32p]
+    L.or_phi_dirichlet.restype = C.c_int32
     L.or_word_tables.argtypes = [C.c_int32, C.c_int32, f64p, f32p, i64p, u16p, f32p, u32p, u16p, f64p]
     L.or_word_tables.restype = C.c_int64
     L.or_z_step.argtypes = [C.c_int64, C.c_int32, C.c_int32, i64p, i32p, u16p, C.c_uint64, C.c_uint32, f32p,
@@ -149,6 +153,25 @@ def phi_normalise(gam):
     phi = np.zeros((K, V), np.float32)
     empty = lib().or_phi_normalise(K, V, _p(gam, C.c_int32), _p(S, C.c_int64), _p(phi, C.c_float))
     return S, phi, empty
+
+
+def gamma_draw(a, seed, c0, c1, c2):
+    """One G(a, 1) draw of Algorithm 1's Phi-step (Marsaglia-Tsang) at
+    Philox counter (c0, c1, c2, PHI_GAMMA + 256 j)."""
+    return lib().or_gamma_draw(float(a), seed, c0, c1, c2)
+
+
+def phi_dirichlet(n, beta, seed, t):
+    """Algorithm 1's Phi-step: phi_k ~ Dir(n_k + beta) via Gamma draws.
+    Returns (gamma fp64 K x V, S fp64 K, phi fp32 K x V, empty rows)."""
+    n = _c(n, np.int32)
+    K, V = n.shape
+    gam = np.zeros((K, V), np.float64)
+    S = np.zeros(K, np.float64)
+    phi = np.zeros((K, V), np.float32)
+    empty = lib().or_phi_dirichlet(K, V, beta, seed, t, _p(n, C.c_int32), _p(gam, C.c_double), _p(S, C.c_double),
+                                   _p(phi, C.c_float))
+    return gam, S, phi, empty
 
 
 @dataclass

@@ -36,6 +36,9 @@
  *      "marginal unnormalized log-posterior for z" of Section 4).
  *   5. Fold-in of a new document against a fixed Phi (z-step restricted to
  *      that document, Phi held fixed).
+ *   6. The Phi-step of Algorithm 1 (the partially collapsed sampler the
+ *      urn replaces): phi_k ~ Dir(n_k + beta) through Gamma draws (see
+ *      or_phi_dirichlet); its z-step is step 2 on the resulting Phi.
  *
  * Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random
  * numbers: as easy as 1, 2, 3", SC'11), keyed by the sampler seed, with the
@@ -47,7 +50,8 @@
 #include <stdlib.h>
 #include <string.h>
 
-enum { TAG_INIT = 0, TAG_PHI_CELL = 1, TAG_PHI_PRIOR = 2, TAG_Z = 3, TAG_FOLDIN_INIT = 4, TAG_FOLDIN_Z = 5 };
+enum { TAG_INIT = 0, TAG_PHI_CELL = 1, TAG_PHI_PRIOR = 2, TAG_Z = 3, TAG_FOLDIN_INIT = 4, TAG_FOLDIN_Z = 5,
+       TAG_PHI_GAMMA = 6 };
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-10 (Salmon et al. 2011): 10 rounds of the 4x32 S-box, the key  */
@@ -288,6 +292,82 @@ int32_t or_phi_normalise(int32_t K, int32_t V, const int32_t *gam, int64_t *S, f
         for (int32_t v = 0; v < V; v++) {
             int32_t g = gam[(size_t)k * V + v];
             phi[(size_t)k * V + v] = g > 0 ? (float)((double)g / (double)s) : 0.0f;
+        }
+    }
+    return empty_rows;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Algorithm 1 Phi-step: phi_k ~ Dir(n_k + beta) for every topic row k, by    */
+/* the Gamma representation of the Dirichlet (Section 3.3):                   */
+/*   gamma_kv ~ G(beta + n_kv, 1),  phi_kv = gamma_kv / sum_v gamma_kv.        */
+/* Gamma draws by Marsaglia and Tsang (2000), the method Section 3.4 names.   */
+/* For shape a >= 1, with d = a - 1/3 and c = 1 / sqrt(9 d):                   */
+/*   x ~ N(0, 1), t = 1 + c x; reject if t <= 0; v = t^3, u ~ U(0, 1);         */
+/*   accept d v if u < 1 - 0.0331 x^4 (their squeeze) or                       */
+/*   log u < x^2 / 2 + d (1 - v + log v); else try again.                       */
+/* For a < 1 their boost: G(a) = G(a + 1) * U^(1/a), U^(1/a) taken as          */
+/* exp(log(U) / a).                                                           */
+/* Random numbers: attempt j of cell (k, v) at sweep t uses Philox counter     */
+/* (v, k, t, PHI_GAMMA + 256 j):                                              */
+/*   x = sqrt(-2 log u(r0)) cos(2 pi u(r1))   (Box and Muller 1958),           */
+/*   u = u(r2), and r3 of attempt 0 is the boost's U,                          */
+/* with u(r) = (r + 1/2) / 2^32 in (0, 1).  After GAMMA_TRIES rejected          */
+/* attempts (probability below 0.05^(2^20)) the draw is d.                    */
+/* ------------------------------------------------------------------------ */
+#define GAMMA_TRIES (1u << 20)
+
+static double u32o(uint32_t r) { return ((double)r + 0.5) * (1.0 / 4294967296.0); }
+
+double or_gamma_draw(double a, uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2)
+{
+    const double two_pi = 6.283185307179586476925286766559;
+    const double a1 = a < 1.0 ? a + 1.0 : a;
+    const double d = a1 - 1.0 / 3.0;
+    const double c = 1.0 / sqrt(9.0 * d);
+    double g = d;
+    uint32_t boost = 0;
+    for (uint32_t j = 0; j < GAMMA_TRIES; j++) {
+        uint32_t r[4];
+        draw4(seed, c0, c1, c2, TAG_PHI_GAMMA + (j << 8), r);
+        if (j == 0) boost = r[3];
+        double x = sqrt(-2.0 * log(u32o(r[0]))) * cos(two_pi * u32o(r[1]));
+        double t1 = 1.0 + c * x;
+        if (t1 <= 0.0) continue;
+        double v = t1 * t1 * t1;
+        double u = u32o(r[2]);
+        double x2 = x * x;
+        if (u < 1.0 - 0.0331 * (x2 * x2) || log(u) < 0.5 * x2 + d * (1.0 - v + log(v))) {
+            g = d * v;
+            break;
+        }
+    }
+    if (a < 1.0) g = g * exp(log(u32o(boost)) / a);
+    return g;
+}
+
+/* Rows: S_k = sum_v gamma_kv, ascending v, in fp64; phi_kv = fp32(gamma_kv / */
+/* S_k) (quotient in fp64, rounded once).  A cell whose phi is below the      */
+/* smallest normal fp32 (2^-126: zero or subnormal) is set to zero, so the    */
+/* sparse Phi is the set of cells with a normal fp32 value.  A row with       */
+/* S_k = 0 is empty.  gam, phi: topic-major K x V.  Returns the empty rows.   */
+int32_t or_phi_dirichlet(int32_t K, int32_t V, double beta, uint64_t seed, uint32_t t, const int32_t *n,
+                         double *gam, double *S, float *phi)
+{
+    const float flt_min = 1.17549435082228750797e-38f;
+    int32_t empty_rows = 0;
+    for (int32_t k = 0; k < K; k++)
+        for (int32_t v = 0; v < V; v++)
+            gam[(size_t)k * V + v] = or_gamma_draw(beta + (double)n[(size_t)k * V + v], seed, (uint32_t)v,
+                                                   (uint32_t)k, t);
+    for (int32_t k = 0; k < K; k++) {
+        double s = 0.0;
+        for (int32_t v = 0; v < V; v++) s += gam[(size_t)k * V + v];
+        S[k] = s;
+        if (s == 0.0) empty_rows++;
+        for (int32_t v = 0; v < V; v++) {
+            float f = s > 0.0 ? (float)(gam[(size_t)k * V + v] / s) : 0.0f;
+            phi[(size_t)k * V + v] = f >= flt_min ? f : 0.0f;
         }
     }
     return empty_rows;

@@ -43,6 +43,17 @@ MUTATIONS = [
     ("foldin_theta_no_prior", "theta[k] = (float)(((double)acc[k] / (double)(S - burn_in) + alpha[k])",
      "theta[k] = (float)(((double)acc[k] / (double)(S - burn_in))",
      [pins.test_foldin_outputs_definition]),
+    ("gamma_d_offset", "const double d = a1 - 1.0 / 3.0;", "const double d = a1 - 1.0 / 2.0;",
+     [lambda: pins.test_gamma_draw_law(2.5)]),
+    ("gamma_boost_power", "exp(log(u32o(boost)) / a)", "exp(log(u32o(boost)) * a)",
+     [lambda: pins.test_gamma_draw_law(0.3)]),
+    ("gamma_normal_variance", "sqrt(-2.0 * log(u32o(r[0])))", "sqrt(-1.0 * log(u32o(r[0])))",
+     [lambda: pins.test_gamma_draw_law(2.5)]),
+    ("dirichlet_shape_prior", "or_gamma_draw(beta + (double)n[", "or_gamma_draw(2.0 * beta + (double)n[",
+     [lambda: pins.test_phi_dirichlet_moments(0.5)]),
+    ("dirichlet_row_sum_skips", "double s = 0.0;\n        for (int32_t v = 0; v < V; v++) s += gam[",
+     "double s = 0.0;\n        for (int32_t v = 1; v < V; v++) s += gam[",
+     [lambda: pins.test_phi_dirichlet_moments(0.5)]),
     ("normalise_wrong_row", "phi[(size_t)k * V + v] = g > 0 ? (float)((double)g / (double)s) : 0.0f;",
      "phi[(size_t)k * V + v] = g > 0 ? (float)((double)g / (double)(s + 1)) : 0.0f;",
      [pins.test_phi_normalise_definition]),

@@ -293,6 +293,73 @@ def test_phi_normalise_definition():
 
 
 # --------------------------------------------------------------------------
+# Algorithm 1's Phi-step: phi_k ~ Dir(n_k + beta) through Gamma draws
+# (Marsaglia-Tsang), pinned to scipy's Gamma law and the Dirichlet's moments
+# --------------------------------------------------------------------------
+def _gamma_sample(a, R=20000, c1=7, t=3):
+    return np.array([oracle.gamma_draw(a, 11, i, c1, t) for i in range(R)])
+
+
+@pytest.mark.parametrize("a", [0.01, 0.3, 1.0, 2.5, 40.0, 3000.0])
+def test_gamma_draw_law(a):
+    x = _gamma_sample(a)
+    assert np.all(x >= 0) and np.all(np.isfinite(x))
+    # Kolmogorov-Smirnov against the G(a, 1) distribution function
+    assert stats.kstest(x, stats.gamma(a).cdf).pvalue > 1e-4
+    # mean and variance both equal a
+    assert abs(x.mean() - a) < 5 * math.sqrt(a / len(x))
+    if a >= 1:
+        se = math.sqrt((x.var() * 2 + 6 * a) / len(x)) * math.sqrt(a)
+        assert abs(x.var() - a) < 6 * se + 1e-12, (x.var(), a)
+
+
+def test_gamma_draw_is_a_function_of_its_counter():
+    assert oracle.gamma_draw(0.5, 3, 4, 5, 6) == oracle.gamma_draw(0.5, 3, 4, 5, 6)
+    assert oracle.gamma_draw(0.5, 3, 4, 5, 6) != oracle.gamma_draw(0.5, 3, 4, 5, 7)
+    # the boost of a < 1 scales the G(a + 1) draw of the same counter
+    g1 = oracle.gamma_draw(1.4, 3, 4, 5, 6)
+    g0 = oracle.gamma_draw(0.4, 3, 4, 5, 6)
+    assert 0 < g0 and (g0 <= g1)
+
+
+@pytest.mark.parametrize("beta", [0.01, 0.5])
+def test_phi_dirichlet_moments(beta):
+    row = np.array([0, 1, 1, 3], np.int32)
+    R = 40000
+    n = np.tile(row, (R, 1))
+    gam, S, phi, empty = oracle.phi_dirichlet(n, beta, 77, 3)
+    assert empty == 0
+    A = (row + beta).sum()
+    F = (row + beta) / A
+    var = F * (1 - F) / (A + 1)
+    x = gam / S[:, None]
+    m = x.mean(axis=0)
+    assert np.all(np.abs(m - F) < 5 * np.sqrt(var / R)), (m, F)
+    dev2 = (x - m) ** 2
+    v_hat = dev2.mean(axis=0)
+    se = dev2.std(axis=0) / np.sqrt(R)
+    assert np.all(np.abs(v_hat - var) < 5 * se), (v_hat, var, se)
+    cov = np.cov(x[:, 1], x[:, 3])[0, 1]
+    assert abs(cov / (-F[1] * F[3] / (A + 1)) - 1) < 0.05
+    # the Gamma draws themselves: shape beta + n per cell
+    assert np.all(np.abs(gam.mean(axis=0) - (row + beta)) < 5 * np.sqrt((row + beta) / R))
+
+
+def test_phi_dirichlet_rows_and_cut():
+    rng = np.random.default_rng(4)
+    n = rng.poisson(0.4, size=(6, 300)).astype(np.int32)
+    gam, S, phi, empty = oracle.phi_dirichlet(n, 0.01, 5, 2)
+    assert empty == 0
+    for k in range(6):
+        assert abs(S[k] - math.fsum(gam[k])) <= 300 * 2.0 ** -52 * S[k]
+        q = (gam[k] / S[k]).astype(np.float32)
+        assert np.array_equal(phi[k], np.where(q >= np.finfo(np.float32).tiny, q, 0))
+        assert abs(float(phi[k].astype(np.float64).sum()) - 1.0) < 300 * 2.0 ** -24
+    # tiny shapes underflow: some cells are cut, every counted cell stays
+    assert (phi == 0).any() and np.all(phi[n > 0] > 0)
+
+
+# --------------------------------------------------------------------------
 # Per-word a-part tables (Section 3.5): law alpha_k phi_kv / sigma_a
 # --------------------------------------------------------------------------
 def _random_phi(K, V, seed, density=0.3):
