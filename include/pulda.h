@@ -196,6 +196,29 @@ typedef struct {
     int64_t *S_dev;             /* [K] row sums of gamma (export only; may be NULL) */
 } pulda_phi_view;
 
+/* The Phi-step that pulda_phi_step and pulda_sweep run (default
+ * PULDA_PHI_POLYA_URN).  Either way the z-step that follows is the same.
+ *   PULDA_PHI_POLYA_URN: Algorithm 2's step, phi_k ~ PPU(n_k + beta): Poisson
+ *     draws gamma_kv ~ Pois(beta + n_kv) (alias tables for n_kv <= L, a
+ *     rounded Gaussian above), phi_kv = fp32(gamma_kv / S_k) (Section 3.4).
+ *   PULDA_PHI_DIRICHLET: Algorithm 1's step, phi_k ~ Dir(n_k + beta) by the
+ *     Gamma representation (Section 3.3): gamma_kv ~ G(beta + n_kv, 1) by
+ *     Marsaglia and Tsang's method (the one Section 3.4 names; boost for
+ *     shapes below 1), S_k = sum_v gamma_kv in fp64 (fixed order: ascending
+ *     within blocks of 256 words, then over the blocks), phi_kv =
+ *     fp32(gamma_kv / S_k); cells whose fp32 phi is below 2^-126 (zero or
+ *     subnormal) are zero, so Phi holds about K * V nonzeros and costs that
+ *     much memory traffic in the z-step.  Philox counter of attempt j of cell
+ *     (k, v) at sweep t: (v, k, t, 6 + 256 j).
+ * Invalid method: PULDA_ERR_INVALID_ARG.  A captured sweep graph is rebuilt. */
+enum { PULDA_PHI_POLYA_URN = 0, PULDA_PHI_DIRICHLET = 1 };
+pulda_status pulda_set_phi_method(pulda_plan *plan, int32_t method);
+
+/* After a Dirichlet Phi-step: its Gamma draws gamma_dev[V*K] (fp64,
+ * word-major: gamma_dev[v*K + k]) and row sums S_dev[K] (fp64); either may be
+ * NULL.  PULDA_ERR_STATE when the last Phi-step was not a Dirichlet one. */
+pulda_status pulda_get_gamma_dense(pulda_plan *plan, double *gamma_dev, double *S_dev, void *stream);
+
 /* Number of nonzeros of Phi after the last Phi-step.  Synchronises. */
 pulda_status pulda_phi_nnz(pulda_plan *plan, int64_t *nnz, void *stream);
 /* Write Phi (CSC by word), its alias tables and sigma_a. */

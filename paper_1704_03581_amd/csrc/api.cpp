@@ -133,7 +133,7 @@ struct pulda_plan {
     uint8_t *ws = nullptr;
     int64_t ws_need = 0;
     struct {
-        int64_t z, n, gam, phid, g16, Rd, ckg, colcnt, colptr, ctopic, cphi, calias, sigma_a, S, nk, alpha, pois, pois_off,
+        int64_t z, n, gam, phid, g16, Rd, gamd, Sd, dpart, ckg, colcnt, colptr, ctopic, cphi, calias, sigma_a, S, nk, alpha, pois, pois_off,
             doc_order, items, queue, stats, ll_part, ll_out, ll_hist, tptr, err, scratch, cnt_a, ptr_a, cnt_b,
             ptr_b, zsave, lg_beta, lg_alpha, lg_A, ll_doc;
     } off;
@@ -174,6 +174,7 @@ struct pulda_plan {
     // graph replay
     bool graph_on = false;
     bool fused_ll = true;  // document terms of the log joint inside the z-step
+    int32_t phi_method = PULDA_PHI_POLYA_URN;  // Phi-step of pulda_phi_step and pulda_sweep
     hipGraphExec_t gexec = nullptr;
     hipStream_t cap_stream = nullptr;  // private stream the sweep is captured on
     // phase timing (hipEvents on the caller's stream around each phase)
@@ -261,6 +262,9 @@ pulda_status pulda_plan_create(const pulda_model_desc *desc, int64_t D, int64_t 
     p->ks16 = (p->K + 63) / 64 * 64;
     p->off.g16 = L.take((int64_t)p->V * p->ks16 * 2);
     p->off.Rd = L.take((int64_t)p->K * 8);
+    p->off.gamd = L.take(VK * 8);
+    p->off.Sd = L.take((int64_t)p->K * 8);
+    p->off.dpart = L.take(((int64_t)p->V + ROWSUM_COLS - 1) / ROWSUM_COLS * p->K * 8);
     p->off.colcnt = L.take((int64_t)p->V * 4);
     p->off.colptr = L.take(((int64_t)p->V + 1) * 4);
     p->off.ctopic = L.take(p->cap * 2);
@@ -328,6 +332,10 @@ pulda_status pulda_plan_bind(pulda_plan *p, void *workspace_dev, int64_t bytes)
     m.g16 = (uint16_t *)(w + p->off.g16);
     m.ks16 = p->ks16;
     m.Rd = (double *)(w + p->off.Rd);
+    m.gamd = (double *)(w + p->off.gamd);
+    m.Sd = (double *)(w + p->off.Sd);
+    m.dpart = (double *)(w + p->off.dpart);
+    m.phi_method = 0;
     m.ckg = (uint32_t *)(w + p->off.ckg);
     m.colcnt = (int32_t *)(w + p->off.colcnt);
     m.colptr = (int32_t *)(w + p->off.colptr);
@@ -575,7 +583,9 @@ static pulda_status enqueue_phi(pulda_plan *p, hipStream_t s)
 {
     size_t a = 0, b = 0;
     if (p->timing) HIP_TRY(phase_event(p, s, &a));
-    HIP_TRY(launch_phi_step(p->m, p->stats, s));
+    p->m.phi_method = p->phi_method;
+    if (p->phi_method == PULDA_PHI_DIRICHLET) HIP_TRY(launch_phi_step_dirichlet(p->m, p->stats, s));
+    else HIP_TRY(launch_phi_step(p->m, p->stats, s));
     if (p->timing) {
         HIP_TRY(phase_event(p, s, &b));
         p->ev_phi.push_back({a, b});
@@ -838,6 +848,7 @@ pulda_status pulda_set_phi(pulda_plan *p, const pulda_phi_view *in, void *stream
     // values without draws behind them: R_k = 0 keeps 0 * R_k finite for the
     // zero cells (every nonzero cell is read from phid)
     HIP_TRY(launch_fill_u64((unsigned long long *)p->m.Rd, 0ull, p->K, s));
+    p->m.phi_method = PULDA_PHI_POLYA_URN;
     p->have_phi = true;
     return PULDA_OK;
 }
@@ -1013,6 +1024,31 @@ pulda_status pulda_set_fused_loglik(pulda_plan *p, int32_t enable)
         (void)hipGraphExecDestroy(p->gexec);
         p->gexec = nullptr;
     }
+    return PULDA_OK;
+}
+
+pulda_status pulda_set_phi_method(pulda_plan *p, int32_t method)
+{
+    if (!p) return fail(PULDA_ERR_INVALID_ARG, "null argument");
+    if (method != PULDA_PHI_POLYA_URN && method != PULDA_PHI_DIRICHLET)
+        return fail(PULDA_ERR_INVALID_ARG, "unknown Phi-step method %d", method);
+    p->phi_method = method;
+    if (p->gexec) {
+        (void)hipGraphExecDestroy(p->gexec);
+        p->gexec = nullptr;
+    }
+    return PULDA_OK;
+}
+
+pulda_status pulda_get_gamma_dense(pulda_plan *p, double *gamma_dev, double *S_dev, void *stream)
+{
+    if (!p) return fail(PULDA_ERR_INVALID_ARG, "null argument");
+    if (!p->have_phi || p->m.phi_method != PULDA_PHI_DIRICHLET)
+        return fail(PULDA_ERR_STATE, "the last Phi-step was not a Dirichlet Phi-step");
+    hipStream_t s = (hipStream_t)stream;
+    if (gamma_dev)
+        HIP_TRY(hipMemcpyAsync(gamma_dev, p->m.gamd, (size_t)p->V * p->K * 8, hipMemcpyDeviceToDevice, s));
+    if (S_dev) HIP_TRY(hipMemcpyAsync(S_dev, p->m.Sd, (size_t)p->K * 8, hipMemcpyDeviceToDevice, s));
     return PULDA_OK;
 }
 

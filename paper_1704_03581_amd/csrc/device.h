@@ -17,6 +17,8 @@ enum : uint32_t {
     TAG_Z = 3,           // token draw: ctr (i_lo, i_hi, t, TAG_Z)
     TAG_FOLDIN_INIT = 4, // fold-in initial topic: ctr (p, request, 0, TAG_FOLDIN_INIT)
     TAG_FOLDIN_Z = 5,    // fold-in token draw: ctr (p, request, sweep, TAG_FOLDIN_Z)
+    TAG_PHI_GAMMA = 6,   // attempt j of the G(beta + n_kv, 1) draw of cell (k, v) (Algorithm 1's
+                         // Phi-step): ctr (v, k, t, TAG_PHI_GAMMA + 256 j)
 };
 
 struct r4 {

@@ -31,6 +31,12 @@ struct DevModel {
     uint16_t *g16;
     int32_t ks16;
     double *Rd;                   // [K] RN64(1 / S_k) (0 for an empty row)
+    // Algorithm 1's Phi-step (phi_k ~ Dir(n_k + beta)): Gamma draws
+    // (word-major dense, fp64), their row sums, and per-block partial sums
+    double *gamd;                 // [V*K]
+    double *Sd;                   // [K]
+    double *dpart;                // [ceil(V / ROWSUM_COLS) * K]
+    int32_t phi_method;           // of the last Phi-step: 0 Polya urn, 1 Dirichlet
     int32_t *colcnt;              // [V]
     int32_t *colptr;              // [V+1]
     uint16_t *ctopic;             // [cap] CSC by word, ascending topic
@@ -100,6 +106,9 @@ hipError_t launch_init_z(const DevCorpus &c, int32_t K, uint32_t key0, uint32_t 
 hipError_t launch_count_rebuild(const DevCorpus &c, const DevModel &m, hipStream_t s);
 hipError_t launch_row_sums(const int32_t *dense, int32_t V, int32_t K, unsigned long long *out, hipStream_t s);
 hipError_t launch_phi_step(const DevModel &m, unsigned long long *stats, hipStream_t s);
+// Algorithm 1's Phi-step into the same Phi tables (m.phi_method must be 1)
+hipError_t launch_phi_step_dirichlet(const DevModel &m, unsigned long long *stats, hipStream_t s);
+constexpr int32_t ROWSUM_COLS = 256;      // words per block of the row-sum kernels
 // z-step: launch_z_prepare clears n and the three work queues; then one
 // persistent kernel per group size (16, 32, 64) over that size's work items.
 // With ll_doc non-null (symmetric alpha) the z-step also writes each

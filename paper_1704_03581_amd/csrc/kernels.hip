@@ -245,7 +245,6 @@ hipError_t launch_count_rebuild(const DevCorpus &c, const DevModel &m, hipStream
 }
 
 // column sums of a word-major V x K table: out[k] += sum_v dense[v*K + k]
-constexpr int ROWSUM_COLS = 256;
 
 __global__ void row_sums_kernel(const int32_t *dense, int32_t V, int32_t K, unsigned long long *out)
 {
@@ -353,6 +352,12 @@ __global__ void __launch_bounds__(256) phi_draw_kernel(DevModel m, int32_t kpad)
 // lists in ascending order; sigma_a = ascending fp64 sum of the weights).
 // One wave per column.
 // ---------------------------------------------------------------------------
+constexpr float FP32_MIN_NORMAL = 0x1p-126f;
+
+// DIR: Algorithm 1's Phi (fp64 Gamma draws gamd, fp64 row sums Sd): a cell
+// is nonzero when its fp32 phi is normal (>= 2^-126), and every nonzero
+// cell's 16-bit draw is the escape 0xFFFF (its phi is read from phid).
+template <bool DIR>
 __global__ void __launch_bounds__(64) phi_fill_kernel(DevModel m, int32_t kpad)
 {
     extern __shared__ double fill_lds[];
@@ -372,14 +377,26 @@ __global__ void __launch_bounds__(64) phi_fill_kernel(DevModel m, int32_t kpad)
     float *pcol = m.phid + (int64_t)v * K;
     uint16_t *g16col = m.g16 + (int64_t)v * m.ks16;
     int32_t run = 0;
+    const double *gdcol = m.gamd + (int64_t)v * K;
     for (int32_t k0 = 0; k0 < m.ks16; k0 += 64) {
         const int32_t k = k0 + lane;
-        int32_t x = k < K ? gcol[k] : 0;
         float f = 0.0f;
-        if (x > 0) f = (float)((double)x / (double)m.S[k]);
+        uint32_t x16 = 0;
+        int32_t x = 0;
+        if constexpr (DIR) {
+            if (k < K && m.Sd[k] > 0.0) {
+                f = (float)(gdcol[k] / m.Sd[k]);
+                f = f >= FP32_MIN_NORMAL ? f : 0.0f;
+            }
+            x = f > 0.0f;
+            x16 = x ? 0xFFFFu : 0u;
+        } else {
+            x = k < K ? gcol[k] : 0;
+            if (x > 0) f = (float)((double)x / (double)m.S[k]);
+            const bool exact = x < 0xFFFF && (k >= K || m.S[k] < (1ull << 27));
+            x16 = exact ? (uint32_t)x : 0xFFFFu;
+        }
         if (k < K) pcol[k] = f;
-        const bool exact = x < 0xFFFF && (k >= K || m.S[k] < (1ull << 27));
-        const uint32_t x16 = exact ? (uint32_t)x : 0xFFFFu;
         g16col[k] = (uint16_t)x16;
         const uint64_t bal = __builtin_amdgcn_ballot_w64(x > 0);
         if (x > 0) {
@@ -493,7 +510,151 @@ hipError_t launch_phi_step(const DevModel &m, unsigned long long *stats, hipStre
     }
     colptr_finish_kernel<<<1, 256, 0, s>>>(m.S, m.K, total, stats, m.Rd);
     const size_t lds = (size_t)kpad * (sizeof(double) + 4 * sizeof(uint16_t) + sizeof(uint32_t));
-    phi_fill_kernel<<<m.V, 64, lds, s>>>(m, kpad);
+    phi_fill_kernel<false><<<m.V, 64, lds, s>>>(m, kpad);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Algorithm 1's Phi-step: phi_k ~ Dir(n_k + beta) for every topic row, by
+// the Gamma representation of the Dirichlet (Section 3.3): gamma_kv ~
+// G(beta + n_kv, 1) and phi_kv = gamma_kv / S_k with S_k = sum_v gamma_kv.
+// Gamma draws by Marsaglia and Tsang's method, which Section 3.4 names: for
+// shape a >= 1, d = a - 1/3 and c = 1 / sqrt(9 d), a normal x gives
+// t = 1 + c x (rejected when t <= 0) and v = t^3, kept as d v when a
+// uniform u passes their squeeze u < 1 - 0.0331 x^4 or
+// log u < x^2 / 2 + d (1 - v + log v); shapes below 1 use their boost
+// G(a) = G(a + 1) U^(1/a), U^(1/a) taken as exp(log(U) / a).
+// Attempt j of cell (k, v) at sweep t reads Philox counter
+// (v, k, t, TAG_PHI_GAMMA + 256 j): the normal is Box-Muller's
+// sqrt(-2 log u(r0)) cos(2 pi u(r1)), u = u(r2), and r3 of attempt 0 is the
+// boost's U, with u(r) = (r + 1/2) 2^-32.  After 2^20 rejected attempts
+// (probability below 0.05^(2^20)) the draw is d.
+// ---------------------------------------------------------------------------
+constexpr uint32_t GAMMA_TRIES = 1u << 20;
+
+__device__ __forceinline__ double unit32o(uint32_t r) { return ((double)r + 0.5) * 0x1p-32; }
+
+__device__ double gamma_draw(double a, uint32_t c0, uint32_t c1, uint32_t t, uint32_t key0, uint32_t key1)
+{
+    const double two_pi = 6.283185307179586476925286766559;
+    const double a1 = a < 1.0 ? a + 1.0 : a;
+    const double d = a1 - 1.0 / 3.0;
+    const double c = 1.0 / sqrt(9.0 * d);
+    double g = d;
+    uint32_t boost = 0;
+    for (uint32_t j = 0; j < GAMMA_TRIES; ++j) {
+        const r4 r = philox(c0, c1, t, TAG_PHI_GAMMA + (j << 8), key0, key1);
+        if (j == 0) boost = r.w;
+        const double x = sqrt(-2.0 * log(unit32o(r.x))) * cos(two_pi * unit32o(r.y));
+        const double t1 = 1.0 + c * x;
+        if (t1 <= 0.0) continue;
+        const double v = t1 * t1 * t1;
+        const double u = unit32o(r.z);
+        const double x2 = x * x;
+        if (u < 1.0 - 0.0331 * (x2 * x2) || log(u) < 0.5 * x2 + d * (1.0 - v + log(v))) {
+            g = d * v;
+            break;
+        }
+    }
+    if (a < 1.0) g = g * exp(log(unit32o(boost)) / a);
+    return g;
+}
+
+// one cell per thread, word-major (cell v * K + k)
+__global__ void __launch_bounds__(256) gamma_kernel(DevModel m)
+{
+    const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t cells = (int64_t)m.V * m.K;
+    if (cell >= cells) return;
+    const uint32_t t = *m.tptr;
+    const int32_t v = (int32_t)(cell / m.K);
+    const int32_t k = (int32_t)(cell - (int64_t)v * m.K);
+    const double a = m.beta + (double)m.n[cell];
+    m.gamd[cell] = gamma_draw(a, (uint32_t)v, (uint32_t)k, t, m.key0, m.key1);
+}
+
+// S_k in two fixed-order passes (so the Phi-step is deterministic): block b
+// sums its ROWSUM_COLS words in ascending order per topic, then the blocks'
+// partial sums are added in ascending block order
+__global__ void dsum_part_kernel(DevModel m)
+{
+    const int32_t v0 = blockIdx.x * ROWSUM_COLS;
+    const int32_t v1 = v0 + ROWSUM_COLS < m.V ? v0 + ROWSUM_COLS : m.V;
+    for (int32_t k = threadIdx.x; k < m.K; k += blockDim.x) {
+        double s = 0.0;
+        for (int32_t v = v0; v < v1; ++v) s += m.gamd[(int64_t)v * m.K + k];
+        m.dpart[(int64_t)blockIdx.x * m.K + k] = s;
+    }
+}
+
+__global__ void dsum_final_kernel(DevModel m, int32_t nb)
+{
+    const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= m.K) return;
+    double s = 0.0;
+    for (int32_t b = 0; b < nb; ++b) s += m.dpart[(int64_t)b * m.K + k];
+    m.Sd[k] = s;
+}
+
+// nonzeros of each column: cells whose fp32 phi is normal; one wave per word
+__global__ void __launch_bounds__(256) dcount_kernel(DevModel m)
+{
+    const int32_t v = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (v >= m.V) return;
+    const int lane = __lane_id();
+    const double *gdcol = m.gamd + (int64_t)v * m.K;
+    int32_t cnt = 0;
+    for (int32_t k = lane; k < m.K; k += 64) {
+        const double S = m.Sd[k];
+        const float f = S > 0.0 ? (float)(gdcol[k] / S) : 0.0f;
+        cnt += f >= FP32_MIN_NORMAL;
+    }
+    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+    if (lane == 0) m.colcnt[v] = cnt;
+}
+
+__global__ void dcolptr_finish_kernel(const double *Sd, int32_t K, const long long *total,
+                                      unsigned long long *stats, double *Rd)
+{
+    if (threadIdx.x == 0 && stats) stats[ST_NNZ_PHI] = (unsigned long long)*total;
+    unsigned long long empty = 0;
+    for (int32_t k = threadIdx.x; k < K; k += blockDim.x) {
+        empty += Sd[k] == 0.0;
+        Rd[k] = 0.0;
+    }
+    for (int o = 32; o > 0; o >>= 1) empty += __shfl_down(empty, o, 64);
+    if ((threadIdx.x & 63) == 0 && empty && stats) atomicAdd(&stats[ST_EMPTY_ROWS], empty);
+}
+
+hipError_t launch_phi_step_dirichlet(const DevModel &m, unsigned long long *stats, hipStream_t s)
+{
+    if (m.phi_method != 1) return hipErrorInvalidValue;
+    const int64_t cells = (int64_t)m.V * m.K;
+    gamma_kernel<<<(unsigned)((cells + 255) / 256), 256, 0, s>>>(m);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int32_t nb = (m.V + ROWSUM_COLS - 1) / ROWSUM_COLS;
+    dsum_part_kernel<<<nb, 256, 0, s>>>(m);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    dsum_final_kernel<<<(m.K + 255) / 256, 256, 0, s>>>(m, nb);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    dcount_kernel<<<(m.V + 3) / 4, 256, 0, s>>>(m);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    long long *scratch = m.scratch;
+    long long *total = scratch + ((m.V + SCAN_BLOCK - 1) / SCAN_BLOCK) + 1;
+    e = scan_excl<int32_t, int32_t>(m.colcnt, m.colptr, m.V, scratch, total, s);
+    if (e != hipSuccess) return e;
+    if (stats) {
+        e = launch_fill_u64(&stats[ST_EMPTY_ROWS], 0ull, 1, s);
+        if (e != hipSuccess) return e;
+    }
+    dcolptr_finish_kernel<<<1, 256, 0, s>>>(m.Sd, m.K, total, stats, m.Rd);
+    const int32_t kpad = (m.K + 63) / 64 * 64;
+    const size_t lds = (size_t)kpad * (sizeof(double) + 4 * sizeof(uint16_t) + sizeof(uint32_t));
+    phi_fill_kernel<true><<<m.V, 64, lds, s>>>(m, kpad);
     return hipGetLastError();
 }
 
@@ -1448,7 +1609,7 @@ __global__ void export_phi_kernel(DevModel m, int64_t *colptr64, uint16_t *topic
         const int32_t k = m.ctopic[e];
         topic[e] = (uint16_t)k;
         phi_e[e] = m.cphi[e];
-        gam_e[e] = m.gam[(int64_t)v * m.K + k];
+        gam_e[e] = m.phi_method == 1 ? 0 : m.gam[(int64_t)v * m.K + k];
         const uint64_t al = m.calias[e];
         thr[e] = (uint32_t)al;
         alias_topic[e] = (uint16_t)(al >> 48);

@@ -94,6 +94,8 @@ _SIGS = {
     "pulda_set_graph": [vp, i32],
     "pulda_set_timing": [vp, i32],
     "pulda_set_fused_loglik": [vp, i32],
+    "pulda_set_phi_method": [vp, i32],
+    "pulda_get_gamma_dense": [vp, vp, vp, vp],
     "pulda_foldin_create": [vp, C.POINTER(FoldinDesc), C.POINTER(vp)],
     "pulda_foldin_workspace_bytes": [vp, C.POINTER(i64)],
     "pulda_foldin_bind": [vp, vp, i64],
@@ -323,6 +325,23 @@ class Plan:
 
     def set_graph(self, enable: bool):
         _check(_lib.pulda_set_graph(self._h, 1 if enable else 0))
+
+    PHI_METHODS = {"polya_urn": 0, "dirichlet": 1}
+
+    def set_phi_method(self, method: str):
+        """Phi-step of phi_step and sweep: "polya_urn" (Algorithm 2, the
+        default) or "dirichlet" (Algorithm 1: Gamma draws)."""
+        if method not in self.PHI_METHODS:
+            raise ValueError(f"unknown Phi-step method {method!r}")
+        _check(_lib.pulda_set_phi_method(self._h, self.PHI_METHODS[method]))
+
+    def gamma_dense(self, stream=None):
+        """After a Dirichlet Phi-step: the Gamma draws as a (K, V) fp64 array
+        (the paper's orientation) and the row sums S (fp64)."""
+        g = torch.empty(self.V * self.K, dtype=torch.float64, device=self.device)
+        S = torch.empty(self.K, dtype=torch.float64, device=self.device)
+        _check(_lib.pulda_get_gamma_dense(self._h, _ptr(g), _ptr(S), _stream(stream)))
+        return g.view(self.V, self.K).t().contiguous().cpu().numpy(), S.cpu().numpy()
 
     def set_fused_loglik(self, enable: bool):
         _check(_lib.pulda_set_fused_loglik(self._h, 1 if enable else 0))

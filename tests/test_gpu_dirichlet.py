@@ -1,0 +1,151 @@
+"""GPU parity of Algorithm 1's Phi-step (phi_k ~ Dir(n_k + beta) through
+Gamma draws), called through the C ABI, against the CPU oracle.
+
+Both sides evaluate the same fp64 expressions of Marsaglia and Tsang's
+method, but log, cos, exp and sqrt come from different libraries (the GPU's
+device library, the host's libm), each within about an ulp.  Through
+x = sqrt(-2 log u) cos(2 pi u'), v = (1 + c x)^3 and the boost
+exp(log(U) / a) the relative difference of a Gamma draw stays below
+|log U| / a * 2^-52 + 16 * 2^-52, at most about 2.4e-13 for shapes a >= 0.01
+and U >= 2^-32; the tests allow 1e-12.  S_k is summed in a different order on
+the two sides: |dS| <= V * 2^-52 * S_k.  phi = fp32(gamma / S) then differs by
+at most one fp32 ulp, and only for cells within that distance of a rounding
+midpoint.  The a-part tables are compared bit for bit with the oracle's built
+from the GPU's phi, and the z-step by the oracle's replay.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1704_03581_amd import synth
+from tests.gpu_helpers import phi_from_gpu, say
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_1704_03581_amd import pulda
+else:
+    pulda = None
+
+GAMMA_RTOL = 1e-12
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+CASES = {
+    "tiny": lambda: synth.generate("tiny", keep_true_z=False),
+    "k100": lambda: synth.small_random(D=120, V=800, K=100, mean_len=220.0, seed=4),
+    "k1000": lambda: synth.small_random(D=50, V=3000, K=1000, mean_len=500.0, seed=5),
+}
+_cache = {}
+
+
+def corpus(name):
+    if name not in _cache:
+        _cache[name] = CASES[name]()
+    return _cache[name]
+
+
+def make_plan(c, seed):
+    p = pulda.Plan(c.K, c.V, c.D, c.N, alpha=c.alpha, beta=c.beta, seed=seed)
+    p.upload(c.doc_off, c.words)
+    p.set_phi_method("dirichlet")
+    p.init()
+    return p
+
+
+def check_gamma(gam_g, S_g, gam_o, S_o, V):
+    scale = np.maximum(np.abs(gam_g), np.abs(gam_o))
+    bad = np.abs(gam_g - gam_o) > GAMMA_RTOL * scale + 1e-300
+    assert not bad.any(), (int(bad.sum()), np.argwhere(bad)[:5])
+    pos = scale > 1e-300
+    say(f"  gamma: max relative difference {float((np.abs(gam_g - gam_o)[pos] / scale[pos]).max()):.3g}")
+    assert np.all(np.abs(S_g - S_o) <= V * 2.0 ** -52 * S_o * 1.01)
+
+
+def check_phi(g, phi_o, alpha, K, V):
+    phi_g, wt_g = phi_from_gpu(g, K, V)
+    assert np.array_equal(phi_g > 0, phi_o > 0), "supports differ"
+    a = phi_g.view(np.int32).astype(np.int64)
+    b = phi_o.view(np.int32).astype(np.int64)
+    assert np.abs(a - b).max() <= 1, "phi differs by more than one fp32 ulp"
+    nz = phi_o > 0
+    same = (a == b)[nz].mean() if nz.any() else 1.0
+    say(f"  phi: {same:.6f} of the nonzero cells bit-equal")
+    assert same >= 0.999, same
+    # the a-part tables from the GPU's own phi, bit for bit
+    wt_o = oracle.word_tables(alpha, phi_g)
+    assert np.array_equal(wt_g.colptr, wt_o.colptr) and np.array_equal(wt_g.topic, wt_o.topic)
+    assert np.array_equal(wt_g.thr, wt_o.thr) and np.array_equal(wt_g.alias_topic, wt_o.alias_topic)
+    assert np.array_equal(wt_g.sigma_a.view(np.uint64), wt_o.sigma_a.view(np.uint64))
+    return phi_g, wt_g
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_dirichlet_phi_step(name):
+    c = corpus(name)
+    say(f"dirichlet phi-step {name} K={c.K} V={c.V}")
+    p = make_plan(c, seed=19)
+    n, _ = p.counts_dense()
+    for t in (1, 2):
+        p.phi_step(t)
+        gam_g, S_g = p.gamma_dense()
+        gam_o, S_o, phi_o, empty = oracle.phi_dirichlet(n, c.beta, 19, t)
+        check_gamma(gam_g, S_g, gam_o, S_o, c.V)
+        check_phi(p.get_phi(), phi_o, np.broadcast_to(c.alpha, (c.K,)), c.K, c.V)
+        st = p.stats()
+        assert st["empty_rows"] == empty
+        assert st["nnz_phi"] == int((phi_o > 0).sum())
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_dirichlet_z_step_replay(name):
+    c = corpus(name)
+    say(f"dirichlet z-step {name}")
+    p = make_plan(c, seed=23)
+    z0 = p.get_z()
+    p.phi_step(1)
+    phi, wt = phi_from_gpu(p.get_phi(), c.K, c.V)
+    p.z_step(1)
+    z1 = p.get_z()
+    r = oracle.replay(c.doc_off, c.words, z0, z1, 23, 1, phi, wt, c.K, c.V)
+    say(f"  replay {r}")
+    assert r["bad"] == 0, r
+    assert r["agree"] >= 0.9999 * c.N
+    n_o, _, _ = oracle.counts(c.doc_off, c.words, z1, c.K, c.V, with_m=False)
+    assert np.array_equal(p.counts_dense()[0], n_o)
+
+
+def test_dirichlet_sweeps_deterministic_and_graph():
+    c = corpus("k100")
+    say("dirichlet sweeps")
+    out = []
+    for graph in (False, False, True):
+        p = make_plan(c, seed=29)
+        p.set_graph(graph)
+        lls = p.sweep(1, 4)
+        out.append((p.get_z(), lls))
+    for z, lls in out[1:]:
+        assert np.array_equal(z, out[0][0]) and np.array_equal(lls, out[0][1])
+    ll_o = oracle.loglik(c.doc_off, c.words, out[0][0], c.alpha, c.beta, c.K, c.V)
+    assert abs(out[0][1][-1] - ll_o) <= 1e-10 * abs(ll_o)
+
+
+def test_switching_methods():
+    """The method applies from the next Phi-step on; the Gamma export refuses
+    a Polya-urn Phi."""
+    c = corpus("tiny")
+    p = make_plan(c, seed=31)
+    p.phi_step(1)
+    p.gamma_dense()
+    p.set_phi_method("polya_urn")
+    p.phi_step(2)
+    with pytest.raises(pulda.PuldaError):
+        p.gamma_dense()
+    with pytest.raises(ValueError):
+        p.set_phi_method("gibbs")
