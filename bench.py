@@ -138,6 +138,23 @@ def foldin_bench(args, torch, pulda, synth):
     return out
 
 
+def alg1_bench(plan, t, N, sweeps):
+    """Algorithm 1 (Phi-step phi_k ~ Dir(n_k + beta) by Gamma draws) on the
+    state the timed sweeps left, with the same z-step schedule: per-phase
+    times from hipEvents, beside the Polya-urn figures of the main run."""
+    plan.set_graph(False)
+    plan.set_timing(True)
+    plan.set_phi_method("dirichlet")
+    plan.stats()
+    plan.sweep(t, sweeps, want_ll=False)
+    st = plan.stats()
+    plan.set_phi_method("polya_urn")
+    z_ms = st["ms_z"] / st["n_z"]
+    return dict(sweeps=sweeps, phi_ms=st["ms_phi"] / st["n_phi"], z_ms=z_ms, z_tokens_per_s=N / (z_ms * 1e-3),
+                mean_J=st["sum_J"] / st["z_steps"] / N, a_fraction=st["sum_A"] / st["z_steps"] / N,
+                nnz_phi=st["nnz_phi"])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -157,6 +174,8 @@ def main():
     ap.add_argument("--cpu-docs", type=int, default=20000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-foldin", action="store_true")
+    ap.add_argument("--alg1-sweeps", type=int, default=3,
+                    help="sweeps with Algorithm 1's Dirichlet Phi-step after the timed region (0: none)")
     ap.add_argument("--foldin-requests", type=int, default=12000)
     ap.add_argument("--plain-requests", type=int, default=60)
     ap.add_argument("--slots", type=int, default=4096)
@@ -263,6 +282,13 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         res["cpu_baseline"] = cpu_baseline(corpus, args.seed, args.cpu_docs)
+    if args.alg1_sweeps > 0:
+        log(f"Algorithm 1 (Dirichlet Phi-step): {args.alg1_sweeps} sweeps")
+        res["alg1"] = alg1_bench(plan, t + args.steps, N, args.alg1_sweeps)
+        if "zstep" in res:
+            res["alg1"]["phi_speedup_polya_urn"] = res["alg1"]["phi_ms"] / res["zstep"]["phi_ms"]
+            res["alg1"]["z_speedup_polya_urn"] = res["alg1"]["z_ms"] / res["zstep"]["kernel_ms"]
+        log(f"alg1 {res['alg1']}")
     del plan
     torch.cuda.empty_cache()
     if not args.no_foldin:

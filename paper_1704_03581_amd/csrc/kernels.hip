@@ -837,6 +837,16 @@ __device__ __forceinline__ void lane_terms(const DevModel &M, const uint16_t *ls
         }
     }
     if constexpr (DOC) {
+        if (M.phi_method == 1) {
+            // Algorithm 1's Phi has no integer draws: phi itself is gathered
+#pragma unroll
+            for (int u = 0; u < KP; ++u) {
+                fk[u] = pcol[(uint32_t)kk[u]];
+                const int32_t m = mt[kk[u]];
+                mk[u] = ok[u] ? m : 0;
+            }
+            return;
+        }
 #pragma unroll
         for (int u = 0; u < KP; ++u) x[u] = g16col[(uint32_t)kk[u]];
     }
