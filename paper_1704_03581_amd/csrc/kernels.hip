@@ -347,89 +347,141 @@ __global__ void __launch_bounds__(256) phi_draw_kernel(DevModel m, int32_t kpad)
 
 // ---------------------------------------------------------------------------
 // Phi-step, part 3: normalise (phi = fp32(gamma / S_k), quotient in fp64),
-// compact the column into the CSC, and build the column's alias table for
-// the a-part (weights alpha_k phi_kv; Vose's construction with FIFO work
-// lists in ascending order; sigma_a = ascending fp64 sum of the weights).
-// One wave per column.
-// ---------------------------------------------------------------------------
-constexpr float FP32_MIN_NORMAL = 0x1p-126f;
-
+// write the dense tables and compact each column into the CSC (one wave per
+// column, no LDS, so many columns are in flight); then build each column's
+// alias table for the a-part (weights alpha_k phi_kv; Vose's construction
+// with FIFO work lists in ascending order; sigma_a = ascending fp64 sum of
+// the weights) from its compacted entries.
 // DIR: Algorithm 1's Phi (fp64 Gamma draws gamd, fp64 row sums Sd): a cell
 // is nonzero when its fp32 phi is normal (>= 2^-126), and every nonzero
 // cell's 16-bit draw is the escape 0xFFFF (its phi is read from phid).
+// ---------------------------------------------------------------------------
+constexpr float FP32_MIN_NORMAL = 0x1p-126f;
+
 template <bool DIR>
-__global__ void __launch_bounds__(64) phi_fill_kernel(DevModel m, int32_t kpad)
+__global__ void __launch_bounds__(256) phi_dense_kernel(DevModel m)
 {
-    extern __shared__ double fill_lds[];
-    const int32_t v = blockIdx.x;
+    const int32_t v = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (v >= m.V) return;
     const int lane = __lane_id();
     const int32_t K = m.K;
-    double *w = fill_lds;                                  // weights, then scaled probabilities
-    uint16_t *tk = (uint16_t *)(w + kpad);                 // topic of entry e
-    uint16_t *small = tk + kpad;                           // entries with p < 1, ascending
-    uint16_t *large = small + kpad;                        // entries with p >= 1, ascending
-    uint16_t *ali = large + kpad;                          // alias entry of e
-    uint32_t *thr = (uint32_t *)(ali + kpad);              // threshold of e
-    __shared__ double W_s;
-
     const int32_t cb = m.colptr[v];
     const int32_t *gcol = m.gam + (int64_t)v * K;
+    const double *gdcol = m.gamd + (int64_t)v * K;
     float *pcol = m.phid + (int64_t)v * K;
     uint16_t *g16col = m.g16 + (int64_t)v * m.ks16;
     int32_t run = 0;
-    const double *gdcol = m.gamd + (int64_t)v * K;
     for (int32_t k0 = 0; k0 < m.ks16; k0 += 64) {
         const int32_t k = k0 + lane;
         float f = 0.0f;
         uint32_t x16 = 0;
-        int32_t x = 0;
+        bool nz;
         if constexpr (DIR) {
             if (k < K && m.Sd[k] > 0.0) {
                 f = (float)(gdcol[k] / m.Sd[k]);
                 f = f >= FP32_MIN_NORMAL ? f : 0.0f;
             }
-            x = f > 0.0f;
-            x16 = x ? 0xFFFFu : 0u;
+            nz = f > 0.0f;
+            x16 = nz ? 0xFFFFu : 0u;
         } else {
-            x = k < K ? gcol[k] : 0;
-            if (x > 0) f = (float)((double)x / (double)m.S[k]);
+            const int32_t x = k < K ? gcol[k] : 0;
+            nz = x > 0;
+            if (nz) f = (float)((double)x / (double)m.S[k]);
             const bool exact = x < 0xFFFF && (k >= K || m.S[k] < (1ull << 27));
             x16 = exact ? (uint32_t)x : 0xFFFFu;
         }
         if (k < K) pcol[k] = f;
         g16col[k] = (uint16_t)x16;
-        const uint64_t bal = __builtin_amdgcn_ballot_w64(x > 0);
-        if (x > 0) {
+        const uint64_t bal = __builtin_amdgcn_ballot_w64(nz);
+        if (nz) {
             const int32_t e = run + __builtin_popcountll(bal & ((1ull << lane) - 1ull));
             m.ctopic[cb + e] = (uint16_t)k;
             m.cphi[cb + e] = f;
             m.ckg[cb + e] = (uint32_t)k | (x16 << 16);
-            tk[e] = (uint16_t)k;
-            w[e] = m.alpha[k] * (double)f;
         }
         run += __builtin_popcountll(bal);
     }
-    const int32_t nv = run;
-    __builtin_amdgcn_wave_barrier();
+}
+
+// Columns with at most ALIAS_SMALL nonzeros: one wave per column, four per
+// block (LDS of ALIAS_SMALL entries each); the others: one column per block
+// with K entries of LDS.  Per entry: a probability (fp64), a work-list
+// entry, its topic and alias entry (u16 each), its threshold (u32).
+constexpr int32_t ALIAS_SMALL = 256;
+constexpr size_t ALIAS_ENTRY_BYTES = sizeof(double) + 3 * sizeof(uint16_t) + sizeof(uint32_t);
+
+template <bool SMALL>
+__global__ void __launch_bounds__(SMALL ? 256 : 64) phi_alias_kernel(DevModel m, int32_t kpad)
+{
+    extern __shared__ double alias_lds[];
+    const int lane = __lane_id();
+    const int wave = threadIdx.x >> 6;
+    const int32_t v = SMALL ? blockIdx.x * 4 + wave : blockIdx.x;
+    if (v >= m.V) return;
+    const int32_t cb = m.colptr[v];
+    const int32_t nv = m.colptr[v + 1] - cb;
+    if (SMALL ? nv > ALIAS_SMALL : nv <= ALIAS_SMALL) return;
     if (nv == 0) {
         if (lane == 0) m.sigma_a[v] = 0.0;
         return;
     }
-    if (lane == 0) {
-        double s = 0.0;
-        for (int32_t e = 0; e < nv; ++e) s += w[e];
-        W_s = s;
-        m.sigma_a[v] = s;
+    const int32_t cap = SMALL ? ALIAS_SMALL : kpad;
+    // this wave's region: cap entries (cap is a multiple of 64, so every
+    // region and array stays 8-byte aligned)
+    double *pq = (double *)((uint8_t *)alias_lds + (size_t)wave * cap * ALIAS_ENTRY_BYTES);
+    uint16_t *lst = (uint16_t *)(pq + cap);   // small entries from the front, large ones from the back
+    uint16_t *tk = lst + cap;                 // topic of entry e
+    uint16_t *ali = tk + cap;                 // alias entry of e
+    uint32_t *thr = (uint32_t *)(ali + cap);  // threshold of e
+    // weights w_e = alpha_k phi_kv in entry order (pq holds them first;
+    // each lane also keeps its first MAXC chunks' weights in registers, all
+    // chunks' loads issued together)
+    constexpr int MAXC = SMALL ? ALIAS_SMALL / 64 : 16;
+    double wr[MAXC];
+#pragma unroll
+    for (int c = 0; c < MAXC; ++c) {
+        const int32_t e = c * 64 + lane;
+        wr[c] = 0.0;
+        if (e < nv) {
+            const int32_t k = m.ctopic[cb + e];
+            tk[e] = (uint16_t)k;
+            wr[c] = m.alpha[k] * (double)m.cphi[cb + e];
+            pq[e] = wr[c];
+        }
+    }
+    for (int32_t e = MAXC * 64 + lane; e < nv; e += 64) {
+        const int32_t k = m.ctopic[cb + e];
+        tk[e] = (uint16_t)k;
+        pq[e] = m.alpha[k] * (double)m.cphi[cb + e];
     }
     __builtin_amdgcn_wave_barrier();
-    const double W = W_s;
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    // sigma_a: the ascending sum, read eight entries at a time
+    double s = 0.0;
+    if (lane == 0) {
+        int32_t e = 0;
+        for (; e + 8 <= nv; e += 8) {
+            double b[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) b[u] = pq[e + u];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += b[u];
+        }
+        for (; e < nv; ++e) s += pq[e];
+        m.sigma_a[v] = s;
+    }
+    const double W = __shfl(s, 0, 64);
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    // p_e = w_e nv / W (w_e from registers: pq is reused); small
+    // entries (p < 1) go to the front of lst in ascending order, large ones
+    // to the back, the first large entry last; pq follows lst
     int32_t ns = 0, nl = 0;
-    for (int32_t e0 = 0; e0 < nv; e0 += 64) {
-        const int32_t e = e0 + lane;
+    auto classify = [&](int32_t e, double w) {
+        double p = 0.0;
         bool is_small = false;
         if (e < nv) {
-            const double p = (w[e] * (double)nv) / W;
-            w[e] = p;
+            p = (w * (double)nv) / W;
             is_small = p < 1.0;
             thr[e] = 0xFFFFFFFFu;
             ali[e] = (uint16_t)e;
@@ -438,43 +490,87 @@ __global__ void __launch_bounds__(64) phi_fill_kernel(DevModel m, int32_t kpad)
         const uint64_t bl = __builtin_amdgcn_ballot_w64(e < nv && !is_small);
         const uint64_t below = (1ull << lane) - 1ull;
         if (e < nv) {
-            if (is_small) small[ns + __builtin_popcountll(bs & below)] = (uint16_t)e;
-            else large[nl + __builtin_popcountll(bl & below)] = (uint16_t)e;
+            const int32_t at = is_small ? ns + __builtin_popcountll(bs & below)
+                                        : nv - 1 - (nl + __builtin_popcountll(bl & below));
+            lst[at] = (uint16_t)e;
+            pq[at] = p;
         }
         ns += __builtin_popcountll(bs);
         nl += __builtin_popcountll(bl);
+    };
+#pragma unroll
+    for (int c = 0; c < MAXC; ++c)
+        if (c * 64 < nv) classify(c * 64 + lane, wr[c]);
+    // chunks past MAXC (K > 64 MAXC) recompute their weights
+    for (int32_t e0 = MAXC * 64; e0 < nv; e0 += 64) {
+        const int32_t e = e0 + lane;
+        classify(e, e < nv ? m.alpha[tk[e]] * (double)m.cphi[cb + e] : 0.0);
     }
     __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     if (lane == 0) {
         // Vose's pairing.  The FIFO of small entries is the initial small
         // list followed by large entries in the order they turn small, and a
         // large entry can only turn small at the head of the large list, so
-        // both lists are walked with one index each.
-        int32_t i = 0, gi = 0;
-        double pg = nl > 0 ? w[large[0]] : 0.0;
-        while (gi < nl) {
-            int32_t s;
-            if (i < ns) s = small[i];
-            else if (i - ns < gi) s = large[i - ns];
-            else break;
-            const int32_t gidx = large[gi];
-            const double ps = w[s];
-            thr[s] = (uint32_t)floor(ps * 4294967296.0);
-            ali[s] = (uint16_t)gidx;
+        // both lists are walked with one index each.  A large entry that
+        // turns small leaves its residual in its own pq slot, where the FIFO
+        // reads it.  The initial small entries are read eight at a time.
+        int32_t gi = 0;
+        double pg = nl > 0 ? pq[nv - 1] : 0.0;
+        int32_t gidx = nl > 0 ? lst[nv - 1] : 0;
+        auto pair = [&](int32_t sm, double ps) {
+            thr[sm] = (uint32_t)floor(ps * 4294967296.0);
+            ali[sm] = (uint16_t)gidx;
             pg = (pg + ps) - 1.0;
-            ++i;
             if (pg < 1.0) {
-                w[gidx] = pg;
+                pq[nv - 1 - gi] = pg;
                 ++gi;
-                if (gi < nl) pg = w[large[gi]];
+                if (gi < nl) {
+                    pg = pq[nv - 1 - gi];
+                    gidx = lst[nv - 1 - gi];
+                }
             }
+        };
+        int32_t i = 0;
+        for (; i < ns && gi < nl; i += 8) {
+            int32_t sb[8];
+            double pb[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int32_t ii = i + u < ns ? i + u : ns - 1;
+                sb[u] = lst[ii];
+                pb[u] = pq[ii];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (i + u < ns && gi < nl) pair(sb[u], pb[u]);
         }
+        // then the large entries that turned small, in that order
+        for (int32_t j = 0; j < gi && gi < nl; ++j) pair(lst[nv - 1 - j], pq[nv - 1 - j]);
     }
     __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     for (int32_t e = lane; e < nv; e += 64) {
         const uint64_t entry = (uint64_t)thr[e] | ((uint64_t)tk[e] << 32) | ((uint64_t)tk[ali[e]] << 48);
         m.calias[cb + e] = entry;
     }
+}
+
+hipError_t launch_phi_fill(const DevModel &m, bool dir, hipStream_t s)
+{
+    if (dir) phi_dense_kernel<true><<<(m.V + 3) / 4, 256, 0, s>>>(m);
+    else phi_dense_kernel<false><<<(m.V + 3) / 4, 256, 0, s>>>(m);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int32_t kpad = (m.K + 63) / 64 * 64;
+    phi_alias_kernel<true><<<(m.V + 3) / 4, 256, 4 * ALIAS_SMALL * ALIAS_ENTRY_BYTES, s>>>(m, kpad);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (m.K > ALIAS_SMALL) {
+        phi_alias_kernel<false><<<m.V, 64, (size_t)kpad * ALIAS_ENTRY_BYTES, s>>>(m, kpad);
+        e = hipGetLastError();
+    }
+    return e;
 }
 
 __global__ void colptr_finish_kernel(const unsigned long long *S, int32_t K, const long long *total,
@@ -509,9 +605,7 @@ hipError_t launch_phi_step(const DevModel &m, unsigned long long *stats, hipStre
         if (e != hipSuccess) return e;
     }
     colptr_finish_kernel<<<1, 256, 0, s>>>(m.S, m.K, total, stats, m.Rd);
-    const size_t lds = (size_t)kpad * (sizeof(double) + 4 * sizeof(uint16_t) + sizeof(uint32_t));
-    phi_fill_kernel<false><<<m.V, 64, lds, s>>>(m, kpad);
-    return hipGetLastError();
+    return launch_phi_fill(m, false, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -652,10 +746,9 @@ hipError_t launch_phi_step_dirichlet(const DevModel &m, unsigned long long *stat
         if (e != hipSuccess) return e;
     }
     dcolptr_finish_kernel<<<1, 256, 0, s>>>(m.Sd, m.K, total, stats, m.Rd);
-    const int32_t kpad = (m.K + 63) / 64 * 64;
-    const size_t lds = (size_t)kpad * (sizeof(double) + 4 * sizeof(uint16_t) + sizeof(uint32_t));
-    phi_fill_kernel<true><<<m.V, 64, lds, s>>>(m, kpad);
-    return hipGetLastError();
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_phi_fill(m, true, s);
 }
 
 // ---------------------------------------------------------------------------
