@@ -406,9 +406,10 @@ __global__ void __launch_bounds__(256) phi_dense_kernel(DevModel m)
 // Columns with at most ALIAS_SMALL nonzeros: one wave per column, four per
 // block (LDS of ALIAS_SMALL entries each); the others: one column per block
 // with K entries of LDS.  Per entry: a probability (fp64), a work-list
-// entry, its topic and alias entry (u16 each), its threshold (u32).
+// entry, its topic, its alias entry and a turn record (u16 each), its
+// threshold (u32).
 constexpr int32_t ALIAS_SMALL = 256;
-constexpr size_t ALIAS_ENTRY_BYTES = sizeof(double) + 3 * sizeof(uint16_t) + sizeof(uint32_t);
+constexpr size_t ALIAS_ENTRY_BYTES = sizeof(double) + 4 * sizeof(uint16_t) + sizeof(uint32_t);
 
 template <bool SMALL>
 __global__ void __launch_bounds__(SMALL ? 256 : 64) phi_alias_kernel(DevModel m, int32_t kpad)
@@ -432,7 +433,8 @@ __global__ void __launch_bounds__(SMALL ? 256 : 64) phi_alias_kernel(DevModel m,
     uint16_t *lst = (uint16_t *)(pq + cap);   // small entries from the front, large ones from the back
     uint16_t *tk = lst + cap;                 // topic of entry e
     uint16_t *ali = tk + cap;                 // alias entry of e
-    uint32_t *thr = (uint32_t *)(ali + cap);  // threshold of e
+    uint16_t *turn = ali + cap;               // FIFO step at which large entry j turned small
+    uint32_t *thr = (uint32_t *)(turn + cap); // threshold of e
     // weights w_e = alpha_k phi_kv in entry order (pq holds them first;
     // each lane also keeps its first MAXC chunks' weights in registers, all
     // chunks' loads issued together)
@@ -508,45 +510,63 @@ __global__ void __launch_bounds__(SMALL ? 256 : 64) phi_alias_kernel(DevModel m,
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    // Vose's pairing.  The FIFO of small entries is the initial small list
+    // followed by large entries in the order they turn small, and a large
+    // entry can only turn small at the head of the large list, so both lists
+    // are walked with one index each.  FIFO step f pairs small entry sm(f),
+    // of probability ps(f), with the head of the large list: its threshold is
+    // floor(ps(f) 2^32), its alias the large entry at the head, and the
+    // head's probability becomes (pg + ps(f)) - 1; below 1 the head turns
+    // small (its residual joins the FIFO) and the next large entry leads.
+    // Only that chain of sums is sequential: lane 0 runs it and records the
+    // step at which each large entry turned small (its residual goes to its
+    // own pq slot); then all lanes write thresholds and aliases, the head
+    // at step f being large entry #{j : turn[j] < f}.
+    int32_t nf = 0, nturn = 0;
     if (lane == 0) {
-        // Vose's pairing.  The FIFO of small entries is the initial small
-        // list followed by large entries in the order they turn small, and a
-        // large entry can only turn small at the head of the large list, so
-        // both lists are walked with one index each.  A large entry that
-        // turns small leaves its residual in its own pq slot, where the FIFO
-        // reads it.  The initial small entries are read eight at a time.
-        int32_t gi = 0;
+        int32_t gi = 0, f = 0;
         double pg = nl > 0 ? pq[nv - 1] : 0.0;
-        int32_t gidx = nl > 0 ? lst[nv - 1] : 0;
-        auto pair = [&](int32_t sm, double ps) {
-            thr[sm] = (uint32_t)floor(ps * 4294967296.0);
-            ali[sm] = (uint16_t)gidx;
+        auto step = [&](double ps) {
             pg = (pg + ps) - 1.0;
             if (pg < 1.0) {
                 pq[nv - 1 - gi] = pg;
+                turn[gi] = (uint16_t)f;
                 ++gi;
-                if (gi < nl) {
-                    pg = pq[nv - 1 - gi];
-                    gidx = lst[nv - 1 - gi];
-                }
+                if (gi < nl) pg = pq[nv - 1 - gi];
             }
+            ++f;
         };
-        int32_t i = 0;
-        for (; i < ns && gi < nl; i += 8) {
-            int32_t sb[8];
+        // the initial small entries, read eight at a time
+        for (int32_t i = 0; i < ns && gi < nl; i += 8) {
             double pb[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int32_t ii = i + u < ns ? i + u : ns - 1;
-                sb[u] = lst[ii];
-                pb[u] = pq[ii];
-            }
+            for (int u = 0; u < 8; ++u) pb[u] = pq[i + u < ns ? i + u : ns - 1];
 #pragma unroll
             for (int u = 0; u < 8; ++u)
-                if (i + u < ns && gi < nl) pair(sb[u], pb[u]);
+                if (i + u < ns && gi < nl) step(pb[u]);
         }
         // then the large entries that turned small, in that order
-        for (int32_t j = 0; j < gi && gi < nl; ++j) pair(lst[nv - 1 - j], pq[nv - 1 - j]);
+        while (gi < nl && f - ns < gi) step(pq[nv - 1 - (f - ns)]);
+        nf = f;
+        nturn = gi;
+    }
+    nf = __shfl(nf, 0, 64);
+    nturn = __shfl(nturn, 0, 64);
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    for (int32_t f = lane; f < nf; f += 64) {
+        const int32_t at = f < ns ? f : nv - 1 - (f - ns);
+        const int32_t sm = lst[at];
+        const double ps = pq[at];
+        // head at step f: the number of large entries that turned before f
+        int32_t lo = 0, hi = nturn;
+        while (lo < hi) {
+            const int32_t mid = (lo + hi) >> 1;
+            if ((int32_t)turn[mid] < f) lo = mid + 1;
+            else hi = mid;
+        }
+        thr[sm] = (uint32_t)floor(ps * 4294967296.0);
+        ali[sm] = lst[nv - 1 - lo];
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
