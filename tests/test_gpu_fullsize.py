@@ -11,7 +11,11 @@ oracle can compute one by one.
   bit for bit;
 * fold-in against the large configuration's Phi (K=1000, V=141000), with the
   serving loop's draw budget: theta bit-exact and log-likelihood within
-  1e-12 for requests of every length class.
+  1e-12 for requests of every length class;
+* Algorithm 1's Dirichlet Phi-step on the large corpus's counts (141M
+  cells): sampled Gamma draws against the oracle's per-cell draw, every row
+  sum against an exact sum of the GPU's draws, phi within one fp32 ulp on the
+  samples, and the z-step on that Phi replayed for sampled documents.
 
 The large corpus is read from /tmp/pulda_large.npz when present (written by
 `bench.py --generate-only`), otherwise generated (about a minute).
@@ -132,3 +136,57 @@ def test_foldin_large_model():
         assert res["kept"] == kept and res["dropped"] == dropped
         assert np.array_equal(res["theta"], theta), rid
         assert abs(res["loglik"] - ll) <= 1e-12 * abs(ll), (rid, res["loglik"], ll)
+
+
+@pytest.mark.timeout(900)
+def test_large_dirichlet_phi_and_z_step():
+    import math
+    _need_gpu()
+    if os.path.exists(LARGE_CACHE):
+        c = synth.load(LARGE_CACHE)
+    else:
+        c = synth.generate("large", keep_true_z=False)
+    say(f"large, Dirichlet Phi: D={c.D} N={c.N}")
+    p = _plan(c, seed=3)
+    p.sweep(1, 2, want_ll=False)
+    p.set_phi_method("dirichlet")
+    t = 3
+    n, _ = p.counts_dense()
+    z0 = p.get_z()
+    p.phi_step(t)
+    gam, S = p.gamma_dense()
+    rng = np.random.default_rng(9)
+    ks = rng.integers(0, c.K, 4000)
+    vs = rng.integers(0, c.V, 4000)
+    # counted cells too: the most frequent word's column
+    top = int(np.argmax(n.sum(axis=0)))
+    ks = np.concatenate([ks, np.arange(c.K)])
+    vs = np.concatenate([vs, np.full(c.K, top)])
+    g_o = np.array([oracle.gamma_draw(c.beta + float(n[k, v]), 3, int(v), int(k), t) for k, v in zip(ks, vs)])
+    g_g = gam[ks, vs]
+    scale = np.maximum(np.abs(g_g), np.abs(g_o))
+    rel = np.abs(g_g - g_o) / np.where(scale > 0, scale, 1.0)
+    say(f"  {len(ks)} sampled Gamma draws: max relative difference {rel.max():.3g}")
+    assert np.all(np.abs(g_g - g_o) <= 1e-12 * scale + 1e-300)
+    # every row against numpy's sum, 50 rows against an exactly rounded sum
+    assert np.all(np.abs(S - gam.sum(axis=1)) <= 2 * c.V * 2.0 ** -52 * S)
+    for k in rng.choice(c.K, 50, replace=False):
+        exact = math.fsum(gam[k])
+        assert abs(S[k] - exact) <= c.V * 2.0 ** -52 * exact
+    g = p.get_phi()
+    phi, wt = phi_from_gpu(g, c.K, c.V)
+    del g
+    q = (g_g / S[ks]).astype(np.float32)
+    q = np.where(q >= np.finfo(np.float32).tiny, q, 0).astype(np.float32)
+    d = np.abs(phi[ks, vs].view(np.int32).astype(np.int64) - q.view(np.int32).astype(np.int64))
+    assert d.max() <= 1
+    del gam
+    p.z_step(t)
+    z1 = p.get_z()
+    lens = np.diff(c.doc_off)
+    docs = np.unique(rng.choice(np.nonzero(lens)[0], 2000, replace=False))
+    r = oracle.replay(c.doc_off, c.words, z0, z1, 3, t, phi, wt, c.K, c.V, docs=docs)
+    n_tok = int(lens[docs].sum())
+    say(f"  replay of {len(docs)} documents ({n_tok} tokens): {r}")
+    assert r["bad"] == 0, r
+    assert r["agree"] >= 0.9999 * n_tok
