@@ -163,6 +163,7 @@ struct pulda_plan {
     // work-item classes: (group size, count width) = (64, 16-bit), (32, 16),
     // (32, 8), (16, 16), (16, 8); 8-bit counts serve documents under 256 tokens
     static constexpr int NCLS = 7;
+    static_assert(NCLS <= Z_QUEUES, "one work queue per class");
     int32_t cls_first[NCLS] = {}, cls_count[NCLS] = {};
     int32_t n_cu = 0;                 // compute units of the device
     // internal streams: the three group-size kernels of a z-step run
@@ -279,7 +280,7 @@ pulda_status pulda_plan_create(const pulda_model_desc *desc, int64_t D, int64_t 
     p->off.pois_off = L.take((int64_t)p->pois_off_h.size() * 4);
     p->off.doc_order = L.take(D * 4);
     p->off.items = L.take(p->items_cap * (int64_t)sizeof(WorkItem));
-    p->off.queue = L.take(32);
+    p->off.queue = L.take(Z_QUEUES * 4);
     p->off.stats = L.take(ST_COUNT * 8);
     p->off.ll_part = L.take((int64_t)(p->n_part_words + p->n_part_docs) * 8);
     p->off.ll_out = L.take(8);

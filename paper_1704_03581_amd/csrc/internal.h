@@ -95,6 +95,10 @@ inline ZLayout z_layout(int32_t group, bool narrow, int32_t K)
 // ST_TOKENS counts z-step launches since the last statistics read
 constexpr int32_t LG_TABLE = 65536;
 
+// work-item queues of a z-step: one atomic counter per class, cleared by
+// launch_z_prepare
+constexpr int32_t Z_QUEUES = 16;
+
 enum StatIndex { ST_DEGENERATE = 0, ST_SUM_J = 1, ST_SUM_A = 2, ST_NNZ_PHI = 3, ST_EMPTY_ROWS = 4, ST_TOKENS = 5,
                  ST_COUNT = 8 };
 
@@ -109,7 +113,7 @@ hipError_t launch_phi_step(const DevModel &m, unsigned long long *stats, hipStre
 // Algorithm 1's Phi-step into the same Phi tables (m.phi_method must be 1)
 hipError_t launch_phi_step_dirichlet(const DevModel &m, unsigned long long *stats, hipStream_t s);
 constexpr int32_t ROWSUM_COLS = 256;      // words per block of the row-sum kernels
-// z-step: launch_z_prepare clears n and the three work queues; then one
+// z-step: launch_z_prepare clears n and the Z_QUEUES work queues; then one
 // persistent kernel per group size (16, 32, 64) over that size's work items.
 // With ll_doc non-null (symmetric alpha) the z-step also writes each
 // document's term of the log joint for the state it leaves.

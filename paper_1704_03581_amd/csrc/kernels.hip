@@ -1514,7 +1514,7 @@ hipError_t launch_z_prepare(const DevModel &m, int32_t *queues, unsigned long lo
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    return launch_fill_u32((uint32_t *)queues, 0u, 8, s);
+    return launch_fill_u32((uint32_t *)queues, 0u, Z_QUEUES, s);
 }
 
 hipError_t launch_z_class(const DevCorpus &c, const DevModel &m, int32_t group, bool narrow, const WorkItem *items,
