@@ -22,7 +22,7 @@ _SRC = os.path.join(_HERE, "pulda_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
-TAG_INIT, TAG_PHI_CELL, TAG_PHI_PRIOR, TAG_Z, TAG_FOLDIN_INIT, TAG_FOLDIN_Z, TAG_PHI_GAMMA = range(7)
+TAG_INIT, TAG_PHI_CELL, TAG_PHI_PRIOR, TAG_Z, TAG_FOLDIN_INIT, TAG_FOLDIN_Z, TAG_PHI_GAMMA, TAG_LTR = range(8)
 
 
 def build() -> str:
@@ -80,6 +80,9 @@ def _declare(L):
     L.or_foldin.argtypes = [C.c_int32, C.c_int32, f32p, i64p, u16p, u32p, u16p, f64p, f64p, C.c_uint64,
                             C.c_uint32, i32p, C.c_int32, C.c_int32, C.c_int32, f32p, f64p, i32p, u16p]
     L.or_foldin.restype = C.c_int32
+    L.or_heldout_ltr.argtypes = [C.c_int32, C.c_int32, f32p, i64p, u16p, u32p, u16p, f64p, f64p, C.c_uint64,
+                                 C.c_uint32, i32p, C.c_int32, C.c_int32, f64p, i32p]
+    L.or_heldout_ltr.restype = C.c_double
     L.or_token_pmf.argtypes = [C.c_int32, C.c_int32, f32p, i64p, u16p, u32p, u16p, f64p, C.c_int32, i32p,
                                f64p, f64p]
 
@@ -311,3 +314,19 @@ class Sampler:
         self.phi_step(t)
         self.z_step(t)
         return self.loglik()
+
+
+def heldout_ltr(phi, wt, alpha, seed, req, words, R, want_Z=False):
+    """Left-to-right held-out estimate of log p(words | Phi, alpha) with R
+    particles.  Returns (estimate, kept tokens[, Z (R x kept)])."""
+    phi = _c(phi, np.float32)
+    K, V = phi.shape
+    alpha = _c(np.broadcast_to(alpha, (K,)), np.float64)
+    words = _c(words, np.int32)
+    kept = C.c_int32()
+    Zs = np.zeros((R, max(len(words), 1)), np.float64) if want_Z else None
+    ll = lib().or_heldout_ltr(K, V, *_model_args(phi, wt), _p(alpha, C.c_double), seed, req, _p(words, C.c_int32),
+                              len(words), R, _p(Zs, C.c_double) if want_Z else None, C.byref(kept))
+    if want_Z:
+        return ll, kept.value, Zs[:, :kept.value].copy() if kept.value else Zs[:, :0]
+    return ll, kept.value

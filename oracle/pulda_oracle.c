@@ -39,6 +39,9 @@
  *   6. The Phi-step of Algorithm 1 (the partially collapsed sampler the
  *      urn replaces): phi_k ~ Dir(n_k + beta) through Gamma draws (see
  *      or_phi_dirichlet); its z-step is step 2 on the resulting Phi.
+ *   7. The held-out log-likelihood of a new document by the left-to-right
+ *      algorithm, which Section 4 uses to compare the two samplers' topics
+ *      (see or_heldout_ltr).
  *
  * Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random
  * numbers: as easy as 1, 2, 3", SC'11), keyed by the sampler seed, with the
@@ -51,7 +54,7 @@
 #include <string.h>
 
 enum { TAG_INIT = 0, TAG_PHI_CELL = 1, TAG_PHI_PRIOR = 2, TAG_Z = 3, TAG_FOLDIN_INIT = 4, TAG_FOLDIN_Z = 5,
-       TAG_PHI_GAMMA = 6 };
+       TAG_PHI_GAMMA = 6, TAG_LTR = 7 };
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-10 (Salmon et al. 2011): 10 rounds of the 4x32 S-box, the key  */
@@ -723,4 +726,67 @@ void or_token_pmf(int32_t K, int32_t V, const float *phi, const int64_t *colptr,
     for (int32_t k = 0; k < K; k++) mass_b[k] = (double)cnt[k] / 16777216.0;
     *mass_a = (double)na / 16777216.0;
     free(cnt);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Held-out log-likelihood of a new document, log p(w_d | Phi, alpha), by the */
+/* left-to-right algorithm of Wallach, Murray, Salakhutdinov and Mimno        */
+/* (2009, "Evaluation methods for topic models"), which Section 4 uses for    */
+/* the held-out comparison.  Tokens whose word is >= V or whose Phi column is */
+/* empty are dropped (as in fold-in); the nk kept tokens are taken in order.  */
+/* R independent particles; at step n (n = 0 .. nk-1) each particle first    */
+/* redraws its topics z_q, q = 0 .. n-1, in order, each from the token        */
+/* conditional of Section 3.5 given its other topics among the first n, then */
+/* takes                                                                      */
+/*   Z_n = sum_k phi_{k,w_n} (m_k + alpha_k) = sigma_a(w_n) + sigma_b(w_n)     */
+/* over its topics z_<n (the normaliser of the conditional of token n), and   */
+/* draws z_n from that conditional.  The estimate is                          */
+/*   sum_n log( (1/R) sum_r Z_n^(r) / (n + A) ),  A = sum_k alpha_k.           */
+/* Random numbers: particle r's draw of token q at step n uses Philox counter */
+/* (q, n, req, LTR + 256 r) (q = n for the new token).  Zs (R x nk, or NULL)   */
+/* receives every Z_n^(r).  Returns the estimate.                             */
+/* ------------------------------------------------------------------------ */
+double or_heldout_ltr(int32_t K, int32_t V, const float *phi, const int64_t *colptr, const uint16_t *topic,
+                      const uint32_t *thr, const uint16_t *alias_topic, const double *sigma_a,
+                      const double *alpha, uint64_t seed, uint32_t req, const int32_t *words, int32_t len,
+                      int32_t R, double *Zs, int32_t *kept_out)
+{
+    or_model M = {K, V, phi, colptr, topic, thr, alias_topic, sigma_a};
+    int32_t *pos = (int32_t *)malloc(sizeof(int32_t) * (size_t)(len > 0 ? len : 1));
+    int32_t nk = 0;
+    for (int32_t p = 0; p < len; p++) {
+        int32_t v = words[p];
+        if (v < 0 || v >= V || colptr[v + 1] == colptr[v]) continue;
+        pos[nk++] = p;
+    }
+    *kept_out = nk;
+    int32_t *z = (int32_t *)malloc(sizeof(int32_t) * (size_t)R * (size_t)(nk > 0 ? nk : 1));
+    int32_t *m = (int32_t *)calloc((size_t)R * (size_t)K, sizeof(int32_t));
+    double A = 0.0;
+    for (int32_t k = 0; k < K; k++) A += alpha[k];
+    double ll = 0.0;
+    for (int32_t n = 0; n < nk; n++) {
+        double sum = 0.0;
+        for (int32_t r = 0; r < R; r++) {
+            int32_t *zr = z + (size_t)r * nk;
+            int32_t *mr = m + (size_t)r * K;
+            uint32_t rr[4];
+            int a;
+            for (int32_t q = 0; q < n; q++) {
+                mr[zr[q]]--;
+                draw4(seed, (uint32_t)q, (uint32_t)n, req, TAG_LTR + ((uint32_t)r << 8), rr);
+                zr[q] = draw_token(&M, words[pos[q]], mr, rr, &a, NULL, NULL);
+                mr[zr[q]]++;
+            }
+            double Z;
+            draw4(seed, (uint32_t)n, (uint32_t)n, req, TAG_LTR + ((uint32_t)r << 8), rr);
+            zr[n] = draw_token(&M, words[pos[n]], mr, rr, &a, NULL, &Z);
+            mr[zr[n]]++;
+            if (Zs) Zs[(size_t)r * nk + n] = Z;
+            sum += Z / ((double)n + A);
+        }
+        ll += log(sum / (double)R);
+    }
+    free(pos); free(z); free(m);
+    return ll;
 }

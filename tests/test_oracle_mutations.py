@@ -54,6 +54,14 @@ MUTATIONS = [
     ("dirichlet_row_sum_skips", "double s = 0.0;\n        for (int32_t v = 0; v < V; v++) s += gam[",
      "double s = 0.0;\n        for (int32_t v = 1; v < V; v++) s += gam[",
      [lambda: pins.test_phi_dirichlet_moments(0.5)]),
+    ("ltr_no_redraws", "for (int32_t q = 0; q < n; q++) {\n                mr[zr[q]]--;",
+     "for (int32_t q = 0; q < 0; q++) {\n                mr[zr[q]]--;",
+     [pins.test_ltr_third_token_expectation]),
+    ("ltr_token_kept_in_counts", "                mr[zr[q]]--;\n                draw4(seed, (uint32_t)q,",
+     "                draw4(seed, (uint32_t)q,",
+     [pins.test_ltr_third_token_expectation]),
+    ("ltr_denominator", "sum += Z / ((double)n + A);", "sum += Z / ((double)n + 1.0 + A);",
+     [pins.test_ltr_single_token_closed_form]),
     ("normalise_wrong_row", "phi[(size_t)k * V + v] = g > 0 ? (float)((double)g / (double)s) : 0.0f;",
      "phi[(size_t)k * V + v] = g > 0 ? (float)((double)g / (double)(s + 1)) : 0.0f;",
      [pins.test_phi_normalise_definition]),

@@ -569,3 +569,85 @@ def test_sweep_invariants_and_column_nonzeros():
         s.z_step(t)
         assert np.array_equal(s.n.sum(axis=0), np.bincount(c.words, minlength=c.V))
     assert s.loglik() > ll0
+
+
+# --------------------------------------------------------------------------
+# Held-out log-likelihood by the left-to-right algorithm (the estimator
+# Section 4 uses): a single token's closed form, the second token's
+# predictive law, and the third token's expectation under the algorithm's own
+# resampling, all by enumeration
+# --------------------------------------------------------------------------
+def _ltr_model(K, V, alpha, seed):
+    rng = np.random.default_rng(seed)
+    phi = rng.dirichlet(np.full(V, 0.7), size=K).astype(np.float32)
+    return phi, oracle.word_tables(alpha, phi)
+
+
+def _cond(phi, alpha, v, m):
+    w = phi[:, v].astype(np.float64) * (m + alpha)
+    return w / w.sum()
+
+
+def test_ltr_single_token_closed_form():
+    alpha = np.array([0.2, 0.5, 0.9, 0.1])
+    phi, wt = _ltr_model(4, 6, alpha, 3)
+    ll, kept = oracle.heldout_ltr(phi, wt, alpha, 5, 1, np.array([6, 2, 9]), R=7)
+    assert kept == 1
+    ref = math.log(float((phi[:, 2].astype(np.float64) * alpha).sum()) / alpha.sum())
+    assert abs(ll - ref) <= 1e-14 * abs(ref)
+
+
+def test_ltr_second_token_predictive():
+    K, V = 3, 4
+    alpha = np.array([0.2, 0.5, 0.9])
+    phi, wt = _ltr_model(K, V, alpha, 4)
+    w = np.array([1, 2])
+    R = 100000
+    ll, kept, Z = oracle.heldout_ltr(phi, wt, alpha, 9, 2, w, R=R, want_Z=True)
+    A = alpha.sum()
+    f = phi.astype(np.float64)
+    assert np.allclose(Z[:, 0], (f[:, 1] * alpha).sum(), rtol=1e-15)
+    p0 = _cond(phi, alpha, 1, np.zeros(K))
+    EZ1 = sum(p0[z] * (f[:, 2] * (np.eye(K)[z] + alpha)).sum() for z in range(K))
+    se = Z[:, 1].std() / math.sqrt(R)
+    assert abs(Z[:, 1].mean() - EZ1) < 5 * se
+    # the estimate's second term is the log of the particles' mean (summed
+    # in another order here: up to R * 2^-52 apart)
+    assert abs(ll - (math.log(Z[0, 0] / A) + math.log(Z[:, 1].mean() / (1 + A)))) < 1e-10
+
+
+def _ltr_third_expectation(phi, alpha, w, resample=True):
+    K = phi.shape[1 - 1]
+    f = phi.astype(np.float64)
+    E = np.eye(K)
+    tot = 0.0
+    p0 = _cond(phi, alpha, w[0], np.zeros(K))
+    for a in range(K):                      # step 1: z_0 redrawn alone, then z_1
+        p1 = _cond(phi, alpha, w[1], E[a])
+        for b in range(K):
+            pr = p0[a] * p1[b]
+            if not resample:
+                tot += pr * (f[:, w[2]] * (E[a] + E[b] + alpha)).sum()
+                continue
+            q0 = _cond(phi, alpha, w[0], E[b])  # step 2: z_0 given z_1, then z_1 given z_0
+            for c in range(K):
+                q1 = _cond(phi, alpha, w[1], E[c])
+                for d in range(K):
+                    tot += pr * q0[c] * q1[d] * (f[:, w[2]] * (E[c] + E[d] + alpha)).sum()
+    return tot
+
+
+def test_ltr_third_token_expectation():
+    K, V = 2, 3
+    alpha = np.array([0.3, 0.7])
+    phi = np.array([[0.8, 0.05, 0.15], [0.1, 0.6, 0.3]], np.float32)
+    wt = oracle.word_tables(alpha, phi)
+    w = np.array([0, 1, 2])
+    R = 200000
+    _, kept, Z = oracle.heldout_ltr(phi, wt, alpha, 13, 3, w, R=R, want_Z=True)
+    assert kept == 3
+    se = Z[:, 2].std() / math.sqrt(R)
+    exact = _ltr_third_expectation(phi, alpha, w)
+    assert abs(Z[:, 2].mean() - exact) < 5 * se, (Z[:, 2].mean(), exact, se)
+    # without step 2's redraws the expectation differs: the pin tells them apart
+    assert abs(_ltr_third_expectation(phi, alpha, w, resample=False) - exact) > 10 * se
