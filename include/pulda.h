@@ -356,6 +356,37 @@ pulda_status pulda_foldin_poll(pulda_foldin *f, pulda_foldin_result *out, float 
 pulda_status pulda_foldin_occupancy(const pulda_foldin *f, int32_t *resident, int32_t *free_slots,
                                     int32_t *free_tokens);
 
+/* ------------------------------------------------------------------------ */
+/* Held-out log-likelihood of new documents                                  */
+/* ------------------------------------------------------------------------ */
+/* log p(w_d | Phi, alpha) of D documents by the left-to-right algorithm of
+ * Wallach, Murray, Salakhutdinov and Mimno (2009), the estimator the paper's
+ * Section 4 uses for its held-out comparison, against the plan's current Phi
+ * (a Phi-step's or pulda_set_phi's).  Tokens whose word is >= V or whose Phi
+ * column is empty are dropped.  Each of R particles, at step n (over the kept
+ * tokens in order), redraws its topics of tokens 0..n-1 in order from the
+ * token conditional of Section 3.5 (phi_kv (alpha_k + m_k), the fold-in and
+ * z-step draw), then takes Z_n = sum_k phi_{k,w_n} (m_k + alpha_k) over its
+ * topics of tokens 0..n-1 and draws z_n.  ll_dev[d] = sum_n log((1/R)
+ * sum_r Z_n^(r) / (n + A)), A = sum_k alpha_k.  The cost is about R n^2 / 2
+ * token draws per document of n tokens.
+ *   doc_off_dev[D+1], words_dev[N]: the documents (device, CSR; each at most
+ *     65535 tokens; the offsets are copied to the host and checked:
+ *     PULDA_ERR_CORPUS).
+ *   req_dev[D]: request ids; particle r's draw of token q at step n uses
+ *     Philox counter (q, n, req, 7 + 256 r) under seed.
+ *   particles in [1, 2^24); group: lanes per particle (16, 32, 64).
+ *   workspace_dev: pulda_heldout_workspace_bytes(model, N, particles) bytes,
+ *     256-byte aligned, caller-owned.
+ *   ll_dev[D] (fp64) and kept_dev[D] (kept tokens) are written; Z_dev (R*N
+ *     fp64, or NULL) receives Z_n^(r) of document d at doc_off[d]*R + r*N_d + n.
+ * Stream-ordered after the offset check (which synchronises the stream). */
+pulda_status pulda_heldout_workspace_bytes(const pulda_plan *model, int64_t N, int32_t particles, int64_t *bytes);
+pulda_status pulda_heldout_loglik(const pulda_plan *model, int64_t D, const int64_t *doc_off_dev,
+                                  const int32_t *words_dev, const uint32_t *req_dev, int32_t particles, int32_t group,
+                                  uint64_t seed, void *workspace_dev, int64_t workspace_bytes, double *ll_dev,
+                                  int32_t *kept_dev, double *Z_dev, void *stream);
+
 /* The plain per-document sampler: runs one request alone, all sweeps in one
  * launch, and waits for it (uses the server's workspace; the server must be
  * empty).  Same results as the batched path. */

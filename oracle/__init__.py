@@ -324,9 +324,10 @@ def heldout_ltr(phi, wt, alpha, seed, req, words, R, want_Z=False):
     alpha = _c(np.broadcast_to(alpha, (K,)), np.float64)
     words = _c(words, np.int32)
     kept = C.c_int32()
-    Zs = np.zeros((R, max(len(words), 1)), np.float64) if want_Z else None
+    # R x kept values, row stride = kept (at most R x len)
+    Zs = np.zeros(R * max(len(words), 1), np.float64) if want_Z else None
     ll = lib().or_heldout_ltr(K, V, *_model_args(phi, wt), _p(alpha, C.c_double), seed, req, _p(words, C.c_int32),
                               len(words), R, _p(Zs, C.c_double) if want_Z else None, C.byref(kept))
     if want_Z:
-        return ll, kept.value, Zs[:, :kept.value].copy() if kept.value else Zs[:, :0]
+        return ll, kept.value, Zs[:R * kept.value].reshape(R, kept.value).copy()
     return ll, kept.value

@@ -1309,4 +1309,76 @@ pulda_status pulda_foldin_run_one(pulda_foldin *f, uint32_t req, const int32_t *
     return PULDA_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Held-out log-likelihood (left-to-right estimate)
+// ---------------------------------------------------------------------------
+static int64_t heldout_bytes(int64_t N, int32_t R)
+{
+    Layout L;
+    L.take(N * R * 4);
+    L.take(N * R * 2);
+    L.take(N * R * 8);
+    return L.total;
+}
+
+pulda_status pulda_heldout_workspace_bytes(const pulda_plan *model, int64_t N, int32_t particles, int64_t *bytes)
+{
+    if (!model || !bytes) return fail(PULDA_ERR_INVALID_ARG, "null argument");
+    if (N < 0 || particles < 1 || particles >= (1 << 24))
+        return fail(PULDA_ERR_INVALID_ARG, "N=%lld, particles=%d", (long long)N, particles);
+    *bytes = heldout_bytes(N, particles);
+    return PULDA_OK;
+}
+
+pulda_status pulda_heldout_loglik(const pulda_plan *model, int64_t D, const int64_t *doc_off_dev,
+                                  const int32_t *words_dev, const uint32_t *req_dev, int32_t particles, int32_t group,
+                                  uint64_t seed, void *workspace_dev, int64_t workspace_bytes, double *ll_dev,
+                                  int32_t *kept_dev, double *Z_dev, void *stream)
+{
+    if (!model || !doc_off_dev || !req_dev || !ll_dev || !kept_dev || (D > 0 && !workspace_dev))
+        return fail(PULDA_ERR_INVALID_ARG, "null argument");
+    if (!model->have_phi) return fail(PULDA_ERR_STATE, "the model has no Phi");
+    if (D < 0 || D >= (1ll << 31)) return fail(PULDA_ERR_INVALID_ARG, "D=%lld", (long long)D);
+    if (particles < 1 || particles >= (1 << 24)) return fail(PULDA_ERR_INVALID_ARG, "particles=%d", particles);
+    if (group != 16 && group != 32 && group != 64) return fail(PULDA_ERR_INVALID_ARG, "group %d", group);
+    if ((uintptr_t)workspace_dev % ALIGN) return fail(PULDA_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    if (D == 0) return PULDA_OK;
+    hipStream_t s = (hipStream_t)stream;
+    // the offsets are checked on the host before any launch
+    std::vector<int64_t> off(D + 1);
+    HIP_TRY(hipMemcpyAsync(off.data(), doc_off_dev, (D + 1) * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (off[0] != 0) return fail(PULDA_ERR_CORPUS, "doc_off[0] = %lld", (long long)off[0]);
+    for (int64_t d = 0; d < D; ++d)
+        if (off[d + 1] < off[d] || off[d + 1] - off[d] > 65535)
+            return fail(PULDA_ERR_CORPUS, "document %lld: offsets %lld..%lld", (long long)d, (long long)off[d],
+                        (long long)off[d + 1]);
+    const int64_t N = off[D];
+    if (N > 0 && !words_dev) return fail(PULDA_ERR_INVALID_ARG, "null words");
+    if (N * particles >= (1ll << 40)) return fail(PULDA_ERR_INVALID_ARG, "N * particles too large");
+    if (workspace_bytes < heldout_bytes(N, particles))
+        return fail(PULDA_ERR_NO_MEMORY, "workspace of %lld bytes, need %lld", (long long)workspace_bytes,
+                    (long long)heldout_bytes(N, particles));
+    Layout L;
+    uint8_t *w = (uint8_t *)workspace_dev;
+    DevHeldout h{};
+    h.D = D;
+    h.R = particles;
+    h.group = group;
+    h.key0 = (uint32_t)seed;
+    h.key1 = (uint32_t)(seed >> 32);
+    h.A = model->A;
+    h.doc_off = doc_off_dev;
+    h.words = words_dev;
+    h.req = req_dev;
+    h.kw = (int32_t *)(w + L.take(N * particles * 4));
+    h.z = (uint16_t *)(w + L.take(N * particles * 2));
+    const int64_t zs_off = L.take(N * particles * 8);
+    h.Zs = Z_dev ? Z_dev : (double *)(w + zs_off);
+    h.kept = kept_dev;
+    h.ll = ll_dev;
+    HIP_TRY(launch_heldout(model->m, h, s));
+    return PULDA_OK;
+}
+
 }  // extern "C"

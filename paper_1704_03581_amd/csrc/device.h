@@ -19,6 +19,8 @@ enum : uint32_t {
     TAG_FOLDIN_Z = 5,    // fold-in token draw: ctr (p, request, sweep, TAG_FOLDIN_Z)
     TAG_PHI_GAMMA = 6,   // attempt j of the G(beta + n_kv, 1) draw of cell (k, v) (Algorithm 1's
                          // Phi-step): ctr (v, k, t, TAG_PHI_GAMMA + 256 j)
+    TAG_LTR = 7,         // held-out estimate, particle r's draw of kept token q at step n:
+                         // ctr (q, n, request, TAG_LTR + 256 r)
 };
 
 struct r4 {

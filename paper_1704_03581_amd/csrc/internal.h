@@ -173,4 +173,24 @@ struct DevFoldin {
 hipError_t launch_foldin_step(const DevModel &m, const DevFoldin &f, const int32_t *active, int32_t n_active,
                               hipStream_t s);
 
+// held-out log-likelihood of new documents (left-to-right estimate): the
+// region of document d's particle r in kw, z and Zs starts at
+// doc_off[d] * R + r * N_d (N_d = the document's length)
+struct DevHeldout {
+    int64_t D;
+    int32_t R, group;
+    uint32_t key0, key1;
+    double A;                  // sum_k alpha_k
+    const int64_t *doc_off;    // [D+1]
+    const int32_t *words;      // [N]
+    const uint32_t *req;       // [D] request ids (keys of the random numbers)
+    int32_t *kw;               // [R*N] each particle's kept words
+    uint16_t *z;               // [R*N] each particle's topics
+    double *Zs;                // [R*N] Z_n of each particle and step
+    int32_t *kept;             // [D]
+    double *ll;                // [D]
+};
+
+hipError_t launch_heldout(const DevModel &m, const DevHeldout &h, hipStream_t s);
+
 }  // namespace pulda

@@ -989,7 +989,7 @@ __device__ __forceinline__ void lane_terms(const DevModel &M, const uint16_t *ls
 // round; the first round's terms stay in registers for the walk.
 template <int G, bool DOC, typename CT, int KP>
 __device__ __forceinline__ int32_t b_part(const DevModel &M, const TokenIn &tk, DocState<CT> &S, const double *R,
-                                          const int g)
+                                          const int g, double &Zo)
 {
     constexpr int LG = log2g<G>();
     const int32_t J = DOC ? S.L : (int32_t)tk.kv;
@@ -1022,6 +1022,7 @@ __device__ __forceinline__ int32_t b_part(const DevModel &M, const TokenIn &tk, 
     const double incl = group_scan_incl<G>(p);
     const double T = group_bcast_f64<G>(incl, G - 1);
     const double Z = tk.sa + T;
+    Zo = Z;
     const double x = unit24(tk.r0) * Z;
     if (x < tk.sa) return -1;
     // b-part: the first lane whose running sum passes y walks its terms
@@ -1072,8 +1073,9 @@ __device__ __forceinline__ int32_t b_part(const DevModel &M, const TokenIn &tk, 
 // draw one token (group-uniform control flow); returns the new topic, or
 // -1 - kold for a token whose word has an empty Phi column (it keeps kold)
 template <int G, typename CT>
+// (Zo: the conditional's normaliser sigma_a + sigma_b, when it is computed)
 __device__ __forceinline__ int32_t draw_token(const DevModel &M, const TokenIn &tk, DocState<CT> &S, const double *R,
-                                              const int g, const int32_t side_ratio, ZCount &cnt)
+                                              const int g, const int32_t side_ratio, ZCount &cnt, double &Zo)
 {
     CT *mt = S.mt;
     // m^{-i}: remove the token from its document's counts
@@ -1109,8 +1111,10 @@ __device__ __forceinline__ int32_t draw_token(const DevModel &M, const TokenIn &
     const int32_t J = doc ? S.L : Kv;
     const bool full = __builtin_amdgcn_ballot_w64(J > (KP / 2) * G) != 0;
     int32_t knew;
-    if (doc) knew = full ? b_part<G, true, CT, KP>(M, tk, S, R, g) : b_part<G, true, CT, KP / 2>(M, tk, S, R, g);
-    else knew = full ? b_part<G, false, CT, KP>(M, tk, S, R, g) : b_part<G, false, CT, KP / 2>(M, tk, S, R, g);
+    if (doc)
+        knew = full ? b_part<G, true, CT, KP>(M, tk, S, R, g, Zo) : b_part<G, true, CT, KP / 2>(M, tk, S, R, g, Zo);
+    else
+        knew = full ? b_part<G, false, CT, KP>(M, tk, S, R, g, Zo) : b_part<G, false, CT, KP / 2>(M, tk, S, R, g, Zo);
     if (knew < 0) {
         // a-part: the word's alias table over alpha_k phi_kv (drawn when the
         // token was staged)
@@ -1213,7 +1217,8 @@ __device__ void z_step_item(const ZArgs &a, const WorkItem &w, const double *R, 
             const int nb = (int)((e - i0) < G ? (e - i0) : G);
             for (int jj = 0; jj < nb; ++jj) {
                 const TokenIn tk = tok[jj];
-                int32_t k = draw_token<G, CT>(M, tk, S, R, g, w.side_ratio, cnt);
+                double Zo;
+                int32_t k = draw_token<G, CT>(M, tk, S, R, g, w.side_ratio, cnt, Zo);
                 if (k < 0) k = -1 - k;
                 if (g == 0) atomicAdd(&M.n[tk.vk + (uint32_t)k], 1);
                 if (g == jj) znew = k;
@@ -1965,7 +1970,8 @@ __device__ void foldin_slot(const DevModel &M, const DevFoldin &F, int32_t sid, 
             const int nb = (t1 - q0) < G ? (t1 - q0) : G;
             for (int jj = 0; jj < nb; ++jj) {
                 const TokenIn tk = tok[jj];
-                int32_t k = draw_token<G, uint16_t>(M, tk, S, R, g, 1, st);
+                double Zo;
+                int32_t k = draw_token<G, uint16_t>(M, tk, S, R, g, 1, st, Zo);
                 if (k < 0) k = -1 - k;
                 if (g == jj) znew = k;
             }
@@ -2057,6 +2063,171 @@ hipError_t launch_foldin_step(const DevModel &m, const DevFoldin &f, const int32
         else PULDA_FOLDIN(16, false);
     }
 #undef PULDA_FOLDIN
+    return hipGetLastError();
+}
+
+
+
+// ---------------------------------------------------------------------------
+// Held-out log-likelihood of new documents, log p(w_d | Phi, alpha), by the
+// left-to-right algorithm of Wallach, Murray, Salakhutdinov and Mimno, the
+// estimator behind the held-out comparison of Section 4.  One group of G
+// lanes per (document, particle).  Tokens whose word is >= V or whose Phi
+// column is empty are dropped; at step n (n = 0 .. nk - 1) the particle
+// redraws its topics z_0 .. z_{n-1} in order, each from the token
+// conditional of Section 3.5 given its other topics among the first n (the
+// fold-in draw), then draws z_n from that conditional given z_<n and keeps
+// its normaliser Z_n = sigma_a(w_n) + sigma_b(w_n).  A second kernel forms
+// sum_n log((1/R) sum_r Z_n^(r) / (n + A)).  Draws use Philox counter
+// (q, n, request, TAG_LTR + 256 r) for token q at step n (q = n: the new
+// token).
+// ---------------------------------------------------------------------------
+template <int G>
+__device__ void ltr_particle(const DevModel &M, const DevHeldout &H, int64_t d, int32_t r, const double *R,
+                             uint16_t *mt, TokenIn *tok)
+{
+    const int32_t Kp = (M.K + 1) & ~1;
+    DocState<uint16_t> S;
+    S.mt = mt;
+    S.lst = mt + Kp;
+    S.L = 0;
+    const int lane = __lane_id();
+    const int g = lane & (G - 1);
+    const int64_t s = H.doc_off[d];
+    const int32_t len = (int32_t)(H.doc_off[d + 1] - s);
+    const int64_t base = s * H.R + (int64_t)r * len;
+    int32_t *kw = H.kw + base;
+    uint16_t *zz = H.z + base;
+    double *Zs = H.Zs + base;
+    const uint32_t req = H.req[d];
+    const uint32_t tag = TAG_LTR + ((uint32_t)r << 8);
+    // kept tokens, in order
+    int32_t nk = 0;
+    for (int32_t p0 = 0; p0 < len; p0 += G) {
+        const int32_t p = p0 + g;
+        int32_t v = -1;
+        bool keep = false;
+        if (p < len) {
+            v = H.words[s + p];
+            keep = v >= 0 && v < M.V && M.colptr[v + 1] > M.colptr[v];
+        }
+        const uint64_t bal = group_ballot<G>(keep);
+        if (keep) kw[nk + __builtin_popcountll(bal & ((1ull << g) - 1ull))] = v;
+        nk += __builtin_popcountll(bal);
+    }
+    if (r == 0 && g == 0) H.kept[d] = nk;
+    for (int32_t k = g; k < Kp; k += G) mt[k] = 0;
+    __threadfence();
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    ZCount st = {0, 0, 0};
+    for (int32_t n = 0; n < nk; ++n) {
+        // redraw z_0 .. z_{n-1} in order (lane q mod G stages token q)
+        for (int32_t q0 = 0; q0 < n; q0 += G) {
+            const int32_t q = q0 + g;
+            const bool valid = q < n;
+            int32_t zo = 0;
+            if (valid) {
+                zo = zz[q];
+                const r4 rr = philox((uint32_t)q, (uint32_t)n, req, tag, H.key0, H.key1);
+                stage_token(M, tok, g, kw[q], zo, rr);
+            }
+            __builtin_amdgcn_wave_barrier();
+            int32_t znew = zo;
+            const int nb = n - q0 < G ? n - q0 : G;
+            for (int jj = 0; jj < nb; ++jj) {
+                const TokenIn tk = tok[jj];
+                double Zd;
+                int32_t k = draw_token<G, uint16_t>(M, tk, S, R, g, 1, st, Zd);
+                if (k < 0) k = -1 - k;
+                if (g == jj) znew = k;
+            }
+            __builtin_amdgcn_wave_barrier();
+            if (valid) zz[q] = (uint16_t)znew;
+        }
+        // the new token: counted under a topic the particle already holds
+        // (topic 0 at the first step), which the draw removes again, so the
+        // draw sees the counts of z_<n
+        const int32_t k0 = S.L > 0 ? S.lst[0] : 0;
+        const int32_t c0 = mt[k0];
+        __builtin_amdgcn_wave_barrier();
+        if (g == 0) mt[k0] = (uint16_t)(c0 + 1);
+        __builtin_amdgcn_wave_barrier();
+        if (c0 == 0) list_insert<G, uint16_t>(S, k0, g);
+        if (g == 0) {
+            const r4 rr = philox((uint32_t)n, (uint32_t)n, req, tag, H.key0, H.key1);
+            stage_token(M, tok, 0, kw[n], k0, rr);
+        }
+        __builtin_amdgcn_wave_barrier();
+        const TokenIn tk = tok[0];
+        double Z = 0.0;
+        int32_t k = draw_token<G, uint16_t>(M, tk, S, R, g, 1, st, Z);
+        if (k < 0) k = -1 - k;
+        __builtin_amdgcn_wave_barrier();
+        if (g == (n & (G - 1))) zz[n] = (uint16_t)k;
+        if (g == 0) Zs[n] = Z;
+    }
+}
+
+template <int G>
+__global__ void __launch_bounds__(256) ltr_kernel(DevModel M, DevHeldout H, int32_t per_group)
+{
+    extern __shared__ __align__(16) uint16_t h_lds[];
+    double *R = (double *)h_lds;
+    for (int32_t k = threadIdx.x; k < M.K; k += blockDim.x) R[k] = M.Rd[k];
+    __syncthreads();
+    uint16_t *blk = h_lds + (M.K * 8 + 15) / 16 * 8;
+    const int lane = __lane_id();
+    const int wave = threadIdx.x >> 6;
+    constexpr int NG = 64 / G;
+    const int grp = lane / G;
+    const int64_t gid = ((int64_t)blockIdx.x * 4 + wave) * NG + grp;
+    uint16_t *mt = blk + (wave * NG + grp) * per_group;
+    TokenIn *tok = (TokenIn *)(blk + 4 * NG * per_group) + wave * 64 + grp * G;
+    if (gid >= H.D * H.R) return;
+    ltr_particle<G>(M, H, gid / H.R, (int32_t)(gid % H.R), R, mt, tok);
+}
+
+// one wave per document: sum over steps of log((1/R) sum_r Z_n^(r) / (n + A)),
+// the particles added in ascending order
+__global__ void __launch_bounds__(256) ltr_finish_kernel(DevHeldout H)
+{
+    const int64_t d = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (d >= H.D) return;
+    const int lane = __lane_id();
+    const int64_t s = H.doc_off[d];
+    const int32_t len = (int32_t)(H.doc_off[d + 1] - s);
+    const int32_t nk = H.kept[d];
+    double part = 0.0;
+    for (int32_t n = lane; n < nk; n += 64) {
+        double sum = 0.0;
+        for (int32_t r = 0; r < H.R; ++r) sum += H.Zs[s * H.R + (int64_t)r * len + n] / ((double)n + H.A);
+        part += log(sum / (double)H.R);
+    }
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+    if (lane == 0) H.ll[d] = part;
+}
+
+hipError_t launch_heldout(const DevModel &m, const DevHeldout &h, hipStream_t s)
+{
+    if (h.D == 0) return hipSuccess;
+    const int per_group = 2 * ((m.K + 1) & ~1);
+    const int ngw = 64 / h.group;
+    const int64_t groups = h.D * h.R;
+    const int64_t waves = (groups + ngw - 1) / ngw;
+    const unsigned blocks = (unsigned)((waves + 3) / 4);
+    const size_t lds = (size_t)(m.K * 8 + 15) / 16 * 16 + 4 * ngw * per_group * sizeof(uint16_t) +
+                       4 * 64 * sizeof(TokenIn);
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ltr_kernel<64>, 256, lds);
+    if (e != hipSuccess) return e;
+    if (per_cu <= 0) return hipErrorInvalidConfiguration;  // the block's LDS exceeds the CU's
+    if (h.group == 64) ltr_kernel<64><<<blocks, 256, lds, s>>>(m, h, per_group);
+    else if (h.group == 32) ltr_kernel<32><<<blocks, 256, lds, s>>>(m, h, per_group);
+    else ltr_kernel<16><<<blocks, 256, lds, s>>>(m, h, per_group);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    ltr_finish_kernel<<<(unsigned)((h.D + 3) / 4), 256, 0, s>>>(h);
     return hipGetLastError();
 }
 

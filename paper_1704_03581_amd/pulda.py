@@ -95,6 +95,8 @@ _SIGS = {
     "pulda_set_timing": [vp, i32],
     "pulda_set_fused_loglik": [vp, i32],
     "pulda_set_phi_method": [vp, i32],
+    "pulda_heldout_workspace_bytes": [vp, i64, i32, C.POINTER(i64)],
+    "pulda_heldout_loglik": [vp, i64, vp, vp, vp, i32, i32, u64, vp, i64, vp, vp, vp, vp],
     "pulda_get_gamma_dense": [vp, vp, vp, vp],
     "pulda_foldin_create": [vp, C.POINTER(FoldinDesc), C.POINTER(vp)],
     "pulda_foldin_workspace_bytes": [vp, C.POINTER(i64)],
@@ -325,6 +327,43 @@ class Plan:
 
     def set_graph(self, enable: bool):
         _check(_lib.pulda_set_graph(self._h, 1 if enable else 0))
+
+    def heldout_loglik(self, docs, req=None, particles: int = 20, group: int = 32, seed: int = 1,
+                       want_Z: bool = False, stream=None):
+        """Left-to-right estimates of log p(w_d | Phi, alpha) for new
+        documents (lists of word ids) against this plan's Phi.  req: request
+        ids (default 0..D-1), the keys of the random numbers.  Returns
+        (ll fp64[D], kept int32[D]) and, with want_Z, each document's
+        Z (particles x kept) array."""
+        D = len(docs)
+        lens = np.array([len(d) for d in docs], dtype=np.int64)
+        off = np.zeros(D + 1, np.int64)
+        np.cumsum(lens, out=off[1:])
+        N = int(off[-1])
+        words = np.concatenate([np.asarray(d, np.int32) for d in docs]) if N else np.zeros(1, np.int32)
+        req = np.arange(D, dtype=np.uint32) if req is None else np.asarray(req, np.uint32)
+        dv = self.device
+        off_t = torch.from_numpy(off).to(dv)
+        words_t = torch.from_numpy(words).to(dv)
+        req_t = torch.from_numpy(np.ascontiguousarray(req).view(np.int32)).to(dv)
+        nbytes = i64()
+        _check(_lib.pulda_heldout_workspace_bytes(self._h, N, particles, C.byref(nbytes)))
+        ws = torch.empty(max(nbytes.value, 1) + 256, dtype=torch.uint8, device=dv)
+        base = (ws.data_ptr() + 255) // 256 * 256
+        ll = torch.empty(max(D, 1), dtype=torch.float64, device=dv)
+        kept = torch.empty(max(D, 1), dtype=torch.int32, device=dv)
+        Z = torch.empty(max(N * particles, 1), dtype=torch.float64, device=dv) if want_Z else None
+        _check(_lib.pulda_heldout_loglik(self._h, D, _ptr(off_t), _ptr(words_t), _ptr(req_t), particles, group,
+                                         seed, C.c_void_p(base), nbytes.value, _ptr(ll), _ptr(kept),
+                                         _ptr(Z) if want_Z else None, _stream(stream)))
+        ll_h = ll.cpu().numpy()[:D]
+        kept_h = kept.cpu().numpy()[:D]
+        if not want_Z:
+            return ll_h, kept_h
+        Zh = Z.cpu().numpy()
+        Zs = [Zh[off[d] * particles: off[d] * particles + particles * lens[d]].reshape(particles, lens[d])[:, :kept_h[d]]
+              for d in range(D)]
+        return ll_h, kept_h, Zs
 
     PHI_METHODS = {"polya_urn": 0, "dirichlet": 1}
 
