@@ -138,6 +138,45 @@ def foldin_bench(args, torch, pulda, synth):
     return out
 
 
+def heldout_bench(plan, docs, particles, seed, torch, oracle_docs=0, K=0, V=0, alpha=0.0):
+    """Held-out log-likelihood of new documents (left-to-right estimate, as in
+    the paper's Section 4) against the plan's current Phi: wall time of the
+    call (document upload included), token draws per second, and the
+    estimate per token; optionally the oracle on the first few documents."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ll, kept = plan.heldout_loglik(docs, particles=particles, group=32, seed=seed)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    n = kept.astype(np.int64)
+    draws = int(particles * (n * (n + 1) // 2).sum())
+    out = dict(docs=len(docs), particles=particles, tokens=int(n.sum()), max_len=int(n.max()), seconds=dt,
+               docs_per_s=len(docs) / dt, token_draws_per_s=draws / dt, ll_per_token=float(ll.sum() / n.sum()))
+    if oracle_docs:
+        # the oracle (single-threaded) on the first few documents, same Phi
+        import oracle
+        g = plan.get_phi()
+        colptr = g["colptr"].astype(np.int64)
+        cols = np.repeat(np.arange(V), np.diff(colptr))
+        phi = np.zeros((K, V), np.float32)
+        phi[g["topic"].astype(np.int64), cols] = g["phi"]
+        wt = oracle.WordTables(colptr, g["topic"].astype(np.uint16), g["phi"].astype(np.float32),
+                               g["alias_thr"].astype(np.uint32), g["alias_topic"].astype(np.uint16),
+                               g["sigma_a"].astype(np.float64))
+        del g
+        a = np.full(K, alpha)
+        sub = docs[:oracle_docs]
+        t0 = time.perf_counter()
+        nd = 0
+        for i, d in enumerate(sub):
+            _, k = oracle.heldout_ltr(phi, wt, a, seed, i, d, particles)
+            nd += particles * k * (k + 1) // 2
+        dto = time.perf_counter() - t0
+        out["cpu_baseline"] = dict(kind="oracle", cores=1, docs=len(sub), docs_per_s=len(sub) / dto,
+                                   token_draws_per_s=nd / dto, seconds=dto)
+    return out
+
+
 def alg1_bench(plan, t, N, sweeps):
     """Algorithm 1 (Phi-step phi_k ~ Dir(n_k + beta) by Gamma draws) on the
     state the timed sweeps left, with the same z-step schedule: per-phase
@@ -174,6 +213,11 @@ def main():
     ap.add_argument("--cpu-docs", type=int, default=20000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-foldin", action="store_true")
+    ap.add_argument("--heldout-docs", type=int, default=2000,
+                    help="new documents for the held-out log-likelihood (0: none)")
+    ap.add_argument("--heldout-max-len", type=int, default=500)
+    ap.add_argument("--particles", type=int, default=10)
+    ap.add_argument("--heldout-oracle-docs", type=int, default=6)
     ap.add_argument("--alg1-sweeps", type=int, default=3,
                     help="sweeps with Algorithm 1's Dirichlet Phi-step after the timed region (0: none)")
     ap.add_argument("--foldin-requests", type=int, default=12000)
@@ -282,6 +326,19 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         res["cpu_baseline"] = cpu_baseline(corpus, args.seed, args.cpu_docs)
+    ho_docs = None
+    if args.heldout_docs > 0:
+        log(f"held-out log-likelihood of {args.heldout_docs} new documents (urn Phi)")
+        ho_docs = synth.foldin_requests(args.heldout_docs, seed=170403581 + 6, base=args.config,
+                                        max_len=args.heldout_max_len)
+        plan.heldout_loglik(ho_docs[:2], particles=2, seed=args.seed)   # load the kernels
+        res["heldout"] = dict(
+            workload=f"{args.heldout_docs} new documents of the fold-in length law up to {args.heldout_max_len} "
+                     f"tokens, words from the generating Phi; left-to-right estimate, {args.particles} particles",
+            polya_urn=heldout_bench(plan, ho_docs, args.particles, args.seed, torch,
+                                    oracle_docs=0 if args.no_cpu_baseline else args.heldout_oracle_docs,
+                                    K=corpus.K, V=corpus.V, alpha=corpus.alpha))
+        log(f"heldout {res['heldout']['polya_urn']}")
     if args.alg1_sweeps > 0:
         log(f"Algorithm 1 (Dirichlet Phi-step): {args.alg1_sweeps} sweeps")
         res["alg1"] = alg1_bench(plan, t + args.steps, N, args.alg1_sweeps)
@@ -289,6 +346,9 @@ def main():
             res["alg1"]["phi_speedup_polya_urn"] = res["alg1"]["phi_ms"] / res["zstep"]["phi_ms"]
             res["alg1"]["z_speedup_polya_urn"] = res["alg1"]["z_ms"] / res["zstep"]["kernel_ms"]
         log(f"alg1 {res['alg1']}")
+        if ho_docs is not None:
+            res["heldout"]["dirichlet"] = heldout_bench(plan, ho_docs, args.particles, args.seed, torch)
+            log(f"heldout (Dirichlet Phi) {res['heldout']['dirichlet']}")
     del plan
     torch.cuda.empty_cache()
     if not args.no_foldin:
