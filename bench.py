@@ -177,6 +177,47 @@ def heldout_bench(plan, docs, particles, seed, torch, oracle_docs=0, K=0, V=0, a
     return out
 
 
+def scaling_study(args, torch, pulda, synth):
+    """Where the urn's speedup comes from (the paper's Section 4 scaling
+    study): both Phi-steps with the same z-step on restrictions of the large
+    corpus by rare-word limit, vocabulary size and data size.  Per
+    configuration: 3 warmup sweeps with the urn, 5 timed urn sweeps, then 5
+    timed sweeps with the Dirichlet Phi-step continuing the chain; per-phase
+    hipEvent times.  (The large corpus fills the GPU with short documents; on
+    a smaller one each z-step waits for its longest document's chain.)"""
+    if args.corpus_cache and os.path.exists(args.corpus_cache):
+        base = synth.load(args.corpus_cache)
+    else:
+        base = synth.generate("large", keep_true_z=False)
+    grid = ([dict(min_count=m) for m in (0, 10, 50, 200)] +
+            [dict(max_vocab=v) for v in (2000, 5000, 10000)] +
+            [dict(doc_fraction=f) for f in (0.125, 0.25, 0.5)])
+    rows = []
+    for g in grid:
+        c = synth.restrict(base, **g)
+        plan = pulda.Plan(c.K, c.V, c.D, c.N, alpha=c.alpha, beta=c.beta, seed=args.seed)
+        plan.upload(c.doc_off, c.words)
+        plan.init()
+        plan.sweep(1, 3, want_ll=False)
+        plan.set_timing(True)
+        row = dict(g, V=c.V, N=c.N)
+        for method, t0 in (("polya_urn", 4), ("dirichlet", 9)):
+            plan.set_phi_method(method)
+            plan.stats()
+            plan.sweep(t0, 5, want_ll=False)
+            st = plan.stats()
+            row[method] = dict(phi_ms=st["ms_phi"] / st["n_phi"], z_ms=st["ms_z"] / st["n_z"], nnz_phi=st["nnz_phi"],
+                               mean_J=st["sum_J"] / st["z_steps"] / c.N)
+        row["z_ratio"] = row["dirichlet"]["z_ms"] / row["polya_urn"]["z_ms"]
+        row["phi_ratio"] = row["dirichlet"]["phi_ms"] / row["polya_urn"]["phi_ms"]
+        log(f"scaling {row}")
+        rows.append(row)
+        del plan
+        torch.cuda.empty_cache()
+    return dict(workload=f"large corpus (D={base.D}, V={base.V}, K={base.K}, N={base.N}) restricted by rare-word "
+                         f"limit, vocabulary size and data size", rows=rows)
+
+
 def alg1_bench(plan, t, N, sweeps):
     """Algorithm 1 (Phi-step phi_k ~ Dir(n_k + beta) by Gamma draws) on the
     state the timed sweeps left, with the same z-step schedule: per-phase
@@ -218,6 +259,9 @@ def main():
     ap.add_argument("--heldout-max-len", type=int, default=500)
     ap.add_argument("--particles", type=int, default=10)
     ap.add_argument("--heldout-oracle-docs", type=int, default=6)
+    ap.add_argument("--scaling", action="store_true",
+                    help="run only the scaling study of both Phi-steps on restrictions of the large corpus "
+                         "(read from --corpus-cache when present)")
     ap.add_argument("--alg1-sweeps", type=int, default=3,
                     help="sweeps with Algorithm 1's Dirichlet Phi-step after the timed region (0: none)")
     ap.add_argument("--foldin-requests", type=int, default=12000)
@@ -237,6 +281,12 @@ def main():
         sys.exit(2)
 
     from paper_1704_03581_amd import synth
+    if args.scaling:
+        import torch
+        from paper_1704_03581_amd import pulda
+        print(json.dumps(dict(metric="scaling study: Phi-step and z-step ms per sweep, Polya urn vs Dirichlet",
+                              **scaling_study(args, torch, pulda, synth))), flush=True)
+        return
     t0 = time.perf_counter()
     if args.corpus_cache and os.path.exists(args.corpus_cache):
         log(f"loading the {args.config} corpus from {args.corpus_cache}")

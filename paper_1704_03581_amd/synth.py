@@ -210,6 +210,44 @@ def load(path: str) -> Corpus:
         return Corpus(str(f["name"]), D, V, K, alpha, beta, f["doc_off"], f["words"], None)
 
 
+def restrict(c: Corpus, min_count: int = 0, max_vocab: Optional[int] = None, doc_fraction: float = 1.0,
+             max_len: Optional[int] = None) -> Corpus:
+    """The preprocessing that the paper's scaling study varies (Section 4):
+    keep the first doc_fraction of the documents (and, with max_len, only
+    those of at most max_len tokens), drop the words that occur
+    fewer than min_count times in them (the rare-word limit), keep at most
+    max_vocab of the rest, most frequent first (the paper ranks by TF-IDF,
+    here by frequency), and renumber the kept words 0 .. V'-1 in their
+    original order.  Tokens of dropped words leave their documents."""
+    D = max(1, int(round(c.D * doc_fraction)))
+    off = c.doc_off[: D + 1]
+    w = c.words[: off[-1]]
+    if max_len is not None:
+        lens = np.diff(off)
+        ok = lens <= max_len
+        w = w[np.repeat(ok, lens)]
+        D = int(ok.sum())
+        off = np.zeros(D + 1, np.int64)
+        np.cumsum(lens[ok], out=off[1:])
+    cnt = np.bincount(w, minlength=c.V)
+    keep = cnt >= max(min_count, 1)
+    if max_vocab is not None and keep.sum() > max_vocab:
+        order = np.argsort(-cnt, kind="stable")
+        top = np.zeros(c.V, bool)
+        top[order[:max_vocab]] = True
+        keep &= top
+    new_id = np.full(c.V, -1, np.int64)
+    new_id[keep] = np.arange(int(keep.sum()))
+    mapped = new_id[w]
+    kept_tok = mapped >= 0
+    doc_of = np.repeat(np.arange(D), np.diff(off))
+    lens = np.bincount(doc_of[kept_tok], minlength=D)
+    new_off = np.zeros(D + 1, np.int64)
+    np.cumsum(lens, out=new_off[1:])
+    return Corpus(f"{c.name}/min{min_count}/V{max_vocab}/f{doc_fraction}/L{max_len}", D, int(keep.sum()), c.K, c.alpha,
+                  c.beta, new_off, mapped[kept_tok].astype(np.int32), None)
+
+
 def small_random(D: int, V: int, K: int, mean_len: float, seed: int, zipf: bool = True,
                  empty_docs: bool = True) -> Corpus:
     """A small corpus of arbitrary shape for tests (Poisson lengths)."""
