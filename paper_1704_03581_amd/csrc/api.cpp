@@ -133,7 +133,7 @@ struct pulda_plan {
     uint8_t *ws = nullptr;
     int64_t ws_need = 0;
     struct {
-        int64_t z, n, gam, phid, g16, Rd, gamd, Sd, dpart, ckg, colcnt, colptr, ctopic, cphi, calias, sigma_a, S, nk, alpha, pois, pois_off,
+        int64_t z, n, gam, phid, g16, Rd, gamd, Sd, dpart, phimax, ckg, colcnt, colptr, ctopic, cphi, calias, sigma_a, S, nk, alpha, pois, pois_off,
             doc_order, items, queue, stats, ll_part, ll_out, ll_hist, tptr, err, scratch, cnt_a, ptr_a, cnt_b,
             ptr_b, zsave, lg_beta, lg_alpha, lg_A, ll_doc;
     } off;
@@ -273,6 +273,7 @@ pulda_status pulda_plan_create(const pulda_model_desc *desc, int64_t D, int64_t 
     p->off.ckg = L.take(p->cap * 4);
     p->off.calias = L.take(p->cap * 8);
     p->off.sigma_a = L.take((int64_t)p->V * 8);
+    p->off.phimax = L.take((int64_t)p->V * 4);
     p->off.S = L.take((int64_t)p->K * 8);
     p->off.nk = L.take((int64_t)p->K * 8);
     p->off.alpha = L.take((int64_t)p->K * 8);
@@ -344,6 +345,7 @@ pulda_status pulda_plan_bind(pulda_plan *p, void *workspace_dev, int64_t bytes)
     m.cphi = (float *)(w + p->off.cphi);
     m.calias = (uint64_t *)(w + p->off.calias);
     m.sigma_a = (double *)(w + p->off.sigma_a);
+    m.phimax = (float *)(w + p->off.phimax);
     m.pois = (const uint64_t *)(w + p->off.pois);
     m.pois_off = (const int32_t *)(w + p->off.pois_off);
     std::memcpy(m.ztp, p->ztp, sizeof(m.ztp));

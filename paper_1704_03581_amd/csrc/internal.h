@@ -44,6 +44,7 @@ struct DevModel {
     uint32_t *ckg;                // [cap] topic | 16-bit draw << 16 (as g16)
     uint64_t *calias;             // [cap] thr | topic << 32 | alias_topic << 48
     double *sigma_a;              // [V]
+    float *phimax;                // [V] the largest phi of each word's column
     const uint64_t *pois;         // Poisson alias tables, thr | x_alias << 32
     const int32_t *pois_off;      // [L+2]
     uint32_t ztp[5];              // zero-truncated Pois(beta) thresholds

@@ -371,6 +371,7 @@ __global__ void __launch_bounds__(256) phi_dense_kernel(DevModel m)
     float *pcol = m.phid + (int64_t)v * K;
     uint16_t *g16col = m.g16 + (int64_t)v * m.ks16;
     int32_t run = 0;
+    float fmax = 0.0f;
     for (int32_t k0 = 0; k0 < m.ks16; k0 += 64) {
         const int32_t k = k0 + lane;
         float f = 0.0f;
@@ -391,6 +392,7 @@ __global__ void __launch_bounds__(256) phi_dense_kernel(DevModel m)
             x16 = exact ? (uint32_t)x : 0xFFFFu;
         }
         if (k < K) pcol[k] = f;
+        fmax = f > fmax ? f : fmax;
         g16col[k] = (uint16_t)x16;
         const uint64_t bal = __builtin_amdgcn_ballot_w64(nz);
         if (nz) {
@@ -401,6 +403,11 @@ __global__ void __launch_bounds__(256) phi_dense_kernel(DevModel m)
         }
         run += __builtin_popcountll(bal);
     }
+    for (int o = 32; o > 0; o >>= 1) {
+        const float y = __shfl_xor(fmax, o, 64);
+        fmax = y > fmax ? y : fmax;
+    }
+    if (lane == 0) m.phimax[v] = fmax;
 }
 
 // Columns with at most ALIAS_SMALL nonzeros: one wave per column, four per
@@ -814,7 +821,7 @@ struct alignas(16) TokenIn {
     uint16_t ka;     // the a-part's topic: the alias draw depends only on the
                      // word and the token's random numbers, so it is taken at
                      // staging time, off the draw's critical path
-    uint16_t pad0;
+    uint16_t sure;   // 1: the a-part is certain whatever the document's counts
     uint32_t vs;     // v * ks16: the word's row of the 16-bit draws (the
                      // products are taken once, at staging)
     double sa;       // sigma_a(v)
@@ -1103,18 +1110,24 @@ __device__ __forceinline__ int32_t draw_token(const DevModel &M, const TokenIn &
     // wave (the document side if any of its groups prefers it: a frequent
     // word's column is long, a document's topic list is not), so the
     // wave's groups do not diverge; the side changes cost, not the law.
-    const bool prefer_doc = Kd == 0 || (uint32_t)Kv > __umul24((uint32_t)side_ratio, (uint32_t)Kd);
-    const bool doc = __builtin_amdgcn_ballot_w64(prefer_doc) != 0;
-    // terms per lane and round: half the registers' worth when no group of
-    // the wave has more than that many per lane (one round either way)
-    constexpr int KP = keep_of<G>();
-    const int32_t J = doc ? S.L : Kv;
-    const bool full = __builtin_amdgcn_ballot_w64(J > (KP / 2) * G) != 0;
-    int32_t knew;
-    if (doc)
-        knew = full ? b_part<G, true, CT, KP>(M, tk, S, R, g, Zo) : b_part<G, true, CT, KP / 2>(M, tk, S, R, g, Zo);
-    else
-        knew = full ? b_part<G, false, CT, KP>(M, tk, S, R, g, Zo) : b_part<G, false, CT, KP / 2>(M, tk, S, R, g, Zo);
+    int32_t knew = -1;
+    // when every group's token in the wave takes the a-part whatever its
+    // b-terms (decided at staging), the b-terms are not needed
+    if (__builtin_amdgcn_ballot_w64(tk.sure == 0) != 0) {
+        const bool prefer_doc = Kd == 0 || (uint32_t)Kv > __umul24((uint32_t)side_ratio, (uint32_t)Kd);
+        const bool doc = __builtin_amdgcn_ballot_w64(prefer_doc) != 0;
+        // terms per lane and round: half the registers' worth when no group
+        // of the wave has more than that many per lane (one round either way)
+        constexpr int KP = keep_of<G>();
+        const int32_t J = doc ? S.L : Kv;
+        const bool full = __builtin_amdgcn_ballot_w64(J > (KP / 2) * G) != 0;
+        if (doc)
+            knew = full ? b_part<G, true, CT, KP>(M, tk, S, R, g, Zo)
+                        : b_part<G, true, CT, KP / 2>(M, tk, S, R, g, Zo);
+        else
+            knew = full ? b_part<G, false, CT, KP>(M, tk, S, R, g, Zo)
+                        : b_part<G, false, CT, KP / 2>(M, tk, S, R, g, Zo);
+    }
     if (knew < 0) {
         // a-part: the word's alias table over alpha_k phi_kv (drawn when the
         // token was staged)
@@ -1153,9 +1166,16 @@ __device__ __forceinline__ void load_doc_counts(DocState<CT> &S, const uint16_t 
     build_list<G, CT>(S, g, K);
 }
 
-// stage the inputs of tokens i0 + g (one per lane) for a block of draws
+// stage the inputs of tokens i0 + g (one per lane) for a block of draws.
+// nd: tokens of the document (0: never decide the a-part here).  The b-terms
+// of a token sum to sigma_b = sum_k phi_kv m_k <= phimax(v) (nd - 1), so when
+// u (sigma_a + phimax(v) (nd - 1)) < sigma_a the token takes the a-part
+// whatever the counts; the test keeps a margin of 2^-36 relative, far above
+// the rounding of either side's sums, so it never decides a token that the
+// full computation (or the definition's order of sums) would send to the
+// b-part.
 __device__ __forceinline__ void stage_token(const DevModel &M, TokenIn *tok, int g, int32_t v, int32_t kold,
-                                            const r4 &r)
+                                            const r4 &r, const int32_t nd)
 {
     TokenIn x;
     x.vk = (uint32_t)v * (uint32_t)M.K;
@@ -1176,7 +1196,12 @@ __device__ __forceinline__ void stage_token(const DevModel &M, TokenIn *tok, int
         ka = (r.z < (uint32_t)a) ? (uint32_t)((a >> 32) & 0xFFFFu) : (uint32_t)(a >> 48);
     }
     x.ka = (uint16_t)ka;
-    x.pad0 = 0;
+    bool sure = false;
+    if (kv > 0 && nd > 0) {
+        const double B = (double)M.phimax[v] * (double)(nd - 1);
+        sure = unit24(r.x) * (x.sa + B) < x.sa * (1.0 - 0x1p-36);
+    }
+    x.sure = sure ? 1 : 0;
     tok[g] = x;
 }
 
@@ -1210,7 +1235,7 @@ __device__ void z_step_item(const ZArgs &a, const WorkItem &w, const double *R, 
                 const int32_t wv = a.c.words[i];
                 zo = a.c.z[i];
                 const r4 r = philox((uint32_t)i, (uint32_t)((uint64_t)i >> 32), t, TAG_Z, M.key0, M.key1);
-                stage_token(M, tok, g, wv, zo, r);
+                stage_token(M, tok, g, wv, zo, r, (int32_t)(e - s));
             }
             __builtin_amdgcn_wave_barrier();
             int32_t znew = zo;
@@ -1769,8 +1794,10 @@ __global__ void import_phi_kernel(DevModel m, const int64_t *colptr64, const uin
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     // values without draws behind them: every nonzero cell is read from phid
+    float fmax = 0.0f;
     for (int64_t e = a + lane; e < b; e += 64) {
         const int32_t k = topic[e];
+        fmax = phi_e[e] > fmax ? phi_e[e] : fmax;
         m.ctopic[e] = (uint16_t)k;
         m.cphi[e] = phi_e[e];
         m.ckg[e] = (uint32_t)k | (0xFFFFu << 16);
@@ -1778,6 +1805,11 @@ __global__ void import_phi_kernel(DevModel m, const int64_t *colptr64, const uin
         g16col[k] = 0xFFFF;
         m.calias[e] = (uint64_t)thr[e] | ((uint64_t)k << 32) | ((uint64_t)alias_topic[e] << 48);
     }
+    for (int o = 32; o > 0; o >>= 1) {
+        const float y = __shfl_xor(fmax, o, 64);
+        fmax = y > fmax ? y : fmax;
+    }
+    if (lane == 0) m.phimax[v] = fmax;
 }
 
 hipError_t launch_import_phi(const DevModel &m, const int64_t *colptr64, const uint16_t *topic, const float *phi_e,
@@ -1963,7 +1995,7 @@ __device__ void foldin_slot(const DevModel &M, const DevFoldin &F, int32_t sid, 
                 const int32_t p = pos[q];
                 zo = zz[q];
                 const r4 r = philox((uint32_t)p, sl.req, (uint32_t)s, TAG_FOLDIN_Z, F.key0, F.key1);
-                stage_token(M, tok, g, wds[p], zo, r);
+                stage_token(M, tok, g, wds[p], zo, r, kept);
             }
             __builtin_amdgcn_wave_barrier();
             int32_t znew = zo;
@@ -2130,7 +2162,7 @@ __device__ void ltr_particle(const DevModel &M, const DevHeldout &H, int64_t d, 
             if (valid) {
                 zo = zz[q];
                 const r4 rr = philox((uint32_t)q, (uint32_t)n, req, tag, H.key0, H.key1);
-                stage_token(M, tok, g, kw[q], zo, rr);
+                stage_token(M, tok, g, kw[q], zo, rr, 0);
             }
             __builtin_amdgcn_wave_barrier();
             int32_t znew = zo;
@@ -2156,7 +2188,7 @@ __device__ void ltr_particle(const DevModel &M, const DevHeldout &H, int64_t d, 
         if (c0 == 0) list_insert<G, uint16_t>(S, k0, g);
         if (g == 0) {
             const r4 rr = philox((uint32_t)n, (uint32_t)n, req, tag, H.key0, H.key1);
-            stage_token(M, tok, 0, kw[n], k0, rr);
+            stage_token(M, tok, 0, kw[n], k0, rr, 0);
         }
         __builtin_amdgcn_wave_barrier();
         const TokenIn tk = tok[0];
