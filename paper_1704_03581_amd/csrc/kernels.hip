@@ -1146,6 +1146,33 @@ __device__ __forceinline__ int32_t draw_token(const DevModel &M, const TokenIn &
     return knew;
 }
 
+// a token whose a-part was decided at staging (tk.sure): the same count and
+// list updates as draw_token, with the new topic the word's alias draw
+template <int G, typename CT>
+__device__ __forceinline__ int32_t move_token(const TokenIn &tk, DocState<CT> &S, const int g, ZCount &cnt)
+{
+    CT *mt = S.mt;
+    const int32_t kold = tk.kold;
+    const int32_t mo = mt[kold];
+    __builtin_amdgcn_wave_barrier();
+    if (g == 0) mt[kold] = (CT)(mo - 1);
+    __builtin_amdgcn_wave_barrier();
+    const int32_t Kv = tk.kv;
+    const int32_t Kd = S.L - (mo == 1 ? 1 : 0);
+    cnt.J += (unsigned long long)(Kd < Kv ? Kd : Kv);
+    const int32_t knew = tk.ka;
+    cnt.A++;
+    const int32_t mn = mt[knew];
+    __builtin_amdgcn_wave_barrier();
+    if (g == 0) mt[knew] = (CT)(mn + 1);
+    __builtin_amdgcn_wave_barrier();
+    if (knew != kold) {
+        if (mo == 1) list_remove<G, CT>(S, kold, g);
+        if (mn == 0) list_insert<G, CT>(S, knew, g);
+    }
+    return knew;
+}
+
 // load a document's topic counts into the group's LDS table (CT: 8-bit
 // counts for documents shorter than 256 tokens, else 16-bit) and list them
 template <int G, typename CT>
@@ -1240,13 +1267,43 @@ __device__ void z_step_item(const ZArgs &a, const WorkItem &w, const double *R, 
             __builtin_amdgcn_wave_barrier();
             int32_t znew = zo;
             const int nb = (int)((e - i0) < G ? (e - i0) : G);
-            for (int jj = 0; jj < nb; ++jj) {
-                const TokenIn tk = tok[jj];
-                double Zo;
-                int32_t k = draw_token<G, CT>(M, tk, S, R, g, w.side_ratio, cnt, Zo);
-                if (k < 0) k = -1 - k;
-                if (g == 0) atomicAdd(&M.n[tk.vk + (uint32_t)k], 1);
-                if (g == jj) znew = k;
+            // each group walks its tokens with its own cursor: the tokens
+            // whose a-part was decided at staging move at once, then every
+            // group with a token left draws it, all groups together, so a
+            // wave runs the b-terms as often as its busiest group needs.
+            // (With 8 groups a wave the runs of decided tokens no longer line
+            // up: those groups draw in step, and skip the b-terms only when
+            // all eight tokens are decided.)
+            if constexpr (G < 16) {
+                for (int jj = 0; jj < nb; ++jj) {
+                    const TokenIn tk = tok[jj];
+                    double Zo;
+                    int32_t k = draw_token<G, CT>(M, tk, S, R, g, w.side_ratio, cnt, Zo);
+                    if (k < 0) k = -1 - k;
+                    if (g == 0) atomicAdd(&M.n[tk.vk + (uint32_t)k], 1);
+                    if (g == jj) znew = k;
+                }
+            } else {
+            int cur = 0;
+            while (true) {
+                while (cur < nb && tok[cur].sure) {
+                    const TokenIn tk = tok[cur];
+                    const int32_t k = move_token<G, CT>(tk, S, g, cnt);
+                    if (g == 0) atomicAdd(&M.n[tk.vk + (uint32_t)k], 1);
+                    if (g == cur) znew = k;
+                    ++cur;
+                }
+                if (cur < nb) {
+                    const TokenIn tk = tok[cur];
+                    double Zo;
+                    int32_t k = draw_token<G, CT>(M, tk, S, R, g, w.side_ratio, cnt, Zo);
+                    if (k < 0) k = -1 - k;
+                    if (g == 0) atomicAdd(&M.n[tk.vk + (uint32_t)k], 1);
+                    if (g == cur) znew = k;
+                    ++cur;
+                }
+                if (__builtin_amdgcn_ballot_w64(cur < nb) == 0) break;
+            }
             }
             __builtin_amdgcn_wave_barrier();
             if (valid) a.c.z[i] = (uint16_t)znew;
