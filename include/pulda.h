@@ -376,12 +376,15 @@ pulda_status pulda_foldin_occupancy(const pulda_foldin *f, int32_t *resident, in
  *   req_dev[D]: request ids; particle r's draw of token q at step n uses
  *     Philox counter (q, n, req, 7 + 256 r) under seed.
  *   particles in [1, 2^24); group: lanes per particle (16, 32, 64).
- *   workspace_dev: pulda_heldout_workspace_bytes(model, N, particles) bytes,
+ *   workspace_dev: pulda_heldout_workspace_bytes(model, D, N, particles) bytes,
  *     256-byte aligned, caller-owned.
  *   ll_dev[D] (fp64) and kept_dev[D] (kept tokens) are written; Z_dev (R*N
  *     fp64, or NULL) receives Z_n^(r) of document d at doc_off[d]*R + r*N_d + n.
- * Stream-ordered after the offset check (which synchronises the stream). */
-pulda_status pulda_heldout_workspace_bytes(const pulda_plan *model, int64_t N, int32_t particles, int64_t *bytes);
+ * Documents are processed longest first (the order is computed on the host
+ * and copied into the workspace).  The call synchronises the stream for the
+ * offset check and for that copy; the kernels are then stream-ordered. */
+pulda_status pulda_heldout_workspace_bytes(const pulda_plan *model, int64_t D, int64_t N, int32_t particles,
+                                           int64_t *bytes);
 pulda_status pulda_heldout_loglik(const pulda_plan *model, int64_t D, const int64_t *doc_off_dev,
                                   const int32_t *words_dev, const uint32_t *req_dev, int32_t particles, int32_t group,
                                   uint64_t seed, void *workspace_dev, int64_t workspace_bytes, double *ll_dev,

@@ -1314,21 +1314,23 @@ pulda_status pulda_foldin_run_one(pulda_foldin *f, uint32_t req, const int32_t *
 // ---------------------------------------------------------------------------
 // Held-out log-likelihood (left-to-right estimate)
 // ---------------------------------------------------------------------------
-static int64_t heldout_bytes(int64_t N, int32_t R)
+static int64_t heldout_bytes(int64_t D, int64_t N, int32_t R)
 {
     Layout L;
+    L.take(D * 4);
     L.take(N * R * 4);
     L.take(N * R * 2);
     L.take(N * R * 8);
     return L.total;
 }
 
-pulda_status pulda_heldout_workspace_bytes(const pulda_plan *model, int64_t N, int32_t particles, int64_t *bytes)
+pulda_status pulda_heldout_workspace_bytes(const pulda_plan *model, int64_t D, int64_t N, int32_t particles,
+                                           int64_t *bytes)
 {
     if (!model || !bytes) return fail(PULDA_ERR_INVALID_ARG, "null argument");
-    if (N < 0 || particles < 1 || particles >= (1 << 24))
-        return fail(PULDA_ERR_INVALID_ARG, "N=%lld, particles=%d", (long long)N, particles);
-    *bytes = heldout_bytes(N, particles);
+    if (D < 0 || N < 0 || particles < 1 || particles >= (1 << 24))
+        return fail(PULDA_ERR_INVALID_ARG, "D=%lld, N=%lld, particles=%d", (long long)D, (long long)N, particles);
+    *bytes = heldout_bytes(D, N, particles);
     return PULDA_OK;
 }
 
@@ -1358,11 +1360,20 @@ pulda_status pulda_heldout_loglik(const pulda_plan *model, int64_t D, const int6
     const int64_t N = off[D];
     if (N > 0 && !words_dev) return fail(PULDA_ERR_INVALID_ARG, "null words");
     if (N * particles >= (1ll << 40)) return fail(PULDA_ERR_INVALID_ARG, "N * particles too large");
-    if (workspace_bytes < heldout_bytes(N, particles))
+    if (workspace_bytes < heldout_bytes(D, N, particles))
         return fail(PULDA_ERR_NO_MEMORY, "workspace of %lld bytes, need %lld", (long long)workspace_bytes,
-                    (long long)heldout_bytes(N, particles));
+                    (long long)heldout_bytes(D, N, particles));
+    // longest documents first: each particle is a chain of ~n^2/2 draws, so
+    // the long ones set the call's time unless they start early
+    std::vector<int32_t> order(D);
+    for (int64_t d = 0; d < D; ++d) order[d] = (int32_t)d;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b) { return off[a + 1] - off[a] > off[b + 1] - off[b]; });
     Layout L;
     uint8_t *w = (uint8_t *)workspace_dev;
+    int32_t *order_dev = (int32_t *)(w + L.take(D * 4));
+    HIP_TRY(hipMemcpyAsync(order_dev, order.data(), D * 4, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));  // the host array ends with this call
     DevHeldout h{};
     h.D = D;
     h.R = particles;
@@ -1373,6 +1384,7 @@ pulda_status pulda_heldout_loglik(const pulda_plan *model, int64_t D, const int6
     h.doc_off = doc_off_dev;
     h.words = words_dev;
     h.req = req_dev;
+    h.order = order_dev;
     h.kw = (int32_t *)(w + L.take(N * particles * 4));
     h.z = (uint16_t *)(w + L.take(N * particles * 2));
     const int64_t zs_off = L.take(N * particles * 8);

@@ -185,6 +185,7 @@ struct DevHeldout {
     const int64_t *doc_off;    // [D+1]
     const int32_t *words;      // [N]
     const uint32_t *req;       // [D] request ids (keys of the random numbers)
+    const int32_t *order;      // [D] documents by decreasing length (longest chains start first)
     int32_t *kw;               // [R*N] each particle's kept words
     uint16_t *z;               // [R*N] each particle's topics
     double *Zs;                // [R*N] Z_n of each particle and step

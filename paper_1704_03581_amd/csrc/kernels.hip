@@ -2219,7 +2219,9 @@ __device__ void ltr_particle(const DevModel &M, const DevHeldout &H, int64_t d, 
             if (valid) {
                 zo = zz[q];
                 const r4 rr = philox((uint32_t)q, (uint32_t)n, req, tag, H.key0, H.key1);
-                stage_token(M, tok, g, kw[q], zo, rr, 0);
+                // (n tokens counted: the redraws may settle the a-part at
+                // staging; only the new token's draw needs its Z)
+                stage_token(M, tok, g, kw[q], zo, rr, n);
             }
             __builtin_amdgcn_wave_barrier();
             int32_t znew = zo;
@@ -2274,7 +2276,7 @@ __global__ void __launch_bounds__(256) ltr_kernel(DevModel M, DevHeldout H, int3
     uint16_t *mt = blk + (wave * NG + grp) * per_group;
     TokenIn *tok = (TokenIn *)(blk + 4 * NG * per_group) + wave * 64 + grp * G;
     if (gid >= H.D * H.R) return;
-    ltr_particle<G>(M, H, gid / H.R, (int32_t)(gid % H.R), R, mt, tok);
+    ltr_particle<G>(M, H, H.order[gid / H.R], (int32_t)(gid % H.R), R, mt, tok);
 }
 
 // one wave per document: sum over steps of log((1/R) sum_r Z_n^(r) / (n + A)),

@@ -95,7 +95,7 @@ _SIGS = {
     "pulda_set_timing": [vp, i32],
     "pulda_set_fused_loglik": [vp, i32],
     "pulda_set_phi_method": [vp, i32],
-    "pulda_heldout_workspace_bytes": [vp, i64, i32, C.POINTER(i64)],
+    "pulda_heldout_workspace_bytes": [vp, i64, i64, i32, C.POINTER(i64)],
     "pulda_heldout_loglik": [vp, i64, vp, vp, vp, i32, i32, u64, vp, i64, vp, vp, vp, vp],
     "pulda_get_gamma_dense": [vp, vp, vp, vp],
     "pulda_foldin_create": [vp, C.POINTER(FoldinDesc), C.POINTER(vp)],
@@ -347,7 +347,7 @@ class Plan:
         words_t = torch.from_numpy(words).to(dv)
         req_t = torch.from_numpy(np.ascontiguousarray(req).view(np.int32)).to(dv)
         nbytes = i64()
-        _check(_lib.pulda_heldout_workspace_bytes(self._h, N, particles, C.byref(nbytes)))
+        _check(_lib.pulda_heldout_workspace_bytes(self._h, D, N, particles, C.byref(nbytes)))
         ws = torch.empty(max(nbytes.value, 1) + 256, dtype=torch.uint8, device=dv)
         base = (ws.data_ptr() + 255) // 256 * 256
         ll = torch.empty(max(D, 1), dtype=torch.float64, device=dv)
