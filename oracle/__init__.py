@@ -58,15 +58,18 @@ def _declare(L):
     L.or_pois_support.argtypes = [C.c_double, C.c_int32]
     L.or_pois_support.restype = C.c_int32
     L.or_pois_table.argtypes = [C.c_double, C.c_int32, u32p, i32p]
-    L.or_ztp_thresholds.argtypes = [C.c_double, u32p]
+    L.or_ztp_thresholds.argtypes = [C.c_double, u32p, C.c_int32]
+    L.or_ztp_thresholds.restype = C.c_int32
     L.or_init_z.argtypes = [C.c_int64, C.c_int32, C.c_uint64, u16p]
     L.or_counts.argtypes = [C.c_int64, C.c_int32, C.c_int32, i64p, i32p, u16p, i32p, i64p, i32p]
-    L.or_phi_counts.argtypes = [C.c_int32, C.c_int32, C.c_double, C.c_int32, C.c_uint64, C.c_uint32, i32p, i32p]
+    L.or_phi_counts.argtypes = [C.c_int32, C.c_int32, C.c_double, f64p, C.c_int32, C.c_uint64, C.c_uint32, i32p,
+                                i32p]
     L.or_phi_normalise.argtypes = [C.c_int32, C.c_int32, i32p, i64p, f32p]
     L.or_phi_normalise.restype = C.c_int32
     L.or_gamma_draw.argtypes = [C.c_double, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32]
     L.or_gamma_draw.restype = C.c_double
-    L.or_phi_dirichlet.argtypes = [C.c_int32, C.c_int32, C.c_double, C.c_uint64, C.c_uint32, i32p, f64p, f64p, f32p]
+    L.or_phi_dirichlet.argtypes = [C.c_int32, C.c_int32, C.c_double, f64p, C.c_uint64, C.c_uint32, i32p, f64p, f64p,
+                                   f32p]
     L.or_phi_dirichlet.restype = C.c_int32
     L.or_word_tables.argtypes = [C.c_int32, C.c_int32, f64p, f32p, i64p, u16p, f32p, u32p, u16p, f64p]
     L.or_word_tables.restype = C.c_int64
@@ -75,7 +78,7 @@ def _declare(L):
     L.or_z_step.restype = C.c_int64
     L.or_replay.argtypes = [C.c_int64, C.c_int32, C.c_int32, i64p, i32p, u16p, u16p, C.c_uint64, C.c_uint32,
                             f32p, i64p, u16p, u32p, u16p, f64p, C.c_double, i64p, f64p, i64p, i64p, C.c_int64]
-    L.or_loglik.argtypes = [C.c_int64, C.c_int32, C.c_int32, i64p, i32p, u16p, f64p, C.c_double]
+    L.or_loglik.argtypes = [C.c_int64, C.c_int32, C.c_int32, i64p, i32p, u16p, f64p, C.c_double, f64p]
     L.or_loglik.restype = C.c_double
     L.or_foldin.argtypes = [C.c_int32, C.c_int32, f32p, i64p, u16p, u32p, u16p, f64p, f64p, C.c_uint64,
                             C.c_uint32, i32p, C.c_int32, C.c_int32, C.c_int32, f32p, f64p, i32p, u16p]
@@ -116,10 +119,19 @@ def pois_table(beta, l):
     return thr, alias
 
 
-def ztp_thresholds(beta):
-    T = np.zeros(5, np.uint32)
-    lib().or_ztp_thresholds(beta, _p(T, C.c_uint32))
-    return T
+def ztp_thresholds(beta, cap=64):
+    """Zero-truncated Pois(beta) thresholds floor(2^32 P(X <= x | X >= 1)),
+    x = 1.., at least 5, up to the first that saturates."""
+    T = np.zeros(cap, np.uint32)
+    n = lib().or_ztp_thresholds(beta, _p(T, C.c_uint32), cap)
+    return T[:n].copy()
+
+
+def _beta_arg(beta_v, V):
+    if beta_v is None:
+        return None, None
+    b = _c(np.broadcast_to(beta_v, (V,)), np.float64)
+    return b, _p(b, C.c_double)
 
 
 def init_z(N, K, seed):
@@ -141,11 +153,14 @@ def counts(doc_off, words, z, K, V, with_m=True):
     return n, nk, m
 
 
-def phi_counts(n, beta, L, seed, t):
+def phi_counts(n, beta, L, seed, t, beta_v=None):
+    """Poisson draws of the Polya-urn Phi-step; beta_v: V priors (or None:
+    the symmetric beta)."""
     n = _c(n, np.int32)
     K, V = n.shape
     gam = np.zeros((K, V), np.int32)
-    lib().or_phi_counts(K, V, beta, L, seed, t, _p(n, C.c_int32), _p(gam, C.c_int32))
+    keep, bp = _beta_arg(beta_v, V)
+    lib().or_phi_counts(K, V, beta, bp, L, seed, t, _p(n, C.c_int32), _p(gam, C.c_int32))
     return gam
 
 
@@ -164,16 +179,17 @@ def gamma_draw(a, seed, c0, c1, c2):
     return lib().or_gamma_draw(float(a), seed, c0, c1, c2)
 
 
-def phi_dirichlet(n, beta, seed, t):
+def phi_dirichlet(n, beta, seed, t, beta_v=None):
     """Algorithm 1's Phi-step: phi_k ~ Dir(n_k + beta) via Gamma draws.
     Returns (gamma fp64 K x V, S fp64 K, phi fp32 K x V, empty rows)."""
     n = _c(n, np.int32)
     K, V = n.shape
+    keep, bp = _beta_arg(beta_v, V)
     gam = np.zeros((K, V), np.float64)
     S = np.zeros(K, np.float64)
     phi = np.zeros((K, V), np.float32)
-    empty = lib().or_phi_dirichlet(K, V, beta, seed, t, _p(n, C.c_int32), _p(gam, C.c_double), _p(S, C.c_double),
-                                   _p(phi, C.c_float))
+    empty = lib().or_phi_dirichlet(K, V, beta, bp, seed, t, _p(n, C.c_int32), _p(gam, C.c_double),
+                                   _p(S, C.c_double), _p(phi, C.c_float))
     return gam, S, phi, empty
 
 
@@ -243,13 +259,14 @@ def replay(doc_off, words, z_before, z_after, seed, t, phi, wt, K, V, tol=1e-6, 
                 worst_rel=float(worst[0]), first_bad=int(first[0]))
 
 
-def loglik(doc_off, words, z, alpha, beta, K, V):
+def loglik(doc_off, words, z, alpha, beta, K, V, beta_v=None):
     doc_off = _c(doc_off, np.int64)
     words = _c(words, np.int32)
     z = _c(z, np.uint16)
     alpha = _c(np.broadcast_to(alpha, (K,)), np.float64)
+    keep, bp = _beta_arg(beta_v, V)
     return float(lib().or_loglik(len(doc_off) - 1, K, V, _p(doc_off, C.c_int64), _p(words, C.c_int32),
-                                 _p(z, C.c_uint16), _p(alpha, C.c_double), beta))
+                                 _p(z, C.c_uint16), _p(alpha, C.c_double), beta, bp))
 
 
 def foldin(phi, wt, alpha, seed, req, words, S=50, burn_in=25):

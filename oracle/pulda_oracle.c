@@ -53,6 +53,10 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* entries of a zero-truncated Poisson threshold table (rates up to 16 saturate
+ * well before) */
+#define ZTP_CAP 64
+
 enum { TAG_INIT = 0, TAG_PHI_CELL = 1, TAG_PHI_PRIOR = 2, TAG_Z = 3, TAG_FOLDIN_INIT = 4, TAG_FOLDIN_Z = 5,
        TAG_PHI_GAMMA = 6, TAG_LTR = 7 };
 
@@ -162,17 +166,22 @@ void or_pois_table(double beta, int32_t l, uint32_t *thr, int32_t *alias)
 
 /* Zero-truncated Pois(beta) by inverse CDF over x = 1..6:
  * T_x = floor(2^32 P(X <= x | X >= 1)), value = 1 + #{x in 1..5 : r >= T_x}. */
-void or_ztp_thresholds(double beta, uint32_t T[5])
+int32_t or_ztp_thresholds(double beta, uint32_t *T, int32_t cap)
 {
     double norm = -expm1(-beta);            /* P(X >= 1) */
     double cdf = 0.0, term = exp(-beta);    /* term = P(X = x) */
-    for (int x = 1; x <= 5; x++) {
+    int32_t n = 0;
+    for (int x = 1; x <= cap; x++) {
         term = term * beta / (double)x;
         cdf += term;
         double c = cdf / norm;
         double t = floor(c * 4294967296.0);
-        T[x - 1] = t >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)t;
+        T[n++] = t >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)t;
+        /* at least 5 entries; then stop at the first that saturates: the
+         * mass above it is below the 2^-32 resolution of r2 */
+        if (x >= 5 && T[n - 1] == 0xFFFFFFFFu) break;
     }
+    return n;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -222,24 +231,33 @@ void or_counts(int64_t D, int32_t K, int32_t V, const int64_t *doc_off, const in
 /*     r2; marks that land on counted cells are ignored (they carry their own */
 /*     draw).  This is the same law as one Pois(beta) draw per zero cell.     */
 /* ------------------------------------------------------------------------ */
-void or_phi_counts(int32_t K, int32_t V, double beta, int32_t L, uint64_t seed, uint32_t t,
+void or_phi_counts(int32_t K, int32_t V, double beta, const double *beta_v, int32_t L, uint64_t seed, uint32_t t,
                    const int32_t *n, int32_t *gam)
 {
+    /* beta_v (V priors, or NULL for the symmetric beta): with a vector,
+     * Pois(beta_v + l) of a counted cell is the sum of Pois(l) (alias tables
+     * of integer rates, a rounded Gaussian of rate l above L) and the cell's
+     * Pois(beta_v) prior mark, which the column's jumps draw for every cell,
+     * counted or not: the same law, with the per-word rate kept in the one
+     * place it varies */
+    const double tb = beta_v ? 0.0 : beta;     /* the tables' rate offset */
     /* Poisson tables, rebuilt here every call: plain, not fast */
     int32_t *sizes = (int32_t *)malloc(sizeof(int32_t) * (size_t)(L + 1));
     uint32_t **thr = (uint32_t **)malloc(sizeof(uint32_t *) * (size_t)(L + 1));
     int32_t **ali = (int32_t **)malloc(sizeof(int32_t *) * (size_t)(L + 1));
     for (int32_t l = 1; l <= L; l++) {
-        sizes[l] = or_pois_support(beta, l);
+        sizes[l] = or_pois_support(tb, l);
         thr[l] = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)sizes[l]);
         ali[l] = (int32_t *)malloc(sizeof(int32_t) * (size_t)sizes[l]);
-        or_pois_table(beta, l, thr[l], ali[l]);
+        or_pois_table(tb, l, thr[l], ali[l]);
     }
-    uint32_t T[5];
-    or_ztp_thresholds(beta, T);
+    uint32_t T[ZTP_CAP];
+    int32_t nT = or_ztp_thresholds(beta, T, ZTP_CAP);
     const double two_pi = 6.283185307179586476925286766559;
 
     for (int32_t v = 0; v < V; v++) {
+        const double bv = beta_v ? beta_v[v] : beta;
+        if (beta_v) nT = or_ztp_thresholds(bv, T, ZTP_CAP);
         for (int32_t k = 0; k < K; k++) {
             int32_t l = n[(size_t)k * V + v];
             int32_t x = 0;
@@ -250,7 +268,7 @@ void or_phi_counts(int32_t K, int32_t V, double beta, int32_t L, uint64_t seed, 
                     uint32_t j = mulhi(r[0], (uint32_t)sizes[l]);
                     x = (r[1] < thr[l][j]) ? (int32_t)j : ali[l][j];
                 } else {
-                    double lam = beta + (double)l;
+                    double lam = tb + (double)l;
                     double g = sqrt(-2.0 * log(1.0 - u53(r[0], r[1]))) * cos(two_pi * u53(r[2], r[3]));
                     double y = floor(lam + sqrt(lam) * g + 0.5);
                     x = y > 0.0 ? (int32_t)y : 0;
@@ -263,15 +281,14 @@ void or_phi_counts(int32_t K, int32_t V, double beta, int32_t L, uint64_t seed, 
         for (uint32_t j = 0;; j++) {
             uint32_t r[4];
             draw4(seed, (uint32_t)v, j, t, TAG_PHI_PRIOR, r);
-            double e = -log(1.0 - u53(r[0], r[1])) / beta;
+            double e = -log(1.0 - u53(r[0], r[1])) / bv;
             int64_t gap = (int64_t)floor(e);
             if (pos + 1 + gap >= (int64_t)K) break;
             pos = pos + 1 + gap;
-            if (n[(size_t)pos * V + v] == 0) {
-                int32_t x = 1;
-                for (int q = 0; q < 5; q++) if (r[2] >= T[q]) x++;
-                gam[(size_t)pos * V + v] = x;
-            }
+            int32_t x = 1;
+            for (int q = 0; q < nT; q++) if (r[2] >= T[q]) x++;
+            if (n[(size_t)pos * V + v] == 0) gam[(size_t)pos * V + v] = x;
+            else if (beta_v) gam[(size_t)pos * V + v] += x;
         }
     }
     for (int32_t l = 1; l <= L; l++) { free(thr[l]); free(ali[l]); }
@@ -354,15 +371,15 @@ double or_gamma_draw(double a, uint64_t seed, uint32_t c0, uint32_t c1, uint32_t
 /* smallest normal fp32 (2^-126: zero or subnormal) is set to zero, so the    */
 /* sparse Phi is the set of cells with a normal fp32 value.  A row with       */
 /* S_k = 0 is empty.  gam, phi: topic-major K x V.  Returns the empty rows.   */
-int32_t or_phi_dirichlet(int32_t K, int32_t V, double beta, uint64_t seed, uint32_t t, const int32_t *n,
-                         double *gam, double *S, float *phi)
+int32_t or_phi_dirichlet(int32_t K, int32_t V, double beta, const double *beta_v, uint64_t seed, uint32_t t,
+                         const int32_t *n, double *gam, double *S, float *phi)
 {
     const float flt_min = 1.17549435082228750797e-38f;
     int32_t empty_rows = 0;
     for (int32_t k = 0; k < K; k++)
         for (int32_t v = 0; v < V; v++)
-            gam[(size_t)k * V + v] = or_gamma_draw(beta + (double)n[(size_t)k * V + v], seed, (uint32_t)v,
-                                                   (uint32_t)k, t);
+            gam[(size_t)k * V + v] = or_gamma_draw((beta_v ? beta_v[v] : beta) + (double)n[(size_t)k * V + v], seed,
+                                                   (uint32_t)v, (uint32_t)k, t);
     for (int32_t k = 0; k < K; k++) {
         double s = 0.0;
         for (int32_t v = 0; v < V; v++) s += gam[(size_t)k * V + v];
@@ -606,19 +623,25 @@ void or_replay(int64_t D, int32_t K, int32_t V, const int64_t *doc_off, const in
 /*  with A = sum_k alpha_k.  Computed from z by counting, k-major then d-major.*/
 /* ------------------------------------------------------------------------ */
 double or_loglik(int64_t D, int32_t K, int32_t V, const int64_t *doc_off, const int32_t *words,
-                 const uint16_t *z, const double *alpha, double beta)
+                 const uint16_t *z, const double *alpha, double beta, const double *beta_v)
 {
     int32_t *n = (int32_t *)calloc((size_t)K * (size_t)V, sizeof(int32_t));
     int64_t *nk = (int64_t *)calloc((size_t)K, sizeof(int64_t));
     int32_t *m = (int32_t *)malloc(sizeof(int32_t) * (size_t)K);
     for (int64_t i = 0; i < doc_off[D]; i++) { n[(size_t)z[i] * V + words[i]]++; nk[z[i]]++; }
+    /* with a vector beta_v: B = sum_v beta_v replaces V beta, and each
+     * cell's term uses its word's beta_v */
     double Vb = (double)V * beta, lgb = lgamma(beta);
+    if (beta_v) {
+        Vb = 0.0;
+        for (int32_t v = 0; v < V; v++) Vb += beta_v[v];
+    }
     double word = (double)K * lgamma(Vb);
     for (int32_t k = 0; k < K; k++) {
         word -= lgamma((double)nk[k] + Vb);
         for (int32_t v = 0; v < V; v++) {
             int32_t c = n[(size_t)k * V + v];
-            if (c > 0) word += lgamma((double)c + beta) - lgb;
+            if (c > 0) word += beta_v ? lgamma((double)c + beta_v[v]) - lgamma(beta_v[v]) : lgamma((double)c + beta) - lgb;
         }
     }
     double A = 0.0;

@@ -26,10 +26,11 @@ MUTATIONS = [
      [pins.test_pois_tables_exact_law]),
     ("gaussian_no_rounding", "floor(lam + sqrt(lam) * g + 0.5)", "floor(lam + sqrt(lam) * g)",
      [lambda: pins.test_rounded_gaussian_closed_form(150)]),
-    ("prior_rate_inverted", "double e = -log(1.0 - u53(r[0], r[1])) / beta;",
-     "double e = -log(1.0 - u53(r[0], r[1])) * (1.0 / (2.0 * beta));",
+    ("prior_rate_inverted", "double e = -log(1.0 - u53(r[0], r[1])) / bv;",
+     "double e = -log(1.0 - u53(r[0], r[1])) * (1.0 / (2.0 * bv));",
      [pins.test_prior_marks_binomial_and_uniform]),
-    ("prior_marks_overwrite_counted", "if (n[(size_t)pos * V + v] == 0) {", "if (1) {",
+    ("prior_marks_overwrite_counted", "if (n[(size_t)pos * V + v] == 0) gam[(size_t)pos * V + v] = x;",
+     "if (1) gam[(size_t)pos * V + v] = x;",
      [pins.test_prior_marks_ignore_counted_cells]),
     ("no_alpha_part", "double sa = M->sigma_a[v];", "double sa = 0.0;",
      [lambda: pins.test_token_law_enumeration("overlap")]),
@@ -49,7 +50,8 @@ MUTATIONS = [
      [lambda: pins.test_gamma_draw_law(0.3)]),
     ("gamma_normal_variance", "sqrt(-2.0 * log(u32o(r[0])))", "sqrt(-1.0 * log(u32o(r[0])))",
      [lambda: pins.test_gamma_draw_law(2.5)]),
-    ("dirichlet_shape_prior", "or_gamma_draw(beta + (double)n[", "or_gamma_draw(2.0 * beta + (double)n[",
+    ("dirichlet_shape_prior", "or_gamma_draw((beta_v ? beta_v[v] : beta) + (double)n[",
+     "or_gamma_draw((beta_v ? beta_v[v] : 2.0 * beta) + (double)n[",
      [lambda: pins.test_phi_dirichlet_moments(0.5)]),
     ("dirichlet_row_sum_skips", "double s = 0.0;\n        for (int32_t v = 0; v < V; v++) s += gam[",
      "double s = 0.0;\n        for (int32_t v = 1; v < V; v++) s += gam[",
@@ -62,6 +64,14 @@ MUTATIONS = [
      [pins.test_ltr_third_token_expectation]),
     ("ltr_denominator", "sum += Z / ((double)n + A);", "sum += Z / ((double)n + 1.0 + A);",
      [pins.test_ltr_single_token_closed_form]),
+    ("vector_mark_not_added", "else if (beta_v) gam[(size_t)pos * V + v] += x;",
+     "else if (0) gam[(size_t)pos * V + v] += x;",
+     [pins.test_vector_beta_cell_law]),
+    ("vector_tables_keep_beta", "const double tb = beta_v ? 0.0 : beta;", "const double tb = beta;",
+     [pins.test_vector_beta_cell_law]),
+    ("vector_loglik_prior_sum", "for (int32_t v = 0; v < V; v++) Vb += beta_v[v];",
+     "for (int32_t v = 0; v < V; v++) Vb += beta;",
+     [pins.test_vector_beta_loglik_and_dirichlet]),
     ("normalise_wrong_row", "phi[(size_t)k * V + v] = g > 0 ? (float)((double)g / (double)s) : 0.0f;",
      "phi[(size_t)k * V + v] = g > 0 ? (float)((double)g / (double)(s + 1)) : 0.0f;",
      [pins.test_phi_normalise_definition]),

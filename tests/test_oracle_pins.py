@@ -217,12 +217,74 @@ def test_prior_marks_ignore_counted_cells():
     assert chisq_p(np.bincount(counted), stats.poisson.pmf(xs, beta + 1) * len(counted)) > 1e-4
 
 
-def test_ztp_thresholds():
-    beta = 0.01
+@pytest.mark.parametrize("beta", [0.01, 0.3, 2.0, 10.0])
+def test_ztp_thresholds(beta):
     T = oracle.ztp_thresholds(beta)
-    xs = np.arange(1, 6)
+    n = len(T)
+    assert n >= 5 and T[-1] == 0xFFFFFFFF and (n == 5 or T[-2] != 0xFFFFFFFF)
+    xs = np.arange(1, n + 1)
     cdf = np.cumsum(stats.poisson.pmf(xs, beta)) / stats.poisson.sf(0, beta)
-    assert np.all(np.abs(T / TWO32 - cdf) <= 2.0 / TWO32)
+    assert np.all(np.abs(T / TWO32 - np.minimum(cdf, 1.0)) <= 2.0 / TWO32)
+    # what the table cannot draw (x > n) is below the 2^-32 resolution
+    assert stats.poisson.sf(n, beta) / stats.poisson.sf(0, beta) < 2.0 / TWO32
+
+
+def test_vector_beta_cell_law():
+    """Per-word priors: each cell's draw is Pois(beta_v + n_kv), counted cells
+    as the sum of an integer-rate draw and the prior mark."""
+    row = np.array([0, 0, 1, 3, 0, 150], np.int32)
+    bv = np.array([0.02, 0.7, 0.3, 1.5, 4.0, 0.8])
+    R = 40000
+    n = np.tile(row, (R, 1))
+    g = oracle.phi_counts(n, 0.5, 100, 21, 2, beta_v=bv).astype(np.float64)
+    lam = row + bv
+    m = g.mean(axis=0)
+    se = np.sqrt(lam / R)
+    assert np.all(np.abs(m - lam) < 5 * se), (m, lam)
+    v = g.var(axis=0)
+    assert np.all(np.abs(v[:5] - lam[:5]) < 6 * np.sqrt(2 * lam[:5] ** 2 / R + lam[:5] / R)), (v, lam)
+    # the zero counts of each cell follow exp(-(beta_v + n))
+    p0 = (g[:, :4] == 0).mean(axis=0)
+    e0 = np.exp(-lam[:4])
+    assert np.all(np.abs(p0 - e0) < 5 * np.sqrt(e0 * (1 - e0) / R) + 1e-12)
+    # the scalar path keeps its own law (Pois(beta + n))
+    gs = oracle.phi_counts(n, 0.5, 100, 21, 2).astype(np.float64)
+    assert np.all(np.abs(gs.mean(axis=0) - (row + 0.5)) < 5 * np.sqrt((row + 0.5) / R))
+
+
+def test_vector_beta_loglik_and_dirichlet():
+    rng = np.random.default_rng(12)
+    K, V = 6, 40
+    bv = rng.uniform(0.005, 0.9, V)
+    c = synth_small(rng, K, V)
+    alpha = np.full(K, 0.3)
+    ll = oracle.loglik(c[0], c[1], c[2], alpha, 0.01, K, V, beta_v=bv)
+    n = np.zeros((K, V), np.int64)
+    np.add.at(n, (c[2].astype(np.int64), c[1]), 1)
+    B = bv.sum()
+    word = K * special.gammaln(B) - special.gammaln(n.sum(axis=1) + B).sum()
+    word += (special.gammaln(n + bv) - special.gammaln(bv))[n > 0].sum()
+    doc = 0.0
+    for d in range(len(c[0]) - 1):
+        m = np.bincount(c[2][c[0][d]:c[0][d + 1]], minlength=K)
+        doc += special.gammaln(alpha.sum()) - special.gammaln(m.sum() + alpha.sum())
+        doc += (special.gammaln(m + alpha) - special.gammaln(alpha))[m > 0].sum()
+    assert abs(ll - (word + doc)) <= 1e-10 * abs(ll)
+    # Dirichlet rows with per-word priors: the mean is (n + beta_v) / sum
+    row = np.array([0, 2, 0, 5], np.int32)
+    b4 = np.array([0.05, 0.5, 1.2, 0.3])
+    gam, S, phi, _ = oracle.phi_dirichlet(np.tile(row, (30000, 1)), 0.01, 4, 1, beta_v=b4)
+    x = gam / S[:, None]
+    F = (row + b4) / (row + b4).sum()
+    var = F * (1 - F) / ((row + b4).sum() + 1)
+    assert np.all(np.abs(x.mean(axis=0) - F) < 5 * np.sqrt(var / 30000))
+
+
+def synth_small(rng, K, V, D=30):
+    lens = rng.integers(0, 25, D)
+    off = np.zeros(D + 1, np.int64)
+    np.cumsum(lens, out=off[1:])
+    return off, rng.integers(0, V, off[-1]).astype(np.int32), rng.integers(0, K, off[-1]).astype(np.uint16)
 
 
 # --------------------------------------------------------------------------
