@@ -83,6 +83,15 @@ typedef struct {
     const double *alpha_k;   /* optional host vector of K priors alpha_k > 0 (copied), or NULL */
     int32_t L;               /* Poisson alias tables for rates beta + l, 1 <= l <= L (Section 3.4); 1..1000 */
     uint64_t seed;           /* Philox key */
+    const double *beta_v;    /* optional host vector of V priors beta_v in (0, 16] (copied; beta is then
+                                ignored), or NULL for the symmetric beta in (0, 16].  The paper's beta is a
+                                V-vector (Section 3.2); with per-word priors the Polya-urn Phi-step draws
+                                a counted cell's Pois(beta_v + n_kv) as Pois(n_kv) (alias tables of integer
+                                rates, a rounded Gaussian above L) plus the cell's prior mark, the
+                                zero-truncated Pois(beta_v) value the column's jumps at rate beta_v give
+                                every marked cell, counted or not: the same law.  The Dirichlet Phi-step
+                                uses shapes beta_v + n_kv and the log joint sum_v beta_v and
+                                lgamma(n_kv + beta_v). */
 } pulda_model_desc;
 
 typedef struct pulda_plan pulda_plan;

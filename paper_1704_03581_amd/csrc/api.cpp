@@ -97,17 +97,27 @@ void poisson_tables(double beta, int32_t L, std::vector<int32_t> &off, std::vect
     off[L + 1] = (int32_t)packed.size();
 }
 
-// zero-truncated Pois(beta): T_x = floor(2^32 P(X <= x | X >= 1)), x = 1..5
-void ztp_thresholds(double beta, uint32_t T[5])
+// zero-truncated Pois(beta): T_x = floor(2^32 P(X <= x | X >= 1)), x = 1..,
+// at least 5 entries, up to the first that saturates (the mass above it is
+// below the 2^-32 resolution of the uniform that reads the table); appended
+// to T, returns the count
+constexpr int ZTP_CAP = 64;
+constexpr double BETA_MAX = 16.0;   // rates whose tables saturate within ZTP_CAP
+
+int32_t ztp_thresholds(double beta, std::vector<uint32_t> &T)
 {
     const double norm = -std::expm1(-beta);
     double cdf = 0.0, term = std::exp(-beta);
-    for (int x = 1; x <= 5; ++x) {
+    int32_t n = 0;
+    for (int x = 1; x <= ZTP_CAP; ++x) {
         term = term * beta / (double)x;
         cdf += term;
         const double t = std::floor((cdf / norm) * 4294967296.0);
-        T[x - 1] = t >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)t;
+        T.push_back(t >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)t);
+        ++n;
+        if (x >= 5 && T.back() == 0xFFFFFFFFu) break;
     }
+    return n;
 }
 
 struct Layout {
@@ -133,7 +143,7 @@ struct pulda_plan {
     uint8_t *ws = nullptr;
     int64_t ws_need = 0;
     struct {
-        int64_t z, n, gam, phid, g16, Rd, gamd, Sd, dpart, phimax, ckg, colcnt, colptr, ctopic, cphi, calias, sigma_a, S, nk, alpha, pois, pois_off,
+        int64_t z, n, gam, phid, g16, Rd, gamd, Sd, dpart, phimax, beta_v, ztp, ztp_off, ckg, colcnt, colptr, ctopic, cphi, calias, sigma_a, S, nk, alpha, pois, pois_off,
             doc_order, items, queue, stats, ll_part, ll_out, ll_hist, tptr, err, scratch, cnt_a, ptr_a, cnt_b,
             ptr_b, zsave, lg_beta, lg_alpha, lg_A, ll_doc;
     } off;
@@ -144,7 +154,11 @@ struct pulda_plan {
     std::vector<uint64_t> pois_h;
     std::vector<double> lg_beta_h, lg_alpha_h, lg_A_h;  // log-joint term tables
     bool symmetric_alpha = true;
-    uint32_t ztp[5];
+    std::vector<double> beta_vh;      // per-word priors (empty: the symmetric beta)
+    std::vector<uint32_t> ztp_h;      // zero-truncated thresholds: one row, or one per word
+    std::vector<int32_t> ztp_off_h;   // [V+1] row offsets for per-word priors
+    int32_t ztp_n = 0;
+    double beta_sum = 0.0;
     // device views
     DevModel m{};
     DevCorpus c{};
@@ -218,7 +232,12 @@ pulda_status pulda_plan_create(const pulda_model_desc *desc, int64_t D, int64_t 
     if ((int64_t)desc->K * desc->V >= (1ll << 31)) return fail(PULDA_ERR_INVALID_ARG, "K*V must be < 2^31");
     if ((int64_t)desc->V * ((desc->K + 63) / 64 * 64) >= (1ll << 32))
         return fail(PULDA_ERR_INVALID_ARG, "V * (K rounded up to 64) must be < 2^32");
-    if (!(desc->beta > 0.0) || !std::isfinite(desc->beta)) return fail(PULDA_ERR_INVALID_ARG, "beta must be > 0");
+    if (!desc->beta_v && !(desc->beta > 0.0 && desc->beta <= BETA_MAX))
+        return fail(PULDA_ERR_INVALID_ARG, "beta must be in (0, %g]", BETA_MAX);
+    if (desc->beta_v)
+        for (int32_t v = 0; v < desc->V; ++v)
+            if (!(desc->beta_v[v] > 0.0 && desc->beta_v[v] <= BETA_MAX))
+                return fail(PULDA_ERR_INVALID_ARG, "beta_v[%d] must be in (0, %g]", v, BETA_MAX);
     if (desc->L < 1 || desc->L > 1000) return fail(PULDA_ERR_INVALID_ARG, "L=%d outside 1..1000", desc->L);
     if (D < 0 || N < 0 || N >= (1ll << 40) || D >= (1ll << 31))
         return fail(PULDA_ERR_INVALID_ARG, "bad corpus size D=%lld N=%lld", (long long)D, (long long)N);
@@ -231,15 +250,28 @@ pulda_status pulda_plan_create(const pulda_model_desc *desc, int64_t D, int64_t 
     p->K = desc->K;
     p->V = desc->V;
     p->L = desc->L;
-    p->beta = desc->beta;
+    p->beta = desc->beta_v ? 1.0 : desc->beta;   // (unused with per-word priors)
+    if (desc->beta_v) p->beta_vh.assign(desc->beta_v, desc->beta_v + desc->V);
     p->seed = desc->seed;
     p->alpha = alpha;
     p->A = 0.0;
     for (double a : alpha) p->A += a;
     p->D = D;
     p->N = N;
-    poisson_tables(p->beta, p->L, p->pois_off_h, p->pois_h);
-    ztp_thresholds(p->beta, p->ztp);
+    // per-word priors: tables of the integer rates l, and every cell's
+    // Pois(beta_v) part from the prior marks
+    poisson_tables(p->beta_vh.empty() ? p->beta : 0.0, p->L, p->pois_off_h, p->pois_h);
+    if (p->beta_vh.empty()) {
+        p->ztp_n = ztp_thresholds(p->beta, p->ztp_h);
+        p->beta_sum = (double)p->V * p->beta;
+    } else {
+        p->ztp_off_h.assign(p->V + 1, 0);
+        for (int32_t v = 0; v < p->V; ++v) {
+            ztp_thresholds(p->beta_vh[v], p->ztp_h);
+            p->ztp_off_h[v + 1] = (int32_t)p->ztp_h.size();
+            p->beta_sum += p->beta_vh[v];
+        }
+    }
     // log-joint terms of small integer counts, evaluated once
     for (double a : alpha) p->symmetric_alpha = p->symmetric_alpha && a == alpha[0];
     p->lg_beta_h.resize(LG_TABLE);
@@ -273,6 +305,9 @@ pulda_status pulda_plan_create(const pulda_model_desc *desc, int64_t D, int64_t 
     p->off.ckg = L.take(p->cap * 4);
     p->off.calias = L.take(p->cap * 8);
     p->off.sigma_a = L.take((int64_t)p->V * 8);
+    p->off.beta_v = L.take(p->beta_vh.empty() ? 8 : (int64_t)p->V * 8);
+    p->off.ztp = L.take((int64_t)p->ztp_h.size() * 4);
+    p->off.ztp_off = L.take(((int64_t)p->V + 1) * 4);
     p->off.phimax = L.take((int64_t)p->V * 4);
     p->off.S = L.take((int64_t)p->K * 8);
     p->off.nk = L.take((int64_t)p->K * 8);
@@ -348,7 +383,11 @@ pulda_status pulda_plan_bind(pulda_plan *p, void *workspace_dev, int64_t bytes)
     m.phimax = (float *)(w + p->off.phimax);
     m.pois = (const uint64_t *)(w + p->off.pois);
     m.pois_off = (const int32_t *)(w + p->off.pois_off);
-    std::memcpy(m.ztp, p->ztp, sizeof(m.ztp));
+    m.beta_v = p->beta_vh.empty() ? nullptr : (const double *)(w + p->off.beta_v);
+    m.ztp_tab = (const uint32_t *)(w + p->off.ztp);
+    m.ztp_off = p->beta_vh.empty() ? nullptr : (const int32_t *)(w + p->off.ztp_off);
+    m.ztp_n = p->ztp_n;
+    m.beta_sum = p->beta_sum;
     m.lg_beta = (const double *)(w + p->off.lg_beta);
     m.lg_alpha = p->symmetric_alpha ? (const double *)(w + p->off.lg_alpha) : nullptr;
     m.lg_A = (const double *)(w + p->off.lg_A);
@@ -377,6 +416,11 @@ pulda_status pulda_plan_bind(pulda_plan *p, void *workspace_dev, int64_t bytes)
     HIP_TRY(hipMemcpy((void *)m.alpha, p->alpha.data(), p->K * sizeof(double), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy((void *)m.pois, p->pois_h.data(), p->pois_h.size() * 8, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy((void *)m.pois_off, p->pois_off_h.data(), p->pois_off_h.size() * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy((void *)m.ztp_tab, p->ztp_h.data(), p->ztp_h.size() * 4, hipMemcpyHostToDevice));
+    if (m.beta_v) {
+        HIP_TRY(hipMemcpy((void *)m.beta_v, p->beta_vh.data(), p->V * 8, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy((void *)m.ztp_off, p->ztp_off_h.data(), (p->V + 1) * 4, hipMemcpyHostToDevice));
+    }
     HIP_TRY(hipMemcpy(w + p->off.lg_beta, p->lg_beta_h.data(), LG_TABLE * 8, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(w + p->off.lg_alpha, p->lg_alpha_h.data(), LG_TABLE * 8, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(w + p->off.lg_A, p->lg_A_h.data(), LG_TABLE * 8, hipMemcpyHostToDevice));

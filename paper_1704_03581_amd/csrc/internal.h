@@ -47,7 +47,14 @@ struct DevModel {
     float *phimax;                // [V] the largest phi of each word's column
     const uint64_t *pois;         // Poisson alias tables, thr | x_alias << 32
     const int32_t *pois_off;      // [L+2]
-    uint32_t ztp[5];              // zero-truncated Pois(beta) thresholds
+    // per-word priors (null: the symmetric beta); zero-truncated
+    // Pois(beta_v) thresholds floor(2^32 P(X <= x | X >= 1)), x = 1.., one row
+    // per word in ztp_tab from ztp_off (null: one row of ztp_n for beta)
+    const double *beta_v;         // [V]
+    const uint32_t *ztp_tab;
+    const int32_t *ztp_off;       // [V+1]
+    int32_t ztp_n;
+    double beta_sum;              // sum_v beta_v (V beta for the symmetric prior)
     // log-joint terms for integer counts x < LG_TABLE:
     //   lg_beta[x] = lgamma(x + beta) - lgamma(beta),
     //   lg_alpha[x] = lgamma(x + alpha) - lgamma(alpha) (symmetric alpha only, else null),

@@ -285,6 +285,13 @@ __global__ void __launch_bounds__(256) phi_draw_kernel(DevModel m, int32_t kpad)
     const int32_t K = m.K;
     const int32_t *ncol = m.n + (int64_t)v * K;
     const double two_pi = 6.283185307179586476925286766559;
+    // per-word priors: the tables are of integer rates l and every cell's
+    // Pois(beta_v) part comes from the prior marks below, added to its draw
+    const bool vec = m.beta_v != nullptr;
+    const double bv = vec ? m.beta_v[v] : m.beta;
+    const double tb = vec ? 0.0 : m.beta;
+    const uint32_t *T = m.ztp_tab + (vec ? m.ztp_off[v] : 0);
+    const int32_t nT = vec ? m.ztp_off[v + 1] - m.ztp_off[v] : m.ztp_n;
 
     for (int32_t k = lane; k < K; k += 64) {
         const int32_t l = ncol[k];
@@ -298,7 +305,7 @@ __global__ void __launch_bounds__(256) phi_draw_kernel(DevModel m, int32_t kpad)
                 const uint64_t e = m.pois[off + j];
                 x = (r.y < (uint32_t)e) ? (int32_t)j : (int32_t)(e >> 32);
             } else {
-                const double lam = m.beta + (double)l;
+                const double lam = tb + (double)l;
                 const double rad = sqrt(-2.0 * log(1.0 - unit53(r.x, r.y)));
                 const double gz = rad * cos(two_pi * unit53(r.z, r.w));
                 const double y = floor(lam + sqrt(lam) * gz + 0.5);
@@ -312,7 +319,7 @@ __global__ void __launch_bounds__(256) phi_draw_kernel(DevModel m, int32_t kpad)
     long long pos_base = -1;
     for (uint32_t jb = 0;; jb += 64) {
         r4 r = philox((uint32_t)v, jb + (uint32_t)lane, t, TAG_PHI_PRIOR, m.key0, m.key1);
-        const double e = -log(1.0 - unit53(r.x, r.y)) / m.beta;
+        const double e = -log(1.0 - unit53(r.x, r.y)) / bv;
         // a jump longer than K ends the column whatever its exact length
         const double capped = e < (double)K ? floor(e) : (double)K;
         const int32_t step = 1 + (int32_t)capped;
@@ -320,12 +327,10 @@ __global__ void __launch_bounds__(256) phi_draw_kernel(DevModel m, int32_t kpad)
         const long long pos = pos_base + incl;
         if (pos < K) {
             int32_t *cell = &g[pos];
-            if (*cell == -1) {
-                int32_t x = 1;
-#pragma unroll
-                for (int q = 0; q < 5; ++q) x += (r.z >= m.ztp[q]) ? 1 : 0;
-                *cell = x;
-            }
+            int32_t x = 1;
+            for (int q = 0; q < nT; ++q) x += (r.z >= T[q]) ? 1 : 0;
+            if (*cell == -1) *cell = x;
+            else if (vec) *cell += x;
         }
         const long long last = pos_base + __builtin_amdgcn_readlane(incl, 63);
         if (last >= K) break;
@@ -690,7 +695,7 @@ __global__ void __launch_bounds__(256) gamma_kernel(DevModel m)
     const uint32_t t = *m.tptr;
     const int32_t v = (int32_t)(cell / m.K);
     const int32_t k = (int32_t)(cell - (int64_t)v * m.K);
-    const double a = m.beta + (double)m.n[cell];
+    const double a = (m.beta_v ? m.beta_v[v] : m.beta) + (double)m.n[cell];
     m.gamd[cell] = gamma_draw(a, (uint32_t)v, (uint32_t)k, t, m.key0, m.key1);
 }
 
@@ -1680,14 +1685,24 @@ __device__ __forceinline__ double block_sum_f64(double x, double *red)
     return t;
 }
 
-__global__ void __launch_bounds__(256) ll_words_kernel(const int32_t *n, int64_t cells, double beta, double lgb,
-                                                       const double *lg_beta, double *partials)
+// (beta_v: per-word priors, cells word-major with K per word; else the
+// symmetric beta through the table of lgamma(x + beta) - lgamma(beta))
+__global__ void __launch_bounds__(256) ll_words_kernel(const int32_t *n, int64_t cells, int32_t K, double beta,
+                                                       double lgb, const double *lg_beta, const double *beta_v,
+                                                       double *partials)
 {
     __shared__ double red[4];
     double acc = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cells; i += (int64_t)gridDim.x * blockDim.x) {
         const int32_t c = n[i];
-        if (c > 0) acc += c < LG_TABLE ? lg_beta[c] : lgamma((double)c + beta) - lgb;
+        if (c > 0) {
+            if (beta_v) {
+                const double b = beta_v[i / K];
+                acc += lgamma((double)c + b) - lgamma(b);
+            } else {
+                acc += c < LG_TABLE ? lg_beta[c] : lgamma((double)c + beta) - lgb;
+            }
+        }
     }
     const double t = block_sum_f64(acc, red);
     if (threadIdx.x == 0) partials[blockIdx.x] = t;
@@ -1778,8 +1793,8 @@ hipError_t launch_loglik(const DevCorpus &c, const DevModel &m, double *partials
 {
     hipError_t e = launch_row_sums(m.n, m.V, m.K, m.nk, s);
     if (e != hipSuccess) return e;
-    ll_words_kernel<<<n_part_words, 256, 0, s>>>(m.n, (int64_t)m.V * m.K, m.beta, lgamma(m.beta), m.lg_beta,
-                                                 partials);
+    ll_words_kernel<<<n_part_words, 256, 0, s>>>(m.n, (int64_t)m.V * m.K, m.K, m.beta, lgamma(m.beta), m.lg_beta,
+                                                 m.beta_v, partials);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (ll_doc) {
@@ -1796,8 +1811,8 @@ hipError_t launch_loglik(const DevCorpus &c, const DevModel &m, double *partials
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    ll_final_kernel<<<1, 64, 0, s>>>(partials, n_part_words + n_part_docs, m.nk, m.K, (double)m.V * m.beta, out,
-                                     hist, hist_idx);
+    ll_final_kernel<<<1, 64, 0, s>>>(partials, n_part_words + n_part_docs, m.nk, m.K, m.beta_sum, out, hist,
+                                     hist_idx);
     return hipGetLastError();
 }
 

@@ -39,7 +39,7 @@ vp, i32, i64, u32, u64, f64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_
 
 class ModelDesc(C.Structure):
     _fields_ = [("K", i32), ("V", i32), ("beta", f64), ("alpha", f64), ("alpha_k", C.POINTER(f64)),
-                ("L", i32), ("seed", u64)]
+                ("L", i32), ("seed", u64), ("beta_v", C.POINTER(f64))]
 
 
 class CountsView(C.Structure):
@@ -157,12 +157,18 @@ class Plan:
                  seed: int = 1, device="cuda"):
         self.K, self.V, self.D, self.N = K, V, D, N
         self.device = torch.device(device)
-        desc = ModelDesc(K=K, V=V, beta=beta, alpha=float(np.mean(alpha)) if np.ndim(alpha) else float(alpha),
-                         alpha_k=None, L=L, seed=seed)
+        # beta: the symmetric prior, or a vector of V per-word priors
+        desc = ModelDesc(K=K, V=V, beta=float(np.mean(beta)) if np.ndim(beta) else float(beta),
+                         alpha=float(np.mean(alpha)) if np.ndim(alpha) else float(alpha),
+                         alpha_k=None, L=L, seed=seed, beta_v=None)
         self._alpha_buf = None
         if np.ndim(alpha):
             self._alpha_buf = np.ascontiguousarray(alpha, dtype=np.float64)
             desc.alpha_k = self._alpha_buf.ctypes.data_as(C.POINTER(f64))
+        self._beta_buf = None
+        if np.ndim(beta):
+            self._beta_buf = np.ascontiguousarray(np.broadcast_to(beta, (V,)), dtype=np.float64)
+            desc.beta_v = self._beta_buf.ctypes.data_as(C.POINTER(f64))
         self.alpha = np.broadcast_to(np.asarray(alpha, dtype=np.float64), (K,)).copy()
         self.beta, self.L, self.seed = beta, L, seed
         h = vp()

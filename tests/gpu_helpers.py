@@ -20,9 +20,9 @@ def phi_from_gpu(g: dict, K: int, V: int):
     return phi, wt
 
 
-def oracle_phi(doc_off, words, z, K, V, alpha, beta, L, seed, t):
+def oracle_phi(doc_off, words, z, K, V, alpha, beta, L, seed, t, beta_v=None):
     n, nk, _ = oracle.counts(doc_off, words, z, K, V, with_m=False)
-    gam = oracle.phi_counts(n, beta, L, seed, t)
+    gam = oracle.phi_counts(n, beta, L, seed, t, beta_v=beta_v)
     S, phi, empty = oracle.phi_normalise(gam)
     wt = oracle.word_tables(alpha, phi)
     return gam, S, phi, wt

@@ -38,7 +38,8 @@ def test_binding_covers_the_header():
 
 class Desc(ctypes.Structure):
     _fields_ = [("K", ctypes.c_int32), ("V", ctypes.c_int32), ("beta", ctypes.c_double), ("alpha", ctypes.c_double),
-                ("alpha_k", ctypes.c_void_p), ("L", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+                ("alpha_k", ctypes.c_void_p), ("L", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("beta_v", ctypes.c_void_p)]
 
 
 @pytest.mark.parametrize("K,V,beta,alpha,L,D,N", [
@@ -47,6 +48,7 @@ class Desc(ctypes.Structure):
     (10, 0, 0.01, 0.1, 100, 1, 1),        # V < 1
     (4096, 600000, 0.01, 0.1, 100, 1, 1),  # K*V >= 2^31
     (10, 10, 0.0, 0.1, 100, 1, 1),        # beta = 0
+    (10, 10, 20.0, 0.1, 100, 1, 1),       # beta > 16 (zero-truncated tables would not saturate)
     (10, 10, 0.01, -1.0, 100, 1, 1),      # alpha < 0
     (10, 10, 0.01, 0.1, 0, 1, 1),         # L = 0
     (10, 10, 0.01, 0.1, 100, -1, 1),      # D < 0
@@ -58,6 +60,20 @@ def test_plan_create_rejects_bad_arguments(lib, K, V, beta, alpha, L, D, N):
     assert st == -1 and not h.value
     lib.pulda_last_error.restype = ctypes.c_char_p
     assert lib.pulda_last_error()
+
+
+def test_plan_create_per_word_priors(lib):
+    import numpy as np
+    good = np.full(10, 0.05)
+    for bv, ok in [(good, True), (np.r_[good[:9], 0.0], False), (np.r_[good[:9], 17.0], False),
+                   (np.r_[good[:9], np.nan], False)]:
+        buf = np.ascontiguousarray(bv, dtype=np.float64)
+        d = Desc(10, 10, 0.0, 0.1, None, 100, 1, buf.ctypes.data_as(ctypes.c_void_p))
+        h = ctypes.c_void_p()
+        st = lib.pulda_plan_create(ctypes.byref(d), ctypes.c_int64(1), ctypes.c_int64(1), ctypes.byref(h))
+        assert (st == 0) == ok, bv
+        if ok:
+            lib.pulda_plan_destroy(h)
 
 
 def test_plan_workspace_and_state_errors(lib):
