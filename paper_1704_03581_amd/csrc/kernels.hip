@@ -1761,16 +1761,22 @@ __global__ void __launch_bounds__(256) ll_docsum_kernel(const double *ll_doc, in
     if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
-__global__ void ll_final_kernel(const double *partials, int32_t np, const unsigned long long *nk, int32_t K,
-                                double Vbeta, double *out, double *hist, const uint32_t *hist_idx)
+// one block of 256: the topics' terms and the partial sums strided over the
+// threads, then a fixed-order block sum (deterministic)
+__global__ void __launch_bounds__(256) ll_final_kernel(const double *partials, int32_t np,
+                                                       const unsigned long long *nk, int32_t K, double Vbeta,
+                                                       double *out, double *hist, const uint32_t *hist_idx)
 {
-    if (threadIdx.x != 0) return;
-    double word = (double)K * lgamma(Vbeta);
-    for (int32_t k = 0; k < K; ++k) word -= lgamma((double)nk[k] + Vbeta);
-    double t = 0.0;
-    for (int32_t i = 0; i < np; ++i) t += partials[i];
-    *out = word + t;
-    if (hist) hist[*hist_idx] = word + t;
+    __shared__ double red[4];
+    double acc = 0.0;
+    for (int32_t k = threadIdx.x; k < K; k += blockDim.x) acc -= lgamma((double)nk[k] + Vbeta);
+    for (int32_t i = threadIdx.x; i < np; i += blockDim.x) acc += partials[i];
+    const double t = block_sum_f64(acc, red);
+    if (threadIdx.x == 0) {
+        const double ll = (double)K * lgamma(Vbeta) + t;
+        *out = ll;
+        if (hist) hist[*hist_idx] = ll;
+    }
 }
 
 __global__ void advance_kernel(uint32_t *tptr, uint32_t *hist_idx)
@@ -1811,8 +1817,8 @@ hipError_t launch_loglik(const DevCorpus &c, const DevModel &m, double *partials
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    ll_final_kernel<<<1, 64, 0, s>>>(partials, n_part_words + n_part_docs, m.nk, m.K, m.beta_sum, out, hist,
-                                     hist_idx);
+    ll_final_kernel<<<1, 256, 0, s>>>(partials, n_part_words + n_part_docs, m.nk, m.K, m.beta_sum, out, hist,
+                                      hist_idx);
     return hipGetLastError();
 }
 
