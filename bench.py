@@ -249,7 +249,7 @@ def main():
     ap.add_argument("--schedule", default=None,
                     help="explicit schedule as JSON [min_len, group, docs_per_item, side_ratio] (no autotuning)")
     ap.add_argument("--force-group", type=int, default=0,
-                    help="one schedule bucket with this group size (16, 32, 64) instead of autotuning")
+                    help="one schedule bucket with this group size (1, 8, 16, 32, 64) instead of autotuning")
     ap.add_argument("--graph", action="store_true", help="replay a captured sweep (no per-phase events)")
     ap.add_argument("--cpu-docs", type=int, default=20000)
     ap.add_argument("--no-cpu-baseline", action="store_true")

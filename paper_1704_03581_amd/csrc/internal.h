@@ -122,7 +122,8 @@ hipError_t launch_phi_step(const DevModel &m, unsigned long long *stats, hipStre
 hipError_t launch_phi_step_dirichlet(const DevModel &m, unsigned long long *stats, hipStream_t s);
 constexpr int32_t ROWSUM_COLS = 256;      // words per block of the row-sum kernels
 // z-step: launch_z_prepare clears n and the Z_QUEUES work queues; then one
-// persistent kernel per group size (16, 32, 64) over that size's work items.
+// persistent kernel per work-item class (group size 8 to 64 and count
+// width, or one document per lane) over that class's items.
 // With ll_doc non-null (symmetric alpha) the z-step also writes each
 // document's term of the log joint for the state it leaves.
 hipError_t launch_z_prepare(const DevModel &m, int32_t *queues, unsigned long long *stats, hipStream_t s);
