@@ -81,9 +81,10 @@ struct WorkItem {
 };
 
 // LDS layout of one z-step class (group size, count width): per group a
-// count table (K counters of 1 or 2 bytes, rounded to 4 bytes) and the
+// count table (K counters of 1 or 2 bytes, rounded to 8 bytes) and the
 // document's topic list (u16; min(K, 255) entries for documents shorter
-// than 256 tokens, else K), 64/G groups per wave, and the block's copy of
+// than 256 tokens, else K, and at least 4 slots per lane and 4 more, for
+// the list's 8-byte windows), 64/G groups per wave, and the block's copy of
 // R_k (K doubles) first
 struct ZLayout {
     int32_t m_bytes, group_bytes, wave_bytes, r_bytes;
@@ -92,9 +93,10 @@ struct ZLayout {
 inline ZLayout z_layout(int32_t group, bool narrow, int32_t K)
 {
     ZLayout L;
-    L.m_bytes = (K * (narrow ? 1 : 2) + 3) / 4 * 4;
-    const int32_t lcap = narrow ? (K < 255 ? K : 255) : K;
-    L.group_bytes = L.m_bytes + (lcap * 2 + 3) / 4 * 4;
+    L.m_bytes = (K * (narrow ? 1 : 2) + 7) / 8 * 8;
+    int32_t lcap = narrow ? (K < 255 ? K : 255) : K;
+    if (lcap < 4 * group + 4) lcap = 4 * group + 4;
+    L.group_bytes = L.m_bytes + (lcap * 2 + 7) / 8 * 8;
     L.wave_bytes = ((64 / group) * L.group_bytes + 15) / 16 * 16;
     L.r_bytes = (K * 8 + 15) / 16 * 16;
     return L;

@@ -856,7 +856,9 @@ constexpr int log2g()
 // lst, its topics with a nonzero count in ascending order (during a draw it
 // also holds the token's old topic, whose count may be zero: that b-term is
 // zero).  lst[0] always holds a valid topic, so padding slots can read it.
-template <typename CT>
+// WIN: lst is 8-byte aligned and has room for 4G + 4 slots, and every slot
+// in [L, 4G + 4) holds 0xFFFF (see list_window_update).
+template <typename CT, bool WIN = false>
 struct DocState {
     CT *mt;
     uint16_t *lst;
@@ -864,9 +866,16 @@ struct DocState {
 };
 
 // lst <- the topics with a nonzero count; lane g scans topics [g*R, g*R + R)
-template <int G, typename CT>
-__device__ __forceinline__ void build_list(DocState<CT> &S, int g, int32_t K)
+template <int G, typename CT, bool WIN>
+__device__ __forceinline__ void build_list(DocState<CT, WIN> &S, int g, int32_t K)
 {
+    if constexpr (WIN) {
+        // the windows read 0xFFFF past the list
+        const uint2 none = make_uint2(0xFFFFFFFFu, 0xFFFFFFFFu);
+        *(uint2 *)(S.lst + 4 * g) = none;
+        if (g == 0) *(uint2 *)(S.lst + 4 * G) = none;
+        __builtin_amdgcn_wave_barrier();
+    }
     const int32_t R = (K + G - 1) / G;
     const int32_t t0 = g * R;
     const int32_t t1 = t0 + R < K ? t0 + R : K;
@@ -891,8 +900,8 @@ __device__ __forceinline__ int32_t list_block(int32_t L, int g, int32_t &base)
 }
 
 // insert topic k (not in lst): the entries above it move up one place
-template <int G, typename CT>
-__device__ __forceinline__ void list_insert(DocState<CT> &S, int32_t k, int g)
+template <int G, typename CT, bool WIN>
+__device__ __forceinline__ void list_insert(DocState<CT, WIN> &S, int32_t k, int g)
 {
     int32_t base;
     const int32_t n = list_block<G>(S.L, g, base);
@@ -917,8 +926,8 @@ __device__ __forceinline__ void list_insert(DocState<CT> &S, int32_t k, int g)
 }
 
 // remove topic k (in lst): the entries above it move down one place
-template <int G, typename CT>
-__device__ __forceinline__ void list_remove(DocState<CT> &S, int32_t k, int g)
+template <int G, typename CT, bool WIN>
+__device__ __forceinline__ void list_remove(DocState<CT, WIN> &S, int32_t k, int g)
 {
     int32_t base;
     const int32_t n = list_block<G>(S.L, g, base);
@@ -930,7 +939,68 @@ __device__ __forceinline__ void list_remove(DocState<CT> &S, int32_t k, int g)
         if (v > k) S.lst[base + j - 1] = (uint16_t)v;
     }
     S.L -= 1;
+    // the slot freed at the end reads 0xFFFF again
+    if constexpr (WIN)
+        if (g == 0) S.lst[S.L] = 0xFFFFu;
     __builtin_amdgcn_wave_barrier();
+}
+
+// The list as 4-slot windows: lane g of the group holds slots [4g, 4g + 4),
+// one 8-byte LDS word.  While every entry lies inside the windows (L <= 4G
+// before and after), removing kout and inserting kin (LIST_NONE: nothing)
+// take one pass: each lane reads its window and the slot on either side,
+// forms its new window in registers and writes it back.  Slots past the list
+// hold 0xFFFF, above every topic, so the same rules cover the list's end.
+constexpr int32_t LIST_NONE = 0x10000;
+
+template <int G, typename CT, bool WIN>
+__device__ __forceinline__ void list_window_update(DocState<CT, WIN> &S, int32_t kout, int32_t kin, int g)
+{
+    static_assert(WIN, "the windows need the padded list");
+    uint16_t *w = S.lst + 4 * g;
+    const uint2 cur = *(const uint2 *)w;
+    const int32_t left = g > 0 ? (int32_t)w[-1] : -1;
+    const int32_t right = w[4];
+    __builtin_amdgcn_wave_barrier();
+    int32_t o[5] = {(int32_t)(cur.x & 0xFFFFu), (int32_t)(cur.x >> 16), (int32_t)(cur.y & 0xFFFFu),
+                    (int32_t)(cur.y >> 16), right};
+    // removal: the entries above kout move down one slot; p becomes the new
+    // content of the slot left of the window
+    int32_t p = left < kout ? left : o[0];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) o[j] = o[j] < kout ? o[j] : o[j + 1];
+    // insertion: the entries above kin move up one slot and kin takes the
+    // first slot whose old entry is above it
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int32_t c = o[j];
+        o[j] = c < kin ? c : (p < kin ? kin : p);
+        p = c;
+    }
+    *(uint2 *)w = make_uint2((uint32_t)o[0] | ((uint32_t)o[1] << 16), (uint32_t)o[2] | ((uint32_t)o[3] << 16));
+    __builtin_amdgcn_wave_barrier();
+}
+
+// after a draw: the old topic leaves the list when its count fell to zero,
+// the new one enters when it was absent
+template <int G, typename CT, bool WIN>
+__device__ __forceinline__ void list_update(DocState<CT, WIN> &S, int32_t kold, int32_t knew, int32_t mo,
+                                            int32_t mn, int g)
+{
+    const bool out = knew != kold && mo == 1;
+    const bool in = knew != kold && mn == 0;
+    if constexpr (WIN) {
+        if (__builtin_amdgcn_ballot_w64(out || in) == 0) return;
+        const int32_t L2 = S.L + (in ? 1 : 0) - (out ? 1 : 0);
+        const bool wide = (out || in) && (S.L > 4 * G || L2 > 4 * G);
+        if (__builtin_amdgcn_ballot_w64(wide) == 0) {
+            list_window_update<G>(S, out ? kold : LIST_NONE, in ? knew : LIST_NONE, g);
+            S.L = L2;
+            return;
+        }
+    }
+    if (out) list_remove<G>(S, kold, g);
+    if (in) list_insert<G>(S, knew, g);
 }
 
 // up to KP b-terms of this lane: entries first + base + u (u < KP) of its
@@ -999,8 +1069,8 @@ __device__ __forceinline__ void lane_terms(const DevModel &M, const uint16_t *ls
 // y = u_sigma - sigma_a (Section 3.5).  Returns the topic, or -1 for the
 // a-part (the caller takes the word's alias draw).  KP terms per lane and
 // round; the first round's terms stay in registers for the walk.
-template <int G, bool DOC, typename CT, int KP>
-__device__ __forceinline__ int32_t b_part(const DevModel &M, const TokenIn &tk, DocState<CT> &S, const double *R,
+template <int G, bool DOC, typename CT, int KP, bool WIN>
+__device__ __forceinline__ int32_t b_part(const DevModel &M, const TokenIn &tk, DocState<CT, WIN> &S, const double *R,
                                           const int g, double &Zo)
 {
     constexpr int LG = log2g<G>();
@@ -1084,9 +1154,9 @@ __device__ __forceinline__ int32_t b_part(const DevModel &M, const TokenIn &tk, 
 
 // draw one token (group-uniform control flow); returns the new topic, or
 // -1 - kold for a token whose word has an empty Phi column (it keeps kold)
-template <int G, typename CT>
+template <int G, typename CT, bool WIN>
 // (Zo: the conditional's normaliser sigma_a + sigma_b, when it is computed)
-__device__ __forceinline__ int32_t draw_token(const DevModel &M, const TokenIn &tk, DocState<CT> &S, const double *R,
+__device__ __forceinline__ int32_t draw_token(const DevModel &M, const TokenIn &tk, DocState<CT, WIN> &S, const double *R,
                                               const int g, const int32_t side_ratio, ZCount &cnt, double &Zo)
 {
     CT *mt = S.mt;
@@ -1144,17 +1214,14 @@ __device__ __forceinline__ int32_t draw_token(const DevModel &M, const TokenIn &
     __builtin_amdgcn_wave_barrier();
     if (g == 0) mt[knew] = (CT)(mn + 1);
     __builtin_amdgcn_wave_barrier();
-    if (knew != kold) {
-        if (mo == 1) list_remove<G, CT>(S, kold, g);
-        if (mn == 0) list_insert<G, CT>(S, knew, g);
-    }
+    list_update<G>(S, kold, knew, mo, mn, g);
     return knew;
 }
 
 // a token whose a-part was decided at staging (tk.sure): the same count and
 // list updates as draw_token, with the new topic the word's alias draw
-template <int G, typename CT>
-__device__ __forceinline__ int32_t move_token(const TokenIn &tk, DocState<CT> &S, const int g, ZCount &cnt)
+template <int G, typename CT, bool WIN>
+__device__ __forceinline__ int32_t move_token(const TokenIn &tk, DocState<CT, WIN> &S, const int g, ZCount &cnt)
 {
     CT *mt = S.mt;
     const int32_t kold = tk.kold;
@@ -1171,17 +1238,14 @@ __device__ __forceinline__ int32_t move_token(const TokenIn &tk, DocState<CT> &S
     __builtin_amdgcn_wave_barrier();
     if (g == 0) mt[knew] = (CT)(mn + 1);
     __builtin_amdgcn_wave_barrier();
-    if (knew != kold) {
-        if (mo == 1) list_remove<G, CT>(S, kold, g);
-        if (mn == 0) list_insert<G, CT>(S, knew, g);
-    }
+    list_update<G>(S, kold, knew, mo, mn, g);
     return knew;
 }
 
 // load a document's topic counts into the group's LDS table (CT: 8-bit
 // counts for documents shorter than 256 tokens, else 16-bit) and list them
-template <int G, typename CT>
-__device__ __forceinline__ void load_doc_counts(DocState<CT> &S, const uint16_t *z, int64_t s, int64_t e, int g,
+template <int G, typename CT, bool WIN>
+__device__ __forceinline__ void load_doc_counts(DocState<CT, WIN> &S, const uint16_t *z, int64_t s, int64_t e, int g,
                                                 int32_t K, int32_t m_words)
 {
     constexpr int PER_WORD = 4 / sizeof(CT);   // counters per 32-bit word
@@ -1245,7 +1309,7 @@ __device__ void z_step_item(const ZArgs &a, const WorkItem &w, const double *R, 
     const int lane = __lane_id();
     const int g = lane & (G - 1);
     const int grp = lane / G;
-    DocState<CT> S;
+    DocState<CT, true> S;
     S.mt = (CT *)(wave_base + grp * a.group_bytes);
     S.lst = (uint16_t *)(wave_base + grp * a.group_bytes + a.m_bytes);
     TokenIn *tok = wave_tok + grp * G;
