@@ -834,8 +834,19 @@ struct alignas(16) TokenIn {
 
 static_assert(sizeof(TokenIn) == 32, "TokenIn is staged as 32-byte records");
 
+// draw statistics of a lane's group: totals, and the current document's J
+// and a-part counts in 32 bits (cheaper to add per draw), moved into the
+// totals when the document is done
 struct ZCount {
     unsigned long long J, A, degenerate;
+    uint32_t j, a;
+    __device__ void flush()
+    {
+        J += j;
+        A += a;
+        j = 0;
+        a = 0;
+    }
 };
 
 // b-terms per lane kept in registers for the walk: one gather round covers
@@ -1176,7 +1187,7 @@ __device__ __forceinline__ int32_t draw_token(const DevModel &M, const TokenIn &
     }
     // the document's topics with a nonzero count besides the token
     const int32_t Kd = S.L - (mo == 1 ? 1 : 0);
-    cnt.J += (unsigned long long)(Kd < Kv ? Kd : Kv);
+    cnt.j += (uint32_t)(Kd < Kv ? Kd : Kv);
     // b-terms over one side: the document's topics (lst) or the word's Phi
     // column, ascending topic order either way.  The column is read
     // contiguously while the document side gathers single draws from the
@@ -1207,7 +1218,7 @@ __device__ __forceinline__ int32_t draw_token(const DevModel &M, const TokenIn &
         // a-part: the word's alias table over alpha_k phi_kv (drawn when the
         // token was staged)
         knew = tk.ka;
-        cnt.A++;
+        cnt.a++;
     }
     // add the token back with its new topic
     const int32_t mn = mt[knew];
@@ -1231,9 +1242,9 @@ __device__ __forceinline__ int32_t move_token(const TokenIn &tk, DocState<CT, WI
     __builtin_amdgcn_wave_barrier();
     const int32_t Kv = tk.kv;
     const int32_t Kd = S.L - (mo == 1 ? 1 : 0);
-    cnt.J += (unsigned long long)(Kd < Kv ? Kd : Kv);
+    cnt.j += (uint32_t)(Kd < Kv ? Kd : Kv);
     const int32_t knew = tk.ka;
-    cnt.A++;
+    cnt.a++;
     const int32_t mn = mt[knew];
     __builtin_amdgcn_wave_barrier();
     if (g == 0) mt[knew] = (CT)(mn + 1);
@@ -1326,9 +1337,9 @@ __device__ void z_step_item(const ZArgs &a, const WorkItem &w, const double *R, 
         for (int64_t i0 = s; i0 < e; i0 += G) {
             const int64_t i = i0 + g;
             const bool valid = i < e;
-            int32_t zo = 0;
+            int32_t zo = 0, wv = 0;
             if (valid) {
-                const int32_t wv = a.c.words[i];
+                wv = a.c.words[i];
                 zo = a.c.z[i];
                 const r4 r = philox((uint32_t)i, (uint32_t)((uint64_t)i >> 32), t, TAG_Z, M.key0, M.key1);
                 stage_token(M, tok, g, wv, zo, r, (int32_t)(e - s));
@@ -1349,7 +1360,6 @@ __device__ void z_step_item(const ZArgs &a, const WorkItem &w, const double *R, 
                     double Zo;
                     int32_t k = draw_token<G, CT>(M, tk, S, R, g, w.side_ratio, cnt, Zo);
                     if (k < 0) k = -1 - k;
-                    if (g == 0) atomicAdd(&M.n[tk.vk + (uint32_t)k], 1);
                     if (g == jj) znew = k;
                 }
             } else {
@@ -1358,7 +1368,6 @@ __device__ void z_step_item(const ZArgs &a, const WorkItem &w, const double *R, 
                 while (cur < nb && tok[cur].sure) {
                     const TokenIn tk = tok[cur];
                     const int32_t k = move_token<G, CT>(tk, S, g, cnt);
-                    if (g == 0) atomicAdd(&M.n[tk.vk + (uint32_t)k], 1);
                     if (g == cur) znew = k;
                     ++cur;
                 }
@@ -1367,7 +1376,6 @@ __device__ void z_step_item(const ZArgs &a, const WorkItem &w, const double *R, 
                     double Zo;
                     int32_t k = draw_token<G, CT>(M, tk, S, R, g, w.side_ratio, cnt, Zo);
                     if (k < 0) k = -1 - k;
-                    if (g == 0) atomicAdd(&M.n[tk.vk + (uint32_t)k], 1);
                     if (g == cur) znew = k;
                     ++cur;
                 }
@@ -1375,8 +1383,14 @@ __device__ void z_step_item(const ZArgs &a, const WorkItem &w, const double *R, 
             }
             }
             __builtin_amdgcn_wave_barrier();
-            if (valid) a.c.z[i] = (uint16_t)znew;
+            // the count rebuild: each lane adds its own token, once the
+            // block's draws are done
+            if (valid) {
+                a.c.z[i] = (uint16_t)znew;
+                atomicAdd(&M.n[(uint32_t)wv * (uint32_t)M.K + (uint32_t)znew], 1);
+            }
         }
+        cnt.flush();
         if (a.ll_doc) {
             // the document's term of log p(z | alpha) for its final counts:
             // lgamma(A) - lgamma(N_d + A) + sum_k [lgamma(m_k + alpha) - lgamma(alpha)]
@@ -1407,7 +1421,7 @@ __global__ void __launch_bounds__(256, (G == 8 ? 2 : 5)) z_step_kernel(ZArgs a)
     uint8_t *blk = z_lds + a.r_bytes;
     uint8_t *wave_base = blk + wave * a.wave_bytes;
     TokenIn *wave_tok = (TokenIn *)(blk + 4 * a.wave_bytes) + wave * 64;
-    ZCount cnt = {0, 0, 0};
+    ZCount cnt = {0, 0, 0, 0, 0};
     while (true) {
         int item = 0;
         if (__lane_id() == 0) item = atomicAdd(a.queue, 1);
@@ -1499,7 +1513,7 @@ __global__ void __launch_bounds__(64) z_lane_kernel(ZArgs a)
     uint8_t *ml = l_lds + LANE_CAP * 64 * sizeof(uint16_t) + lane;      // entry j at ml[j * 64]
     const DevModel &M = a.m;
     const uint32_t t = *M.tptr;
-    ZCount cnt = {0, 0, 0};
+    ZCount cnt = {0, 0, 0, 0, 0};
     while (true) {
         int item = 0;
         if (lane == 0) item = atomicAdd(a.queue, 1);
@@ -2124,7 +2138,7 @@ __device__ void foldin_slot(const DevModel &M, const DevFoldin &F, int32_t sid, 
         next = F.prog[2 * sid + 1];
     }
     load_doc_counts<G, uint16_t>(S, zz, 0, kept, g, K, Kp / 2);
-    ZCount st = {0, 0, 0};
+    ZCount st = {0, 0, 0, 0, 0};
     int32_t budget = sl.budget;
     while (budget > 0 && done < F.sweeps) {
         const int32_t s = done + 1;
@@ -2294,7 +2308,7 @@ __device__ void ltr_particle(const DevModel &M, const DevHeldout &H, int64_t d, 
     __threadfence();
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    ZCount st = {0, 0, 0};
+    ZCount st = {0, 0, 0, 0, 0};
     for (int32_t n = 0; n < nk; ++n) {
         // redraw z_0 .. z_{n-1} in order (lane q mod G stages token q)
         for (int32_t q0 = 0; q0 < n; q0 += G) {
