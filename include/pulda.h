@@ -77,7 +77,7 @@ const char *pulda_version(void);
 /* ------------------------------------------------------------------------ */
 typedef struct {
     int32_t K;               /* topics, 1 <= K <= 4096 */
-    int32_t V;               /* vocabulary size, >= 1; K * V < 2^31 */
+    int32_t V;               /* vocabulary size, >= 1; V * (K rounded up to 64) < 2^30 */
     double beta;             /* symmetric prior on each phi_k (Table 1), > 0 */
     double alpha;            /* symmetric prior on each theta_d, > 0; used when alpha_k is NULL */
     const double *alpha_k;   /* optional host vector of K priors alpha_k > 0 (copied), or NULL */

@@ -229,9 +229,10 @@ pulda_status pulda_plan_create(const pulda_model_desc *desc, int64_t D, int64_t 
     *out = nullptr;
     if (desc->K < 1 || desc->K > 4096) return fail(PULDA_ERR_INVALID_ARG, "K=%d outside 1..4096", desc->K);
     if (desc->V < 1) return fail(PULDA_ERR_INVALID_ARG, "V=%d must be >= 1", desc->V);
-    if ((int64_t)desc->K * desc->V >= (1ll << 31)) return fail(PULDA_ERR_INVALID_ARG, "K*V must be < 2^31");
-    if ((int64_t)desc->V * ((desc->K + 63) / 64 * 64) >= (1ll << 32))
-        return fail(PULDA_ERR_INVALID_ARG, "V * (K rounded up to 64) must be < 2^32");
+    // the kernels address the V x K tables (4-byte cells) with 32-bit byte
+    // offsets
+    if ((int64_t)desc->V * ((desc->K + 63) / 64 * 64) >= (1ll << 30))
+        return fail(PULDA_ERR_INVALID_ARG, "V * (K rounded up to 64) must be < 2^30");
     if (!desc->beta_v && !(desc->beta > 0.0 && desc->beta <= BETA_MAX))
         return fail(PULDA_ERR_INVALID_ARG, "beta must be in (0, %g]", BETA_MAX);
     if (desc->beta_v)

@@ -153,6 +153,8 @@ __device__ __forceinline__ uint64_t group_ballot(bool pred)
     const uint64_t all = __builtin_amdgcn_ballot_w64(pred);
     if constexpr (G == 64) {
         return all;
+    } else if constexpr (G == 32) {
+        return __lane_id() < 32 ? (uint32_t)all : (uint32_t)(all >> 32);
     } else {
         const int base = (int)(__lane_id() & ~(G - 1));
         return (all >> base) & ((1ull << G) - 1ull);

@@ -822,7 +822,8 @@ struct alignas(16) TokenIn {
     int32_t cb;      // first CSC entry of the word's Phi column
     uint16_t kold;   // topic before the draw
     uint16_t kv;     // nonzeros in the column (K_v^Phi <= K <= 4096)
-    uint32_t r0;     // uniform of the a/b decision and the b-walk
+    float u0;        // the 24-bit uniform of the a/b decision and the b-walk
+                     // (r >> 8) 2^-24, exact in fp32
     uint16_t ka;     // the a-part's topic: the alias draw depends only on the
                      // word and the token's random numbers, so it is taken at
                      // staging time, off the draw's critical path
@@ -1022,9 +1023,17 @@ __device__ __forceinline__ void list_update(DocState<CT, WIN> &S, int32_t kold, 
 // contiguously.  R (LDS) holds R_k.  Every slot loads from a valid address
 // (padding slots read entry `pad`), so all loads of a round are in flight
 // together.
+// Global reads take a 32-bit byte offset from the table's base (the plan
+// keeps every table under 4 GiB), so each address is one 32-bit add.
+template <typename T>
+__device__ __forceinline__ T load_at(const T *base, uint32_t byte_off)
+{
+    return *(const T *)((const char *)base + byte_off);
+}
+
 template <int KP, bool DOC, typename CT>
-__device__ __forceinline__ void lane_terms(const DevModel &M, const uint16_t *lst, const uint16_t *g16col,
-                                           const float *pcol, const double *R, const CT *mt, const int32_t pad,
+__device__ __forceinline__ void lane_terms(const DevModel &M, const uint16_t *lst, const uint32_t g16o,
+                                           const uint32_t vk, const double *R, const CT *mt, const int32_t pad,
                                            const int32_t first, const int32_t base, const int32_t nl,
                                            int32_t (&kk)[KP], float (&fk)[KP], int32_t (&mk)[KP])
 {
@@ -1037,7 +1046,7 @@ __device__ __forceinline__ void lane_terms(const DevModel &M, const uint16_t *ls
         if constexpr (DOC) {
             kk[u] = lst[e];
         } else {
-            const uint32_t kg = M.ckg[e];
+            const uint32_t kg = load_at(M.ckg, e << 2);
             kk[u] = (int32_t)(kg & 0xFFFFu);
             x[u] = kg >> 16;
         }
@@ -1047,14 +1056,14 @@ __device__ __forceinline__ void lane_terms(const DevModel &M, const uint16_t *ls
             // Algorithm 1's Phi has no integer draws: phi itself is gathered
 #pragma unroll
             for (int u = 0; u < KP; ++u) {
-                fk[u] = pcol[(uint32_t)kk[u]];
+                fk[u] = load_at(M.phid, (vk + (uint32_t)kk[u]) << 2);
                 const int32_t m = mt[kk[u]];
                 mk[u] = ok[u] ? m : 0;
             }
             return;
         }
 #pragma unroll
-        for (int u = 0; u < KP; ++u) x[u] = g16col[(uint32_t)kk[u]];
+        for (int u = 0; u < KP; ++u) x[u] = load_at(M.g16, g16o + ((uint32_t)kk[u] << 1));
     }
     // phi_kv = fp32(x * R_k) == fp32(RN64(x / S_k)) for x < 2^16 and
     // S_k < 2^27; every other nonzero cell carries 0xFFFF and its phi is
@@ -1071,7 +1080,7 @@ __device__ __forceinline__ void lane_terms(const DevModel &M, const uint16_t *ls
     if (__builtin_amdgcn_ballot_w64(esc)) {
 #pragma unroll
         for (int u = 0; u < KP; ++u)
-            if (x[u] == 0xFFFFu) fk[u] = pcol[kk[u]];
+            if (x[u] == 0xFFFFu) fk[u] = load_at(M.phid, (vk + (uint32_t)kk[u]) << 2);
     }
 }
 
@@ -1089,13 +1098,12 @@ __device__ __forceinline__ int32_t b_part(const DevModel &M, const TokenIn &tk, 
     const int32_t q = (J + G - 1) >> LG;
     int32_t nl = J - g * q < q ? J - g * q : q;
     nl = nl > 0 ? nl : 0;
-    const uint16_t *g16col = M.g16 + tk.vs;
-    const float *pcol = M.phid + tk.vk;
+    const uint32_t g16o = tk.vs << 1;
     const int32_t pad = DOC ? 0 : tk.cb;
     const int32_t first = pad + (int32_t)__umul24((uint32_t)g, (uint32_t)q);
     int32_t kk[KP], mk[KP];
     float fk[KP];
-    lane_terms<KP, DOC, CT>(M, S.lst, g16col, pcol, R, S.mt, pad, first, 0, nl, kk, fk, mk);
+    lane_terms<KP, DOC, CT>(M, S.lst, g16o, tk.vk, R, S.mt, pad, first, 0, nl, kk, fk, mk);
     // the products phi * m are exact in fp64, so adding them (or an fma)
     // rounds exactly like the sum of the products
     double bk[KP];
@@ -1108,7 +1116,7 @@ __device__ __forceinline__ int32_t b_part(const DevModel &M, const TokenIn &tk, 
     for (int32_t base = KP; base < nl; base += KP) {
         int32_t k2[KP], m2[KP];
         float f2[KP];
-        lane_terms<KP, DOC, CT>(M, S.lst, g16col, pcol, R, S.mt, pad, first, base, nl, k2, f2, m2);
+        lane_terms<KP, DOC, CT>(M, S.lst, g16o, tk.vk, R, S.mt, pad, first, base, nl, k2, f2, m2);
 #pragma unroll
         for (int u = 0; u < KP; ++u) p = __builtin_fma((double)f2[u], (double)m2[u], p);
     }
@@ -1116,14 +1124,14 @@ __device__ __forceinline__ int32_t b_part(const DevModel &M, const TokenIn &tk, 
     const double T = group_bcast_f64<G>(incl, G - 1);
     const double Z = tk.sa + T;
     Zo = Z;
-    const double x = unit24(tk.r0) * Z;
+    const double x = (double)tk.u0 * Z;
     if (x < tk.sa) return -1;
     // b-part: the first lane whose running sum passes y walks its terms
     const double y = x - tk.sa;
     const uint64_t bal = group_ballot<G>(incl > y);
     int f = -1;
     if (bal) {
-        f = __builtin_ctzll(bal);
+        f = G <= 32 ? __builtin_ctz((uint32_t)bal) : __builtin_ctzll(bal);
     } else {
         const uint64_t pos = group_ballot<G>(p > 0.0);
         if (pos) f = 63 - __builtin_clzll(pos);
@@ -1146,7 +1154,7 @@ __device__ __forceinline__ int32_t b_part(const DevModel &M, const TokenIn &tk, 
             for (int32_t base = 0; base < nl && kf < 0; base += KP) {
                 int32_t k2[KP], m2[KP];
                 float f2[KP];
-                lane_terms<KP, DOC, CT>(M, S.lst, g16col, pcol, R, S.mt, pad, first, base, nl, k2, f2, m2);
+                lane_terms<KP, DOC, CT>(M, S.lst, g16o, tk.vk, R, S.mt, pad, first, base, nl, k2, f2, m2);
 #pragma unroll
                 for (int u = 0; u < KP; ++u) {
                     const double bv = (double)f2[u] * (double)m2[u];
@@ -1291,7 +1299,7 @@ __device__ __forceinline__ void stage_token(const DevModel &M, TokenIn *tok, int
     x.kold = (uint16_t)kold;
     const int32_t kv = M.colptr[v + 1] - x.cb;
     x.kv = (uint16_t)kv;
-    x.r0 = r.x;
+    x.u0 = (float)(r.x >> 8) * 0x1p-24f;
     x.sa = M.sigma_a[v];
     // the a-part's draw from the word's alias table over alpha_k phi_kv:
     // slot j = floor(r1 * K_v / 2^32), kept when r2 < its threshold, else

@@ -47,6 +47,7 @@ class Desc(ctypes.Structure):
     (5000, 10, 0.01, 0.1, 100, 1, 1),     # K > 4096
     (10, 0, 0.01, 0.1, 100, 1, 1),        # V < 1
     (4096, 600000, 0.01, 0.1, 100, 1, 1),  # K*V >= 2^31
+    (1000, 1048576, 0.01, 0.1, 100, 1, 1),  # V * (K rounded up to 64) = 2^30
     (10, 10, 0.0, 0.1, 100, 1, 1),        # beta = 0
     (10, 10, 20.0, 0.1, 100, 1, 1),       # beta > 16 (zero-truncated tables would not saturate)
     (10, 10, 0.01, -1.0, 100, 1, 1),      # alpha < 0
