@@ -1179,16 +1179,18 @@ __device__ __forceinline__ int32_t draw_token(const DevModel &M, const TokenIn &
                                               const int g, const int32_t side_ratio, ZCount &cnt, double &Zo)
 {
     CT *mt = S.mt;
-    // m^{-i}: remove the token from its document's counts
+    // m^{-i}: remove the token from its document's counts.  (Every lane of
+    // the group stores the same count to the same address: one store without
+    // a lane mask, cheaper than the branch around a single lane's store.)
     const int32_t kold = tk.kold;
     const int32_t mo = mt[kold];
     __builtin_amdgcn_wave_barrier();
-    if (g == 0) mt[kold] = (CT)(mo - 1);
+    mt[kold] = (CT)(mo - 1);
     __builtin_amdgcn_wave_barrier();
     const int32_t Kv = tk.kv;
     if (Kv == 0) {
         // 0/0 conditional: the token keeps its topic
-        if (g == 0) mt[kold] = (CT)mo;
+        mt[kold] = (CT)mo;
         __builtin_amdgcn_wave_barrier();
         cnt.degenerate++;
         return -1 - kold;
@@ -1231,7 +1233,7 @@ __device__ __forceinline__ int32_t draw_token(const DevModel &M, const TokenIn &
     // add the token back with its new topic
     const int32_t mn = mt[knew];
     __builtin_amdgcn_wave_barrier();
-    if (g == 0) mt[knew] = (CT)(mn + 1);
+    mt[knew] = (CT)(mn + 1);
     __builtin_amdgcn_wave_barrier();
     list_update<G>(S, kold, knew, mo, mn, g);
     return knew;
@@ -1246,7 +1248,7 @@ __device__ __forceinline__ int32_t move_token(const TokenIn &tk, DocState<CT, WI
     const int32_t kold = tk.kold;
     const int32_t mo = mt[kold];
     __builtin_amdgcn_wave_barrier();
-    if (g == 0) mt[kold] = (CT)(mo - 1);
+    mt[kold] = (CT)(mo - 1);
     __builtin_amdgcn_wave_barrier();
     const int32_t Kv = tk.kv;
     const int32_t Kd = S.L - (mo == 1 ? 1 : 0);
@@ -1255,7 +1257,7 @@ __device__ __forceinline__ int32_t move_token(const TokenIn &tk, DocState<CT, WI
     cnt.a++;
     const int32_t mn = mt[knew];
     __builtin_amdgcn_wave_barrier();
-    if (g == 0) mt[knew] = (CT)(mn + 1);
+    mt[knew] = (CT)(mn + 1);
     __builtin_amdgcn_wave_barrier();
     list_update<G>(S, kold, knew, mo, mn, g);
     return knew;
