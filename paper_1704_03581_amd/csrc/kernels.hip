@@ -1137,20 +1137,28 @@ __device__ __forceinline__ int32_t b_part(const DevModel &M, const TokenIn &tk, 
         if (pos) f = 63 - __builtin_clzll(pos);
     }
     if (f < 0) return -1;  // no positive b-term survived rounding: the a-part is the whole law
+    // every lane walks its kept terms (registers only, no branch around the
+    // crossing lane); the crossing lane's result is the draw, unless its
+    // block holds more terms than were kept: then that lane walks them all
     int32_t kf = -1;
-    if (g == f) {
+    {
         double c = incl - p;
         int32_t last = -1;
-        if (nl <= KP) {
 #pragma unroll
-            for (int u = 0; u < KP; ++u) {
-                if (bk[u] > 0.0) {
-                    c += bk[u];
-                    last = kk[u];
-                    if (kf < 0 && c > y) kf = kk[u];
-                }
+        for (int u = 0; u < KP; ++u) {
+            if (bk[u] > 0.0) {
+                c += bk[u];
+                last = kk[u];
+                if (kf < 0 && c > y) kf = kk[u];
             }
-        } else {
+        }
+        if (kf < 0) kf = last;
+    }
+    if (nl > KP && g == f) {
+        double c = incl - p;
+        int32_t last = -1;
+        kf = -1;
+        {
             for (int32_t base = 0; base < nl && kf < 0; base += KP) {
                 int32_t k2[KP], m2[KP];
                 float f2[KP];
