@@ -1220,17 +1220,21 @@ __device__ __forceinline__ int32_t draw_token(const DevModel &M, const TokenIn &
     if (__builtin_amdgcn_ballot_w64(tk.sure == 0) != 0) {
         const bool prefer_doc = Kd == 0 || (uint32_t)Kv > __umul24((uint32_t)side_ratio, (uint32_t)Kd);
         const bool doc = __builtin_amdgcn_ballot_w64(prefer_doc) != 0;
-        // terms per lane and round: half the registers' worth when no group
-        // of the wave has more than that many per lane (one round either way)
+        // terms per lane and round: a half or three quarters of the
+        // registers' worth when no group of the wave has more than that many
+        // per lane (one round either way)
         constexpr int KP = keep_of<G>();
         const int32_t J = doc ? S.L : Kv;
-        const bool full = __builtin_amdgcn_ballot_w64(J > (KP / 2) * G) != 0;
+        const bool over2 = __builtin_amdgcn_ballot_w64(J > (KP / 2) * G) != 0;
+        const bool over3 = __builtin_amdgcn_ballot_w64(J > (3 * KP / 4) * G) != 0;
         if (doc)
-            knew = full ? b_part<G, true, CT, KP>(M, tk, S, R, g, Zo)
-                        : b_part<G, true, CT, KP / 2>(M, tk, S, R, g, Zo);
+            knew = !over2 ? b_part<G, true, CT, KP / 2>(M, tk, S, R, g, Zo)
+                          : (!over3 ? b_part<G, true, CT, 3 * KP / 4>(M, tk, S, R, g, Zo)
+                                    : b_part<G, true, CT, KP>(M, tk, S, R, g, Zo));
         else
-            knew = full ? b_part<G, false, CT, KP>(M, tk, S, R, g, Zo)
-                        : b_part<G, false, CT, KP / 2>(M, tk, S, R, g, Zo);
+            knew = !over2 ? b_part<G, false, CT, KP / 2>(M, tk, S, R, g, Zo)
+                          : (!over3 ? b_part<G, false, CT, 3 * KP / 4>(M, tk, S, R, g, Zo)
+                                    : b_part<G, false, CT, KP>(M, tk, S, R, g, Zo));
     }
     if (knew < 0) {
         // a-part: the word's alias table over alpha_k phi_kv (drawn when the
