@@ -386,20 +386,35 @@ __global__ void __launch_bounds__(256) phi_dense_kernel(DevModel m)
     uint16_t *g16col = m.g16 + (int64_t)v * m.ks16;
     int32_t run = 0;
     float fmax = 0.0f;
-    for (int32_t k0 = 0; k0 < m.ks16; k0 += 64) {
+    // the column's draws are read PB rounds of 64 cells at a time, so that
+    // many loads are in flight before the rounds are processed in order
+    constexpr int PB = 8;
+    for (int32_t kb = 0; kb < m.ks16; kb += 64 * PB) {
+    int32_t xs[PB];
+    double gs[PB];
+#pragma unroll
+    for (int j = 0; j < PB; ++j) {
+        const int32_t k = kb + 64 * j + lane;
+        if constexpr (DIR) gs[j] = k < K ? gdcol[k] : 0.0;
+        else xs[j] = k < K ? gcol[k] : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < PB; ++j) {
+        const int32_t k0 = kb + 64 * j;
+        if (k0 >= m.ks16) break;
         const int32_t k = k0 + lane;
         float f = 0.0f;
         uint32_t x16 = 0;
         bool nz;
         if constexpr (DIR) {
             if (k < K && m.Sd[k] > 0.0) {
-                f = (float)(gdcol[k] / m.Sd[k]);
+                f = (float)(gs[j] / m.Sd[k]);
                 f = f >= FP32_MIN_NORMAL ? f : 0.0f;
             }
             nz = f > 0.0f;
             x16 = nz ? 0xFFFFu : 0u;
         } else {
-            const int32_t x = k < K ? gcol[k] : 0;
+            const int32_t x = xs[j];
             nz = x > 0;
             if (nz) f = (float)((double)x / (double)m.S[k]);
             const bool exact = x < 0xFFFF && (k >= K || m.S[k] < (1ull << 27));
@@ -416,6 +431,7 @@ __global__ void __launch_bounds__(256) phi_dense_kernel(DevModel m)
             m.ckg[cb + e] = (uint32_t)k | (x16 << 16);
         }
         run += __builtin_popcountll(bal);
+    }
     }
     for (int o = 32; o > 0; o >>= 1) {
         const float y = __shfl_xor(fmax, o, 64);
@@ -1821,7 +1837,6 @@ __global__ void __launch_bounds__(256) ll_words_kernel(const int32_t *n, int64_t
         int4 a[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) a[j] = q[i + j * stride];
-#pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int64_t c0 = 4 * (i + j * stride);
             acc += term(a[j].x, c0) + term(a[j].y, c0 + 1) + term(a[j].z, c0 + 2) + term(a[j].w, c0 + 3);
