@@ -996,7 +996,10 @@ __device__ __forceinline__ void list_window_update(DocState<CT, WIN> &S, int32_t
     static_assert(WIN, "the windows need the padded list");
     uint16_t *w = S.lst + 4 * g;
     const uint2 cur = *(const uint2 *)w;
-    const int32_t left = g > 0 ? (int32_t)w[-1] : -1;
+    // (lane 0 reads the slot before the list, inside the count table, and
+    // drops it: an unconditional read needs no lane mask)
+    const int32_t lraw = w[-1];
+    const int32_t left = g > 0 ? lraw : -1;
     const int32_t right = w[4];
     __builtin_amdgcn_wave_barrier();
     int32_t o[5] = {(int32_t)(cur.x & 0xFFFFu), (int32_t)(cur.x >> 16), (int32_t)(cur.y & 0xFFFFu),
@@ -1221,7 +1224,9 @@ __device__ __forceinline__ int32_t draw_token(const DevModel &M, const TokenIn &
     mt[kold] = (CT)(mo - 1);
     __builtin_amdgcn_wave_barrier();
     const int32_t Kv = tk.kv;
-    if (Kv == 0) {
+    // (tested for the wave first: a wave without such a token skips the
+    // lane-masked branch)
+    if (__builtin_amdgcn_ballot_w64(Kv == 0) != 0 && Kv == 0) {
         // 0/0 conditional: the token keeps its topic
         mt[kold] = (CT)mo;
         __builtin_amdgcn_wave_barrier();
