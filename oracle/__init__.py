@@ -76,6 +76,8 @@ def _declare(L):
     L.or_z_step.argtypes = [C.c_int64, C.c_int32, C.c_int32, i64p, i32p, u16p, C.c_uint64, C.c_uint32, f32p,
                             i64p, u16p, u32p, u16p, f64p, i64p]
     L.or_z_step.restype = C.c_int64
+    L.or_z_step_sparse.argtypes = L.or_z_step.argtypes
+    L.or_z_step_sparse.restype = C.c_int64
     L.or_replay.argtypes = [C.c_int64, C.c_int32, C.c_int32, i64p, i32p, u16p, u16p, C.c_uint64, C.c_uint32,
                             f32p, i64p, u16p, u32p, u16p, f64p, C.c_double, i64p, f64p, i64p, i64p, C.c_int64]
     L.or_loglik.argtypes = [C.c_int64, C.c_int32, C.c_int32, i64p, i32p, u16p, f64p, C.c_double, f64p]
@@ -225,15 +227,20 @@ def _model_args(phi, wt):
             _p(wt.alias_topic, C.c_uint16), _p(wt.sigma_a, C.c_double))
 
 
-def z_step(doc_off, words, z, seed, t, phi, wt, K, V):
-    """One z-step.  Returns (new z, degenerate count, sum_J, sum_A)."""
+def z_step(doc_off, words, z, seed, t, phi, wt, K, V, sparse=False):
+    """One z-step.  Returns (new z, degenerate count, sum_J, sum_A).
+
+    sparse=False walks every topic per token (the plain definition);
+    sparse=True iterates the smaller of the document's topics and the word's
+    Phi column, with the same results bit for bit (the timed CPU mode)."""
     doc_off = _c(doc_off, np.int64)
     words = _c(words, np.int32)
     z = np.array(z, dtype=np.uint16, copy=True)
     phi = _c(phi, np.float32)
     stats = np.zeros(2, np.int64)
-    deg = lib().or_z_step(len(doc_off) - 1, K, V, _p(doc_off, C.c_int64), _p(words, C.c_int32),
-                          _p(z, C.c_uint16), seed, t, *_model_args(phi, wt), _p(stats, C.c_int64))
+    fn = lib().or_z_step_sparse if sparse else lib().or_z_step
+    deg = fn(len(doc_off) - 1, K, V, _p(doc_off, C.c_int64), _p(words, C.c_int32),
+             _p(z, C.c_uint16), seed, t, *_model_args(phi, wt), _p(stats, C.c_int64))
     return z, int(deg), int(stats[0]), int(stats[1])
 
 
@@ -303,12 +310,12 @@ def token_pmf(phi, wt, v, m):
 class Sampler:
     """Algorithm 2 end to end on the CPU: Phi-step then z-step per sweep."""
 
-    def __init__(self, doc_off, words, K, V, alpha=0.1, beta=0.01, L=100, seed=1, z0=None):
+    def __init__(self, doc_off, words, K, V, alpha=0.1, beta=0.01, L=100, seed=1, z0=None, sparse=False):
         self.doc_off = _c(doc_off, np.int64)
         self.words = _c(words, np.int32)
         self.K, self.V = K, V
         self.alpha = _c(np.broadcast_to(alpha, (K,)), np.float64)
-        self.beta, self.L, self.seed = beta, L, seed
+        self.beta, self.L, self.seed, self.sparse = beta, L, seed, sparse
         N = int(self.doc_off[-1])
         self.z = init_z(N, K, seed) if z0 is None else np.array(z0, dtype=np.uint16, copy=True)
         self.n, self.nk, _ = counts(self.doc_off, self.words, self.z, K, V, with_m=False)
@@ -321,7 +328,7 @@ class Sampler:
     def z_step(self, t):
         self.z_prev = self.z
         self.z, self.degenerate, self.sum_J, self.sum_A = z_step(
-            self.doc_off, self.words, self.z, self.seed, t, self.phi, self.wt, self.K, self.V)
+            self.doc_off, self.words, self.z, self.seed, t, self.phi, self.wt, self.K, self.V, sparse=self.sparse)
         self.n, self.nk, _ = counts(self.doc_off, self.words, self.z, self.K, self.V, with_m=False)
 
     def loglik(self):

@@ -539,6 +539,99 @@ int64_t or_z_step(int64_t D, int32_t K, int32_t V, const int64_t *doc_off, const
 }
 
 /* ------------------------------------------------------------------------ */
+/* The same z-step, doubly sparse (Section 3.5, cost in Section 3.6): the     */
+/* b-terms phi_kv m_k are nonzero only where both the document's counts and   */
+/* the word's Phi column are, so each token iterates the smaller of the two:  */
+/* the document's topics with a nonzero count (kept as an ascending list      */
+/* beside the dense m) or the word's column (its CSC entries, ascending).     */
+/* Either way the nonzero products are added in ascending topic order, the    */
+/* order of the dense sum above, whose zero terms add exactly 0.0; so z, the  */
+/* statistics and the random numbers used are bit-identical to or_z_step.     */
+/* This is the mode the CPU throughput baseline times.                        */
+/* ------------------------------------------------------------------------ */
+int64_t or_z_step_sparse(int64_t D, int32_t K, int32_t V, const int64_t *doc_off, const int32_t *words,
+                         uint16_t *z, uint64_t seed, uint32_t t, const float *phi, const int64_t *colptr,
+                         const uint16_t *topic, const uint32_t *thr, const uint16_t *alias_topic,
+                         const double *sigma_a, int64_t *stats /* [sum_J, sum_A] or NULL */)
+{
+    int32_t *m = (int32_t *)calloc((size_t)K, sizeof(int32_t));
+    int32_t *lst = (int32_t *)malloc(sizeof(int32_t) * (size_t)K);   /* nonzero topics, ascending */
+    int32_t *bk = (int32_t *)malloc(sizeof(int32_t) * (size_t)K);    /* topics of the iterated side */
+    double *bv = (double *)malloc(sizeof(double) * (size_t)K);       /* their b-terms */
+    int64_t degenerate = 0, sumJ = 0, sumA = 0;
+    for (int64_t d = 0; d < D; d++) {
+        for (int64_t i = doc_off[d]; i < doc_off[d + 1]; i++) m[z[i]]++;
+        int32_t kd = 0;
+        for (int32_t k = 0; k < K; k++)
+            if (m[k]) lst[kd++] = k;
+        for (int64_t i = doc_off[d]; i < doc_off[d + 1]; i++) {
+            int32_t v = words[i];
+            int32_t kold = z[i];
+            if (--m[kold] == 0) {
+                /* kold leaves the list */
+                int32_t j = 0;
+                while (lst[j] != kold) j++;
+                for (; j + 1 < kd; j++) lst[j] = lst[j + 1];
+                kd--;
+            }
+            uint32_t r[4];
+            draw4(seed, (uint32_t)i, (uint32_t)((uint64_t)i >> 32), t, TAG_Z, r);
+            int64_t c0 = colptr[v], nv = colptr[v + 1] - c0;
+            int32_t knew;
+            if (nv == 0) {
+                degenerate++;
+                knew = kold;
+            } else {
+                sumJ += (kd < nv) ? kd : nv;
+                /* the nonzero b-terms in ascending topic order */
+                int32_t nb = 0;
+                if (kd <= nv) {
+                    for (int32_t j = 0; j < kd; j++) {
+                        double b = (double)phi[(size_t)lst[j] * V + v] * (double)m[lst[j]];
+                        if (b > 0.0) { bk[nb] = lst[j]; bv[nb] = b; nb++; }
+                    }
+                } else {
+                    for (int64_t e = c0; e < c0 + nv; e++) {
+                        int32_t k = topic[e];
+                        double b = (double)phi[(size_t)k * V + v] * (double)m[k];
+                        if (b > 0.0) { bk[nb] = k; bv[nb] = b; nb++; }
+                    }
+                }
+                double sb = 0.0;
+                for (int32_t j = 0; j < nb; j++) sb += bv[j];
+                double sa = sigma_a[v];
+                double x = u24(r[0]) * (sa + sb);
+                if (x < sa) {
+                    uint32_t j = mulhi(r[1], (uint32_t)nv);
+                    knew = (r[2] < thr[c0 + j]) ? topic[c0 + j] : alias_topic[c0 + j];
+                    sumA++;
+                } else {
+                    double y = x - sa, c = 0.0;
+                    knew = -1;
+                    for (int32_t j = 0; j < nb && knew < 0; j++) {
+                        c += bv[j];
+                        if (c > y) knew = bk[j];
+                    }
+                    if (knew < 0) knew = bk[nb - 1];
+                }
+            }
+            if (m[knew]++ == 0) {
+                /* knew enters the list */
+                int32_t j = kd;
+                while (j > 0 && lst[j - 1] > knew) { lst[j] = lst[j - 1]; j--; }
+                lst[j] = knew;
+                kd++;
+            }
+            z[i] = (uint16_t)knew;
+        }
+        for (int32_t j = 0; j < kd; j++) m[lst[j]] = 0;
+    }
+    free(m); free(lst); free(bk); free(bv);
+    if (stats) { stats[0] = sumJ; stats[1] = sumA; }
+    return degenerate;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Teacher-forced replay of one z-step.  z_before is the state the other      */
 /* implementation started from, z_after its result.  Each token is redrawn by */
 /* the oracle given the other side's preceding draws in the same document,    */
@@ -547,8 +640,10 @@ int64_t or_z_step(int64_t D, int32_t K, int32_t V, const int64_t *doc_off, const
 /* that would have produced the other side's topic (its a-part slot with the  */
 /* same r1, r2, or its b-part interval).  out[0] = agreements, out[1] = ties, */
 /* out[2] = other disagreements, out[3] = degenerate tokens; worst[0] =       */
-/* largest relative distance seen among disagreements.  With docs != NULL    */
-/* only the listed documents are checked (each is independent given Phi).     */
+/* largest relative distance seen among disagreements (infinite when a value */
+/* is not a topic: z_after >= K counts as a disagreement, z_before >= K makes */
+/* every token of its document one).  With docs != NULL only the listed      */
+/* documents are checked (each is independent given Phi).                     */
 /* ------------------------------------------------------------------------ */
 void or_replay(int64_t D, int32_t K, int32_t V, const int64_t *doc_off, const int32_t *words,
                const uint16_t *z_before, const uint16_t *z_after, uint64_t seed, uint32_t t,
@@ -566,7 +661,19 @@ void or_replay(int64_t D, int32_t K, int32_t V, const int64_t *doc_off, const in
     for (int64_t di = 0; di < nd; di++) {
         int64_t d = docs ? docs[di] : di;
         memset(m, 0, sizeof(int32_t) * (size_t)K);
-        for (int64_t i = doc_off[d]; i < doc_off[d + 1]; i++) m[z_before[i]]++;
+        int64_t bad_start = -1;
+        for (int64_t i = doc_off[d]; i < doc_off[d + 1]; i++) {
+            if (z_before[i] >= K) { bad_start = i; break; }
+            m[z_before[i]]++;
+        }
+        if (bad_start >= 0) {
+            /* the starting state holds a value that is not a topic: nothing
+             * of this document can be replayed */
+            out[2] += doc_off[d + 1] - doc_off[d];
+            if (*first_bad < 0) *first_bad = bad_start;
+            worst[0] = INFINITY;
+            continue;
+        }
         for (int64_t i = doc_off[d]; i < doc_off[d + 1]; i++) {
             int32_t v = words[i];
             int32_t kold = z_before[i];
@@ -578,12 +685,21 @@ void or_replay(int64_t D, int32_t K, int32_t V, const int64_t *doc_off, const in
                 out[3]++;
                 if (kg == kold) out[0]++;
                 else { out[2]++; if (*first_bad < 0) *first_bad = i; }
-                m[kg]++;
+                m[kold]++;   /* the token keeps its topic (0/0 conditional) */
                 continue;
             }
             int a;
             double x, Z;
             int32_t ko = draw_token(&M, v, m, r, &a, &x, &Z);
+            if (kg >= K) {
+                /* not a topic at all: a disagreement whatever x is; the rest
+                 * of the document is replayed with the oracle's own draw */
+                out[2]++;
+                if (*first_bad < 0) *first_bad = i;
+                worst[0] = INFINITY;
+                m[ko]++;
+                continue;
+            }
             if (ko == kg) { out[0]++; m[kg]++; continue; }
             /* distance from x to the x-values that yield kg */
             double sa = sigma_a[v];

@@ -13,6 +13,7 @@ import pytest
 
 import oracle
 from tests import test_oracle_pins as pins
+from tests import test_oracle_replay as rp
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "pulda_oracle.c")
 
@@ -72,6 +73,22 @@ MUTATIONS = [
     ("vector_loglik_prior_sum", "for (int32_t v = 0; v < V; v++) Vb += beta_v[v];",
      "for (int32_t v = 0; v < V; v++) Vb += beta;",
      [pins.test_vector_beta_loglik_and_dirichlet]),
+    ("replay_wrong_scale", "double rel = dist / Z;", "double rel = dist / sa;",
+     [lambda: rp.test_replay_constructed_tie("b"), lambda: rp.test_replay_constructed_tie("a")]),
+    ("replay_every_mismatch_a_tie", "if (rel <= tol) out[1]++;", "if (1) out[1]++;",
+     [rp.test_replay_wrong_neighbour_far_from_boundary_is_bad, rp.test_replay_wrong_topic_is_bad]),
+    ("replay_interval_counts_token", "double b = (double)phi[(size_t)k * V + v] * (double)m[k];\n                if (b > 0.0) {\n                    lo = c;",
+     "double b = (double)phi[(size_t)k * V + v] * (double)(m[k] + (k == kold));\n                if (b > 0.0) {\n                    lo = c;",
+     [lambda: rp.test_replay_constructed_tie("b")]),
+    ("replay_interval_upper_edge", "double dd = x < lo ? lo - x : (x >= c ? x - c : 0.0);",
+     "double dd = x < lo ? lo - x : 0.0;",
+     [rp.test_replay_wrong_neighbour_far_from_boundary_is_bad]),
+    ("sparse_column_descending", "for (int64_t e = c0; e < c0 + nv; e++) {\n                        int32_t k = topic[e];",
+     "for (int64_t e = c0 + nv - 1; e >= c0; e--) {\n                        int32_t k = topic[e];",
+     [lambda: rp.test_sparse_mode_bit_identical(300, 500, 400, 0.6)]),
+    ("sparse_list_insert_unsorted", "while (j > 0 && lst[j - 1] > knew) { lst[j] = lst[j - 1]; j--; }",
+     "(void)0;",
+     [lambda: rp.test_sparse_mode_bit_identical(50, 200, 60, 0.3)]),
     ("normalise_wrong_row", "phi[(size_t)k * V + v] = g > 0 ? (float)((double)g / (double)s) : 0.0f;",
      "phi[(size_t)k * V + v] = g > 0 ? (float)((double)g / (double)(s + 1)) : 0.0f;",
      [pins.test_phi_normalise_definition]),
