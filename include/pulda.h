@@ -42,7 +42,9 @@
  *    on it and the call returns without waiting, except where a function is
  *    documented as synchronising (it then waits for that stream).
  *  - The library allocates no device memory.  A plan (and a fold-in server)
- *    carves all its device buffers from one caller-owned workspace.
+ *    carves all its device buffers from one caller-owned workspace.  (A
+ *    fold-in server holds pinned host staging buffers, see
+ *    pulda_foldin_bind.)
  *  - One plan must not be used from two threads at the same time; distinct
  *    plans are independent.
  */
@@ -338,6 +340,12 @@ typedef struct {
  * must outlive the server and its Phi must not change meanwhile). */
 pulda_status pulda_foldin_create(const pulda_plan *model, const pulda_foldin_desc *desc, pulda_foldin **out);
 pulda_status pulda_foldin_workspace_bytes(const pulda_foldin *f, int64_t *bytes);
+/* Bind the caller's device workspace.  The first bind also allocates the
+ * server's pinned host staging (arena_tokens * 4 bytes for request words and
+ * two copies of the slot table), through which every host-to-device copy of
+ * submit and step goes, so no copy reads the caller's memory after the call
+ * returns; pulda_foldin_destroy frees it.  PULDA_ERR_NO_MEMORY if the
+ * workspace is too small or the staging cannot be allocated. */
 pulda_status pulda_foldin_bind(pulda_foldin *f, void *workspace_dev, int64_t bytes);
 void pulda_foldin_destroy(pulda_foldin *f);
 

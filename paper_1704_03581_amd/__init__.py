@@ -3,4 +3,4 @@
 Submodules are imported on demand: ``synth`` (seeded synthetic corpora) has no
 dependency on the compiled library; ``pulda`` is the binding to libpulda.so.
 """
-__all__ = ["synth", "pulda", "server", "autotune"]
+__all__ = ["synth", "pulda", "server"]

@@ -216,6 +216,25 @@ struct pulda_foldin {
     std::vector<int32_t> finished;    // 1 if its last sweep is known done (not yet collected)
     std::vector<std::pair<int32_t, int32_t>> free_blocks;  // arena [off, len), by offset
     int32_t free_tokens = 0;
+    // pinned host staging for the host-to-device copies, so that a copy
+    // never reads caller or library memory after the call returns:
+    // stage_words mirrors the arena (a region is rewritten only after its
+    // request was polled, which waits for the stream), and the slot table
+    // and active list alternate between two buffers, each reused only after
+    // the event recorded behind its previous copy
+    int32_t *stage_words = nullptr;
+    uint8_t *stage_ctl[2] = {nullptr, nullptr};
+    hipEvent_t stage_ev[2] = {nullptr, nullptr};
+    bool stage_used[2] = {false, false};
+    int stage_cur = 0;
+    ~pulda_foldin()
+    {
+        if (stage_words) (void)hipHostFree(stage_words);
+        for (int b = 0; b < 2; ++b) {
+            if (stage_ctl[b]) (void)hipHostFree(stage_ctl[b]);
+            if (stage_ev[b]) (void)hipEventDestroy(stage_ev[b]);
+        }
+    }
 };
 
 extern "C" {
@@ -1162,6 +1181,22 @@ pulda_status pulda_foldin_bind(pulda_foldin *f, void *ws, int64_t bytes)
     if ((uintptr_t)ws % ALIGN) return fail(PULDA_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
     if (bytes < f->ws_need)
         return fail(PULDA_ERR_NO_MEMORY, "workspace of %lld bytes, need %lld", (long long)bytes, (long long)f->ws_need);
+    if (!f->stage_words) {
+        const size_t S = (size_t)f->desc.max_slots;
+        if (hipHostMalloc((void **)&f->stage_words, (size_t)f->desc.arena_tokens * 4, hipHostMallocDefault) !=
+            hipSuccess) {
+            f->stage_words = nullptr;
+            return fail(PULDA_ERR_NO_MEMORY, "pinned host staging of %d tokens", f->desc.arena_tokens);
+        }
+        for (int b = 0; b < 2; ++b) {
+            if (hipHostMalloc((void **)&f->stage_ctl[b], S * (sizeof(FoldSlot) + 4), hipHostMallocDefault) !=
+                hipSuccess) {
+                f->stage_ctl[b] = nullptr;
+                return fail(PULDA_ERR_NO_MEMORY, "pinned host staging of %zu slots", S);
+            }
+            HIP_TRY(hipEventCreateWithFlags(&f->stage_ev[b], hipEventDisableTiming));
+        }
+    }
     uint8_t *w = (uint8_t *)ws;
     f->ws = w;
     f->slots_dev = (FoldSlot *)(w + f->off.slots);
@@ -1239,7 +1274,8 @@ pulda_status pulda_foldin_submit(pulda_foldin *f, uint32_t req, const int32_t *w
     if (!arena_alloc(f, len, &at)) return fail(PULDA_ERR_CAPACITY, "no arena space for %d tokens", len);
     hipStream_t s = (hipStream_t)stream;
     if (len > 0) {
-        hipError_t e = hipMemcpyAsync(f->f.words + at, words, (size_t)len * 4, hipMemcpyHostToDevice, s);
+        std::memcpy(f->stage_words + at, words, (size_t)len * 4);
+        hipError_t e = hipMemcpyAsync(f->f.words + at, f->stage_words + at, (size_t)len * 4, hipMemcpyHostToDevice, s);
         if (e != hipSuccess) {
             arena_free(f, at, len);
             return fail(PULDA_ERR_DEVICE, "copy request: %s", hipGetErrorString(e));
@@ -1261,24 +1297,32 @@ pulda_status pulda_foldin_step(pulda_foldin *f, int32_t draws, void *stream)
     if (!f || draws < 1) return fail(PULDA_ERR_INVALID_ARG, "bad argument");
     if (!f->ws) return fail(PULDA_ERR_STATE, "no workspace bound");
     hipStream_t s = (hipStream_t)stream;
-    std::vector<int32_t> active;
-    for (int32_t i = 0; i < f->desc.max_slots; ++i) {
+    const int b = f->stage_cur;
+    if (f->stage_used[b]) HIP_TRY(hipEventSynchronize(f->stage_ev[b]));
+    const int32_t S = f->desc.max_slots;
+    FoldSlot *slots_pin = (FoldSlot *)f->stage_ctl[b];
+    int32_t *active = (int32_t *)(f->stage_ctl[b] + (size_t)S * sizeof(FoldSlot));
+    int32_t n_active = 0;
+    for (int32_t i = 0; i < S; ++i) {
         FoldSlot &sl = f->slots[i];
         if (f->resident[i] && !f->finished[i]) {
             sl.budget = draws;
-            active.push_back(i);
+            active[n_active++] = i;
         } else {
             sl.budget = 0;
         }
     }
-    if (active.empty()) return PULDA_OK;
-    HIP_TRY(hipMemcpyAsync(f->slots_dev, f->slots.data(), f->slots.size() * sizeof(FoldSlot), hipMemcpyHostToDevice,
-                           s));
-    HIP_TRY(hipMemcpyAsync(f->active_dev, active.data(), active.size() * 4, hipMemcpyHostToDevice, s));
-    HIP_TRY(launch_foldin_step(f->model->m, f->f, f->active_dev, (int32_t)active.size(), s));
-    for (int32_t i : active) {
-        f->slots[i].fresh = 0;
-        f->slots[i].budget = 0;
+    if (n_active == 0) return PULDA_OK;
+    std::memcpy(slots_pin, f->slots.data(), (size_t)S * sizeof(FoldSlot));
+    HIP_TRY(hipMemcpyAsync(f->slots_dev, slots_pin, (size_t)S * sizeof(FoldSlot), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(f->active_dev, active, (size_t)n_active * 4, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipEventRecord(f->stage_ev[b], s));
+    f->stage_used[b] = true;
+    f->stage_cur = b ^ 1;
+    HIP_TRY(launch_foldin_step(f->model->m, f->f, f->active_dev, n_active, s));
+    for (int32_t j = 0; j < n_active; ++j) {
+        f->slots[active[j]].fresh = 0;
+        f->slots[active[j]].budget = 0;
     }
     return PULDA_OK;
 }

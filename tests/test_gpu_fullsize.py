@@ -7,8 +7,8 @@ oracle can compute one by one.
 * large corpus (D=8.2M, V=141000, K=1000, 738M tokens): the z-step of the
   fourth sweep after warmup and autotuning, as the benchmark runs it, with a
   sample of documents (random ones plus the longest and shortest) replayed
-  by the oracle, and the whole count table rebuilt by the z-step compared
-  bit for bit;
+  by the oracle, the whole count table rebuilt by the z-step compared bit
+  for bit, and the next Phi-step compared with the oracle's on every cell;
 * fold-in against the large configuration's Phi (K=1000, V=141000), with the
   serving loop's draw budget: theta bit-exact and log-likelihood within
   1e-12 for requests of every length class;
@@ -27,7 +27,7 @@ import pytest
 
 import oracle
 from paper_1704_03581_amd import server, synth
-from tests.gpu_helpers import phi_from_gpu, say
+from tests.gpu_helpers import assert_phi_equal, phi_from_gpu, say
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -107,7 +107,23 @@ def test_large_sampled_documents():
     assert r["bad"] == 0, r
     assert r["agree"] >= 0.9999 * n_tok
     n_o, _, _ = oracle.counts(c.doc_off, c.words, z1, c.K, c.V, with_m=False)
-    assert np.array_equal(p.counts_dense()[0], n_o)
+    n_g, nk_g = p.counts_dense()
+    assert np.array_equal(n_g, n_o)
+    del n_o
+    # the next sweep's Phi-step at full size, every cell against the
+    # oracle's from the same counts: Poisson draws (alias tables, rounded
+    # Gaussians above L, draws past the 16-bit range), prior marks, row sums,
+    # phi, column layout, alias tables and sigma_a, bit for bit
+    t2 = t + 1
+    p.phi_step(t2)
+    g = p.get_phi()
+    gam = oracle.phi_counts(n_g, c.beta, 100, 1, t2)
+    S, phi2, _ = oracle.phi_normalise(gam)
+    wt2 = oracle.word_tables(np.full(c.K, c.alpha), phi2)
+    say(f"  Phi-step t={t2}: nnz {len(wt2.topic)}, counted cells {int((n_g > 0).sum())}, "
+        f"cells with n > 100 {int((n_g > 100).sum())}, draws >= 0xFFFF {int((gam >= 0xFFFF).sum())}, "
+        f"largest column {int(np.diff(wt2.colptr).max())}, largest S_k {int(S.max())}")
+    assert_phi_equal(g, gam, S, phi2, wt2, c.K, c.V)
 
 
 @pytest.mark.timeout(600)
