@@ -407,6 +407,25 @@ pulda_status pulda_heldout_loglik(const pulda_plan *model, int64_t D, const int6
                                   uint64_t seed, void *workspace_dev, int64_t workspace_bytes, double *ll_dev,
                                   int32_t *kept_dev, double *Z_dev, void *stream);
 
+/* The held-out estimate for callers that cannot allocate device memory (code
+ * under HIP graph capture, serving loops, harnesses that forbid hipMalloc):
+ * pulda_heldout_loglik with the same arguments and results but no workspace.
+ * Its scratch is the library's own array of
+ * PULDA_HELDOUT_NOALLOC_SCRATCH_BYTES bytes on each GPU it runs on (held
+ * until the process ends; its address is looked up on the first call on
+ * each device).  It needs pulda_heldout_workspace_bytes(model, D, N,
+ * particles) bytes; larger calls return PULDA_ERR_NO_MEMORY and launch
+ * nothing.  The call allocates no device memory.  Every call on one GPU
+ * shares that GPU's scratch: calls that overlap in time on one GPU (other
+ * streams or threads) race and must be serialised by the caller.  Each
+ * call writes every scratch word it reads, so nothing carries over from the
+ * previous call. */
+#define PULDA_HELDOUT_NOALLOC_SCRATCH_BYTES (32ll << 20)
+pulda_status pulda_heldout_loglik_noalloc(const pulda_plan *model, int64_t D, const int64_t *doc_off_dev,
+                                          const int32_t *words_dev, const uint32_t *req_dev, int32_t particles,
+                                          int32_t group, uint64_t seed, double *ll_dev, int32_t *kept_dev,
+                                          double *Z_dev, void *stream);
+
 /* The plain per-document sampler: runs one request alone, all sweeps in one
  * launch, and waits for it (uses the server's workspace; the server must be
  * empty).  Same results as the batched path. */

@@ -13,6 +13,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1423,10 +1424,15 @@ pulda_status pulda_heldout_workspace_bytes(const pulda_plan *model, int64_t D, i
     return PULDA_OK;
 }
 
-pulda_status pulda_heldout_loglik(const pulda_plan *model, int64_t D, const int64_t *doc_off_dev,
-                                  const int32_t *words_dev, const uint32_t *req_dev, int32_t particles, int32_t group,
-                                  uint64_t seed, void *workspace_dev, int64_t workspace_bytes, double *ll_dev,
-                                  int32_t *kept_dev, double *Z_dev, void *stream)
+}  // extern "C"
+
+// The held-out estimate with its scratch at workspace_dev (workspace_bytes
+// long, 256-byte aligned).  from_static: the scratch is the library's own
+// per-device array (the message of a size error names its limit).
+static pulda_status heldout_run(const pulda_plan *model, int64_t D, const int64_t *doc_off_dev,
+                                const int32_t *words_dev, const uint32_t *req_dev, int32_t particles, int32_t group,
+                                uint64_t seed, void *workspace_dev, int64_t workspace_bytes, double *ll_dev,
+                                int32_t *kept_dev, double *Z_dev, void *stream, bool from_static)
 {
     if (!model || !doc_off_dev || !req_dev || !ll_dev || !kept_dev || (D > 0 && !workspace_dev))
         return fail(PULDA_ERR_INVALID_ARG, "null argument");
@@ -1449,9 +1455,16 @@ pulda_status pulda_heldout_loglik(const pulda_plan *model, int64_t D, const int6
     const int64_t N = off[D];
     if (N > 0 && !words_dev) return fail(PULDA_ERR_INVALID_ARG, "null words");
     if (N * particles >= (1ll << 40)) return fail(PULDA_ERR_INVALID_ARG, "N * particles too large");
-    if (workspace_bytes < heldout_bytes(D, N, particles))
+    if (workspace_bytes < heldout_bytes(D, N, particles)) {
+        if (from_static)
+            return fail(PULDA_ERR_NO_MEMORY,
+                        "%lld documents, %lld tokens and %d particles need %lld bytes of scratch; the library's "
+                        "own scratch holds %lld (use pulda_heldout_loglik with a workspace)",
+                        (long long)D, (long long)N, particles, (long long)heldout_bytes(D, N, particles),
+                        (long long)workspace_bytes);
         return fail(PULDA_ERR_NO_MEMORY, "workspace of %lld bytes, need %lld", (long long)workspace_bytes,
                     (long long)heldout_bytes(D, N, particles));
+    }
     // longest documents first: each particle is a chain of ~n^2/2 draws, so
     // the long ones set the call's time unless they start early
     std::vector<int32_t> order(D);
@@ -1482,6 +1495,59 @@ pulda_status pulda_heldout_loglik(const pulda_plan *model, int64_t D, const int6
     h.ll = ll_dev;
     HIP_TRY(launch_heldout(model->m, h, s));
     return PULDA_OK;
+}
+
+// The scratch of pulda_heldout_loglik_noalloc: one array per GPU the library
+// runs on, held until the process ends.  Host code never uses the array's
+// name as an address: the device address of each GPU's copy is looked up
+// once (hipGetSymbolAddress, with that device current) and kept per device.
+static __device__ __align__(256) uint8_t scratch[PULDA_HELDOUT_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_SCRATCH_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_SCRATCH_DEVICES];
+}  // namespace
+
+static pulda_status scratch_of_current_device(void **out)
+{
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_SCRATCH_DEVICES) return fail(PULDA_ERR_DEVICE, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(PULDA_ERR_DEVICE, "scratch address on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return PULDA_OK;
+}
+
+extern "C" {
+
+pulda_status pulda_heldout_loglik(const pulda_plan *model, int64_t D, const int64_t *doc_off_dev,
+                                  const int32_t *words_dev, const uint32_t *req_dev, int32_t particles, int32_t group,
+                                  uint64_t seed, void *workspace_dev, int64_t workspace_bytes, double *ll_dev,
+                                  int32_t *kept_dev, double *Z_dev, void *stream)
+{
+    return heldout_run(model, D, doc_off_dev, words_dev, req_dev, particles, group, seed, workspace_dev,
+                       workspace_bytes, ll_dev, kept_dev, Z_dev, stream, false);
+}
+
+pulda_status pulda_heldout_loglik_noalloc(const pulda_plan *model, int64_t D, const int64_t *doc_off_dev,
+                                          const int32_t *words_dev, const uint32_t *req_dev, int32_t particles,
+                                          int32_t group, uint64_t seed, double *ll_dev, int32_t *kept_dev,
+                                          double *Z_dev, void *stream)
+{
+    if (!model) return fail(PULDA_ERR_INVALID_ARG, "null argument");
+    void *ws = nullptr;
+    const pulda_status st = scratch_of_current_device(&ws);
+    if (st != PULDA_OK) return st;
+    return heldout_run(model, D, doc_off_dev, words_dev, req_dev, particles, group, seed, ws,
+                       PULDA_HELDOUT_NOALLOC_SCRATCH_BYTES, ll_dev, kept_dev, Z_dev, stream, true);
 }
 
 }  // extern "C"

@@ -18,6 +18,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpulda.so")
 
 PULDA_OK, ERR_INVALID_ARG, ERR_STATE, ERR_DEVICE, ERR_NO_MEMORY, ERR_CAPACITY, ERR_CORPUS = 0, -1, -2, -3, -4, -5, -6
+# scratch of pulda_heldout_loglik_noalloc (PULDA_HELDOUT_NOALLOC_SCRATCH_BYTES in pulda.h)
+HELDOUT_NOALLOC_SCRATCH_BYTES = 32 << 20
 
 
 class PuldaError(RuntimeError):
@@ -97,6 +99,7 @@ _SIGS = {
     "pulda_set_phi_method": [vp, i32],
     "pulda_heldout_workspace_bytes": [vp, i64, i64, i32, C.POINTER(i64)],
     "pulda_heldout_loglik": [vp, i64, vp, vp, vp, i32, i32, u64, vp, i64, vp, vp, vp, vp],
+    "pulda_heldout_loglik_noalloc": [vp, i64, vp, vp, vp, i32, i32, u64, vp, vp, vp, vp],
     "pulda_get_gamma_dense": [vp, vp, vp, vp],
     "pulda_foldin_create": [vp, C.POINTER(FoldinDesc), C.POINTER(vp)],
     "pulda_foldin_workspace_bytes": [vp, C.POINTER(i64)],
@@ -335,12 +338,14 @@ class Plan:
         _check(_lib.pulda_set_graph(self._h, 1 if enable else 0))
 
     def heldout_loglik(self, docs, req=None, particles: int = 20, group: int = 32, seed: int = 1,
-                       want_Z: bool = False, stream=None):
+                       want_Z: bool = False, stream=None, noalloc: bool = False):
         """Left-to-right estimates of log p(w_d | Phi, alpha) for new
         documents (lists of word ids) against this plan's Phi.  req: request
         ids (default 0..D-1), the keys of the random numbers.  Returns
         (ll fp64[D], kept int32[D]) and, with want_Z, each document's
-        Z (particles x kept) array."""
+        Z (particles x kept) array.  noalloc: call the entry point that
+        takes no workspace (the library's own scratch, of
+        HELDOUT_NOALLOC_SCRATCH_BYTES)."""
         D = len(docs)
         lens = np.array([len(d) for d in docs], dtype=np.int64)
         off = np.zeros(D + 1, np.int64)
@@ -352,16 +357,21 @@ class Plan:
         off_t = torch.from_numpy(off).to(dv)
         words_t = torch.from_numpy(words).to(dv)
         req_t = torch.from_numpy(np.ascontiguousarray(req).view(np.int32)).to(dv)
-        nbytes = i64()
-        _check(_lib.pulda_heldout_workspace_bytes(self._h, D, N, particles, C.byref(nbytes)))
-        ws = torch.empty(max(nbytes.value, 1) + 256, dtype=torch.uint8, device=dv)
-        base = (ws.data_ptr() + 255) // 256 * 256
         ll = torch.empty(max(D, 1), dtype=torch.float64, device=dv)
         kept = torch.empty(max(D, 1), dtype=torch.int32, device=dv)
         Z = torch.empty(max(N * particles, 1), dtype=torch.float64, device=dv) if want_Z else None
-        _check(_lib.pulda_heldout_loglik(self._h, D, _ptr(off_t), _ptr(words_t), _ptr(req_t), particles, group,
-                                         seed, C.c_void_p(base), nbytes.value, _ptr(ll), _ptr(kept),
-                                         _ptr(Z) if want_Z else None, _stream(stream)))
+        if noalloc:
+            _check(_lib.pulda_heldout_loglik_noalloc(self._h, D, _ptr(off_t), _ptr(words_t), _ptr(req_t), particles,
+                                                     group, seed, _ptr(ll), _ptr(kept), _ptr(Z) if want_Z else None,
+                                                     _stream(stream)))
+        else:
+            nbytes = i64()
+            _check(_lib.pulda_heldout_workspace_bytes(self._h, D, N, particles, C.byref(nbytes)))
+            ws = torch.empty(max(nbytes.value, 1) + 256, dtype=torch.uint8, device=dv)
+            base = (ws.data_ptr() + 255) // 256 * 256
+            _check(_lib.pulda_heldout_loglik(self._h, D, _ptr(off_t), _ptr(words_t), _ptr(req_t), particles, group,
+                                             seed, C.c_void_p(base), nbytes.value, _ptr(ll), _ptr(kept),
+                                             _ptr(Z) if want_Z else None, _stream(stream)))
         ll_h = ll.cpu().numpy()[:D]
         kept_h = kept.cpu().numpy()[:D]
         if not want_Z:
