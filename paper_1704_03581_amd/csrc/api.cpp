@@ -144,7 +144,7 @@ struct pulda_plan {
     uint8_t *ws = nullptr;
     int64_t ws_need = 0;
     struct {
-        int64_t z, n, gam, phid, g16, Rd, gamd, Sd, dpart, phimax, beta_v, ztp, ztp_off, ckg, colcnt, colptr, ctopic, cphi, calias, sigma_a, S, nk, alpha, pois, pois_off,
+        int64_t z, n, gam, phid, g16, Rd, gamd, Sd, dpart, phimax, wrec, beta_v, ztp, ztp_off, ckg, colcnt, colptr, ctopic, cphi, calias, sigma_a, S, nk, alpha, pois, pois_off,
             doc_order, items, queue, stats, ll_part, ll_out, ll_hist, tptr, err, scratch, cnt_a, ptr_a, cnt_b,
             ptr_b, zsave, lg_beta, lg_alpha, lg_A, ll_doc;
     } off;
@@ -330,6 +330,7 @@ pulda_status pulda_plan_create(const pulda_model_desc *desc, int64_t D, int64_t 
     p->off.ztp = L.take((int64_t)p->ztp_h.size() * 4);
     p->off.ztp_off = L.take(((int64_t)p->V + 1) * 4);
     p->off.phimax = L.take((int64_t)p->V * 4);
+    p->off.wrec = L.take((int64_t)p->V * 16);
     p->off.S = L.take((int64_t)p->K * 8);
     p->off.nk = L.take((int64_t)p->K * 8);
     p->off.alpha = L.take((int64_t)p->K * 8);
@@ -402,6 +403,7 @@ pulda_status pulda_plan_bind(pulda_plan *p, void *workspace_dev, int64_t bytes)
     m.calias = (uint64_t *)(w + p->off.calias);
     m.sigma_a = (double *)(w + p->off.sigma_a);
     m.phimax = (float *)(w + p->off.phimax);
+    m.wrec = (uint4 *)(w + p->off.wrec);
     m.pois = (const uint64_t *)(w + p->off.pois);
     m.pois_off = (const int32_t *)(w + p->off.pois_off);
     m.beta_v = p->beta_vh.empty() ? nullptr : (const double *)(w + p->off.beta_v);
@@ -913,6 +915,7 @@ pulda_status pulda_set_phi(pulda_plan *p, const pulda_phi_view *in, void *stream
     HIP_TRY(launch_import_phi(p->m, in->colptr_dev, in->topic_dev, in->phi_dev, in->alias_thr_dev,
                               in->alias_topic_dev, s));
     HIP_TRY(hipMemcpyAsync(p->m.sigma_a, in->sigma_a_dev, p->V * 8, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(launch_word_records(p->m, s));
     // values without draws behind them: R_k = 0 keeps 0 * R_k finite for the
     // zero cells (every nonzero cell is read from phid)
     HIP_TRY(launch_fill_u64((unsigned long long *)p->m.Rd, 0ull, p->K, s));

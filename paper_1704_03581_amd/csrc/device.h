@@ -105,6 +105,35 @@ __device__ __forceinline__ double group_scan_incl(double x)
     return x;
 }
 
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_f32(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xF, true));
+}
+
+// the same scan in fp32 (one DPP add per level)
+template <int G>
+__device__ __forceinline__ float group_scan_incl_f32(float x)
+{
+    if constexpr (G == 8) {
+        const int gi = __lane_id() & 7;
+        float y = dpp_f32<0x111, 0xF>(x);
+        x += gi >= 1 ? y : 0.0f;
+        y = dpp_f32<0x112, 0xF>(x);
+        x += gi >= 2 ? y : 0.0f;
+        y = dpp_f32<0x114, 0xF>(x);
+        x += gi >= 4 ? y : 0.0f;
+        return x;
+    }
+    x += dpp_f32<0x111, 0xF>(x);
+    x += dpp_f32<0x112, 0xF>(x);
+    x += dpp_f32<0x114, 0xF>(x);
+    x += dpp_f32<0x118, 0xF>(x);
+    if constexpr (G >= 32) x += dpp_f32<0x142, 0xA>(x);
+    if constexpr (G >= 64) x += dpp_f32<0x143, 0xC>(x);
+    return x;
+}
+
 template <int G>
 __device__ __forceinline__ int group_scan_incl_i32(int x)
 {
@@ -136,6 +165,12 @@ __device__ __forceinline__ int group_bcast(int x, int src)
     } else {
         return __shfl(x, src, G);
     }
+}
+
+template <int G>
+__device__ __forceinline__ float group_bcast_f32(float x, int src)
+{
+    return __int_as_float(group_bcast<G>(__float_as_int(x), src));
 }
 
 template <int G>

@@ -45,6 +45,9 @@ struct DevModel {
     uint64_t *calias;             // [cap] thr | topic << 32 | alias_topic << 48
     double *sigma_a;              // [V]
     float *phimax;                // [V] the largest phi of each word's column
+    // per word, what a z-step token needs of its word in one 16-byte load:
+    // {first CSC entry, column length, fp32(sigma_a), phimax} (as bits)
+    uint4 *wrec;                  // [V]
     const uint64_t *pois;         // Poisson alias tables, thr | x_alias << 32
     const int32_t *pois_off;      // [L+2]
     // per-word priors (null: the symmetric beta); zero-truncated
@@ -80,12 +83,16 @@ struct WorkItem {
     int32_t first, count, group, side_ratio;
 };
 
+// slots per lane of the z-step's windowed topic list (groups of 16: 8,
+// else 4)
+inline int32_t z_window(int32_t group) { return group == 16 ? 8 : 4; }
+
 // LDS layout of one z-step class (group size, count width): per group a
-// count table (K counters of 1 or 2 bytes, rounded to 8 bytes) and the
+// count table (K counters of 1 or 2 bytes, rounded to 16 bytes) and the
 // document's topic list (u16; min(K, 255) entries for documents shorter
-// than 256 tokens, else K, and at least 4 slots per lane and 4 more, for
-// the list's 8-byte windows), 64/G groups per wave, and the block's copy of
-// R_k (K doubles) first
+// than 256 tokens, else K, and at least W slots per lane and W more, for
+// the list's windows of W = z_window(group) slots, 16-byte aligned), 64/G
+// groups per wave, and the block's copy of R_k (K floats) first
 struct ZLayout {
     int32_t m_bytes, group_bytes, wave_bytes, r_bytes;
 };
@@ -93,12 +100,13 @@ struct ZLayout {
 inline ZLayout z_layout(int32_t group, bool narrow, int32_t K)
 {
     ZLayout L;
-    L.m_bytes = (K * (narrow ? 1 : 2) + 7) / 8 * 8;
+    const int32_t W = z_window(group);
+    L.m_bytes = (K * (narrow ? 1 : 2) + 15) / 16 * 16;
     int32_t lcap = narrow ? (K < 255 ? K : 255) : K;
-    if (lcap < 4 * group + 4) lcap = 4 * group + 4;
-    L.group_bytes = L.m_bytes + (lcap * 2 + 7) / 8 * 8;
+    if (lcap < W * group + W) lcap = W * group + W;
+    L.group_bytes = L.m_bytes + (lcap * 2 + 15) / 16 * 16;
     L.wave_bytes = ((64 / group) * L.group_bytes + 15) / 16 * 16;
-    L.r_bytes = (K * 8 + 15) / 16 * 16;
+    L.r_bytes = (K * 4 + 15) / 16 * 16;
     return L;
 }
 
@@ -142,6 +150,8 @@ hipError_t launch_loglik(const DevCorpus &c, const DevModel &m, double *partials
                          const uint32_t *hist_idx, hipStream_t s);
 hipError_t launch_advance(uint32_t *tptr, uint32_t *hist_idx, hipStream_t s);
 hipError_t launch_n_colcount(const DevModel &m, int64_t *cnt, hipStream_t s);
+// rebuild the per-word records from colptr, sigma_a and phimax
+hipError_t launch_word_records(const DevModel &m, hipStream_t s);
 hipError_t launch_export_phi(const DevModel &m, int64_t *colptr64, uint16_t *topic, int32_t *gam_e, float *phi_e,
                              uint32_t *thr, uint16_t *alias_topic, hipStream_t s);
 hipError_t launch_import_phi(const DevModel &m, const int64_t *colptr64, const uint16_t *topic, const float *phi_e,

@@ -613,6 +613,21 @@ __global__ void __launch_bounds__(SMALL ? 256 : 64) phi_alias_kernel(DevModel m,
     }
 }
 
+__global__ void word_records_kernel(DevModel m)
+{
+    const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= m.V) return;
+    const int32_t cb = m.colptr[v];
+    m.wrec[v] = make_uint4((uint32_t)cb, (uint32_t)(m.colptr[v + 1] - cb), __float_as_uint((float)m.sigma_a[v]),
+                           __float_as_uint(m.phimax[v]));
+}
+
+hipError_t launch_word_records(const DevModel &m, hipStream_t s)
+{
+    word_records_kernel<<<(m.V + 255) / 256, 256, 0, s>>>(m);
+    return hipGetLastError();
+}
+
 hipError_t launch_phi_fill(const DevModel &m, bool dir, hipStream_t s)
 {
     if (dir) phi_dense_kernel<true><<<(m.V + 3) / 4, 256, 0, s>>>(m);
@@ -626,8 +641,9 @@ hipError_t launch_phi_fill(const DevModel &m, bool dir, hipStream_t s)
     if (m.K > ALIAS_SMALL) {
         phi_alias_kernel<false><<<m.V, 64, (size_t)kpad * ALIAS_ENTRY_BYTES, s>>>(m, kpad);
         e = hipGetLastError();
+        if (e != hipSuccess) return e;
     }
-    return e;
+    return launch_word_records(m, s);
 }
 
 __global__ void colptr_finish_kernel(const unsigned long long *S, int32_t K, const long long *total,
@@ -860,6 +876,23 @@ struct alignas(16) TokenIn {
 
 static_assert(sizeof(TokenIn) == 32, "TokenIn is staged as 32-byte records");
 
+// the z-step's staged token: as TokenIn, with sigma_a in fp32 (its fp32
+// b-part) and the word id (the fp64 b-part reads sigma_a(v) itself)
+struct alignas(16) TokenZ {
+    uint32_t vk;     // v * K
+    int32_t cb;      // first CSC entry of the word's Phi column
+    uint16_t kold;   // topic before the draw
+    uint16_t kv;     // nonzeros in the column
+    float u0;        // (r0 >> 8) 2^-24
+    uint16_t ka;     // the a-part's alias draw
+    uint16_t sure;   // 1: the a-part is certain whatever the document's counts
+    uint32_t vs;     // v * ks16
+    float saf;       // fp32(sigma_a(v))
+    uint32_t v;      // the word
+};
+
+static_assert(sizeof(TokenZ) == 32, "TokenZ is staged as 32-byte records");
+
 // draw statistics of a lane's group: totals, and the current document's J
 // and a-part counts in 32 bits (cheaper to add per draw), moved into the
 // totals when the document is done
@@ -873,6 +906,12 @@ struct ZCount {
         j = 0;
         a = 0;
     }
+};
+
+// the z-step's draw statistics of the current document (group-uniform,
+// 32-bit), added to the wave's 64-bit totals in LDS when the document is done
+struct ZCount32 {
+    uint32_t j, a, deg;
 };
 
 // b-terms per lane kept in registers for the walk: one gather round covers
@@ -889,12 +928,26 @@ constexpr int log2g()
     return G == 64 ? 6 : (G == 32 ? 5 : (G == 16 ? 4 : 3));
 }
 
+// list slots per lane in the windowed topic list: W G slots hold the list
+// while it is no longer than that (128 for groups of 16 and 32)
+template <int G>
+constexpr int win_of()
+{
+    return G == 16 ? 8 : 4;
+}
+
+// value of the windowed list's slots past its end: above every topic
+// (K <= 4096) and below 2^15, so that packed signed 16-bit differences of
+// slot values never overflow
+constexpr int32_t LIST_PAD = 0x7FFF;
+
 // The state of the document a group is working on: m_d by topic (mt) and
 // lst, its topics with a nonzero count in ascending order (during a draw it
 // also holds the token's old topic, whose count may be zero: that b-term is
 // zero).  lst[0] always holds a valid topic, so padding slots can read it.
-// WIN: lst is 8-byte aligned and has room for 4G + 4 slots, and every slot
-// in [L, 4G + 4) holds 0xFFFF (see list_window_update).
+// WIN: lst is 16-byte aligned and has room for W G + W slots (W =
+// win_of<G>()), and every slot in [L, W G + W) holds LIST_PAD (see
+// list_window_update).
 template <typename CT, bool WIN = false>
 struct DocState {
     CT *mt;
@@ -907,10 +960,15 @@ template <int G, typename CT, bool WIN>
 __device__ __forceinline__ void build_list(DocState<CT, WIN> &S, int g, int32_t K)
 {
     if constexpr (WIN) {
-        // the windows read 0xFFFF past the list
-        const uint2 none = make_uint2(0xFFFFFFFFu, 0xFFFFFFFFu);
-        *(uint2 *)(S.lst + 4 * g) = none;
-        if (g == 0) *(uint2 *)(S.lst + 4 * G) = none;
+        // the windows read LIST_PAD past the list
+        constexpr int W = win_of<G>();
+        const uint32_t pad2 = (uint32_t)LIST_PAD * 0x10001u;
+#pragma unroll
+        for (int j = 0; j < W; j += 2) *(uint32_t *)(S.lst + W * g + j) = pad2;
+        if (g == 0) {
+#pragma unroll
+            for (int j = 0; j < W; j += 2) *(uint32_t *)(S.lst + W * G + j) = pad2;
+        }
         __builtin_amdgcn_wave_barrier();
     }
     const int32_t R = (K + G - 1) / G;
@@ -976,48 +1034,72 @@ __device__ __forceinline__ void list_remove(DocState<CT, WIN> &S, int32_t k, int
         if (v > k) S.lst[base + j - 1] = (uint16_t)v;
     }
     S.L -= 1;
-    // the slot freed at the end reads 0xFFFF again
+    // the slot freed at the end reads LIST_PAD again
     if constexpr (WIN)
-        if (g == 0) S.lst[S.L] = 0xFFFFu;
+        if (g == 0) S.lst[S.L] = (uint16_t)LIST_PAD;
     __builtin_amdgcn_wave_barrier();
 }
 
-// The list as 4-slot windows: lane g of the group holds slots [4g, 4g + 4),
-// one 8-byte LDS word.  While every entry lies inside the windows (L <= 4G
-// before and after), removing kout and inserting kin (LIST_NONE: nothing)
-// take one pass: each lane reads its window and the slot on either side,
-// forms its new window in registers and writes it back.  Slots past the list
-// hold 0xFFFF, above every topic, so the same rules cover the list's end.
-constexpr int32_t LIST_NONE = 0x10000;
+// The list as windows of W slots: lane g of the group holds slots
+// [W g, W g + W), W/2 32-bit LDS words of two slots each.  While every entry
+// lies inside the windows (L <= W G before and after), removing kout and
+// inserting kin (LIST_PAD: nothing) take one pass: each lane reads its window
+// and the slot on either side, forms its new window in registers and writes
+// it back.  Slots past the list hold LIST_PAD, so the same rules cover the
+// list's end.  With o the old slots (ascending) the two steps are
+//   removal:   o'[j] = o[j] < kout ? o[j] : o[j+1]
+//              = min(max(o[j], M_j), o[j+1]),  M_j = (o[j] >= kout) ? 0xFFFF : 0
+//   insertion: o''[j] = min(o'[j], max(o'[j-1], kin))
+// (for a sorted list the first entry not below kin takes kin and the ones
+// above it take their left neighbour), evaluated two slots at a time with
+// packed 16-bit min, max, subtract and shift.
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+typedef short i16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ u16x2 as_u16x2(uint32_t x) { return __builtin_bit_cast(u16x2, x); }
+__device__ __forceinline__ uint32_t as_u32(u16x2 x) { return __builtin_bit_cast(uint32_t, x); }
+
+template <int W>
+struct alignas(2 * W) WinWords {
+    uint32_t w[W / 2];
+};
 
 template <int G, typename CT, bool WIN>
 __device__ __forceinline__ void list_window_update(DocState<CT, WIN> &S, int32_t kout, int32_t kin, int g)
 {
     static_assert(WIN, "the windows need the padded list");
-    uint16_t *w = S.lst + 4 * g;
-    const uint2 cur = *(const uint2 *)w;
+    constexpr int W = win_of<G>();
+    constexpr int NW = W / 2;
+    uint16_t *w = S.lst + W * g;
+    WinWords<W> cur = *(const WinWords<W> *)w;
     // (lane 0 reads the slot before the list, inside the count table, and
     // drops it: an unconditional read needs no lane mask)
-    const int32_t lraw = w[-1];
-    const int32_t left = g > 0 ? lraw : -1;
-    const int32_t right = w[4];
+    const uint32_t lraw = w[-1];
+    const uint32_t left = g > 0 ? lraw : 0u;
+    const uint32_t right = w[W];
     __builtin_amdgcn_wave_barrier();
-    int32_t o[5] = {(int32_t)(cur.x & 0xFFFFu), (int32_t)(cur.x >> 16), (int32_t)(cur.y & 0xFFFFu),
-                    (int32_t)(cur.y >> 16), right};
-    // removal: the entries above kout move down one slot; p becomes the new
-    // content of the slot left of the window
-    int32_t p = left < kout ? left : o[0];
+    // removal (kout - 1 wraps to 0xFFFF for kout = 0: every slot moves)
+    const u16x2 km1 = (u16x2)(unsigned short)(kout - 1);
+    uint32_t r[NW];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) o[j] = o[j] < kout ? o[j] : o[j + 1];
-    // insertion: the entries above kin move up one slot and kin takes the
-    // first slot whose old entry is above it
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int32_t c = o[j];
-        o[j] = c < kin ? c : (p < kin ? kin : p);
-        p = c;
+    for (int i = 0; i < NW; ++i) {
+        const uint32_t nxt = __builtin_amdgcn_alignbit(i + 1 < NW ? cur.w[i + 1] : right, cur.w[i], 16);
+        const u16x2 a = as_u16x2(cur.w[i]);
+        const u16x2 m = __builtin_bit_cast(u16x2, __builtin_bit_cast(i16x2, km1 - a) >> (i16x2)15);
+        r[i] = as_u32(__builtin_elementwise_min(__builtin_elementwise_max(a, m), as_u16x2(nxt)));
     }
-    *(uint2 *)w = make_uint2((uint32_t)o[0] | ((uint32_t)o[1] << 16), (uint32_t)o[2] | ((uint32_t)o[3] << 16));
+    // the new value of the slot left of the window
+    const uint32_t o0 = cur.w[0] & 0xFFFFu;
+    const uint32_t p = (int32_t)left < kout ? left : o0;
+    // insertion
+    const u16x2 kin2 = (u16x2)(unsigned short)kin;
+    WinWords<W> out;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+        const uint32_t prv = __builtin_amdgcn_alignbit(r[i], i > 0 ? r[i - 1] : p << 16, 16);
+        out.w[i] = as_u32(__builtin_elementwise_min(as_u16x2(r[i]), __builtin_elementwise_max(as_u16x2(prv), kin2)));
+    }
+    *(WinWords<W> *)w = out;
     __builtin_amdgcn_wave_barrier();
 }
 
@@ -1031,10 +1113,11 @@ __device__ __forceinline__ void list_update(DocState<CT, WIN> &S, int32_t kold, 
     const bool in = knew != kold && mn == 0;
     if constexpr (WIN) {
         if (__builtin_amdgcn_ballot_w64(out || in) == 0) return;
+        constexpr int32_t CAP = win_of<G>() * G;
         const int32_t L2 = S.L + (in ? 1 : 0) - (out ? 1 : 0);
-        const bool wide = (out || in) && (S.L > 4 * G || L2 > 4 * G);
+        const bool wide = (out || in) && (S.L > CAP || L2 > CAP);
         if (__builtin_amdgcn_ballot_w64(wide) == 0) {
-            list_window_update<G>(S, out ? kold : LIST_NONE, in ? knew : LIST_NONE, g);
+            list_window_update<G>(S, out ? kold : LIST_PAD, in ? knew : LIST_PAD, g);
             S.L = L2;
             return;
         }
@@ -1207,6 +1290,146 @@ __device__ __forceinline__ int32_t b_part(const DevModel &M, const TokenIn &tk, 
     return group_bcast<G>(kf, f);
 }
 
+// ---------------------------------------------------------------------------
+// The same b-part in fp32 with a proven error bound, the z-step's common
+// path.  Every quantity is within a known relative error of its exact value:
+// a term b~ = fp32(fp32(x R~_k) m) (R~_k = fp32(R_k)) or fp32(phi m) is
+// within 4.01 u of phi_kv m_k (u = 2^-24), a lane's partial sum of q terms
+// adds (q - 1) u, the group scan log2(G) u and the exclusive prefix u
+// (relative to sigma_b), and the walk over the crossing lane's terms q u
+// more.  x = u0 (sigma_a + sigma_b) and y = x - sigma_a are within
+// (q + 8 + log2 G) u Z of their exact values, so every comparison of y with
+// 0 or with a running sum errs by less than (3q + 2 log2 G + 13) u Z.  The
+// decision is taken here only when y lies farther than
+// tol = (64 + 8q) u Z from the boundary it is compared with (at least 2.4
+// times that error); it is then the exact-arithmetic decision, which is also
+// the fp64 path's (b_part).  Otherwise (returned as -2, about 2e-5 of the
+// draws) the caller runs b_part.  So the result is b_part's bit for bit.
+// Returns the topic, -1 for the a-part or -2 for undecided.
+// ---------------------------------------------------------------------------
+template <int KP, bool DOC, typename CT>
+__device__ __forceinline__ void lane_terms_f32(const DevModel &M, const uint16_t *lst, const uint32_t g16o,
+                                               const uint32_t vk, const float *Rf, const CT *mt, const int32_t pad,
+                                               const int32_t first, const int32_t base, const int32_t nl,
+                                               int32_t (&kk)[KP], float (&bf)[KP])
+{
+    bool ok[KP];
+    uint32_t x[KP];
+#pragma unroll
+    for (int u = 0; u < KP; ++u) {
+        ok[u] = base + u < nl;
+        const uint32_t e = (uint32_t)(ok[u] ? first + base + u : pad);
+        if constexpr (DOC) {
+            kk[u] = lst[e];
+        } else {
+            const uint32_t kg = load_at(M.ckg, e << 2);
+            kk[u] = (int32_t)(kg & 0xFFFFu);
+            x[u] = kg >> 16;
+        }
+    }
+    if constexpr (DOC) {
+        if (M.phi_method == 1) {
+#pragma unroll
+            for (int u = 0; u < KP; ++u) {
+                const float f = load_at(M.phid, (vk + (uint32_t)kk[u]) << 2);
+                const int32_t m = mt[kk[u]];
+                bf[u] = f * (float)(ok[u] ? m : 0);
+            }
+            return;
+        }
+#pragma unroll
+        for (int u = 0; u < KP; ++u) x[u] = load_at(M.g16, g16o + ((uint32_t)kk[u] << 1));
+    }
+    bool esc = false;
+    float mf[KP];
+#pragma unroll
+    for (int u = 0; u < KP; ++u) {
+        const float r = Rf[kk[u]];
+        const int32_t m = mt[kk[u]];
+        mf[u] = (float)(ok[u] ? m : 0);
+        bf[u] = ((float)x[u] * r) * mf[u];
+        esc |= x[u] == 0xFFFFu;
+    }
+    if (__builtin_amdgcn_ballot_w64(esc)) {
+#pragma unroll
+        for (int u = 0; u < KP; ++u)
+            if (x[u] == 0xFFFFu) bf[u] = load_at(M.phid, (vk + (uint32_t)kk[u]) << 2) * mf[u];
+    }
+}
+
+template <int G, bool DOC, typename CT, int KP, bool WIN>
+__device__ __forceinline__ int32_t b_part_f32(const DevModel &M, const TokenZ &tk, DocState<CT, WIN> &S,
+                                              const float *Rf, const int g)
+{
+    constexpr int LG = log2g<G>();
+    const int32_t J = DOC ? S.L : (int32_t)tk.kv;
+    const int32_t q = (J + G - 1) >> LG;
+    int32_t nl = J - g * q < q ? J - g * q : q;
+    nl = nl > 0 ? nl : 0;
+    const uint32_t g16o = tk.vs << 1;
+    const int32_t pad = DOC ? 0 : tk.cb;
+    const int32_t first = pad + (int32_t)__umul24((uint32_t)g, (uint32_t)q);
+    int32_t kk[KP];
+    float bf[KP];
+    lane_terms_f32<KP, DOC, CT>(M, S.lst, g16o, tk.vk, Rf, S.mt, pad, first, 0, nl, kk, bf);
+    float p = 0.0f;
+#pragma unroll
+    for (int u = 0; u < KP; ++u) p += bf[u];
+    for (int32_t base = KP; base < nl; base += KP) {
+        int32_t k2[KP];
+        float f2[KP];
+        lane_terms_f32<KP, DOC, CT>(M, S.lst, g16o, tk.vk, Rf, S.mt, pad, first, base, nl, k2, f2);
+#pragma unroll
+        for (int u = 0; u < KP; ++u) p += f2[u];
+    }
+    const float incl = group_scan_incl_f32<G>(p);
+    const float T = group_bcast_f32<G>(incl, G - 1);
+    const float sa = tk.saf;
+    const float Z = sa + T;
+    const float y = tk.u0 * Z - sa;
+    const float tol = Z * ((float)(64 + 8 * q) * 0x1p-24f);
+    // (a sigma_a too small for fp32's normal range goes to the fp64 path)
+    if (y < -tol && sa > 0x1p-100f) return -1;
+    if (!(y > tol) || !(sa > 0x1p-100f)) return -2;
+    const uint64_t bal = group_ballot<G>(incl > y);
+    if (!bal) return -2;
+    const int f = G <= 32 ? __builtin_ctz((uint32_t)bal) : __builtin_ctzll(bal);
+    // every lane walks its kept terms; the crossing lane's result is the
+    // draw when its interval [lo, hi) keeps tol from y on both sides
+    float c = incl - p;
+    int32_t kf = -1;
+    float lo = 0.0f, hi = 0.0f;
+#pragma unroll
+    for (int u = 0; u < KP; ++u) {
+        const float c2 = c + bf[u];
+        if (kf < 0 && bf[u] > 0.0f && c2 > y) {
+            kf = kk[u];
+            lo = c;
+            hi = c2;
+        }
+        c = c2;
+    }
+    if (nl > KP && g == f && kf < 0) {
+        for (int32_t base = KP; base < nl && kf < 0; base += KP) {
+            int32_t k2[KP];
+            float f2[KP];
+            lane_terms_f32<KP, DOC, CT>(M, S.lst, g16o, tk.vk, Rf, S.mt, pad, first, base, nl, k2, f2);
+#pragma unroll
+            for (int u = 0; u < KP; ++u) {
+                const float c2 = c + f2[u];
+                if (kf < 0 && f2[u] > 0.0f && c2 > y) {
+                    kf = k2[u];
+                    lo = c;
+                    hi = c2;
+                }
+                c = c2;
+            }
+        }
+    }
+    const int32_t res = (kf >= 0 && y - lo > tol && hi - y > tol) ? kf : -2;
+    return group_bcast<G>(res, f);
+}
+
 // draw one token (group-uniform control flow); returns the new topic, or
 // -1 - kold for a token whose word has an empty Phi column (it keeps kold)
 template <int G, typename CT, bool WIN>
@@ -1281,10 +1504,98 @@ __device__ __forceinline__ int32_t draw_token(const DevModel &M, const TokenIn &
     return knew;
 }
 
+// the fp64 b-part out of line: it runs for about 2e-5 of the draws, and
+// inlined it would hold registers the common path needs
+template <int G, bool DOC, typename CT, int KP>
+__device__ __forceinline__ int32_t b_part_fp64(uint32_t *ckg, uint16_t *g16, float *phid, const double *Rd,
+                                               const double *sigma_a, const int32_t phi_method, const TokenZ tz,
+                                               CT *mt, uint16_t *lst, const int32_t L, const int g)
+{
+    // the fields b_part reads, in registers
+    DevModel M;
+    M.ckg = ckg;
+    M.g16 = g16;
+    M.phid = phid;
+    M.phi_method = phi_method;
+    TokenIn tk;
+    tk.vk = tz.vk;
+    tk.cb = tz.cb;
+    tk.kv = tz.kv;
+    tk.u0 = tz.u0;
+    tk.vs = tz.vs;
+    tk.sa = sigma_a[tz.v];
+    DocState<CT, true> S;
+    S.mt = mt;
+    S.lst = lst;
+    S.L = L;
+    double Zo;
+    return b_part<G, DOC, CT, KP>(M, tk, S, Rd, g, Zo);
+}
+
+// draw_token with the b-part in fp32 (b_part_f32), the fp64 b_part for the
+// draws it leaves undecided: the same results.  Rf (LDS) holds fp32(R_k);
+// the fp64 path reads R_k from global memory.
+template <int G, typename CT, bool WIN>
+__device__ __forceinline__ int32_t draw_token_f32(const DevModel &M, const TokenZ &tk, DocState<CT, WIN> &S,
+                                                  const float *Rf, const int g, const int32_t side_ratio,
+                                                  ZCount32 &cnt)
+{
+    CT *mt = S.mt;
+    const int32_t kold = tk.kold;
+    const int32_t mo = mt[kold];
+    __builtin_amdgcn_wave_barrier();
+    mt[kold] = (CT)(mo - 1);
+    __builtin_amdgcn_wave_barrier();
+    const int32_t Kv = tk.kv;
+    if (__builtin_amdgcn_ballot_w64(Kv == 0) != 0 && Kv == 0) {
+        mt[kold] = (CT)mo;
+        __builtin_amdgcn_wave_barrier();
+        cnt.deg++;
+        return -1 - kold;
+    }
+    const int32_t Kd = S.L - (mo == 1 ? 1 : 0);
+    cnt.j += (uint32_t)(Kd < Kv ? Kd : Kv);
+    int32_t knew = -1;
+    if (__builtin_amdgcn_ballot_w64(tk.sure == 0) != 0) {
+        const bool prefer_doc = Kd == 0 || (uint32_t)Kv > __umul24((uint32_t)side_ratio, (uint32_t)Kd);
+        const bool doc = __builtin_amdgcn_ballot_w64(prefer_doc) != 0;
+        constexpr int KP = keep_of<G>();
+        const int32_t J = doc ? S.L : Kv;
+        const bool over2 = __builtin_amdgcn_ballot_w64(J > (KP / 2) * G) != 0;
+        const bool over3 = __builtin_amdgcn_ballot_w64(J > (3 * KP / 4) * G) != 0;
+        if (doc)
+            knew = !over2 ? b_part_f32<G, true, CT, KP / 2>(M, tk, S, Rf, g)
+                          : (!over3 ? b_part_f32<G, true, CT, 3 * KP / 4>(M, tk, S, Rf, g)
+                                    : b_part_f32<G, true, CT, KP>(M, tk, S, Rf, g));
+        else
+            knew = !over2 ? b_part_f32<G, false, CT, KP / 2>(M, tk, S, Rf, g)
+                          : (!over3 ? b_part_f32<G, false, CT, 3 * KP / 4>(M, tk, S, Rf, g)
+                                    : b_part_f32<G, false, CT, KP>(M, tk, S, Rf, g));
+        if (__builtin_amdgcn_ballot_w64(knew == -2) != 0) {
+            // a draw too close to a boundary for fp32: the fp64 b-part
+            const int32_t k64 = doc ? b_part_fp64<G, true, CT, KP>(M.ckg, M.g16, M.phid, M.Rd, M.sigma_a,
+                                                                   M.phi_method, tk, S.mt, S.lst, S.L, g)
+                                    : b_part_fp64<G, false, CT, KP>(M.ckg, M.g16, M.phid, M.Rd, M.sigma_a,
+                                                                    M.phi_method, tk, S.mt, S.lst, S.L, g);
+            if (knew == -2) knew = k64;
+        }
+    }
+    if (knew < 0) {
+        knew = tk.ka;
+        cnt.a++;
+    }
+    const int32_t mn = mt[knew];
+    __builtin_amdgcn_wave_barrier();
+    mt[knew] = (CT)(mn + 1);
+    __builtin_amdgcn_wave_barrier();
+    list_update<G>(S, kold, knew, mo, mn, g);
+    return knew;
+}
+
 // a token whose a-part was decided at staging (tk.sure): the same count and
 // list updates as draw_token, with the new topic the word's alias draw
 template <int G, typename CT, bool WIN>
-__device__ __forceinline__ int32_t move_token(const TokenIn &tk, DocState<CT, WIN> &S, const int g, ZCount &cnt)
+__device__ __forceinline__ int32_t move_token(const TokenZ &tk, DocState<CT, WIN> &S, const int g, ZCount32 &cnt)
 {
     CT *mt = S.mt;
     const int32_t kold = tk.kold;
@@ -1364,9 +1675,45 @@ __device__ __forceinline__ void stage_token(const DevModel &M, TokenIn *tok, int
     tok[g] = x;
 }
 
+// stage the inputs of the z-step's token at lane g from its word's record:
+// as stage_token, with the a-part decided at staging by the same bound in
+// fp32: u (sigma_a + phimax(v) (nd - 1)) < sigma_a (1 - 2^-20), both sides
+// rounded to fp32 (a relative error below 6 2^-24 each), so a token so
+// decided has x < sigma_a (1 - 10 2^-24) exactly, far outside any rounding
+// of the sums (the fp64 and exact decisions agree)
+__device__ __forceinline__ void stage_token_z(const DevModel &M, TokenZ *tok, int g, int32_t v, int32_t kold,
+                                              const r4 &r, const int32_t nd)
+{
+    const uint4 rec = M.wrec[v];
+    TokenZ x;
+    x.vk = (uint32_t)v * (uint32_t)M.K;
+    x.vs = (uint32_t)v * (uint32_t)M.ks16;
+    x.cb = (int32_t)rec.x;
+    x.kold = (uint16_t)kold;
+    const uint32_t kv = rec.y;
+    x.kv = (uint16_t)kv;
+    x.u0 = (float)(r.x >> 8) * 0x1p-24f;
+    x.saf = __uint_as_float(rec.z);
+    x.v = (uint32_t)v;
+    uint32_t ka = 0;
+    if (kv > 0) {
+        const uint32_t j = scale32(r.y, kv);
+        const uint64_t a = M.calias[rec.x + j];
+        ka = (r.z < (uint32_t)a) ? (uint32_t)((a >> 32) & 0xFFFFu) : (uint32_t)(a >> 48);
+    }
+    x.ka = (uint16_t)ka;
+    bool sure = false;
+    if (kv > 0 && nd > 0) {
+        const float B = __uint_as_float(rec.w) * (float)(nd - 1);
+        sure = x.u0 * (x.saf + B) < x.saf * (1.0f - 0x1p-20f);
+    }
+    x.sure = sure ? 1 : 0;
+    tok[g] = x;
+}
+
 template <int G, typename CT>
-__device__ void z_step_item(const ZArgs &a, const WorkItem &w, const double *R, uint8_t *wave_base,
-                            TokenIn *wave_tok, ZCount &cnt)
+__device__ void z_step_item(const ZArgs &a, const WorkItem &w, const float *R, uint8_t *wave_base,
+                            TokenZ *wave_tok, unsigned long long *wave_cnt)
 {
     constexpr int NG = 64 / G;
     const int lane = __lane_id();
@@ -1375,7 +1722,7 @@ __device__ void z_step_item(const ZArgs &a, const WorkItem &w, const double *R, 
     DocState<CT, true> S;
     S.mt = (CT *)(wave_base + grp * a.group_bytes);
     S.lst = (uint16_t *)(wave_base + grp * a.group_bytes + a.m_bytes);
-    TokenIn *tok = wave_tok + grp * G;
+    TokenZ *tok = wave_tok + grp * G;
     const DevModel &M = a.m;
     const uint32_t t = *M.tptr;
     for (int32_t di = grp; di < w.count; di += NG) {
@@ -1386,15 +1733,18 @@ __device__ void z_step_item(const ZArgs &a, const WorkItem &w, const double *R, 
             continue;
         }
         load_doc_counts<G, CT>(S, a.c.z, s, e, g, M.K, a.m_bytes / 4);
+        ZCount32 cnt = {0, 0, 0};
         for (int64_t i0 = s; i0 < e; i0 += G) {
             const int64_t i = i0 + g;
             const bool valid = i < e;
             int32_t zo = 0, wv = 0;
             if (valid) {
-                wv = a.c.words[i];
-                zo = a.c.z[i];
+                // the token stream is read once per sweep: non-temporal, so
+                // it does not displace the tables the draws reuse
+                wv = __builtin_nontemporal_load(a.c.words + i);
+                zo = __builtin_nontemporal_load(a.c.z + i);
                 const r4 r = philox((uint32_t)i, (uint32_t)((uint64_t)i >> 32), t, TAG_Z, M.key0, M.key1);
-                stage_token(M, tok, g, wv, zo, r, (int32_t)(e - s));
+                stage_token_z(M, tok, g, wv, zo, r, (int32_t)(e - s));
             }
             __builtin_amdgcn_wave_barrier();
             int32_t znew = zo;
@@ -1408,9 +1758,8 @@ __device__ void z_step_item(const ZArgs &a, const WorkItem &w, const double *R, 
             // all eight tokens are decided.)
             if constexpr (G < 16) {
                 for (int jj = 0; jj < nb; ++jj) {
-                    const TokenIn tk = tok[jj];
-                    double Zo;
-                    int32_t k = draw_token<G, CT>(M, tk, S, R, g, w.side_ratio, cnt, Zo);
+                    const TokenZ tk = tok[jj];
+                    int32_t k = draw_token_f32<G, CT>(M, tk, S, R, g, w.side_ratio, cnt);
                     if (k < 0) k = -1 - k;
                     if (g == jj) znew = k;
                 }
@@ -1418,15 +1767,14 @@ __device__ void z_step_item(const ZArgs &a, const WorkItem &w, const double *R, 
             int cur = 0;
             while (true) {
                 while (cur < nb && tok[cur].sure) {
-                    const TokenIn tk = tok[cur];
+                    const TokenZ tk = tok[cur];
                     const int32_t k = move_token<G, CT>(tk, S, g, cnt);
                     if (g == cur) znew = k;
                     ++cur;
                 }
                 if (cur < nb) {
-                    const TokenIn tk = tok[cur];
-                    double Zo;
-                    int32_t k = draw_token<G, CT>(M, tk, S, R, g, w.side_ratio, cnt, Zo);
+                    const TokenZ tk = tok[cur];
+                    int32_t k = draw_token_f32<G, CT>(M, tk, S, R, g, w.side_ratio, cnt);
                     if (k < 0) k = -1 - k;
                     if (g == cur) znew = k;
                     ++cur;
@@ -1438,11 +1786,15 @@ __device__ void z_step_item(const ZArgs &a, const WorkItem &w, const double *R, 
             // the count rebuild: each lane adds its own token, once the
             // block's draws are done
             if (valid) {
-                a.c.z[i] = (uint16_t)znew;
+                __builtin_nontemporal_store((uint16_t)znew, a.c.z + i);
                 atomicAdd(&M.n[(uint32_t)wv * (uint32_t)M.K + (uint32_t)znew], 1);
             }
         }
-        cnt.flush();
+        if (g == 0) {
+            atomicAdd(&wave_cnt[0], (unsigned long long)cnt.j);
+            atomicAdd(&wave_cnt[1], (unsigned long long)cnt.a);
+            atomicAdd(&wave_cnt[2], (unsigned long long)cnt.deg);
+        }
         if (a.ll_doc) {
             // the document's term of log p(z | alpha) for its final counts:
             // lgamma(A) - lgamma(N_d + A) + sum_k [lgamma(m_k + alpha) - lgamma(alpha)]
@@ -1466,14 +1818,19 @@ template <int G, typename CT>
 __global__ void __launch_bounds__(256, (G == 8 ? 2 : 5)) z_step_kernel(ZArgs a)
 {
     extern __shared__ __align__(16) uint8_t z_lds[];
-    double *R = (double *)z_lds;
-    for (int32_t k = threadIdx.x; k < a.m.K; k += blockDim.x) R[k] = a.m.Rd[k];
+    // fp32(R_k) for the fp32 b-terms (the fp64 path reads R_k from global
+    // memory)
+    float *R = (float *)z_lds;
+    for (int32_t k = threadIdx.x; k < a.m.K; k += blockDim.x) R[k] = (float)a.m.Rd[k];
     __syncthreads();
     const int wave = threadIdx.x >> 6;
     uint8_t *blk = z_lds + a.r_bytes;
     uint8_t *wave_base = blk + wave * a.wave_bytes;
-    TokenIn *wave_tok = (TokenIn *)(blk + 4 * a.wave_bytes) + wave * 64;
-    ZCount cnt = {0, 0, 0, 0, 0};
+    TokenZ *wave_tok = (TokenZ *)(blk + 4 * a.wave_bytes) + wave * 64;
+    // the wave's statistics: sum of J, a-part draws, degenerate tokens
+    unsigned long long *wave_cnt = (unsigned long long *)(blk + 4 * a.wave_bytes + 4 * 64 * sizeof(TokenIn)) + 4 * wave;
+    if (__lane_id() < 3) wave_cnt[__lane_id()] = 0ull;
+    __builtin_amdgcn_wave_barrier();
     while (true) {
         int item = 0;
         if (__lane_id() == 0) item = atomicAdd(a.queue, 1);
@@ -1482,13 +1839,14 @@ __global__ void __launch_bounds__(256, (G == 8 ? 2 : 5)) z_step_kernel(ZArgs a)
         // a private copy: a reference into global memory would be reloaded
         // after every store of the item (stores may alias it)
         const WorkItem w = a.items[item];
-        z_step_item<G, CT>(a, w, R, wave_base, wave_tok, cnt);
+        z_step_item<G, CT>(a, w, R, wave_base, wave_tok, wave_cnt);
     }
-    // every lane of a group counted the group's tokens; its first lane reports
-    if (a.stats && (__lane_id() & (G - 1)) == 0) {
-        if (cnt.J) atomicAdd(&a.stats[ST_SUM_J], (unsigned long long)cnt.J);
-        if (cnt.A) atomicAdd(&a.stats[ST_SUM_A], (unsigned long long)cnt.A);
-        if (cnt.degenerate) atomicAdd(&a.stats[ST_DEGENERATE], (unsigned long long)cnt.degenerate);
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    if (a.stats && __lane_id() < 3) {
+        const unsigned long long v = wave_cnt[__lane_id()];
+        const int idx = __lane_id() == 0 ? ST_SUM_J : (__lane_id() == 1 ? ST_SUM_A : ST_DEGENERATE);
+        if (v) atomicAdd(&a.stats[idx], v);
     }
 }
 
@@ -1758,7 +2116,7 @@ hipError_t launch_z_class(const DevCorpus &c, const DevModel &m, int32_t group, 
     a.group_bytes = L.group_bytes;
     a.wave_bytes = L.wave_bytes;
     a.r_bytes = L.r_bytes;
-    const size_t lds = (size_t)a.r_bytes + 4 * ((size_t)a.wave_bytes + 64 * sizeof(TokenIn));
+    const size_t lds = (size_t)a.r_bytes + 4 * ((size_t)a.wave_bytes + 64 * sizeof(TokenIn) + 32);
     auto launch = [&](auto kernel) -> hipError_t {
         // persistent: exactly the blocks the device holds at once, and no
         // more waves than work items (a wave takes one item at a time)
