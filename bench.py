@@ -62,8 +62,25 @@ def recorded_traffic(config):
     return float(kv["traffic_bytes_per_launch"]), path
 
 
+def host_cpu():
+    """The host's CPU model (lscpu's model name) and its core count."""
+    model = "unknown"
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except Exception:
+        pass
+    return model, os.cpu_count()
+
+
 def cpu_baseline(corpus, seed, budget_docs):
-    """The oracle (single-threaded C) on a bounded sample of the same corpus."""
+    """The oracle (single-threaded C) on a bounded sample of the same corpus:
+    its doubly sparse z-step mode (bit-identical to its dense definition),
+    pinned to one core, one sweep from the initial state."""
     import oracle
     d = min(budget_docs, corpus.D)
     off = corpus.doc_off[: d + 1].copy()
@@ -71,60 +88,86 @@ def cpu_baseline(corpus, seed, budget_docs):
     n_tok = int(off[-1])
     z = oracle.init_z(n_tok, corpus.K, seed)
     alpha = np.full(corpus.K, corpus.alpha)
-    t0 = time.perf_counter()
-    n, _, _ = oracle.counts(off, words, z, corpus.K, corpus.V, with_m=False)
-    gam = oracle.phi_counts(n, corpus.beta, 100, seed, 1)
-    S, phi, _ = oracle.phi_normalise(gam)
-    wt = oracle.word_tables(alpha, phi)
-    t1 = time.perf_counter()
-    oracle.z_step(off, words, z, seed, 1, phi, wt, corpus.K, corpus.V)
-    t2 = time.perf_counter()
-    oracle.loglik(off, words, z, alpha, corpus.beta, corpus.K, corpus.V)
-    t3 = time.perf_counter()
+    model, ncpu = host_cpu()
+    old_aff = os.sched_getaffinity(0) if hasattr(os, "sched_getaffinity") else None
+    if old_aff:
+        os.sched_setaffinity(0, {min(old_aff)})
+    try:
+        t0 = time.perf_counter()
+        n, _, _ = oracle.counts(off, words, z, corpus.K, corpus.V, with_m=False)
+        gam = oracle.phi_counts(n, corpus.beta, 100, seed, 1)
+        S, phi, _ = oracle.phi_normalise(gam)
+        wt = oracle.word_tables(alpha, phi)
+        t1 = time.perf_counter()
+        oracle.z_step(off, words, z, seed, 1, phi, wt, corpus.K, corpus.V, sparse=True)
+        t2 = time.perf_counter()
+        oracle.loglik(off, words, z, alpha, corpus.beta, corpus.K, corpus.V)
+        t3 = time.perf_counter()
+    finally:
+        if old_aff:
+            os.sched_setaffinity(0, old_aff)
     return dict(value=n_tok / (t2 - t1), unit="tokens/s", cores=1, kind="oracle",
                 sample=f"first {d} documents ({n_tok} tokens) of the same corpus, one sweep from the "
-                       f"initial state; z-step {t2 - t1:.2f}s, Phi-step {t1 - t0:.2f}s, log joint {t3 - t2:.2f}s "
-                       f"(oracle is single-threaded)",
-                sweep_tokens_per_s=n_tok / (t3 - t0))
+                       f"initial state, the oracle's doubly sparse z-step (bit-identical to its dense mode) on one "
+                       f"pinned core; z-step {t2 - t1:.2f}s, Phi-step {t1 - t0:.2f}s, log joint {t3 - t2:.2f}s",
+                host_cpu=model, host_cores=ncpu, sweep_tokens_per_s=n_tok / (t3 - t0))
 
 
-def foldin_bench(args, torch, pulda, synth):
+def foldin_bench(args, torch, pulda, synth, model=None, phi_source=None):
     """Fold-in serving against a resident Phi (K=1000, V=141000): continuous
-    batching (closed loop, then open-loop Poisson arrivals) and the plain
-    per-document sampler on the same requests."""
+    batching (closed loop, then open-loop Poisson arrivals of at least
+    args.trace_s seconds per rate) and the plain per-document sampler on the
+    same requests.  model: a plan holding the serving Phi (default: a Phi-step
+    from counts drawn from the generating topics, see phi_source)."""
     from paper_1704_03581_amd import server
     cfg = synth.CONFIGS["large"]
     K, V = cfg["K"], cfg["V"]
-    log("fold-in: drawing serving counts and Phi")
-    n = synth.topic_word_counts_draw("large")
-    model = pulda.Plan(K, V, 0, 0, alpha=synth.ALPHA, beta=synth.BETA, seed=args.seed)
-    model.set_counts(np.ascontiguousarray(n.T).reshape(-1))
-    del n
-    model.phi_step(1)
+    if model is None:
+        log("fold-in: drawing serving counts and Phi")
+        n = synth.topic_word_counts_draw("large")
+        model = pulda.Plan(K, V, 0, 0, alpha=synth.ALPHA, beta=synth.BETA, seed=args.seed)
+        model.set_counts(np.ascontiguousarray(n.T).reshape(-1))
+        del n
+        model.phi_step(1)
+        phi_source = ("one Phi-step from topic-word counts drawn from the generating topics (738M tokens); "
+                      "bench.py --converged serves the Phi of a 1000-sweep run")
     torch.cuda.synchronize()
-    reqs = synth.foldin_requests(args.foldin_requests + args.plain_requests, seed=170403581 + 5)
+    # enough requests for trace_s seconds of arrivals at the highest rate
+    n_trace = args.foldin_requests
+    reqs = synth.foldin_requests(max(n_trace, 1) + args.plain_requests, seed=170403581 + 5)
     lens = np.array([len(r) for r in reqs])
     fi = pulda.FoldIn(model, sweeps=50, burn_in=25, max_slots=args.slots, arena_tokens=args.slots * 600,
                       max_len=5000, group=64, seed=args.seed)
-    nb = args.foldin_requests
+    nb = min(args.closed_requests, n_trace)
     batched = reqs[:nb]
     log(f"fold-in: closed loop, {nb} requests")
     rep = server.serve(fi, batched, draws=args.draws)
     # the service rate: completions between the 10% and 90% marks (the run's
     # end waits for its longest requests, 50 sweeps of up to 5000 tokens)
     xmax = rep.steady_docs_per_s()
-    out = dict(saturation_docs_per_s=xmax, closed_loop_docs_per_s=rep.docs_per_s,
-               saturation_p50_ms=rep.percentile_ms(50),
-               saturation_p99_ms=rep.percentile_ms(99), requests=nb, mean_len=float(lens[:nb].mean()),
-               sweeps=50, burn_in=25, slots=args.slots, draws_per_step=args.draws, rates={})
+    out = dict(phi=phi_source, service_rate_docs_per_s=xmax, closed_loop_docs_per_s=rep.docs_per_s,
+               closed_loop_p50_ms=rep.percentile_ms(50), closed_loop_p99_ms=rep.percentile_ms(99),
+               closed_loop_requests=nb, mean_len=float(lens[:n_trace].mean()),
+               sweeps=50, burn_in=25, slots=args.slots, draws_per_step=args.draws, trace_s=args.trace_s,
+               rates={})
+    sustained = 0.0
     for i, frac in enumerate(args.rates):
-        arr = server.poisson_arrivals(nb, frac * xmax, seed=170403581 + 5 + i)
-        rep = server.serve(fi, batched, arrivals=arr, draws=args.draws)
-        out["rates"][f"{frac:.2f}"] = dict(offered_docs_per_s=frac * xmax, docs_per_s=rep.docs_per_s,
-                                           p50_ms=rep.percentile_ms(50), p99_ms=rep.percentile_ms(99),
-                                           max_resident=rep.max_resident)
+        # open loop: Poisson arrivals for trace_s seconds at frac x the
+        # service rate; delivered rate and latencies over the arrivals
+        # between the 10% and 90% marks (start-up and drain left out)
+        rate = frac * xmax
+        n_req = min(n_trace, max(1000, int(rate * args.trace_s)))
+        arr = server.poisson_arrivals(n_req, rate, seed=170403581 + 5 + i)
+        rep = server.serve(fi, reqs[:n_req], arrivals=arr, draws=args.draws)
+        delivered, p50, p99 = rep.arrival_window(arr)
+        out["rates"][f"{frac:.2f}"] = dict(offered_docs_per_s=rate, requests=n_req, arrival_s=float(arr[-1]),
+                                           delivered_docs_per_s=delivered, p50_ms=p50, p99_ms=p99,
+                                           whole_run_docs_per_s=rep.docs_per_s, max_resident=rep.max_resident)
+        if delivered >= 0.97 * rate:
+            sustained = max(sustained, rate)
         log(f"fold-in: rate {frac:.2f} x -> {out['rates'][f'{frac:.2f}']}")
-    plain = reqs[nb:nb + args.plain_requests]
+    out["sustained_docs_per_s"] = sustained
+    plain = reqs[n_trace:n_trace + args.plain_requests]
     rep_p = server.serve_plain(fi, plain)
     out["plain_docs_per_s"] = rep_p.docs_per_s
     out["plain_p50_ms"] = rep_p.percentile_ms(50)
@@ -134,7 +177,12 @@ def foldin_bench(args, torch, pulda, synth):
     out["batched_equals_plain"] = bool(all(
         np.array_equal(rep_b.results[j]["theta"], rep_p.results[j]["theta"]) and
         rep_b.results[j]["loglik"] == rep_p.results[j]["loglik"] for j in range(len(plain))))
-    out["speedup_vs_plain"] = xmax / out["plain_docs_per_s"]
+    # like with like: whole-run rate against whole-run rate (the closed loop
+    # includes its start-up and its drain; the plain sampler, one request at
+    # a time, has neither, so its rate does not depend on the count)
+    out["speedup_vs_plain"] = out["closed_loop_docs_per_s"] / out["plain_docs_per_s"]
+    # and the steady service rate against the same plain rate
+    out["service_rate_vs_plain"] = xmax / out["plain_docs_per_s"]
     return out
 
 
@@ -218,6 +266,138 @@ def scaling_study(args, torch, pulda, synth):
                          f"limit, vocabulary size and data size", rows=rows)
 
 
+def ksweep_study(args, torch, pulda, synth):
+    """The paper's K comparison (Section 4: K = 10, 100, 1000; time per
+    iteration of both samplers and their log-posterior traces) on synthetic
+    data: both Phi-steps with the same z-step at each K on the large corpus
+    (3 warmup sweeps, autotuned schedule, 5 timed sweeps of each method
+    continuing the chain, per-phase hipEvent times), and per-sweep log-joint
+    traces of Algorithm 2 and Algorithm 1 from the same initial state on an
+    eighth of its documents (args.trace_sweeps sweeps each)."""
+    if args.corpus_cache and os.path.exists(args.corpus_cache):
+        base = synth.load(args.corpus_cache)
+    else:
+        base = synth.generate("large", keep_true_z=False)
+    small = synth.restrict(base, doc_fraction=0.125)
+    rows = []
+    for K in (10, 100, 1000):
+        plan = pulda.Plan(K, base.V, base.D, base.N, alpha=base.alpha, beta=base.beta, seed=args.seed)
+        plan.upload(base.doc_off, base.words)
+        plan.init()
+        plan.sweep(1, 3, want_ll=False)
+        plan.phi_step(4)
+        sched = plan.autotune(4, reps=1)
+        plan.set_timing(True)
+        row = dict(K=K, N=base.N, schedule=sched)
+        for method, t0 in (("polya_urn", 4), ("dirichlet", 9)):
+            plan.set_phi_method(method)
+            plan.stats()
+            plan.sweep(t0, 5, want_ll=False)
+            st = plan.stats()
+            z_ms = st["ms_z"] / st["n_z"]
+            row[method] = dict(phi_ms=st["ms_phi"] / st["n_phi"], z_ms=z_ms, ll_ms=st["ms_ll"] / max(st["n_ll"], 1),
+                               z_tokens_per_s=base.N / (z_ms * 1e-3), nnz_phi=st["nnz_phi"],
+                               mean_J=st["sum_J"] / st["z_steps"] / base.N,
+                               a_fraction=st["sum_A"] / st["z_steps"] / base.N)
+        row["z_ratio_dirichlet_over_urn"] = row["dirichlet"]["z_ms"] / row["polya_urn"]["z_ms"]
+        row["phi_ratio_dirichlet_over_urn"] = row["dirichlet"]["phi_ms"] / row["polya_urn"]["phi_ms"]
+        del plan
+        torch.cuda.empty_cache()
+        # log-joint traces of both samplers from the same initial state
+        traces = {}
+        for method in ("polya_urn", "dirichlet"):
+            tp = pulda.Plan(K, small.V, small.D, small.N, alpha=small.alpha, beta=small.beta, seed=args.seed)
+            tp.upload(small.doc_off, small.words)
+            tp.init()
+            tp.set_phi_method(method)
+            lls = []
+            for t in range(1, args.trace_sweeps + 1, 50):
+                n = min(50, args.trace_sweeps + 1 - t)
+                lls.extend(tp.sweep(t, n))
+            traces[method] = np.asarray(lls)
+            del tp
+            torch.cuda.empty_cache()
+        marks = [1, 2, 5, 10, 20, 50, 100, 200, 300, 500, 1000]
+        marks = [m for m in marks if m <= args.trace_sweeps]
+        row["trace"] = dict(corpus=f"an eighth of the documents (D={small.D}, N={small.N})",
+                            sweeps=marks,
+                            polya_urn=[float(traces["polya_urn"][m - 1]) for m in marks],
+                            dirichlet=[float(traces["dirichlet"][m - 1]) for m in marks])
+        tail = max(1, args.trace_sweeps // 4)
+        u, d = traces["polya_urn"][-tail:], traces["dirichlet"][-tail:]
+        row["trace"]["last_quarter_mean"] = dict(polya_urn=float(u.mean()), dirichlet=float(d.mean()),
+                                                 relative_gap=float((u.mean() - d.mean()) / abs(d.mean())),
+                                                 polya_urn_sd=float(u.std()), dirichlet_sd=float(d.std()))
+        log(f"ksweep K={K}: {json.dumps({k: v for k, v in row.items() if k != 'trace'})}")
+        log(f"ksweep K={K} trace: {json.dumps(row['trace'])}")
+        rows.append(row)
+    return dict(workload=f"large corpus (D={base.D}, V={base.V}, N={base.N}, generated with K=1000) sampled with "
+                         f"K = 10, 100, 1000", rows=rows)
+
+
+def converged_study(args, torch, pulda, synth):
+    """The large workload run for 1000 sweeps: z-step throughput over the
+    first sweeps (dense initial state) and over sweeps 901-1000 (converged),
+    both with per-phase events and a schedule autotuned on that state, the
+    sweeps between replayed from a captured graph; log joint every 100
+    sweeps; then fold-in serving against the Phi of sweep 1001, as the
+    serving workload specifies."""
+    if args.corpus_cache and os.path.exists(args.corpus_cache):
+        c = synth.load(args.corpus_cache)
+    else:
+        c = synth.generate("large", keep_true_z=False)
+    N = c.N
+    plan = pulda.Plan(c.K, c.V, c.D, c.N, alpha=c.alpha, beta=c.beta, seed=args.seed)
+    plan.upload(c.doc_off, c.words)
+    plan.init()
+
+    def window(t0, n):
+        plan.set_graph(False)
+        plan.phi_step(t0)
+        sched = plan.autotune(t0, reps=1)
+        plan.set_timing(True)
+        plan.stats()
+        plan.sweep(t0, n, want_ll=False)
+        st = plan.stats()
+        plan.set_timing(False)
+        z_ms = st["ms_z"] / st["n_z"]
+        bytes_launch = algorithmic_bytes(N, st["sum_J"] / st["z_steps"], st["sum_A"] / st["z_steps"])
+        bytes_b = algorithmic_bytes(N, st["sum_J_b"] / st["z_steps"], st["sum_A"] / st["z_steps"])
+        return dict(sweeps=[t0, t0 + n - 1], schedule=sched, z_ms=z_ms, z_tokens_per_s=N / (z_ms * 1e-3),
+                    phi_ms=st["ms_phi"] / st["n_phi"], loglik_ms=st["ms_ll"] / max(st["n_ll"], 1),
+                    sweep_ms=(st["ms_phi"] + st["ms_z"] + st["ms_ll"]) / st["n_z"],
+                    mean_J=st["sum_J"] / st["z_steps"] / N, mean_J_b_terms_read=st["sum_J_b"] / st["z_steps"] / N,
+                    a_fraction=st["sum_A"] / st["z_steps"] / N, nnz_phi=st["nnz_phi"],
+                    frac=bytes_launch / (z_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                    frac_b_terms_read=bytes_b / (z_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, loglik=plan.loglik())
+
+    out = dict(workload=f"large: D={c.D} V={c.V} K={c.K} N={N}", lls={})
+    log("converged: sweeps 1-10")
+    out["first"] = window(1, 10)
+    log(f"converged: first window {out['first']}")
+    plan.set_graph(True)
+    t = 11
+    w0 = time.perf_counter()
+    for target in range(101, 902, 100):
+        plan.sweep(t, target - t, want_ll=False)
+        t = target
+        out["lls"][t - 1] = plan.loglik()
+        log(f"converged: sweep {t - 1}, log joint {out['lls'][t - 1]:.6e}, "
+            f"{(time.perf_counter() - w0) / (t - 11) * 1e3:.1f} ms per replayed sweep")
+    out["replayed_ms_per_sweep"] = (time.perf_counter() - w0) / (901 - 11) * 1e3
+    log("converged: sweeps 901-1000")
+    out["converged"] = window(901, 100)
+    out["lls"][1000] = plan.loglik()
+    log(f"converged: last window {out['converged']}")
+    plan.set_graph(False)
+    plan.phi_step(1001)
+    if not args.no_foldin:
+        out["foldin"] = foldin_bench(args, torch, pulda, synth, model=plan,
+                                     phi_source="Phi-step of sweep 1001 of a 1000-sweep run on the large corpus "
+                                                "(seed %d)" % args.seed)
+    return out
+
+
 def alg1_bench(plan, t, N, sweeps):
     """Algorithm 1 (Phi-step phi_k ~ Dir(n_k + beta) by Gamma draws) on the
     state the timed sweeps left, with the same z-step schedule: per-phase
@@ -251,6 +431,8 @@ def main():
     ap.add_argument("--force-group", type=int, default=0,
                     help="one schedule bucket with this group size (1, 8, 16, 32, 64) instead of autotuning")
     ap.add_argument("--graph", action="store_true", help="replay a captured sweep (no per-phase events)")
+    ap.add_argument("--graph-steps", type=int, default=10,
+                    help="after the timed sweeps, this many sweeps replayed from a captured graph (0: none)")
     ap.add_argument("--cpu-docs", type=int, default=20000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-foldin", action="store_true")
@@ -262,9 +444,18 @@ def main():
     ap.add_argument("--scaling", action="store_true",
                     help="run only the scaling study of both Phi-steps on restrictions of the large corpus "
                          "(read from --corpus-cache when present)")
+    ap.add_argument("--ksweep", action="store_true",
+                    help="run only the K = 10, 100, 1000 comparison of both Phi-steps with log-joint traces")
+    ap.add_argument("--trace-sweeps", type=int, default=200, help="sweeps of each log-joint trace in --ksweep")
+    ap.add_argument("--converged", action="store_true",
+                    help="run only the 1000-sweep large run (sweeps 1-10 and 901-1000 timed) and fold-in serving "
+                         "on its Phi")
     ap.add_argument("--alg1-sweeps", type=int, default=3,
                     help="sweeps with Algorithm 1's Dirichlet Phi-step after the timed region (0: none)")
-    ap.add_argument("--foldin-requests", type=int, default=12000)
+    ap.add_argument("--foldin-requests", type=int, default=300000,
+                    help="requests drawn for the fold-in traces (open-loop traces use what trace_s needs)")
+    ap.add_argument("--closed-requests", type=int, default=12000, help="requests of the closed-loop run")
+    ap.add_argument("--trace-s", type=float, default=10.0, help="seconds of Poisson arrivals per rate point")
     ap.add_argument("--plain-requests", type=int, default=60)
     ap.add_argument("--slots", type=int, default=4096)
     ap.add_argument("--draws", type=int, default=2048, help="fold-in token draws per request per step")
@@ -281,6 +472,18 @@ def main():
         sys.exit(2)
 
     from paper_1704_03581_amd import synth
+    if args.ksweep:
+        import torch
+        from paper_1704_03581_amd import pulda
+        print(json.dumps(dict(metric="K sweep: Phi-step and z-step ms per sweep, Polya urn vs Dirichlet, and "
+                                     "log-joint traces", **ksweep_study(args, torch, pulda, synth))), flush=True)
+        return
+    if args.converged:
+        import torch
+        from paper_1704_03581_amd import pulda
+        print(json.dumps(dict(metric="converged z-step throughput (sweeps 901-1000) and fold-in serving on the "
+                                     "converged Phi", **converged_study(args, torch, pulda, synth))), flush=True)
+        return
     if args.scaling:
         import torch
         from paper_1704_03581_amd import pulda
@@ -360,6 +563,9 @@ def main():
     if not args.graph and st["n_z"]:
         z_ms = st["ms_z"] / st["n_z"]
         bytes_launch = algorithmic_bytes(N, st["sum_J"] / st["z_steps"], st["sum_A"] / st["z_steps"])
+        # the same with the b-terms of the tokens whose b-part was computed
+        # (a token whose a-part is certain at staging reads none of its J)
+        bytes_b = algorithmic_bytes(N, st["sum_J_b"] / st["z_steps"], st["sum_A"] / st["z_steps"])
         achieved = bytes_launch / (z_ms * 1e-3) / 1e9
         res["zstep"] = dict(tokens_per_s=N / (z_ms * 1e-3), kernel_ms=z_ms, phi_ms=st["ms_phi"] / st["n_phi"],
                             loglik_ms=st["ms_ll"] / st["n_ll"],
@@ -370,9 +576,32 @@ def main():
         res["roofline"] = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                                frac=achieved / HBM_PEAK_GBS, traffic=traffic,
                                kernel="z_step_kernel", algorithmic_bytes_per_launch=bytes_launch,
+                               frac_b_terms_read=bytes_b / (z_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                               algorithmic_bytes_b_terms_read=bytes_b,
+                               frac_rocprof=(traffic / (z_ms * 1e-3) / 1e9 / HBM_PEAK_GBS) if traffic else None,
+                               target_frac=0.40, target_met=achieved / HBM_PEAK_GBS >= 0.40,
                                traffic_unit="bytes per launch (FETCH_SIZE x2.0 + WRITE_SIZE x1.0, calibrated)",
                                traffic_source=os.path.relpath(tsrc, ROOT) if tsrc else None)
+        res["zstep"]["mean_J_b_terms_read"] = st["sum_J_b"] / st["z_steps"] / N
     log(f"sweep {ms_step:.2f} ms, {tokens_per_s / 1e9:.3f} G tokens/s; {res.get('zstep')}")
+    t = t + args.steps
+    if not args.graph and args.graph_steps > 0:
+        # the same sweeps replayed from a captured hipGraph (no per-phase
+        # events), timed by the host clock
+        plan.set_timing(False)
+        plan.set_graph(True)
+        plan.sweep(t, 1, want_ll=False)      # capture
+        t += 1
+        torch.cuda.synchronize()
+        g0 = time.perf_counter()
+        plan.sweep(t, args.graph_steps, want_ll=False)
+        torch.cuda.synchronize()
+        gwall = time.perf_counter() - g0
+        t += args.graph_steps
+        plan.set_graph(False)
+        res["graph"] = dict(steps=args.graph_steps, ms_per_step=gwall * 1e3 / args.graph_steps,
+                            tokens_per_s=N * args.graph_steps / gwall)
+        log(f"graph replay: {res['graph']}")
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         res["cpu_baseline"] = cpu_baseline(corpus, args.seed, args.cpu_docs)
@@ -391,7 +620,7 @@ def main():
         log(f"heldout {res['heldout']['polya_urn']}")
     if args.alg1_sweeps > 0:
         log(f"Algorithm 1 (Dirichlet Phi-step): {args.alg1_sweeps} sweeps")
-        res["alg1"] = alg1_bench(plan, t + args.steps, N, args.alg1_sweeps)
+        res["alg1"] = alg1_bench(plan, t, N, args.alg1_sweeps)
         if "zstep" in res:
             res["alg1"]["phi_speedup_polya_urn"] = res["alg1"]["phi_ms"] / res["zstep"]["phi_ms"]
             res["alg1"]["z_speedup_polya_urn"] = res["alg1"]["z_ms"] / res["zstep"]["kernel_ms"]

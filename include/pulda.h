@@ -258,6 +258,10 @@ typedef struct {
      * how many of each */
     double ms_phi, ms_z, ms_ll;
     int64_t n_phi, n_z, n_ll;
+    /* sum_J over the tokens whose b-terms were computed: a token whose
+     * a-part is certain from sigma_a and a bound on sigma_b (decided when it
+     * is staged) counts in sum_J but not here */
+    int64_t sum_J_b;
 } pulda_sweep_stats;
 
 /* Read (and restart) the counters above.  Synchronises. */

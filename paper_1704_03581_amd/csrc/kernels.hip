@@ -909,9 +909,11 @@ struct ZCount {
 };
 
 // the z-step's draw statistics of the current document (group-uniform,
-// 32-bit), added to the wave's 64-bit totals in LDS when the document is done
+// 32-bit), added to the wave's 64-bit totals in LDS when the document is
+// done: sum of J, the same over the tokens whose b-terms were computed (not
+// decided at staging), a-part draws, degenerate tokens
 struct ZCount32 {
-    uint32_t j, a, deg;
+    uint32_t j, jb, a, deg;
 };
 
 // b-terms per lane kept in registers for the walk: one gather round covers
@@ -1554,7 +1556,9 @@ __device__ __forceinline__ int32_t draw_token_f32(const DevModel &M, const Token
         return -1 - kold;
     }
     const int32_t Kd = S.L - (mo == 1 ? 1 : 0);
-    cnt.j += (uint32_t)(Kd < Kv ? Kd : Kv);
+    const uint32_t jt = (uint32_t)(Kd < Kv ? Kd : Kv);
+    cnt.j += jt;
+    cnt.jb += tk.sure ? 0u : jt;
     int32_t knew = -1;
     if (__builtin_amdgcn_ballot_w64(tk.sure == 0) != 0) {
         const bool prefer_doc = Kd == 0 || (uint32_t)Kv > __umul24((uint32_t)side_ratio, (uint32_t)Kd);
@@ -1733,7 +1737,7 @@ __device__ void z_step_item(const ZArgs &a, const WorkItem &w, const float *R, u
             continue;
         }
         load_doc_counts<G, CT>(S, a.c.z, s, e, g, M.K, a.m_bytes / 4);
-        ZCount32 cnt = {0, 0, 0};
+        ZCount32 cnt = {0, 0, 0, 0};
         for (int64_t i0 = s; i0 < e; i0 += G) {
             const int64_t i = i0 + g;
             const bool valid = i < e;
@@ -1794,6 +1798,7 @@ __device__ void z_step_item(const ZArgs &a, const WorkItem &w, const float *R, u
             atomicAdd(&wave_cnt[0], (unsigned long long)cnt.j);
             atomicAdd(&wave_cnt[1], (unsigned long long)cnt.a);
             atomicAdd(&wave_cnt[2], (unsigned long long)cnt.deg);
+            atomicAdd(&wave_cnt[3], (unsigned long long)cnt.jb);
         }
         if (a.ll_doc) {
             // the document's term of log p(z | alpha) for its final counts:
@@ -1827,9 +1832,10 @@ __global__ void __launch_bounds__(256, (G == 8 ? 2 : 5)) z_step_kernel(ZArgs a)
     uint8_t *blk = z_lds + a.r_bytes;
     uint8_t *wave_base = blk + wave * a.wave_bytes;
     TokenZ *wave_tok = (TokenZ *)(blk + 4 * a.wave_bytes) + wave * 64;
-    // the wave's statistics: sum of J, a-part draws, degenerate tokens
-    unsigned long long *wave_cnt = (unsigned long long *)(blk + 4 * a.wave_bytes + 4 * 64 * sizeof(TokenIn)) + 4 * wave;
-    if (__lane_id() < 3) wave_cnt[__lane_id()] = 0ull;
+    // the wave's statistics: sum of J, a-part draws, degenerate tokens, sum
+    // of J over the tokens whose b-terms were computed
+    unsigned long long *wave_cnt = (unsigned long long *)(blk + 4 * a.wave_bytes + 4 * 64 * sizeof(TokenZ)) + 4 * wave;
+    if (__lane_id() < 4) wave_cnt[__lane_id()] = 0ull;
     __builtin_amdgcn_wave_barrier();
     while (true) {
         int item = 0;
@@ -1843,9 +1849,10 @@ __global__ void __launch_bounds__(256, (G == 8 ? 2 : 5)) z_step_kernel(ZArgs a)
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    if (a.stats && __lane_id() < 3) {
+    if (a.stats && __lane_id() < 4) {
         const unsigned long long v = wave_cnt[__lane_id()];
-        const int idx = __lane_id() == 0 ? ST_SUM_J : (__lane_id() == 1 ? ST_SUM_A : ST_DEGENERATE);
+        const int l = __lane_id();
+        const int idx = l == 0 ? ST_SUM_J : (l == 1 ? ST_SUM_A : (l == 2 ? ST_DEGENERATE : ST_SUM_JB));
         if (v) atomicAdd(&a.stats[idx], v);
     }
 }
@@ -2058,7 +2065,10 @@ __global__ void __launch_bounds__(64) z_lane_kernel(ZArgs a)
         }
     }
     if (a.stats) {
-        if (cnt.J) atomicAdd(&a.stats[ST_SUM_J], (unsigned long long)cnt.J);
+        if (cnt.J) {
+            atomicAdd(&a.stats[ST_SUM_J], (unsigned long long)cnt.J);
+            atomicAdd(&a.stats[ST_SUM_JB], (unsigned long long)cnt.J);
+        }
         if (cnt.A) atomicAdd(&a.stats[ST_SUM_A], (unsigned long long)cnt.A);
         if (cnt.degenerate) atomicAdd(&a.stats[ST_DEGENERATE], (unsigned long long)cnt.degenerate);
     }

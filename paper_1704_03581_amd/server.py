@@ -40,6 +40,23 @@ class ServeReport:
     def percentile_ms(self, q: float) -> float:
         return float(np.percentile(self.latency_s, q) * 1e3) if len(self.latency_s) else 0.0
 
+    def arrival_window(self, arrivals, lo: float = 0.1, hi: float = 0.9):
+        """Open-loop steady state: the requests arriving between the lo and
+        hi quantiles of the arrival times.  Returns (delivered docs/s over
+        that window: completions inside it per second, p50 ms, p99 ms of
+        the requests arriving inside it)."""
+        arr = np.asarray(arrivals, dtype=np.float64)
+        n = len(arr)
+        if n < 10:
+            return self.docs_per_s, self.percentile_ms(50), self.percentile_ms(99)
+        t_a, t_b = arr[int(lo * n)], arr[int(hi * n) - 1]
+        done = self.completion_s
+        delivered = float(((done >= t_a) & (done <= t_b)).sum()) / (t_b - t_a) if t_b > t_a else float("inf")
+        inside = (arr >= t_a) & (arr <= t_b)
+        lat = self.latency_s[inside]
+        return (delivered, float(np.percentile(lat, 50) * 1e3) if len(lat) else 0.0,
+                float(np.percentile(lat, 99) * 1e3) if len(lat) else 0.0)
+
     def steady_docs_per_s(self, lo: float = 0.1, hi: float = 0.9) -> float:
         """Completions per second between the lo and hi quantiles of the
         completion times: the service rate with the start-up and the drain

@@ -137,6 +137,8 @@ def test_z_step_replay(name, group, side):
     assert st["degenerate_tokens"] == deg
     if r["ties"] == 0:
         assert st["sum_J"] == sumJ and st["sum_A"] == sumA
+    # b-terms computed: every token's but those decided at staging
+    assert 0 <= st["sum_J_b"] <= st["sum_J"]
 
 
 @pytest.mark.parametrize("name", list(CASES))
