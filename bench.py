@@ -280,7 +280,7 @@ def ksweep_study(args, torch, pulda, synth):
         base = synth.generate("large", keep_true_z=False)
     small = synth.restrict(base, doc_fraction=0.125)
     rows = []
-    for K in (10, 100, 1000):
+    for K in args.ks:
         plan = pulda.Plan(K, base.V, base.D, base.N, alpha=base.alpha, beta=base.beta, seed=args.seed)
         plan.upload(base.doc_off, base.words)
         plan.init()
@@ -447,6 +447,7 @@ def main():
     ap.add_argument("--ksweep", action="store_true",
                     help="run only the K = 10, 100, 1000 comparison of both Phi-steps with log-joint traces")
     ap.add_argument("--trace-sweeps", type=int, default=200, help="sweeps of each log-joint trace in --ksweep")
+    ap.add_argument("--ks", type=int, nargs="*", default=[10, 100, 1000], help="topic counts of --ksweep")
     ap.add_argument("--converged", action="store_true",
                     help="run only the 1000-sweep large run (sweeps 1-10 and 901-1000 timed) and fold-in serving "
                          "on its Phi")

@@ -277,7 +277,8 @@ pulda_status pulda_set_timing(pulda_plan *plan, int32_t enable);
  * group[b] lanes (1, 8, 16, 32 or 64) with docs_per_item[b] documents per
  * work item (a multiple of 64 / group).  Group 1 runs one document per lane
  * (its b-sum is the sequential ascending sum) and takes documents shorter
- * than 128 tokens; groups of 8 take documents shorter than 256 tokens; a
+ * than 128 tokens (256 when K <= 127); groups of 8 take documents shorter than 256
+ * tokens; a
  * work item whose group would not fit runs on a larger group size.  A token's b-terms (Section 3.5) are summed
  * over the word's Phi column or over the document's topics; a group prefers
  * the column when K_v <= side_ratio[b] * K_d (side_ratio NULL: all 1, the

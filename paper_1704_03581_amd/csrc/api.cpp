@@ -496,7 +496,9 @@ static hipError_t phase_event(pulda_plan *p, hipStream_t s, size_t *idx)
 // than 128 tokens (longest is the work item's longest document)
 static bool class_fits(int32_t g, bool narrow, int32_t K, int32_t longest)
 {
-    if (g == 1) return longest < 128;
+    // one document per lane: a list of at most 127 topics with 8-bit
+    // counts (every list fits when K <= 127; a count stays below 256)
+    if (g == 1) return longest < 128 || (K <= 127 && longest < 256);
     if (g == 8 && !narrow) return false;
     return z_layout(g, narrow, K).wave_bytes + 64 * 32 <= 32 * 1024;
 }

@@ -46,11 +46,21 @@ def _ragged(seed=3):
                         np.concatenate(words).astype(np.int32), None)
 
 
+def _lane_wide(seed=6):
+    """K=100 with every document between 128 and 255 tokens: at K <= 127 the
+    one-document-per-lane class takes such documents too."""
+    c = synth.small_random(D=192, V=800, K=100, mean_len=190.0, seed=seed)
+    lens = c.lengths()
+    assert lens.min() >= 128 and lens.max() <= 255, (lens.min(), lens.max())
+    return c
+
+
 CASES = {
     "tiny": lambda: synth.generate("tiny", keep_true_z=False),
     "k100": lambda: synth.small_random(D=120, V=800, K=100, mean_len=220.0, seed=4),
     "k1000": lambda: synth.small_random(D=50, V=3000, K=1000, mean_len=500.0, seed=5),
     "ragged": _ragged,
+    "k100_lane": _lane_wide,
 }
 _cache = {}
 
