@@ -1685,7 +1685,8 @@ __device__ __forceinline__ void stage_token(const DevModel &M, TokenIn *tok, int
 // rounded to fp32 (a relative error below 6 2^-24 each), so a token so
 // decided has x < sigma_a (1 - 10 2^-24) exactly, far outside any rounding
 // of the sums (the fp64 and exact decisions agree)
-__device__ __forceinline__ void stage_token_z(const DevModel &M, TokenZ *tok, int g, int32_t v, int32_t kold,
+// (returns the token's sure flag)
+__device__ __forceinline__ bool stage_token_z(const DevModel &M, TokenZ *tok, int g, int32_t v, int32_t kold,
                                               const r4 &r, const int32_t nd)
 {
     const uint4 rec = M.wrec[v];
@@ -1713,6 +1714,7 @@ __device__ __forceinline__ void stage_token_z(const DevModel &M, TokenZ *tok, in
     }
     x.sure = sure ? 1 : 0;
     tok[g] = x;
+    return sure;
 }
 
 template <int G, typename CT>
@@ -1742,14 +1744,18 @@ __device__ void z_step_item(const ZArgs &a, const WorkItem &w, const float *R, u
             const int64_t i = i0 + g;
             const bool valid = i < e;
             int32_t zo = 0, wv = 0;
+            bool sure = false;
             if (valid) {
                 // the token stream is read once per sweep: non-temporal, so
                 // it does not displace the tables the draws reuse
                 wv = __builtin_nontemporal_load(a.c.words + i);
                 zo = __builtin_nontemporal_load(a.c.z + i);
                 const r4 r = philox((uint32_t)i, (uint32_t)((uint64_t)i >> 32), t, TAG_Z, M.key0, M.key1);
-                stage_token_z(M, tok, g, wv, zo, r, (int32_t)(e - s));
+                sure = stage_token_z(M, tok, g, wv, zo, r, (int32_t)(e - s));
             }
+            // bit j: the group's token j was decided at staging (the cursor
+            // tests it in a register instead of reading LDS)
+            const auto sure_bits = (typename std::conditional<(G > 32), uint64_t, uint32_t>::type)group_ballot<G>(sure);
             __builtin_amdgcn_wave_barrier();
             int32_t znew = zo;
             const int nb = (int)((e - i0) < G ? (e - i0) : G);
@@ -1770,7 +1776,7 @@ __device__ void z_step_item(const ZArgs &a, const WorkItem &w, const float *R, u
             } else {
             int cur = 0;
             while (true) {
-                while (cur < nb && tok[cur].sure) {
+                while (cur < nb && ((sure_bits >> cur) & 1u)) {
                     const TokenZ tk = tok[cur];
                     const int32_t k = move_token<G, CT>(tk, S, g, cnt);
                     if (g == cur) znew = k;
