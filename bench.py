@@ -148,6 +148,7 @@ def foldin_bench(args, torch, pulda, synth, model=None, phi_source=None):
     out = dict(phi=phi_source, service_rate_docs_per_s=xmax, closed_loop_docs_per_s=rep.docs_per_s,
                closed_loop_p50_ms=rep.percentile_ms(50), closed_loop_p99_ms=rep.percentile_ms(99),
                closed_loop_requests=nb, mean_len=float(lens[:n_trace].mean()),
+               closed_loop_steps=rep.steps, closed_loop_ms_per_step=1e3 * rep.wall_s / max(rep.steps, 1),
                sweeps=50, burn_in=25, slots=args.slots, draws_per_step=args.draws, trace_s=args.trace_s,
                rates={})
     sustained = 0.0
@@ -162,7 +163,8 @@ def foldin_bench(args, torch, pulda, synth, model=None, phi_source=None):
         delivered, p50, p99 = rep.arrival_window(arr)
         out["rates"][f"{frac:.2f}"] = dict(offered_docs_per_s=rate, requests=n_req, arrival_s=float(arr[-1]),
                                            delivered_docs_per_s=delivered, p50_ms=p50, p99_ms=p99,
-                                           whole_run_docs_per_s=rep.docs_per_s, max_resident=rep.max_resident)
+                                           whole_run_docs_per_s=rep.docs_per_s, max_resident=rep.max_resident,
+                                           steps=rep.steps, ms_per_step=1e3 * rep.wall_s / max(rep.steps, 1))
         if delivered >= 0.97 * rate:
             sustained = max(sustained, rate)
         log(f"fold-in: rate {frac:.2f} x -> {out['rates'][f'{frac:.2f}']}")
@@ -183,7 +185,47 @@ def foldin_bench(args, torch, pulda, synth, model=None, phi_source=None):
     out["speedup_vs_plain"] = out["closed_loop_docs_per_s"] / out["plain_docs_per_s"]
     # and the steady service rate against the same plain rate
     out["service_rate_vs_plain"] = xmax / out["plain_docs_per_s"]
+    if args.foldin_cpu_requests > 0 and not args.no_cpu_baseline:
+        # the oracle's fold-in (single-threaded, one pinned core) on the first
+        # of the plain sampler's requests, same Phi, request ids and seed; its
+        # theta must equal the GPU's bit for bit
+        import oracle
+        phi, wt = oracle_tables(model, K, V)
+        a = np.full(K, synth.ALPHA)
+        sub = plain[:args.foldin_cpu_requests]
+        old_aff = os.sched_getaffinity(0) if hasattr(os, "sched_getaffinity") else None
+        try:
+            if old_aff:
+                os.sched_setaffinity(0, {min(old_aff)})
+            t0 = time.perf_counter()
+            same = True
+            for j, wj in enumerate(sub):
+                theta, ll, kept, _, _ = oracle.foldin(phi, wt, a, args.seed, j, wj, S=50, burn_in=25)
+                same &= bool(np.array_equal(theta, rep_p.results[j]["theta"]) and kept == rep_p.results[j]["kept"])
+            dto = time.perf_counter() - t0
+        finally:
+            if old_aff:
+                os.sched_setaffinity(0, old_aff)
+        draws = 50 * sum(len(w) for w in sub)
+        out["cpu_baseline"] = dict(kind="oracle", cores=1, requests=len(sub), docs_per_s=len(sub) / dto,
+                                   token_draws_per_s=draws / dto, seconds=dto, theta_equal_gpu=same)
     return out
+
+
+def oracle_tables(plan, K, V):
+    """The plan's current Phi as the oracle takes it: dense fp32 phi (K x V)
+    and the per-word tables (CSC, alias tables, sigma_a), read back from the
+    GPU."""
+    import oracle
+    g = plan.get_phi()
+    colptr = g["colptr"].astype(np.int64)
+    cols = np.repeat(np.arange(V), np.diff(colptr))
+    phi = np.zeros((K, V), np.float32)
+    phi[g["topic"].astype(np.int64), cols] = g["phi"]
+    wt = oracle.WordTables(colptr, g["topic"].astype(np.uint16), g["phi"].astype(np.float32),
+                           g["alias_thr"].astype(np.uint32), g["alias_topic"].astype(np.uint16),
+                           g["sigma_a"].astype(np.float64))
+    return phi, wt
 
 
 def heldout_bench(plan, docs, particles, seed, torch, oracle_docs=0, K=0, V=0, alpha=0.0):
@@ -203,15 +245,7 @@ def heldout_bench(plan, docs, particles, seed, torch, oracle_docs=0, K=0, V=0, a
     if oracle_docs:
         # the oracle (single-threaded) on the first few documents, same Phi
         import oracle
-        g = plan.get_phi()
-        colptr = g["colptr"].astype(np.int64)
-        cols = np.repeat(np.arange(V), np.diff(colptr))
-        phi = np.zeros((K, V), np.float32)
-        phi[g["topic"].astype(np.int64), cols] = g["phi"]
-        wt = oracle.WordTables(colptr, g["topic"].astype(np.uint16), g["phi"].astype(np.float32),
-                               g["alias_thr"].astype(np.uint32), g["alias_topic"].astype(np.uint16),
-                               g["sigma_a"].astype(np.float64))
-        del g
+        phi, wt = oracle_tables(plan, K, V)
         a = np.full(K, alpha)
         sub = docs[:oracle_docs]
         t0 = time.perf_counter()
@@ -453,11 +487,13 @@ def main():
                          "on its Phi")
     ap.add_argument("--alg1-sweeps", type=int, default=3,
                     help="sweeps with Algorithm 1's Dirichlet Phi-step after the timed region (0: none)")
-    ap.add_argument("--foldin-requests", type=int, default=300000,
+    ap.add_argument("--foldin-requests", type=int, default=450000,
                     help="requests drawn for the fold-in traces (open-loop traces use what trace_s needs)")
     ap.add_argument("--closed-requests", type=int, default=12000, help="requests of the closed-loop run")
     ap.add_argument("--trace-s", type=float, default=10.0, help="seconds of Poisson arrivals per rate point")
     ap.add_argument("--plain-requests", type=int, default=60)
+    ap.add_argument("--foldin-cpu-requests", type=int, default=40,
+                    help="requests of the oracle's fold-in baseline (0: none)")
     ap.add_argument("--slots", type=int, default=4096)
     ap.add_argument("--draws", type=int, default=2048, help="fold-in token draws per request per step")
     ap.add_argument("--rates", type=float, nargs="*", default=[0.5, 0.8, 0.95])

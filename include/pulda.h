@@ -370,9 +370,23 @@ pulda_status pulda_foldin_step(pulda_foldin *f, int32_t draws, void *stream);
 
 /* Collect finished requests (at most cap): results into out[], theta into
  * theta_host[cap * K] (row j for out[j]); frees their slots.  Reads the
- * requests' progress from the device.  Synchronises. */
+ * requests' progress from the device after every step launched on `stream`.
+ * Synchronises the stream. */
 pulda_status pulda_foldin_poll(pulda_foldin *f, pulda_foldin_result *out, float *theta_host, int32_t cap,
                                int32_t *n_done, void *stream);
+
+/* As pulda_foldin_poll, for the requests finished by the step before the
+ * latest pulda_foldin_step: the copies run on the server's own stream behind
+ * that step only, so the latest step keeps running meanwhile.  A serving
+ * loop that launches step s, then collects step s-1's results and admits new
+ * requests while step s runs keeps the GPU busy through its own host work.
+ * Step s skips the requests that finished before it (their results stay as
+ * written), and a request finished by step s is collected by the poll after
+ * step s+1 (one more step, of no work for it, may be needed at the end).
+ * Nothing to collect before the second step.  Synchronises the server's
+ * stream only. */
+pulda_status pulda_foldin_poll_previous(pulda_foldin *f, pulda_foldin_result *out, float *theta_host, int32_t cap,
+                                        int32_t *n_done);
 
 /* Resident and free slot counts. */
 pulda_status pulda_foldin_occupancy(const pulda_foldin *f, int32_t *resident, int32_t *free_slots,

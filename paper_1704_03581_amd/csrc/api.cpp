@@ -205,7 +205,7 @@ struct pulda_foldin {
     pulda_foldin_desc desc{};
     int64_t ws_need = 0;
     struct {
-        int64_t slots, kept, prog, words, pos, z, acc, theta, ll, active;
+        int64_t slots, kept, prog, words, pos, z, acc, theta, ll, fin, active;
     } off;
     uint8_t *ws = nullptr;
     DevFoldin f{};
@@ -215,12 +215,20 @@ struct pulda_foldin {
     std::vector<FoldSlot> slots;      // control mirror
     std::vector<int32_t> resident;    // 1 if the slot holds a request
     std::vector<int32_t> finished;    // 1 if its last sweep is known done (not yet collected)
+    std::vector<int64_t> first_step;  // the step that took the occupant first (-1: none yet)
     std::vector<std::pair<int32_t, int32_t>> free_blocks;  // arena [off, len), by offset
     int32_t free_tokens = 0;
+    int64_t n_steps = 0;              // steps launched
+    // behind each step launch, an event (by step parity), and the stream on
+    // which pulda_foldin_poll_previous reads results while the latest step
+    // still runs
+    hipEvent_t step_ev[2] = {nullptr, nullptr};
+    hipStream_t cstream = nullptr;
     // pinned host staging for the host-to-device copies, so that a copy
     // never reads caller or library memory after the call returns:
     // stage_words mirrors the arena (a region is rewritten only after its
-    // request was polled, which waits for the stream), and the slot table
+    // request was polled, which waits for a step that ran after the region's
+    // copy), and the slot table
     // and active list alternate between two buffers, each reused only after
     // the event recorded behind its previous copy
     int32_t *stage_words = nullptr;
@@ -234,7 +242,9 @@ struct pulda_foldin {
         for (int b = 0; b < 2; ++b) {
             if (stage_ctl[b]) (void)hipHostFree(stage_ctl[b]);
             if (stage_ev[b]) (void)hipEventDestroy(stage_ev[b]);
+            if (step_ev[b]) (void)hipEventDestroy(step_ev[b]);
         }
+        if (cstream) (void)hipStreamDestroy(cstream);
     }
 };
 
@@ -1164,11 +1174,13 @@ pulda_status pulda_foldin_create(const pulda_plan *model, const pulda_foldin_des
     f->off.acc = L.take(S * K * 4);
     f->off.theta = L.take(S * K * 4);
     f->off.ll = L.take(S * 8);
+    f->off.fin = L.take(S * 8);
     f->off.active = L.take(S * 4);
     f->ws_need = L.total;
     f->slots.assign(S, FoldSlot{});
     f->resident.assign(S, 0);
     f->finished.assign(S, 0);
+    f->first_step.assign(S, -1);
     f->free_blocks = {{0, (int32_t)T}};
     f->free_tokens = (int32_t)T;
     *out = f;
@@ -1202,7 +1214,9 @@ pulda_status pulda_foldin_bind(pulda_foldin *f, void *ws, int64_t bytes)
                 return fail(PULDA_ERR_NO_MEMORY, "pinned host staging of %zu slots", S);
             }
             HIP_TRY(hipEventCreateWithFlags(&f->stage_ev[b], hipEventDisableTiming));
+            HIP_TRY(hipEventCreateWithFlags(&f->step_ev[b], hipEventDisableTiming));
         }
+        HIP_TRY(hipStreamCreateWithFlags(&f->cstream, hipStreamNonBlocking));
     }
     uint8_t *w = (uint8_t *)ws;
     f->ws = w;
@@ -1224,6 +1238,7 @@ pulda_status pulda_foldin_bind(pulda_foldin *f, void *ws, int64_t bytes)
     F.acc = (uint32_t *)(w + f->off.acc);
     F.theta = (float *)(w + f->off.theta);
     F.ll = (double *)(w + f->off.ll);
+    F.fin = (int64_t *)(w + f->off.fin);
     return PULDA_OK;
 }
 
@@ -1296,6 +1311,7 @@ pulda_status pulda_foldin_submit(pulda_foldin *f, uint32_t req, const int32_t *w
     sl.budget = 0;
     f->resident[sid] = 1;
     f->finished[sid] = 0;
+    f->first_step[sid] = -1;
     return PULDA_OK;
 }
 
@@ -1310,11 +1326,13 @@ pulda_status pulda_foldin_step(pulda_foldin *f, int32_t draws, void *stream)
     FoldSlot *slots_pin = (FoldSlot *)f->stage_ctl[b];
     int32_t *active = (int32_t *)(f->stage_ctl[b] + (size_t)S * sizeof(FoldSlot));
     int32_t n_active = 0;
+    const int64_t step_no = f->n_steps + 1;
     for (int32_t i = 0; i < S; ++i) {
         FoldSlot &sl = f->slots[i];
         if (f->resident[i] && !f->finished[i]) {
             sl.budget = draws;
             active[n_active++] = i;
+            if (sl.fresh) f->first_step[i] = step_no;
         } else {
             sl.budget = 0;
         }
@@ -1326,11 +1344,60 @@ pulda_status pulda_foldin_step(pulda_foldin *f, int32_t draws, void *stream)
     HIP_TRY(hipEventRecord(f->stage_ev[b], s));
     f->stage_used[b] = true;
     f->stage_cur = b ^ 1;
+    f->f.step_no = step_no;
     HIP_TRY(launch_foldin_step(f->model->m, f->f, f->active_dev, n_active, s));
+    f->n_steps = step_no;
+    HIP_TRY(hipEventRecord(f->step_ev[step_no & 1], s));
     for (int32_t j = 0; j < n_active; ++j) {
         f->slots[active[j]].fresh = 0;
         f->slots[active[j]].budget = 0;
     }
+    return PULDA_OK;
+}
+
+// the requests finished by step `limit` (every step up to it complete on
+// stream s): their results, up to cap of them, and their slots freed
+static pulda_status foldin_collect(pulda_foldin *f, int64_t limit, hipStream_t s, pulda_foldin_result *out,
+                                   float *theta, int32_t cap, int32_t *n_done)
+{
+    const int32_t K = f->model->K, S = f->desc.max_slots;
+    *n_done = 0;
+    bool any = false;
+    for (int32_t i = 0; i < S; ++i) any |= f->resident[i] && f->first_step[i] > 0 && f->first_step[i] <= limit;
+    if (!any) return PULDA_OK;
+    // a slot's fin is the step that wrote its theta and log-likelihood;
+    // steps after `limit` may be running, so later values are not yet safe
+    std::vector<int64_t> fin(S);
+    std::vector<int32_t> kept(2 * S);
+    std::vector<double> ll(S);
+    HIP_TRY(hipMemcpyAsync(fin.data(), f->f.fin, fin.size() * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(kept.data(), f->f.kept, kept.size() * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(ll.data(), f->f.ll, ll.size() * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    std::vector<int32_t> done;
+    for (int32_t i = 0; i < S; ++i) {
+        if (!f->resident[i] || f->first_step[i] < 1 || f->first_step[i] > limit) continue;
+        if (fin[i] < f->first_step[i] || fin[i] > limit) continue;
+        f->finished[i] = 1;
+        if ((int32_t)done.size() < cap) done.push_back(i);
+    }
+    if (done.empty()) return PULDA_OK;
+    for (size_t j = 0; j < done.size(); ++j)
+        HIP_TRY(hipMemcpyAsync(theta + j * K, f->f.theta + (int64_t)done[j] * K, K * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (size_t j = 0; j < done.size(); ++j) {
+        const int32_t i = done[j];
+        out[j].request_id = f->slots[i].req;
+        out[j].kept = kept[2 * i];
+        out[j].dropped = kept[2 * i + 1];
+        out[j].pad = 0;
+        out[j].loglik = ll[i];
+        f->resident[i] = 0;
+        f->finished[i] = 0;
+        f->first_step[i] = -1;
+        arena_free(f, f->slots[i].arena_off, f->slots[i].len);
+    }
+    *n_done = (int32_t)done.size();
     return PULDA_OK;
 }
 
@@ -1339,42 +1406,22 @@ pulda_status pulda_foldin_poll(pulda_foldin *f, pulda_foldin_result *out, float 
 {
     if (!f || !n_done || (cap > 0 && (!out || !theta))) return fail(PULDA_ERR_INVALID_ARG, "null argument");
     if (!f->ws) return fail(PULDA_ERR_STATE, "no workspace bound");
-    hipStream_t s = (hipStream_t)stream;
-    const int32_t K = f->model->K, S = f->desc.max_slots;
+    // (the copies queue behind every step launched on the stream)
+    return foldin_collect(f, f->n_steps, (hipStream_t)stream, out, theta, cap, n_done);
+}
+
+pulda_status pulda_foldin_poll_previous(pulda_foldin *f, pulda_foldin_result *out, float *theta, int32_t cap,
+                                        int32_t *n_done)
+{
+    if (!f || !n_done || (cap > 0 && (!out || !theta))) return fail(PULDA_ERR_INVALID_ARG, "null argument");
+    if (!f->ws) return fail(PULDA_ERR_STATE, "no workspace bound");
     *n_done = 0;
-    bool any = false;
-    for (int32_t i = 0; i < S; ++i) any |= f->resident[i] && !f->slots[i].fresh;
-    if (!any) return PULDA_OK;
-    // progress is kept on the device: read it with the results
-    std::vector<int32_t> prog(2 * S), kept(2 * S);
-    std::vector<double> ll(S);
-    HIP_TRY(hipMemcpyAsync(prog.data(), f->f.prog, prog.size() * 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(kept.data(), f->f.kept, kept.size() * 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(ll.data(), f->f.ll, ll.size() * 8, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    std::vector<int32_t> fin;
-    for (int32_t i = 0; i < S; ++i) {
-        if (!f->resident[i] || f->slots[i].fresh || prog[2 * i] < f->desc.sweeps) continue;
-        f->finished[i] = 1;
-        if ((int32_t)fin.size() < cap) fin.push_back(i);
-    }
-    if (fin.empty()) return PULDA_OK;
-    for (size_t j = 0; j < fin.size(); ++j)
-        HIP_TRY(hipMemcpyAsync(theta + j * K, f->f.theta + (int64_t)fin[j] * K, K * 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    for (size_t j = 0; j < fin.size(); ++j) {
-        const int32_t i = fin[j];
-        out[j].request_id = f->slots[i].req;
-        out[j].kept = kept[2 * i];
-        out[j].dropped = kept[2 * i + 1];
-        out[j].pad = 0;
-        out[j].loglik = ll[i];
-        f->resident[i] = 0;
-        f->finished[i] = 0;
-        arena_free(f, f->slots[i].arena_off, f->slots[i].len);
-    }
-    *n_done = (int32_t)fin.size();
-    return PULDA_OK;
+    const int64_t limit = f->n_steps - 1;
+    if (limit < 1) return PULDA_OK;
+    // the library's copy stream waits for step `limit` only; the latest step
+    // keeps running (it skips the requests finished before it)
+    HIP_TRY(hipStreamWaitEvent(f->cstream, f->step_ev[limit & 1], 0));
+    return foldin_collect(f, limit, f->cstream, out, theta, cap, n_done);
 }
 
 pulda_status pulda_foldin_occupancy(const pulda_foldin *f, int32_t *resident, int32_t *free_slots,

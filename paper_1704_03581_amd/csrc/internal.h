@@ -189,6 +189,9 @@ struct DevFoldin {
     uint32_t *acc;          // [max_slots*K]
     float *theta;           // [max_slots*K]
     double *ll;             // [max_slots]
+    int64_t *fin;           // [max_slots] the step that finished the request
+                            // (written after theta and ll; 0 until then)
+    int64_t step_no;        // this launch's step number (from 1)
 };
 
 hipError_t launch_foldin_step(const DevModel &m, const DevFoldin &f, const int32_t *active, int32_t n_active,

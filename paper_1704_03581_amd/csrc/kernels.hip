@@ -2575,12 +2575,16 @@ __device__ void foldin_slot(const DevModel &M, const DevFoldin &F, int32_t sid, 
         if (g == 0) {
             F.kept[2 * sid] = kept;
             F.kept[2 * sid + 1] = sl.len - kept;
+            F.fin[sid] = 0;
         }
         __threadfence();
     } else {
         kept = F.kept[2 * sid];
         done = F.prog[2 * sid];
         next = F.prog[2 * sid + 1];
+        // finished in an earlier step (a step launched before the host
+        // collected it): its results stay as they are
+        if (done >= F.sweeps) return;
     }
     load_doc_counts<G, uint16_t>(S, zz, 0, kept, g, K, Kp / 2);
     ZCount st = {0, 0, 0, 0, 0};
@@ -2643,6 +2647,10 @@ __device__ void foldin_slot(const DevModel &M, const DevFoldin &F, int32_t sid, 
         }
         const double tot = group_bcast_f64<G>(group_scan_incl<G>(part), G - 1);
         if (g == 0) F.ll[sid] = tot + M.lg_A[kept];
+        // the step number last, once theta and ll are written (the group is
+        // one wave: the fence orders every lane's writes before it)
+        __threadfence();
+        if (g == 0) F.fin[sid] = F.step_no;
     }
 }
 

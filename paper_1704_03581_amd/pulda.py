@@ -107,6 +107,7 @@ _SIGS = {
     "pulda_foldin_submit": [vp, u32, vp, i32, vp],
     "pulda_foldin_step": [vp, i32, vp],
     "pulda_foldin_poll": [vp, C.POINTER(FoldinResult), vp, i32, C.POINTER(i32), vp],
+    "pulda_foldin_poll_previous": [vp, C.POINTER(FoldinResult), vp, i32, C.POINTER(i32)],
     "pulda_foldin_occupancy": [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)],
     "pulda_foldin_run_one": [vp, u32, vp, i32, vp, C.POINTER(FoldinResult), vp],
 }
@@ -444,7 +445,9 @@ class FoldIn:
         """Advance every resident request by up to `draws` token draws."""
         _check(_lib.pulda_foldin_step(self._h, draws, _stream(stream)))
 
-    def poll(self, cap: int = 4096, stream=None):
+    def poll(self, cap: int = 4096, stream=None, previous: bool = False):
+        """Finished requests.  previous: those finished by the step before the
+        latest (pulda_foldin_poll_previous: the latest step keeps running)."""
         # result buffers are reused across polls
         if getattr(self, "_poll_cap", 0) < cap:
             self._poll_res = (FoldinResult * cap)()
@@ -452,7 +455,11 @@ class FoldIn:
             self._poll_cap = cap
         res, theta = self._poll_res, self._poll_theta
         n = i32()
-        _check(_lib.pulda_foldin_poll(self._h, res, theta.ctypes.data_as(vp), cap, C.byref(n), _stream(stream)))
+        if previous:
+            _check(_lib.pulda_foldin_poll_previous(self._h, res, theta.ctypes.data_as(vp), cap, C.byref(n)))
+        else:
+            _check(_lib.pulda_foldin_poll(self._h, res, theta.ctypes.data_as(vp), cap, C.byref(n),
+                                          _stream(stream)))
         out = []
         for j in range(n.value):
             r = res[j]

@@ -9,6 +9,10 @@ the previous step stopped, so long and short requests take the same time per
 step), collects the finished ones and admits more: requests that arrive
 while others are on the GPU join the running batch.
 
+Pipelined (the default): after launching step s the loop collects the
+requests finished by step s-1 and admits new ones while step s runs, so the
+host's work overlaps the GPU's instead of leaving it idle between steps.
+
 The loop drives any backend with the FoldIn interface (submit / step / poll /
 occupancy), so its bookkeeping is testable without a GPU.
 """
@@ -71,12 +75,15 @@ class ServeReport:
 
 def serve(backend, requests: Sequence[np.ndarray], arrivals: Optional[Sequence[float]] = None,
           draws: int = 2048, clock: Callable[[], float] = time.perf_counter,
-          sleep: Callable[[float], None] = time.sleep, max_poll: int = 4096) -> ServeReport:
+          sleep: Callable[[float], None] = time.sleep, max_poll: int = 4096,
+          pipelined: bool = True) -> ServeReport:
     """Serve requests[i] arriving at arrivals[i] seconds (None: all at 0).
 
     Request ids are the indices into `requests`.  Admission is first come,
     first served: a request that does not fit waits (and blocks those behind
-    it) until a poll frees a slot and arena space.
+    it) until a poll frees a slot and arena space.  pipelined: each step's
+    poll collects the previous step's finished requests (backend.poll with
+    previous=True) while the step runs; otherwise it waits for the step.
     """
     n = len(requests)
     arr = np.zeros(n) if arrivals is None else np.asarray(arrivals, dtype=np.float64)
@@ -110,7 +117,7 @@ def serve(backend, requests: Sequence[np.ndarray], arrivals: Optional[Sequence[f
             continue
         backend.step(draws)
         rep.steps += 1
-        for r in backend.poll(cap=max_poll):
+        for r in (backend.poll(cap=max_poll, previous=True) if pipelined else backend.poll(cap=max_poll)):
             rid = r["request_id"]
             now = clock() - t0
             rep.completion_s[rid] = now

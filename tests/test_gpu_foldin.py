@@ -73,8 +73,11 @@ def test_foldin_alone_equals_in_the_mix(model):
     f = pulda.FoldIn(p, sweeps=10, burn_in=5, max_slots=8, arena_tokens=2000, max_len=400, group=64, seed=33)
     reqs = _requests(c.V, 20, 8)
     alone = {rid: f.run_one(rid, w) for rid, w in enumerate(reqs)}
-    for q in (7, 100, 1000):
-        rep = server.serve(f, reqs, draws=q)
+    # both serving loops: collecting each step's results after it (the poll
+    # waits for the step) and the previous step's while the next one runs
+    for q, pipelined in ((7, True), (100, True), (1000, True), (100, False)):
+        rep = server.serve(f, reqs, draws=q, pipelined=pipelined)
+        assert sorted(rep.results) == list(range(len(reqs)))
         for rid, r in rep.results.items():
             assert np.array_equal(r["theta"], alone[rid]["theta"]) and r["loglik"] == alone[rid]["loglik"]
     _check(alone[0], phi, wt, np.full(c.K, c.alpha), 33, 0, reqs[0], 10, 5)

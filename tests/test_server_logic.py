@@ -27,14 +27,15 @@ class FakeFoldIn:
         self.clock = clock
         self.sweeps, self.burn_in = sweeps, burn_in
         self.max_slots, self.arena_tokens = max_slots, arena_tokens
-        self.res = {}          # rid -> [words, draws done]
+        self.res = {}          # rid -> [words, draws done, step that finished it]
         self.used = 0
         self.submits = []
+        self.steps = 0
 
     def submit(self, rid, words):
         if len(self.res) >= self.max_slots or self.used + max(len(words), 1) > self.arena_tokens:
             return False
-        self.res[rid] = [np.asarray(words), 0]
+        self.res[rid] = [np.asarray(words), 0, None]
         self.used += max(len(words), 1)
         self.submits.append(rid)
         return True
@@ -44,8 +45,12 @@ class FakeFoldIn:
                     free_tokens=self.arena_tokens - self.used)
 
     def step(self, draws):
+        self.steps += 1
         for r in self.res.values():
-            r[1] = min(self.sweeps * len(r[0]), r[1] + draws)
+            if r[2] is None:
+                r[1] = min(self.sweeps * len(r[0]), r[1] + draws)
+                if r[1] >= self.sweeps * len(r[0]):
+                    r[2] = self.steps
         self.clock.t += 1e-3
 
     def _result(self, rid, words):
@@ -53,11 +58,13 @@ class FakeFoldIn:
                                                     S=self.sweeps, burn_in=self.burn_in)
         return dict(request_id=rid, theta=theta, loglik=ll, kept=kept, dropped=dropped)
 
-    def poll(self, cap=4096):
-        done = [rid for rid, r in self.res.items() if r[1] >= self.sweeps * len(r[0])][:cap]
+    def poll(self, cap=4096, previous=False):
+        # previous: what the step before the latest finished (the latest runs on)
+        limit = self.steps - 1 if previous else self.steps
+        done = [rid for rid, r in self.res.items() if r[2] is not None and r[2] <= limit][:cap]
         out = []
         for rid in done:
-            words, _ = self.res.pop(rid)
+            words, _, _ = self.res.pop(rid)
             self.used -= max(len(words), 1)
             out.append(self._result(rid, words))
         return out
@@ -81,12 +88,13 @@ def _requests(n, V, seed):
     return [rng.integers(0, V + 5, size=int(rng.integers(0, 60))).astype(np.int32) for _ in range(n)]
 
 
-def test_all_served_fifo_and_identical_to_alone(model):
+@pytest.mark.parametrize("pipelined", [True, False])
+def test_all_served_fifo_and_identical_to_alone(model, pipelined):
     phi, wt, alpha = model
     reqs = _requests(30, phi.shape[1], 1)
     clk = FakeClock()
     be = FakeFoldIn(phi, wt, alpha, 9, clk)
-    rep = server.serve(be, reqs, arrivals=None, draws=100, clock=clk, sleep=clk.sleep)
+    rep = server.serve(be, reqs, arrivals=None, draws=100, clock=clk, sleep=clk.sleep, pipelined=pipelined)
     assert sorted(rep.results) == list(range(30))
     assert rep.order_admitted == sorted(rep.order_admitted)          # first come, first served
     assert rep.max_resident <= be.max_slots and rep.admission_waits > 0
@@ -132,6 +140,26 @@ def test_open_loop_latency_arithmetic(model):
     assert np.all(rep.latency_s >= need - 1e-12)
     assert rep.percentile_ms(50) <= rep.percentile_ms(99)
     assert abs(rep.percentile_ms(50) - np.percentile(rep.latency_s, 50) * 1e3) < 1e-9
+
+
+def test_pipelined_collects_one_step_later(model):
+    """The pipelined loop collects a request after the step following the
+    one that finished it: the same results, each one step (1 ms) later, and
+    the admissions that the freed slots allow shift by that step too."""
+    phi, wt, alpha = model
+    reqs = _requests(12, phi.shape[1], 6)
+    reps = {}
+    for pipelined in (False, True):
+        clk = FakeClock()
+        be = FakeFoldIn(phi, wt, alpha, 9, clk, max_slots=16, arena_tokens=10000)
+        reps[pipelined] = server.serve(be, reqs, draws=100, clock=clk, sleep=clk.sleep, pipelined=pipelined)
+    a, b = reps[False], reps[True]
+    assert sorted(a.results) == sorted(b.results) == list(range(12))
+    for rid in range(12):
+        assert np.array_equal(a.results[rid]["theta"], b.results[rid]["theta"])
+    # everything fits at once: each completion comes exactly one step later
+    assert np.allclose(b.completion_s - a.completion_s, 1e-3)
+    assert b.steps == a.steps + 1
 
 
 def test_plain_sampler_same_results(model):
