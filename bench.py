@@ -137,7 +137,7 @@ def foldin_bench(args, torch, pulda, synth, model=None, phi_source=None):
     reqs = synth.foldin_requests(max(n_trace, 1) + args.plain_requests, seed=170403581 + 5)
     lens = np.array([len(r) for r in reqs])
     fi = pulda.FoldIn(model, sweeps=50, burn_in=25, max_slots=args.slots, arena_tokens=args.slots * 600,
-                      max_len=5000, group=64, seed=args.seed)
+                      max_len=5000, group=args.foldin_group, seed=args.seed)
     nb = min(args.closed_requests, n_trace)
     batched = reqs[:nb]
     log(f"fold-in: closed loop, {nb} requests")
@@ -149,7 +149,8 @@ def foldin_bench(args, torch, pulda, synth, model=None, phi_source=None):
                closed_loop_p50_ms=rep.percentile_ms(50), closed_loop_p99_ms=rep.percentile_ms(99),
                closed_loop_requests=nb, mean_len=float(lens[:n_trace].mean()),
                closed_loop_steps=rep.steps, closed_loop_ms_per_step=1e3 * rep.wall_s / max(rep.steps, 1),
-               sweeps=50, burn_in=25, slots=args.slots, draws_per_step=args.draws, trace_s=args.trace_s,
+               sweeps=50, burn_in=25, slots=args.slots, draws_per_step=args.draws, group=args.foldin_group,
+               trace_s=args.trace_s,
                rates={})
     sustained = 0.0
     for i, frac in enumerate(args.rates):
@@ -496,6 +497,7 @@ def main():
                     help="requests of the oracle's fold-in baseline (0: none)")
     ap.add_argument("--slots", type=int, default=4096)
     ap.add_argument("--draws", type=int, default=2048, help="fold-in token draws per request per step")
+    ap.add_argument("--foldin-group", type=int, default=64, choices=[16, 32, 64], help="lanes per fold-in request")
     ap.add_argument("--rates", type=float, nargs="*", default=[0.5, 0.8, 0.95])
     ap.add_argument("--corpus-cache", default=None,
                     help=".npz file: load the corpus from it if present, else generate and save it there")

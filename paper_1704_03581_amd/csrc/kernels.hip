@@ -2535,8 +2535,8 @@ hipError_t launch_scan_i64(const int64_t *in, int64_t *out_excl, int64_t n, long
 // final state.
 // ---------------------------------------------------------------------------
 template <int G, bool SYM>
-__device__ void foldin_slot(const DevModel &M, const DevFoldin &F, int32_t sid, const double *R, uint16_t *mt,
-                            TokenIn *tok)
+__device__ void foldin_slot(const DevModel &M, const DevFoldin &F, int32_t sid, const float *Rf, uint16_t *mt,
+                            TokenZ *tok)
 {
     const int32_t Kp = (M.K + 1) & ~1;
     DocState<uint16_t> S;
@@ -2587,7 +2587,7 @@ __device__ void foldin_slot(const DevModel &M, const DevFoldin &F, int32_t sid, 
         if (done >= F.sweeps) return;
     }
     load_doc_counts<G, uint16_t>(S, zz, 0, kept, g, K, Kp / 2);
-    ZCount st = {0, 0, 0, 0, 0};
+    ZCount32 st = {0, 0, 0, 0};
     int32_t budget = sl.budget;
     while (budget > 0 && done < F.sweeps) {
         const int32_t s = done + 1;
@@ -2600,15 +2600,16 @@ __device__ void foldin_slot(const DevModel &M, const DevFoldin &F, int32_t sid, 
                 const int32_t p = pos[q];
                 zo = zz[q];
                 const r4 r = philox((uint32_t)p, sl.req, (uint32_t)s, TAG_FOLDIN_Z, F.key0, F.key1);
-                stage_token(M, tok, g, wds[p], zo, r, kept);
+                stage_token_z(M, tok, g, wds[p], zo, r, kept);
             }
             __builtin_amdgcn_wave_barrier();
             int32_t znew = zo;
             const int nb = (t1 - q0) < G ? (t1 - q0) : G;
+            // the z-step's draw: b-terms in fp32 where a rounding bound proves
+            // the decision, the fp64 b-part elsewhere (the same results)
             for (int jj = 0; jj < nb; ++jj) {
-                const TokenIn tk = tok[jj];
-                double Zo;
-                int32_t k = draw_token<G, uint16_t>(M, tk, S, R, g, 1, st, Zo);
+                const TokenZ tk = tok[jj];
+                int32_t k = draw_token_f32<G, uint16_t>(M, tk, S, Rf, g, 1, st);
                 if (k < 0) k = -1 - k;
                 if (g == jj) znew = k;
             }
@@ -2659,11 +2660,12 @@ __global__ void __launch_bounds__(256) foldin_step_kernel(DevModel M, DevFoldin 
                                                           int32_t n_active, int32_t per_group)
 {
     extern __shared__ __align__(16) uint16_t f_lds[];
-    // the block's copy of R_k, then the groups' tables, then staged tokens
-    double *R = (double *)f_lds;
-    for (int32_t k = threadIdx.x; k < M.K; k += blockDim.x) R[k] = M.Rd[k];
+    // the block's copy of fp32(R_k), then the groups' tables, then staged
+    // tokens
+    float *R = (float *)f_lds;
+    for (int32_t k = threadIdx.x; k < M.K; k += blockDim.x) R[k] = (float)M.Rd[k];
     __syncthreads();
-    uint16_t *blk = f_lds + (M.K * 8 + 15) / 16 * 8;
+    uint16_t *blk = f_lds + (M.K * 4 + 15) / 16 * 8;
     const int lane = __lane_id();
     const int wave = threadIdx.x >> 6;
     constexpr int gsz = G;
@@ -2671,7 +2673,7 @@ __global__ void __launch_bounds__(256) foldin_step_kernel(DevModel M, DevFoldin 
     const int ngw = 64 / gsz;
     const int64_t gid = ((int64_t)blockIdx.x * 4 + wave) * ngw + grp;
     uint16_t *mt = blk + (wave * ngw + grp) * per_group;
-    TokenIn *tok = (TokenIn *)(blk + 4 * ngw * per_group) + wave * 64 + grp * gsz;
+    TokenZ *tok = (TokenZ *)(blk + 4 * ngw * per_group) + wave * 64 + grp * gsz;
     if (gid >= n_active) return;
     const int32_t sid = active[gid];
     foldin_slot<G, SYM>(M, F, sid, R, mt, tok);
@@ -2687,8 +2689,8 @@ hipError_t launch_foldin_step(const DevModel &m, const DevFoldin &f, const int32
     const int ngw = 64 / f.group;
     const int64_t waves = (n_active + ngw - 1) / ngw;
     const unsigned blocks = (unsigned)((waves + 3) / 4);
-    const size_t lds = (size_t)(m.K * 8 + 15) / 16 * 16 + 4 * ngw * per_group * sizeof(uint16_t) +
-                       4 * 64 * sizeof(TokenIn);
+    const size_t lds = (size_t)(m.K * 4 + 15) / 16 * 16 + 4 * ngw * per_group * sizeof(uint16_t) +
+                       4 * 64 * sizeof(TokenZ);
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, foldin_step_kernel<64, true>, 256, lds);
     if (e != hipSuccess) return e;
