@@ -447,7 +447,7 @@ def alg1_bench(plan, t, N, sweeps):
     z_ms = st["ms_z"] / st["n_z"]
     return dict(sweeps=sweeps, phi_ms=st["ms_phi"] / st["n_phi"], z_ms=z_ms, z_tokens_per_s=N / (z_ms * 1e-3),
                 mean_J=st["sum_J"] / st["z_steps"] / N, a_fraction=st["sum_A"] / st["z_steps"] / N,
-                nnz_phi=st["nnz_phi"])
+                nnz_phi=st["nnz_phi"], fp64_fallbacks_per_token=st["fallback_draws"] / st["z_steps"] / N)
 
 
 def main():
@@ -622,6 +622,8 @@ def main():
                                traffic_unit="bytes per launch (FETCH_SIZE x2.0 + WRITE_SIZE x1.0, calibrated)",
                                traffic_source=os.path.relpath(tsrc, ROOT) if tsrc else None)
         res["zstep"]["mean_J_b_terms_read"] = st["sum_J_b"] / st["z_steps"] / N
+        # draws whose fp32 b-part was too close to a boundary to decide
+        res["zstep"]["fp64_fallbacks_per_token"] = st["fallback_draws"] / st["z_steps"] / N
     log(f"sweep {ms_step:.2f} ms, {tokens_per_s / 1e9:.3f} G tokens/s; {res.get('zstep')}")
     t = t + args.steps
     if not args.graph and args.graph_steps > 0:

@@ -262,6 +262,9 @@ typedef struct {
      * a-part is certain from sigma_a and a bound on sigma_b (decided when it
      * is staged) counts in sum_J but not here */
     int64_t sum_J_b;
+    /* z-step draws whose fp32 b-part left the decision to the fp64 one (y
+     * within its rounding bound of a boundary) */
+    int64_t fallback_draws;
 } pulda_sweep_stats;
 
 /* Read (and restart) the counters above.  Synchronises. */

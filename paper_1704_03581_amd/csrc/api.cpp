@@ -950,6 +950,7 @@ pulda_status pulda_stats(pulda_plan *p, pulda_sweep_stats *out, void *stream)
     out->degenerate_tokens = (int64_t)st[ST_DEGENERATE];
     out->sum_J = (int64_t)st[ST_SUM_J];
     out->sum_J_b = (int64_t)st[ST_SUM_JB];
+    out->fallback_draws = (int64_t)st[ST_FALLBACK];
     out->sum_A = (int64_t)st[ST_SUM_A];
     out->z_steps = (int64_t)st[ST_TOKENS];
     out->nnz_phi = (int64_t)st[ST_NNZ_PHI];
@@ -973,7 +974,7 @@ pulda_status pulda_stats(pulda_plan *p, pulda_sweep_stats *out, void *stream)
     p->ev_used = 0;
     // z-step counters restart from zero
     HIP_TRY(launch_fill_u64(p->stats, 0ull, 3, s));
-    HIP_TRY(launch_fill_u64(p->stats + ST_TOKENS, 0ull, 2, s));
+    HIP_TRY(launch_fill_u64(p->stats + ST_TOKENS, 0ull, 3, s));
     HIP_TRY(hipStreamSynchronize(s));
     return PULDA_OK;
 }

@@ -118,7 +118,7 @@ constexpr int32_t LG_TABLE = 65536;
 constexpr int32_t Z_QUEUES = 16;
 
 enum StatIndex { ST_DEGENERATE = 0, ST_SUM_J = 1, ST_SUM_A = 2, ST_NNZ_PHI = 3, ST_EMPTY_ROWS = 4, ST_TOKENS = 5,
-                 ST_SUM_JB = 6, ST_COUNT = 8 };
+                 ST_SUM_JB = 6, ST_FALLBACK = 7, ST_COUNT = 8 };
 
 // launchers (stream-ordered; return the launch status)
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream_t s);

@@ -913,7 +913,7 @@ struct ZCount {
 // done: sum of J, the same over the tokens whose b-terms were computed (not
 // decided at staging), a-part draws, degenerate tokens
 struct ZCount32 {
-    uint32_t j, jb, a, deg;
+    uint32_t j, jb, a, deg, fb;   // fb: draws the fp32 b-part left to the fp64 one
 };
 
 // b-terms per lane kept in registers for the walk: one gather round covers
@@ -1305,8 +1305,9 @@ __device__ __forceinline__ int32_t b_part(const DevModel &M, const TokenIn &tk, 
 // decision is taken here only when y lies farther than
 // tol = (64 + 8q) u Z from the boundary it is compared with (at least 2.4
 // times that error); it is then the exact-arithmetic decision, which is also
-// the fp64 path's (b_part).  Otherwise (returned as -2, about 2e-5 of the
-// draws) the caller runs b_part.  So the result is b_part's bit for bit.
+// the fp64 path's (b_part).  Otherwise (returned as -2; the z-step counts
+// these draws: about 5e-4 per token on a 1000-topic corpus) the caller runs
+// b_part.  So the result is b_part's bit for bit.
 // Returns the topic, -1 for the a-part or -2 for undecided.
 // ---------------------------------------------------------------------------
 template <int KP, bool DOC, typename CT>
@@ -1506,8 +1507,8 @@ __device__ __forceinline__ int32_t draw_token(const DevModel &M, const TokenIn &
     return knew;
 }
 
-// the fp64 b-part out of line: it runs for about 2e-5 of the draws, and
-// inlined it would hold registers the common path needs
+// the fp64 b-part for the draws the fp32 one leaves undecided (a few per
+// ten thousand tokens), with the fields it reads in registers
 template <int G, bool DOC, typename CT, int KP>
 __device__ __forceinline__ int32_t b_part_fp64(uint32_t *ckg, uint16_t *g16, float *phid, const double *Rd,
                                                const double *sigma_a, const int32_t phi_method, const TokenZ tz,
@@ -1581,7 +1582,10 @@ __device__ __forceinline__ int32_t draw_token_f32(const DevModel &M, const Token
                                                                    M.phi_method, tk, S.mt, S.lst, S.L, g)
                                     : b_part_fp64<G, false, CT, KP>(M.ckg, M.g16, M.phid, M.Rd, M.sigma_a,
                                                                     M.phi_method, tk, S.mt, S.lst, S.L, g);
-            if (knew == -2) knew = k64;
+            if (knew == -2) {
+                knew = k64;
+                cnt.fb++;
+            }
         }
     }
     if (knew < 0) {
@@ -1739,7 +1743,7 @@ __device__ void z_step_item(const ZArgs &a, const WorkItem &w, const float *R, u
             continue;
         }
         load_doc_counts<G, CT>(S, a.c.z, s, e, g, M.K, a.m_bytes / 4);
-        ZCount32 cnt = {0, 0, 0, 0};
+        ZCount32 cnt = {0, 0, 0, 0, 0};
         for (int64_t i0 = s; i0 < e; i0 += G) {
             const int64_t i = i0 + g;
             const bool valid = i < e;
@@ -1805,6 +1809,7 @@ __device__ void z_step_item(const ZArgs &a, const WorkItem &w, const float *R, u
             atomicAdd(&wave_cnt[1], (unsigned long long)cnt.a);
             atomicAdd(&wave_cnt[2], (unsigned long long)cnt.deg);
             atomicAdd(&wave_cnt[3], (unsigned long long)cnt.jb);
+            atomicAdd(&wave_cnt[4], (unsigned long long)cnt.fb);
         }
         if (a.ll_doc) {
             // the document's term of log p(z | alpha) for its final counts:
@@ -1839,9 +1844,9 @@ __global__ void __launch_bounds__(256, (G == 8 ? 2 : 5)) z_step_kernel(ZArgs a)
     uint8_t *wave_base = blk + wave * a.wave_bytes;
     TokenZ *wave_tok = (TokenZ *)(blk + 4 * a.wave_bytes) + wave * 64;
     // the wave's statistics: sum of J, a-part draws, degenerate tokens, sum
-    // of J over the tokens whose b-terms were computed
-    unsigned long long *wave_cnt = (unsigned long long *)(blk + 4 * a.wave_bytes + 4 * 64 * sizeof(TokenZ)) + 4 * wave;
-    if (__lane_id() < 4) wave_cnt[__lane_id()] = 0ull;
+    // of J over the tokens whose b-terms were computed, fp64 fallbacks
+    unsigned long long *wave_cnt = (unsigned long long *)(blk + 4 * a.wave_bytes + 4 * 64 * sizeof(TokenZ)) + 5 * wave;
+    if (__lane_id() < 5) wave_cnt[__lane_id()] = 0ull;
     __builtin_amdgcn_wave_barrier();
     while (true) {
         int item = 0;
@@ -1855,10 +1860,10 @@ __global__ void __launch_bounds__(256, (G == 8 ? 2 : 5)) z_step_kernel(ZArgs a)
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    if (a.stats && __lane_id() < 4) {
+    if (a.stats && __lane_id() < 5) {
         const unsigned long long v = wave_cnt[__lane_id()];
         const int l = __lane_id();
-        const int idx = l == 0 ? ST_SUM_J : (l == 1 ? ST_SUM_A : (l == 2 ? ST_DEGENERATE : ST_SUM_JB));
+        const int idx = l == 0 ? ST_SUM_J : (l == 1 ? ST_SUM_A : (l == 2 ? ST_DEGENERATE : (l == 3 ? ST_SUM_JB : ST_FALLBACK)));
         if (v) atomicAdd(&a.stats[idx], v);
     }
 }
@@ -2132,7 +2137,7 @@ hipError_t launch_z_class(const DevCorpus &c, const DevModel &m, int32_t group, 
     a.group_bytes = L.group_bytes;
     a.wave_bytes = L.wave_bytes;
     a.r_bytes = L.r_bytes;
-    const size_t lds = (size_t)a.r_bytes + 4 * ((size_t)a.wave_bytes + 64 * sizeof(TokenIn) + 32);
+    const size_t lds = (size_t)a.r_bytes + 4 * ((size_t)a.wave_bytes + 64 * sizeof(TokenIn) + 40);
     auto launch = [&](auto kernel) -> hipError_t {
         // persistent: exactly the blocks the device holds at once, and no
         // more waves than work items (a wave takes one item at a time)
@@ -2587,7 +2592,7 @@ __device__ void foldin_slot(const DevModel &M, const DevFoldin &F, int32_t sid, 
         if (done >= F.sweeps) return;
     }
     load_doc_counts<G, uint16_t>(S, zz, 0, kept, g, K, Kp / 2);
-    ZCount32 st = {0, 0, 0, 0};
+    ZCount32 st = {0, 0, 0, 0, 0};
     int32_t budget = sl.budget;
     while (budget > 0 && done < F.sweeps) {
         const int32_t s = done + 1;

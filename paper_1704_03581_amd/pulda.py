@@ -57,7 +57,7 @@ class PhiView(C.Structure):
 class SweepStats(C.Structure):
     _fields_ = [("degenerate_tokens", i64), ("sum_J", i64), ("sum_A", i64), ("z_steps", i64), ("nnz_phi", i64),
                 ("empty_rows", i64), ("ms_phi", f64), ("ms_z", f64), ("ms_ll", f64), ("n_phi", i64), ("n_z", i64),
-                ("n_ll", i64), ("sum_J_b", i64)]
+                ("n_ll", i64), ("sum_J_b", i64), ("fallback_draws", i64)]
 
 
 class FoldinDesc(C.Structure):
