@@ -55,12 +55,30 @@ def _lane_wide(seed=6):
     return c
 
 
+def _max_document(seed=8):
+    """The longest document the library takes, 65,535 tokens (16-bit
+    counts), among short ones, K=100."""
+    a = synth.small_random(D=12, V=2000, K=100, mean_len=6000.0, seed=seed)
+    b = synth.small_random(D=10, V=2000, K=100, mean_len=40.0, seed=seed + 1)
+    assert a.N >= 65535
+    words = [a.words[:65535]] + list(np.split(b.words, b.doc_off[1:-1]))
+    lens = np.array([len(w) for w in words])
+    off = np.zeros(len(words) + 1, np.int64)
+    np.cumsum(lens, out=off[1:])
+    return synth.Corpus("maxdoc", len(words), a.V, a.K, a.alpha, a.beta, off,
+                        np.concatenate(words).astype(np.int32), None)
+
+
 CASES = {
     "tiny": lambda: synth.generate("tiny", keep_true_z=False),
     "k100": lambda: synth.small_random(D=120, V=800, K=100, mean_len=220.0, seed=4),
     "k1000": lambda: synth.small_random(D=50, V=3000, K=1000, mean_len=500.0, seed=5),
     "ragged": _ragged,
     "k100_lane": _lane_wide,
+    # the largest K the library takes, and the smallest
+    "k4096": lambda: synth.small_random(D=30, V=3000, K=4096, mean_len=400.0, seed=7),
+    "k1": lambda: synth.small_random(D=40, V=300, K=1, mean_len=30.0, seed=9),
+    "maxdoc": _max_document,
 }
 _cache = {}
 
