@@ -134,7 +134,8 @@ def foldin_bench(args, torch, pulda, synth, model=None, phi_source=None):
     torch.cuda.synchronize()
     # enough requests for trace_s seconds of arrivals at the highest rate
     n_trace = args.foldin_requests
-    reqs = synth.foldin_requests(max(n_trace, 1) + args.plain_requests, seed=170403581 + 5)
+    reqs = synth.foldin_requests(max(n_trace, 1) + max(args.plain_requests, args.foldin_cpu_requests),
+                                 seed=170403581 + 5)
     lens = np.array([len(r) for r in reqs])
     fi = pulda.FoldIn(model, sweeps=50, burn_in=25, max_slots=args.slots, arena_tokens=args.slots * 600,
                       max_len=5000, group=args.foldin_group, seed=args.seed)
@@ -187,13 +188,13 @@ def foldin_bench(args, torch, pulda, synth, model=None, phi_source=None):
     # and the steady service rate against the same plain rate
     out["service_rate_vs_plain"] = xmax / out["plain_docs_per_s"]
     if args.foldin_cpu_requests > 0 and not args.no_cpu_baseline:
-        # the oracle's fold-in (single-threaded, one pinned core) on the first
-        # of the plain sampler's requests, same Phi, request ids and seed; its
-        # theta must equal the GPU's bit for bit
+        # the oracle's fold-in (single-threaded, one pinned core) on the
+        # requests the plain sampler takes (and more after them), same Phi,
+        # request ids and seed; its theta must equal the GPU's bit for bit
         import oracle
         phi, wt = oracle_tables(model, K, V)
         a = np.full(K, synth.ALPHA)
-        sub = plain[:args.foldin_cpu_requests]
+        sub = reqs[n_trace:n_trace + args.foldin_cpu_requests]
         old_aff = os.sched_getaffinity(0) if hasattr(os, "sched_getaffinity") else None
         try:
             if old_aff:
@@ -202,14 +203,16 @@ def foldin_bench(args, torch, pulda, synth, model=None, phi_source=None):
             same = True
             for j, wj in enumerate(sub):
                 theta, ll, kept, _, _ = oracle.foldin(phi, wt, a, args.seed, j, wj, S=50, burn_in=25)
-                same &= bool(np.array_equal(theta, rep_p.results[j]["theta"]) and kept == rep_p.results[j]["kept"])
+                if j in rep_p.results:
+                    same &= bool(np.array_equal(theta, rep_p.results[j]["theta"]) and kept == rep_p.results[j]["kept"])
             dto = time.perf_counter() - t0
         finally:
             if old_aff:
                 os.sched_setaffinity(0, old_aff)
         draws = 50 * sum(len(w) for w in sub)
         out["cpu_baseline"] = dict(kind="oracle", cores=1, requests=len(sub), docs_per_s=len(sub) / dto,
-                                   token_draws_per_s=draws / dto, seconds=dto, theta_equal_gpu=same)
+                                   token_draws_per_s=draws / dto, seconds=dto,
+                                   theta_equal_gpu=same, compared=min(len(sub), len(plain)))
     return out
 
 
@@ -468,7 +471,8 @@ def main():
     ap.add_argument("--graph", action="store_true", help="replay a captured sweep (no per-phase events)")
     ap.add_argument("--graph-steps", type=int, default=10,
                     help="after the timed sweeps, this many sweeps replayed from a captured graph (0: none)")
-    ap.add_argument("--cpu-docs", type=int, default=20000)
+    ap.add_argument("--cpu-docs", type=int, default=200000,
+                    help="documents of the oracle's z-step baseline (about 10 s of one core at the large config)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-foldin", action="store_true")
     ap.add_argument("--heldout-docs", type=int, default=2000,
@@ -493,7 +497,7 @@ def main():
     ap.add_argument("--closed-requests", type=int, default=12000, help="requests of the closed-loop run")
     ap.add_argument("--trace-s", type=float, default=10.0, help="seconds of Poisson arrivals per rate point")
     ap.add_argument("--plain-requests", type=int, default=60)
-    ap.add_argument("--foldin-cpu-requests", type=int, default=40,
+    ap.add_argument("--foldin-cpu-requests", type=int, default=200,
                     help="requests of the oracle's fold-in baseline (0: none)")
     ap.add_argument("--slots", type=int, default=4096)
     ap.add_argument("--draws", type=int, default=2048, help="fold-in token draws per request per step")
