@@ -97,3 +97,26 @@ def test_foldin_admission_under_memory_cap(model):
     assert occ["resident"] == 0 and occ["free_tokens"] == 500 and occ["free_slots"] == 32
     for rid in (0, 5, 24):
         _check(rep.results[rid], phi, wt, np.full(c.K, c.alpha), 5, rid, reqs[rid], 6, 3)
+
+
+def test_foldin_poll_previous_lags_one_step(model):
+    """pulda_foldin_poll_previous reports what the step before the latest
+    finished: nothing after the first step, a request finished by step s
+    after step s+1 (whose launch skips it), the same results as the
+    synchronous poll."""
+    p, phi, wt, c = model
+    say("fold-in lagged poll")
+    reqs = _requests(c.V, 6, 11)[:6]
+    f = pulda.FoldIn(p, sweeps=4, burn_in=2, max_slots=8, arena_tokens=4000, max_len=400, group=64, seed=17)
+    alone = {rid: f.run_one(rid, w) for rid, w in enumerate(reqs)}
+    for rid, w in enumerate(reqs):
+        assert f.submit(rid, w)
+    big = 1 << 30
+    f.step(big)                                   # every request finishes in this step
+    assert f.poll(previous=True) == []            # nothing before the second step
+    f.step(big)                                   # finished ones are skipped
+    got = {r["request_id"]: r for r in f.poll(previous=True)}
+    assert sorted(got) == list(range(len(reqs)))
+    for rid, r in got.items():
+        assert np.array_equal(r["theta"], alone[rid]["theta"]) and r["loglik"] == alone[rid]["loglik"]
+    assert f.occupancy()["resident"] == 0
