@@ -296,7 +296,10 @@ pulda_status pulda_get_schedule(const pulda_plan *plan, int32_t cap, int32_t *n_
 
 /* Time each candidate group size (1, 8, 16, 32, 64) and side ratio (1, 4, 16) on
  * each bucket (z-step at sweep t, reps repetitions, current Phi) and keep the
- * fastest.  Restores z and n.  Synchronises. */
+ * fastest; then time the whole z-step, as a sweep launches it, with each
+ * bucket moved into every other bucket's group and side ratio, and keep a
+ * move that makes it faster (a bucket alone in its kernel may run after the
+ * others).  Restores z and n.  Synchronises. */
 pulda_status pulda_autotune(pulda_plan *plan, uint32_t t, int32_t reps, void *stream);
 
 /* In pulda_sweep, let the z-step write each document's term of the log

@@ -675,18 +675,17 @@ static pulda_status enqueue_phi(pulda_plan *p, hipStream_t s)
     return PULDA_OK;
 }
 
-static pulda_status enqueue_z(pulda_plan *p, hipStream_t s, double *ll_doc = nullptr)
+// the z-step's launches (statistics into `stats`, or none)
+static pulda_status enqueue_z_classes(pulda_plan *p, hipStream_t s, double *ll_doc, unsigned long long *stats)
 {
-    size_t ta = 0, tb = 0;
-    if (p->timing) HIP_TRY(phase_event(p, s, &ta));
-    HIP_TRY(launch_z_prepare(p->m, p->queue, p->stats, s));
+    HIP_TRY(launch_z_prepare(p->m, p->queue, stats, s));
     int used = 0;
     for (int c = 0; c < pulda_plan::NCLS; ++c) used += p->cls_count[c] > 0;
     if (used <= 1) {
         for (int c = 0; c < pulda_plan::NCLS; ++c)
             if (p->cls_count[c])
                 HIP_TRY(launch_z_class(p->c, p->m, kClassGroup[c], kClassNarrow[c], p->items + p->cls_first[c],
-                                       p->cls_count[c], p->n_cu, p->queue + c, p->stats, ll_doc, s));
+                                       p->cls_count[c], p->n_cu, p->queue + c, stats, ll_doc, s));
     } else {
         // classes run concurrently: long documents (large groups) next to
         // the bulk of short ones
@@ -695,11 +694,20 @@ static pulda_status enqueue_z(pulda_plan *p, hipStream_t s, double *ll_doc = nul
             if (!p->cls_count[c]) continue;
             HIP_TRY(hipStreamWaitEvent(p->aux[c], p->fork_ev, 0));
             HIP_TRY(launch_z_class(p->c, p->m, kClassGroup[c], kClassNarrow[c], p->items + p->cls_first[c],
-                                   p->cls_count[c], p->n_cu, p->queue + c, p->stats, ll_doc, p->aux[c]));
+                                   p->cls_count[c], p->n_cu, p->queue + c, stats, ll_doc, p->aux[c]));
             HIP_TRY(hipEventRecord(p->join_ev[c], p->aux[c]));
             HIP_TRY(hipStreamWaitEvent(s, p->join_ev[c], 0));
         }
     }
+    return PULDA_OK;
+}
+
+static pulda_status enqueue_z(pulda_plan *p, hipStream_t s, double *ll_doc = nullptr)
+{
+    size_t ta = 0, tb = 0;
+    if (p->timing) HIP_TRY(phase_event(p, s, &ta));
+    pulda_status st = enqueue_z_classes(p, s, ll_doc, p->stats);
+    if (st != PULDA_OK) return st;
     if (p->timing) {
         HIP_TRY(phase_event(p, s, &tb));
         p->ev_z.push_back({ta, tb});
@@ -1028,6 +1036,7 @@ pulda_status pulda_autotune(pulda_plan *p, uint32_t t, int32_t reps, void *strea
     const std::vector<int32_t> keep_group = p->group, keep_dpi = p->dpi;
     const int32_t nb = (int32_t)p->min_len.size();
     std::vector<int32_t> best_g(keep_group), best_d(keep_dpi), best_r(p->side);
+    std::vector<double> bucket_mean(nb, 0.0);   // mean document length (0: empty bucket)
     for (int32_t b = 0; b < nb; ++b) {
         // documents of bucket b
         int64_t lo = 0, hi = 0;
@@ -1043,6 +1052,7 @@ pulda_status pulda_autotune(pulda_plan *p, uint32_t t, int32_t reps, void *strea
         double mean_len = 0;
         for (int64_t i = lo; i < hi; ++i) mean_len += p->len_sorted[i];
         mean_len /= (double)(hi - lo);
+        bucket_mean[b] = mean_len;
         float best_ms = 1e30f;
         const bool narrow = p->len_sorted[lo] < 256;
         for (int gsz : {64, 32, 16, 8, 1}) {
@@ -1077,12 +1087,65 @@ pulda_status pulda_autotune(pulda_plan *p, uint32_t t, int32_t reps, void *strea
             }
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     p->group = best_g;
     p->dpi = best_d;
     p->side = best_r;
     pulda_status st = build_items(p);
+    if (st != PULDA_OK) return st;
+    // Then the whole z-step.  Each work-item class is a kernel of its own on
+    // a forked stream, and a small class whose stream shares a hardware
+    // queue with the caller's runs only after the others.  So each bucket is
+    // also tried in every other bucket's group (and side ratio), and a change
+    // is kept when the whole z-step, timed as the sweep launches it, is
+    // faster.
+    auto whole = [&](float *out) -> pulda_status {
+        float total = 0;
+        for (int r = 0; r <= reps; ++r) {
+            if (p->N) HIP_TRY(hipMemcpyAsync(p->c.z, p->zsave, p->N * 2, hipMemcpyDeviceToDevice, s));
+            HIP_TRY(hipEventRecord(e0, s));
+            pulda_status q = enqueue_z_classes(p, s, nullptr, nullptr);
+            if (q != PULDA_OK) return q;
+            HIP_TRY(hipEventRecord(e1, s));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            if (r > 0) total += ms;
+        }
+        *out = total;
+        return PULDA_OK;
+    };
+    float best_all = 0;
+    st = whole(&best_all);
+    if (st != PULDA_OK) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return st;
+    }
+    for (int32_t b = 0; b < nb; ++b) {
+        if (bucket_mean[b] == 0) continue;
+        for (int32_t b2 = 0; b2 < nb; ++b2) {
+            if (b2 == b || bucket_mean[b2] == 0 || p->group[b2] == p->group[b]) continue;
+            const int32_t g0 = p->group[b], d0 = p->dpi[b], r0 = p->side[b];
+            const int32_t gsz = p->group[b2];
+            const int ng = 64 / gsz;
+            p->group[b] = gsz;
+            p->dpi[b] = (int32_t)std::max(1.0, std::round(4096.0 / std::max(1.0, bucket_mean[b]) / ng)) * ng;
+            p->side[b] = p->side[b2];
+            float ms = 0;
+            st = build_items(p);
+            if (st == PULDA_OK) st = whole(&ms);
+            if (st == PULDA_OK && ms < best_all) {
+                best_all = ms;
+            } else {
+                p->group[b] = g0;
+                p->dpi[b] = d0;
+                p->side[b] = r0;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    st = build_items(p);
     if (st != PULDA_OK) return st;
     if (p->N) HIP_TRY(hipMemcpyAsync(p->c.z, p->zsave, p->N * 2, hipMemcpyDeviceToDevice, s));
     HIP_TRY(launch_count_rebuild(p->c, p->m, s));
