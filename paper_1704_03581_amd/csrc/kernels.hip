@@ -2742,8 +2742,8 @@ hipError_t launch_foldin_step(const DevModel &m, const DevFoldin &f, const int32
 // token).
 // ---------------------------------------------------------------------------
 template <int G>
-__device__ void ltr_particle(const DevModel &M, const DevHeldout &H, int64_t d, int32_t r, const double *R,
-                             uint16_t *mt, TokenIn *tok)
+__device__ void ltr_particle(const DevModel &M, const DevHeldout &H, int64_t d, int32_t r, const float *Rf,
+                             uint16_t *mt, TokenZ *tok)
 {
     const int32_t Kp = (M.K + 1) & ~1;
     DocState<uint16_t> S;
@@ -2780,8 +2780,11 @@ __device__ void ltr_particle(const DevModel &M, const DevHeldout &H, int64_t d, 
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     ZCount st = {0, 0, 0, 0, 0};
+    ZCount32 st32 = {0, 0, 0, 0, 0};
     for (int32_t n = 0; n < nk; ++n) {
-        // redraw z_0 .. z_{n-1} in order (lane q mod G stages token q)
+        // redraw z_0 .. z_{n-1} in order (lane q mod G stages token q), with
+        // the z-step's draw (fp32 b-terms where the rounding bound proves the
+        // decision, fp64 elsewhere: the fp64 draws' results)
         for (int32_t q0 = 0; q0 < n; q0 += G) {
             const int32_t q = q0 + g;
             const bool valid = q < n;
@@ -2791,15 +2794,14 @@ __device__ void ltr_particle(const DevModel &M, const DevHeldout &H, int64_t d, 
                 const r4 rr = philox((uint32_t)q, (uint32_t)n, req, tag, H.key0, H.key1);
                 // (n tokens counted: the redraws may settle the a-part at
                 // staging; only the new token's draw needs its Z)
-                stage_token(M, tok, g, kw[q], zo, rr, n);
+                stage_token_z(M, tok, g, kw[q], zo, rr, n);
             }
             __builtin_amdgcn_wave_barrier();
             int32_t znew = zo;
             const int nb = n - q0 < G ? n - q0 : G;
             for (int jj = 0; jj < nb; ++jj) {
-                const TokenIn tk = tok[jj];
-                double Zd;
-                int32_t k = draw_token<G, uint16_t>(M, tk, S, R, g, 1, st, Zd);
+                const TokenZ tk = tok[jj];
+                int32_t k = draw_token_f32<G, uint16_t>(M, tk, S, Rf, g, 1, st32);
                 if (k < 0) k = -1 - k;
                 if (g == jj) znew = k;
             }
@@ -2815,14 +2817,17 @@ __device__ void ltr_particle(const DevModel &M, const DevHeldout &H, int64_t d, 
         if (g == 0) mt[k0] = (uint16_t)(c0 + 1);
         __builtin_amdgcn_wave_barrier();
         if (c0 == 0) list_insert<G, uint16_t>(S, k0, g);
+        // (the fp64 draw, which hands back Z; its R_k from global memory:
+        // one such draw per step)
+        TokenIn *tin = (TokenIn *)tok;
         if (g == 0) {
             const r4 rr = philox((uint32_t)n, (uint32_t)n, req, tag, H.key0, H.key1);
-            stage_token(M, tok, 0, kw[n], k0, rr, 0);
+            stage_token(M, tin, 0, kw[n], k0, rr, 0);
         }
         __builtin_amdgcn_wave_barrier();
-        const TokenIn tk = tok[0];
+        const TokenIn tk = tin[0];
         double Z = 0.0;
-        int32_t k = draw_token<G, uint16_t>(M, tk, S, R, g, 1, st, Z);
+        int32_t k = draw_token<G, uint16_t>(M, tk, S, M.Rd, g, 1, st, Z);
         if (k < 0) k = -1 - k;
         __builtin_amdgcn_wave_barrier();
         if (g == (n & (G - 1))) zz[n] = (uint16_t)k;
@@ -2834,17 +2839,17 @@ template <int G>
 __global__ void __launch_bounds__(256) ltr_kernel(DevModel M, DevHeldout H, int32_t per_group)
 {
     extern __shared__ __align__(16) uint16_t h_lds[];
-    double *R = (double *)h_lds;
-    for (int32_t k = threadIdx.x; k < M.K; k += blockDim.x) R[k] = M.Rd[k];
+    float *R = (float *)h_lds;
+    for (int32_t k = threadIdx.x; k < M.K; k += blockDim.x) R[k] = (float)M.Rd[k];
     __syncthreads();
-    uint16_t *blk = h_lds + (M.K * 8 + 15) / 16 * 8;
+    uint16_t *blk = h_lds + (M.K * 4 + 15) / 16 * 8;
     const int lane = __lane_id();
     const int wave = threadIdx.x >> 6;
     constexpr int NG = 64 / G;
     const int grp = lane / G;
     const int64_t gid = ((int64_t)blockIdx.x * 4 + wave) * NG + grp;
     uint16_t *mt = blk + (wave * NG + grp) * per_group;
-    TokenIn *tok = (TokenIn *)(blk + 4 * NG * per_group) + wave * 64 + grp * G;
+    TokenZ *tok = (TokenZ *)(blk + 4 * NG * per_group) + wave * 64 + grp * G;
     if (gid >= H.D * H.R) return;
     ltr_particle<G>(M, H, H.order[gid / H.R], (int32_t)(gid % H.R), R, mt, tok);
 }
@@ -2877,8 +2882,8 @@ hipError_t launch_heldout(const DevModel &m, const DevHeldout &h, hipStream_t s)
     const int64_t groups = h.D * h.R;
     const int64_t waves = (groups + ngw - 1) / ngw;
     const unsigned blocks = (unsigned)((waves + 3) / 4);
-    const size_t lds = (size_t)(m.K * 8 + 15) / 16 * 16 + 4 * ngw * per_group * sizeof(uint16_t) +
-                       4 * 64 * sizeof(TokenIn);
+    const size_t lds = (size_t)(m.K * 4 + 15) / 16 * 16 + 4 * ngw * per_group * sizeof(uint16_t) +
+                       4 * 64 * sizeof(TokenZ);
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ltr_kernel<64>, 256, lds);
     if (e != hipSuccess) return e;
