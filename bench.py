@@ -597,7 +597,7 @@ def main():
     tokens_per_s = N * args.steps / wall
     res = dict(metric="z-step tokens/sec at K=1000 (% HBM roofline); fold-in docs/sec + p50/p99 latency",
                value=tokens_per_s, unit="tokens/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
-               ms_per_step=ms_step, higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64",
+               ms_per_step=ms_step, higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32+f64",
                data="synthetic",
                config=dict(workload=f"{args.config}: synthetic LDA corpus D={corpus.D} V={corpus.V} K={corpus.K} "
                                     f"N={N}, alpha={corpus.alpha}, beta={corpus.beta}; one sweep = Phi-step + "
