@@ -443,10 +443,10 @@ __global__ void __launch_bounds__(256) phi_dense_kernel(DevModel m)
 // Columns with at most ALIAS_SMALL nonzeros: one wave per column, four per
 // block (LDS of ALIAS_SMALL entries each); the others: one column per block
 // with K entries of LDS.  Per entry: a probability (fp64), a work-list
-// entry, its topic, its alias entry and a turn record (u16 each), its
-// threshold (u32).
+// entry (u16) and a turn mark (u8), so that many columns' chains run on a
+// CU at once.
 constexpr int32_t ALIAS_SMALL = 256;
-constexpr size_t ALIAS_ENTRY_BYTES = sizeof(double) + 4 * sizeof(uint16_t) + sizeof(uint32_t);
+constexpr size_t ALIAS_ENTRY_BYTES = sizeof(double) + sizeof(uint16_t) + sizeof(uint8_t);
 
 template <bool SMALL>
 __global__ void __launch_bounds__(SMALL ? 256 : 64) phi_alias_kernel(DevModel m, int32_t kpad)
@@ -468,10 +468,8 @@ __global__ void __launch_bounds__(SMALL ? 256 : 64) phi_alias_kernel(DevModel m,
     // region and array stays 8-byte aligned)
     double *pq = (double *)((uint8_t *)alias_lds + (size_t)wave * cap * ALIAS_ENTRY_BYTES);
     uint16_t *lst = (uint16_t *)(pq + cap);   // small entries from the front, large ones from the back
-    uint16_t *tk = lst + cap;                 // topic of entry e
-    uint16_t *ali = tk + cap;                 // alias entry of e
-    uint16_t *turn = ali + cap;               // FIFO step at which large entry j turned small
-    uint32_t *thr = (uint32_t *)(turn + cap); // threshold of e
+    uint8_t *mark = (uint8_t *)(lst + cap);   // 1 at the FIFO steps where the head turned small
+    const uint16_t *ctop = m.ctopic + cb;     // topic of entry e
     // weights w_e = alpha_k phi_kv in entry order (pq holds them first;
     // each lane also keeps its first MAXC chunks' weights in registers, all
     // chunks' loads issued together)
@@ -482,17 +480,12 @@ __global__ void __launch_bounds__(SMALL ? 256 : 64) phi_alias_kernel(DevModel m,
         const int32_t e = c * 64 + lane;
         wr[c] = 0.0;
         if (e < nv) {
-            const int32_t k = m.ctopic[cb + e];
-            tk[e] = (uint16_t)k;
-            wr[c] = m.alpha[k] * (double)m.cphi[cb + e];
+            wr[c] = m.alpha[ctop[e]] * (double)m.cphi[cb + e];
             pq[e] = wr[c];
         }
     }
-    for (int32_t e = MAXC * 64 + lane; e < nv; e += 64) {
-        const int32_t k = m.ctopic[cb + e];
-        tk[e] = (uint16_t)k;
-        pq[e] = m.alpha[k] * (double)m.cphi[cb + e];
-    }
+    for (int32_t e = MAXC * 64 + lane; e < nv; e += 64) pq[e] = m.alpha[ctop[e]] * (double)m.cphi[cb + e];
+    for (int32_t e = lane; e < nv; e += 64) mark[e] = 0;
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     // sigma_a: the ascending sum, read eight entries at a time
@@ -522,8 +515,6 @@ __global__ void __launch_bounds__(SMALL ? 256 : 64) phi_alias_kernel(DevModel m,
         if (e < nv) {
             p = (w * (double)nv) / W;
             is_small = p < 1.0;
-            thr[e] = 0xFFFFFFFFu;
-            ali[e] = (uint16_t)e;
         }
         const uint64_t bs = __builtin_amdgcn_ballot_w64(e < nv && is_small);
         const uint64_t bl = __builtin_amdgcn_ballot_w64(e < nv && !is_small);
@@ -543,7 +534,7 @@ __global__ void __launch_bounds__(SMALL ? 256 : 64) phi_alias_kernel(DevModel m,
     // chunks past MAXC (K > 64 MAXC) recompute their weights
     for (int32_t e0 = MAXC * 64; e0 < nv; e0 += 64) {
         const int32_t e = e0 + lane;
-        classify(e, e < nv ? m.alpha[tk[e]] * (double)m.cphi[cb + e] : 0.0);
+        classify(e, e < nv ? m.alpha[ctop[e]] * (double)m.cphi[cb + e] : 0.0);
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -555,11 +546,11 @@ __global__ void __launch_bounds__(SMALL ? 256 : 64) phi_alias_kernel(DevModel m,
     // floor(ps(f) 2^32), its alias the large entry at the head, and the
     // head's probability becomes (pg + ps(f)) - 1; below 1 the head turns
     // small (its residual joins the FIFO) and the next large entry leads.
-    // Only that chain of sums is sequential: lane 0 runs it and records the
-    // step at which each large entry turned small (its residual goes to its
-    // own pq slot); then all lanes write thresholds and aliases, the head
-    // at step f being large entry #{j : turn[j] < f}.
-    int32_t nf = 0, nturn = 0;
+    // Only that chain of sums is sequential: lane 0 runs it and marks the
+    // steps at which the head turned small (its residual goes to its own pq
+    // slot); then all lanes write the records, the head at step f being
+    // large entry number sum_{f' < f} mark[f'] (a prefix sum over the wave).
+    int32_t nf = 0;
     if (lane == 0) {
         int32_t gi = 0, f = 0;
         double pg = nl > 0 ? pq[nv - 1] : 0.0;
@@ -567,7 +558,7 @@ __global__ void __launch_bounds__(SMALL ? 256 : 64) phi_alias_kernel(DevModel m,
             pg = (pg + ps) - 1.0;
             if (pg < 1.0) {
                 pq[nv - 1 - gi] = pg;
-                turn[gi] = (uint16_t)f;
+                mark[f] = 1;
                 ++gi;
                 if (gi < nl) pg = pq[nv - 1 - gi];
             }
@@ -585,31 +576,38 @@ __global__ void __launch_bounds__(SMALL ? 256 : 64) phi_alias_kernel(DevModel m,
         // then the large entries that turned small, in that order
         while (gi < nl && f - ns < gi) step(pq[nv - 1 - (f - ns)]);
         nf = f;
-        nturn = gi;
     }
     nf = __shfl(nf, 0, 64);
-    nturn = __shfl(nturn, 0, 64);
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    for (int32_t f = lane; f < nf; f += 64) {
-        const int32_t at = f < ns ? f : nv - 1 - (f - ns);
-        const int32_t sm = lst[at];
-        const double ps = pq[at];
-        // head at step f: the number of large entries that turned before f
-        int32_t lo = 0, hi = nturn;
-        while (lo < hi) {
-            const int32_t mid = (lo + hi) >> 1;
-            if ((int32_t)turn[mid] < f) lo = mid + 1;
-            else hi = mid;
+    // each entry's record: thr | topic << 32 | alias topic << 48.  The FIFO's
+    // first nf entries are paired (threshold floor(ps 2^32), alias the head
+    // at their step); the others keep themselves (threshold 2^32 - 1)
+    uint64_t *rec = m.calias + cb;
+    int32_t heads = 0;   // turns before this chunk of steps
+    for (int32_t f0 = 0; f0 < nf; f0 += 64) {
+        const int32_t f = f0 + lane;
+        const int32_t mk = f < nf ? mark[f] : 0;
+        const int32_t incl = group_scan_incl_i32<64>(mk);
+        if (f < nf) {
+            const int32_t at = f < ns ? f : nv - 1 - (f - ns);
+            const int32_t sm = lst[at];
+            const double ps = pq[at];
+            const int32_t head = heads + incl - mk;
+            const uint32_t al = lst[nv - 1 - head];
+            rec[sm] = (uint64_t)(uint32_t)floor(ps * 4294967296.0) | ((uint64_t)ctop[sm] << 32) |
+                      ((uint64_t)ctop[al] << 48);
         }
-        thr[sm] = (uint32_t)floor(ps * 4294967296.0);
-        ali[sm] = lst[nv - 1 - lo];
+        heads += __builtin_amdgcn_readlane(incl, 63);
     }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    for (int32_t e = lane; e < nv; e += 64) {
-        const uint64_t entry = (uint64_t)thr[e] | ((uint64_t)tk[e] << 32) | ((uint64_t)tk[ali[e]] << 48);
-        m.calias[cb + e] = entry;
+    for (int32_t i = (nf < ns ? nf : ns) + lane; i < ns; i += 64) {
+        const uint64_t k = ctop[lst[i]];
+        rec[lst[i]] = 0xFFFFFFFFull | (k << 32) | (k << 48);
+    }
+    for (int32_t j = (nf > ns ? nf - ns : 0) + lane; j < nl; j += 64) {
+        const int32_t sm = lst[nv - 1 - j];
+        const uint64_t k = ctop[sm];
+        rec[sm] = 0xFFFFFFFFull | (k << 32) | (k << 48);
     }
 }
 
