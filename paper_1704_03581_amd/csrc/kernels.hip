@@ -302,26 +302,61 @@ __global__ void __launch_bounds__(256) phi_draw_kernel(DevModel m, int32_t kpad)
     const uint32_t *T = m.ztp_tab + (vec ? m.ztp_off[v] : 0);
     const int32_t nT = vec ? m.ztp_off[v + 1] - m.ztp_off[v] : m.ztp_n;
 
-    for (int32_t k = lane; k < K; k += 64) {
-        const int32_t l = ncol[k];
-        int32_t x = -1;  // -1 marks a zero-count cell
-        if (l > 0) {
-            r4 r = philox((uint32_t)v, (uint32_t)k, t, TAG_PHI_CELL, m.key0, m.key1);
-            if (l <= m.L) {
-                const int32_t off = m.pois_off[l];
-                const uint32_t sz = (uint32_t)(m.pois_off[l + 1] - off);
-                const uint32_t j = scale32(r.x, sz);
-                const uint64_t e = m.pois[off + j];
-                x = (r.y < (uint32_t)e) ? (int32_t)j : (int32_t)(e >> 32);
-            } else {
-                const double lam = tb + (double)l;
-                const double rad = sqrt(-2.0 * log(1.0 - unit53(r.x, r.y)));
-                const double gz = rad * cos(two_pi * unit53(r.z, r.w));
-                const double y = floor(lam + sqrt(lam) * gz + 0.5);
-                x = y > 0.0 ? (int32_t)y : 0;
+    // counted cells, PR rounds of 64 cells at a time: the rounds' counts,
+    // then their tables' offsets, then their alias entries are each loaded
+    // for all rounds before any is used, so a column waits for three
+    // dependent loads per PR rounds instead of per round
+    constexpr int PR = 4;
+    for (int32_t kb = 0; kb < K; kb += 64 * PR) {
+        int32_t lv[PR];
+#pragma unroll
+        for (int u = 0; u < PR; ++u) {
+            const int32_t k = kb + 64 * u + lane;
+            lv[u] = k < K ? ncol[k] : 0;
+        }
+        int32_t lo[PR], hi[PR];
+#pragma unroll
+        for (int u = 0; u < PR; ++u) {
+            const bool tab = lv[u] > 0 && lv[u] <= m.L;
+            lo[u] = tab ? m.pois_off[lv[u]] : 0;
+            hi[u] = tab ? m.pois_off[lv[u] + 1] : 0;
+        }
+        int32_t x[PR];
+        uint32_t jv[PR], ry[PR];
+        uint64_t ev[PR];
+#pragma unroll
+        for (int u = 0; u < PR; ++u) {
+            const int32_t k = kb + 64 * u + lane;
+            const int32_t l = lv[u];
+            x[u] = -1;  // -1 marks a zero-count cell
+            jv[u] = 0;
+            ry[u] = 0;
+            ev[u] = 0;
+            if (l > 0) {
+                const r4 r = philox((uint32_t)v, (uint32_t)k, t, TAG_PHI_CELL, m.key0, m.key1);
+                if (l <= m.L) {
+                    // alias table of rate l: slot j, kept when r.y is below
+                    // its threshold, else its alias
+                    jv[u] = scale32(r.x, (uint32_t)(hi[u] - lo[u]));
+                    ry[u] = r.y;
+                    ev[u] = m.pois[lo[u] + jv[u]];
+                } else {
+                    // rounded Gaussian of mean and variance lambda
+                    const double lam = tb + (double)l;
+                    const double rad = sqrt(-2.0 * log(1.0 - unit53(r.x, r.y)));
+                    const double gz = rad * cos(two_pi * unit53(r.z, r.w));
+                    const double y = floor(lam + sqrt(lam) * gz + 0.5);
+                    x[u] = y > 0.0 ? (int32_t)y : 0;
+                }
             }
         }
-        g[k] = x;
+#pragma unroll
+        for (int u = 0; u < PR; ++u) {
+            const int32_t k = kb + 64 * u + lane;
+            const int32_t l = lv[u];
+            if (l > 0 && l <= m.L) x[u] = (ry[u] < (uint32_t)ev[u]) ? (int32_t)jv[u] : (int32_t)(ev[u] >> 32);
+            if (k < K) g[k] = x[u];
+        }
     }
     __builtin_amdgcn_wave_barrier();
 
