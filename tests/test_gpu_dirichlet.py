@@ -41,6 +41,9 @@ CASES = {
     "tiny": lambda: synth.generate("tiny", keep_true_z=False),
     "k100": lambda: synth.small_random(D=120, V=800, K=100, mean_len=220.0, seed=4),
     "k1000": lambda: synth.small_random(D=50, V=3000, K=1000, mean_len=500.0, seed=5),
+    # dense columns of about 2048 entries: the alias construction's long
+    # columns past the 16 chunks of 64 entries it keeps in registers
+    "k2048": lambda: synth.small_random(D=20, V=300, K=2048, mean_len=300.0, seed=6),
 }
 _cache = {}
 
