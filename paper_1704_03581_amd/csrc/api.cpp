@@ -144,7 +144,7 @@ struct pulda_plan {
     uint8_t *ws = nullptr;
     int64_t ws_need = 0;
     struct {
-        int64_t z, n, gam, phid, g16, Rd, gamd, Sd, dpart, phimax, wrec, beta_v, ztp, ztp_off, ckg, colcnt, colptr, ctopic, cphi, calias, sigma_a, S, nk, alpha, pois, pois_off,
+        int64_t z, n, gam, phid, g16, Rd, gamd, Sd, dpart, phimax, wrec, hot, hot_word, beta_v, ztp, ztp_off, ckg, colcnt, colptr, ctopic, cphi, calias, sigma_a, S, nk, alpha, pois, pois_off,
             doc_order, items, queue, stats, ll_part, ll_out, ll_hist, tptr, err, scratch, cnt_a, ptr_a, cnt_b,
             ptr_b, zsave, lg_beta, lg_alpha, lg_A, ll_doc;
     } off;
@@ -340,6 +340,8 @@ pulda_status pulda_plan_create(const pulda_model_desc *desc, int64_t D, int64_t 
     p->off.ztp = L.take((int64_t)p->ztp_h.size() * 4);
     p->off.ztp_off = L.take(((int64_t)p->V + 1) * 4);
     p->off.phimax = L.take((int64_t)p->V * 4);
+    p->off.hot = L.take((int64_t)p->V * 4);
+    p->off.hot_word = L.take((int64_t)HOT_MAX * 4);
     p->off.wrec = L.take((int64_t)p->V * 16);
     p->off.S = L.take((int64_t)p->K * 8);
     p->off.nk = L.take((int64_t)p->K * 8);
@@ -413,6 +415,9 @@ pulda_status pulda_plan_bind(pulda_plan *p, void *workspace_dev, int64_t bytes)
     m.calias = (uint64_t *)(w + p->off.calias);
     m.sigma_a = (double *)(w + p->off.sigma_a);
     m.phimax = (float *)(w + p->off.phimax);
+    m.hot = (int32_t *)(w + p->off.hot);
+    m.hot_word = (int32_t *)(w + p->off.hot_word);
+    m.n_hot = 0;
     m.wrec = (uint4 *)(w + p->off.wrec);
     m.pois = (const uint64_t *)(w + p->off.pois);
     m.pois_off = (const int32_t *)(w + p->off.pois_off);
@@ -568,6 +573,38 @@ static pulda_status build_items(pulda_plan *p)
     return PULDA_OK;
 }
 
+// The most frequent words (counted on a prefix of the corpus, at most 8M
+// tokens): their count increments contend for few counters when K is small,
+// so the z-step adds them up per block in LDS first.  As many words as
+// HOT_BYTES of 32-bit counters hold at this K (none when that is under
+// HOT_MIN).  Only where the increments are added changes, not the counts.
+static hipError_t choose_hot_words(pulda_plan *p)
+{
+    p->m.n_hot = 0;
+    const int32_t cap = HOT_BYTES / (4 * p->K);
+    if (cap < HOT_MIN || p->N == 0) return hipSuccess;
+    const int32_t n_hot = cap < p->V ? cap : p->V;
+    const int64_t ns = p->N < (8ll << 20) ? p->N : (8ll << 20);
+    std::vector<int32_t> w((size_t)ns);
+    hipError_t e = hipMemcpy(w.data(), p->c.words, (size_t)ns * 4, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return e;
+    std::vector<int64_t> cnt((size_t)p->V, 0);
+    for (int32_t v : w) cnt[(size_t)v]++;
+    std::vector<int32_t> ids((size_t)p->V);
+    for (int32_t v = 0; v < p->V; ++v) ids[(size_t)v] = v;
+    std::partial_sort(ids.begin(), ids.begin() + n_hot, ids.end(), [&](int32_t a, int32_t b) {
+        return cnt[(size_t)a] != cnt[(size_t)b] ? cnt[(size_t)a] > cnt[(size_t)b] : a < b;
+    });
+    std::vector<int32_t> hot((size_t)p->V, -1);
+    for (int32_t h = 0; h < n_hot; ++h) hot[(size_t)ids[(size_t)h]] = h;
+    e = hipMemcpy(p->m.hot, hot.data(), (size_t)p->V * 4, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return e;
+    e = hipMemcpy(p->m.hot_word, ids.data(), (size_t)n_hot * 4, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return e;
+    p->m.n_hot = n_hot;
+    return hipSuccess;
+}
+
 pulda_status pulda_corpus_upload(pulda_plan *p, const int64_t *doc_off_dev, const int32_t *words_dev, void *stream)
 {
     if (!p || (!doc_off_dev) || (!words_dev && p->N > 0)) return fail(PULDA_ERR_INVALID_ARG, "null argument");
@@ -605,6 +642,7 @@ pulda_status pulda_corpus_upload(pulda_plan *p, const int64_t *doc_off_dev, cons
         p->len_sorted[at] = (int32_t)l;
     }
     if (p->D) HIP_TRY(hipMemcpy((void *)p->c.doc_order, order.data(), p->D * 4, hipMemcpyHostToDevice));
+    HIP_TRY(choose_hot_words(p));
     pulda_status st = build_items(p);
     if (st != PULDA_OK) return st;
     p->uploaded = true;

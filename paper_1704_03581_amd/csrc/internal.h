@@ -48,6 +48,12 @@ struct DevModel {
     // per word, what a z-step token needs of its word in one 16-byte load:
     // {first CSC entry, column length, fp32(sigma_a), phimax} (as bits)
     uint4 *wrec;                  // [V]
+    // the corpus's most frequent words, whose count increments the z-step
+    // gathers per block in LDS when K is small (hot[v]: the word's index
+    // among them, or -1; hot_word[h]: the word of index h)
+    int32_t *hot;                 // [V]
+    int32_t *hot_word;            // [HOT_MAX]
+    int32_t n_hot;
     const uint64_t *pois;         // Poisson alias tables, thr | x_alias << 32
     const int32_t *pois_off;      // [L+2]
     // per-word priors (null: the symmetric beta); zero-truncated
@@ -109,6 +115,12 @@ inline ZLayout z_layout(int32_t group, bool narrow, int32_t K)
     L.r_bytes = (K * 4 + 15) / 16 * 16;
     return L;
 }
+
+// LDS for the per-block counts of the frequent words (hot words) and the
+// fewest such words worth it
+constexpr int32_t HOT_BYTES = 16384;
+constexpr int32_t HOT_MIN = 16;
+constexpr int32_t HOT_MAX = HOT_BYTES / 4;
 
 // ST_TOKENS counts z-step launches since the last statistics read
 constexpr int32_t LG_TABLE = 65536;

@@ -884,6 +884,8 @@ struct ZArgs {
     int32_t group_bytes;       // count table and topic list of one group
     int32_t wave_bytes;        // the groups of one wave
     int32_t r_bytes;           // the block's copy of R_k, at the start of LDS
+    int32_t n_hot;             // frequent words counted per block in LDS (0: none)
+    int32_t hot_off;           // their counters' byte offset in LDS
     int32_t *queue;
     unsigned long long *stats;
     double *ll_doc;         // per-document log-joint terms (or null)
@@ -1765,9 +1767,11 @@ __device__ __forceinline__ bool stage_token_z(const DevModel &M, TokenZ *tok, in
     return sure;
 }
 
-template <int G, typename CT>
+// HOT: the frequent words' count increments go to the block's counters in
+// LDS (hist), the others' to n
+template <int G, typename CT, bool HOT>
 __device__ void z_step_item(const ZArgs &a, const WorkItem &w, const float *R, uint8_t *wave_base,
-                            TokenZ *wave_tok, unsigned long long *wave_cnt)
+                            TokenZ *wave_tok, unsigned long long *wave_cnt, uint32_t *hist)
 {
     constexpr int NG = 64 / G;
     const int lane = __lane_id();
@@ -1842,10 +1846,13 @@ __device__ void z_step_item(const ZArgs &a, const WorkItem &w, const float *R, u
             }
             __builtin_amdgcn_wave_barrier();
             // the count rebuild: each lane adds its own token, once the
-            // block's draws are done
+            // block's draws are done (a frequent word's into the block's
+            // counters in LDS, added to n when the kernel ends)
             if (valid) {
                 __builtin_nontemporal_store((uint16_t)znew, a.c.z + i);
-                atomicAdd(&M.n[(uint32_t)wv * (uint32_t)M.K + (uint32_t)znew], 1);
+                const int32_t h = HOT ? M.hot[wv] : -1;
+                if (HOT && h >= 0) atomicAdd(&hist[(uint32_t)h * (uint32_t)M.K + (uint32_t)znew], 1u);
+                else atomicAdd(&M.n[(uint32_t)wv * (uint32_t)M.K + (uint32_t)znew], 1);
             }
         }
         if (g == 0) {
@@ -1874,7 +1881,7 @@ __device__ void z_step_item(const ZArgs &a, const WorkItem &w, const float *R, u
 // latency, more than 96 registers would spill in the draw loop.  Groups of
 // 8 keep 8 b-terms per lane and their LDS allows 2 waves per SIMD, so they
 // take the registers instead.
-template <int G, typename CT>
+template <int G, typename CT, bool HOT>
 __global__ void __launch_bounds__(256, (G == 8 ? 2 : 5)) z_step_kernel(ZArgs a)
 {
     extern __shared__ __align__(16) uint8_t z_lds[];
@@ -1882,6 +1889,10 @@ __global__ void __launch_bounds__(256, (G == 8 ? 2 : 5)) z_step_kernel(ZArgs a)
     // memory)
     float *R = (float *)z_lds;
     for (int32_t k = threadIdx.x; k < a.m.K; k += blockDim.x) R[k] = (float)a.m.Rd[k];
+    // the block's counters of the frequent words' increments
+    uint32_t *hist = (uint32_t *)(z_lds + a.hot_off);
+    const int32_t n_hist = HOT ? a.n_hot * a.m.K : 0;
+    for (int32_t i = threadIdx.x; i < n_hist; i += blockDim.x) hist[i] = 0u;
     __syncthreads();
     const int wave = threadIdx.x >> 6;
     uint8_t *blk = z_lds + a.r_bytes;
@@ -1900,7 +1911,7 @@ __global__ void __launch_bounds__(256, (G == 8 ? 2 : 5)) z_step_kernel(ZArgs a)
         // a private copy: a reference into global memory would be reloaded
         // after every store of the item (stores may alias it)
         const WorkItem w = a.items[item];
-        z_step_item<G, CT>(a, w, R, wave_base, wave_tok, wave_cnt);
+        z_step_item<G, CT, HOT>(a, w, R, wave_base, wave_tok, wave_cnt, hist);
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -1909,6 +1920,16 @@ __global__ void __launch_bounds__(256, (G == 8 ? 2 : 5)) z_step_kernel(ZArgs a)
         const int l = __lane_id();
         const int idx = l == 0 ? ST_SUM_J : (l == 1 ? ST_SUM_A : (l == 2 ? ST_DEGENERATE : (l == 3 ? ST_SUM_JB : ST_FALLBACK)));
         if (v) atomicAdd(&a.stats[idx], v);
+    }
+    if (HOT) {
+        // every wave of the block is done: add the block's counters to n
+        __syncthreads();
+        const int32_t K = a.m.K;
+        for (int32_t i = threadIdx.x; i < n_hist; i += blockDim.x) {
+            const uint32_t c = hist[i];
+            const int32_t h = i / K;
+            if (c) atomicAdd(&a.m.n[(uint32_t)a.m.hot_word[h] * (uint32_t)K + (uint32_t)(i - h * K)], (int32_t)c);
+        }
     }
 }
 
@@ -2181,18 +2202,34 @@ hipError_t launch_z_class(const DevCorpus &c, const DevModel &m, int32_t group, 
     a.group_bytes = L.group_bytes;
     a.wave_bytes = L.wave_bytes;
     a.r_bytes = L.r_bytes;
-    const size_t lds = (size_t)a.r_bytes + 4 * ((size_t)a.wave_bytes + 64 * sizeof(TokenIn) + 40);
-    auto launch = [&](auto kernel) -> hipError_t {
+    size_t lds = ((size_t)a.r_bytes + 4 * ((size_t)a.wave_bytes + 64 * sizeof(TokenIn) + 40) + 15) / 16 * 16;
+    a.n_hot = 0;
+    a.hot_off = (int32_t)lds;
+    auto launch = [&](auto kernel, auto kernel_hot) -> hipError_t {
         // persistent: exactly the blocks the device holds at once, and no
         // more waves than work items (a wave takes one item at a time)
         int per_cu = 0;
         hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, lds);
         if (e != hipSuccess) return e;
+        bool hot = false;
+        if (m.n_hot > 0) {
+            // the frequent words' counters in LDS, unless they cost blocks
+            const size_t with = lds + (size_t)m.n_hot * m.K * 4;
+            int per_cu_hot = 0;
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_hot, kernel_hot, 256, with);
+            if (e != hipSuccess) return e;
+            if (per_cu_hot == per_cu) {
+                a.n_hot = m.n_hot;
+                lds = with;
+                hot = true;
+            }
+        }
         if (per_cu <= 0) return hipErrorInvalidConfiguration;  // the block's LDS exceeds the CU's
         int64_t blocks = (int64_t)per_cu * (n_cu > 0 ? n_cu : 1);
         const int64_t need = ((int64_t)n_items + 3) / 4;
         if (blocks > need) blocks = need;
-        kernel<<<(unsigned)blocks, 256, lds, s>>>(a);
+        if (hot) kernel_hot<<<(unsigned)blocks, 256, lds, s>>>(a);
+        else kernel<<<(unsigned)blocks, 256, lds, s>>>(a);
         return hipGetLastError();
     };
     if (group == 1) {
@@ -2208,13 +2245,13 @@ hipError_t launch_z_class(const DevCorpus &c, const DevModel &m, int32_t group, 
         return hipGetLastError();
     }
     if (narrow) {
-        if (group == 32) return launch(z_step_kernel<32, uint8_t>);
-        if (group == 16) return launch(z_step_kernel<16, uint8_t>);
-        return launch(z_step_kernel<8, uint8_t>);
+        if (group == 32) return launch(z_step_kernel<32, uint8_t, false>, z_step_kernel<32, uint8_t, true>);
+        if (group == 16) return launch(z_step_kernel<16, uint8_t, false>, z_step_kernel<16, uint8_t, true>);
+        return launch(z_step_kernel<8, uint8_t, false>, z_step_kernel<8, uint8_t, true>);
     }
-    if (group == 64) return launch(z_step_kernel<64, uint16_t>);
-    if (group == 32) return launch(z_step_kernel<32, uint16_t>);
-    return launch(z_step_kernel<16, uint16_t>);
+    if (group == 64) return launch(z_step_kernel<64, uint16_t, false>, z_step_kernel<64, uint16_t, true>);
+    if (group == 32) return launch(z_step_kernel<32, uint16_t, false>, z_step_kernel<32, uint16_t, true>);
+    return launch(z_step_kernel<16, uint16_t, false>, z_step_kernel<16, uint16_t, true>);
 }
 
 // ---------------------------------------------------------------------------
