@@ -124,7 +124,10 @@ void pulda_plan_destroy(pulda_plan *plan);
  * while the plan uses them.  Synchronises: validates the content on the
  * device (PULDA_ERR_CORPUS for bad offsets, word ids, or a document longer
  * than 65535 tokens) and orders documents by length for the z-step
- * schedule. */
+ * schedule.  When K <= 256 it also counts the words of the first 8M tokens
+ * on the host and keeps the most frequent ones (as many as 4096 / K), whose
+ * count increments the z-step gathers per block before adding them to n
+ * (the counts are the same). */
 pulda_status pulda_corpus_upload(pulda_plan *plan, const int64_t *doc_off_dev, const int32_t *words_dev,
                                  void *stream);
 
