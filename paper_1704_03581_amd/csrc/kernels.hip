@@ -1406,7 +1406,7 @@ __device__ __forceinline__ void lane_terms_f32(const DevModel &M, const uint16_t
     }
 }
 
-template <int G, bool DOC, typename CT, int KP, bool WIN>
+template <int G, bool DOC, typename CT, int KP, bool WIN, bool EARLY>
 __device__ __forceinline__ int32_t b_part_f32(const DevModel &M, const TokenZ &tk, DocState<CT, WIN> &S,
                                               const float *Rf, const int g)
 {
@@ -1420,14 +1420,14 @@ __device__ __forceinline__ int32_t b_part_f32(const DevModel &M, const TokenZ &t
     const int32_t first = pad + (int32_t)__umul24((uint32_t)g, (uint32_t)q);
     int32_t kk[KP];
     float bf[KP];
-    lane_terms_f32<KP, DOC, CT, WIN>(M, S.lst, g16o, tk.vk, Rf, S.mt, pad, first, 0, nl, kk, bf);
+    lane_terms_f32<KP, DOC, CT, EARLY>(M, S.lst, g16o, tk.vk, Rf, S.mt, pad, first, 0, nl, kk, bf);
     float p = 0.0f;
 #pragma unroll
     for (int u = 0; u < KP; ++u) p += bf[u];
     for (int32_t base = KP; base < nl; base += KP) {
         int32_t k2[KP];
         float f2[KP];
-        lane_terms_f32<KP, DOC, CT, WIN>(M, S.lst, g16o, tk.vk, Rf, S.mt, pad, first, base, nl, k2, f2);
+        lane_terms_f32<KP, DOC, CT, EARLY>(M, S.lst, g16o, tk.vk, Rf, S.mt, pad, first, base, nl, k2, f2);
 #pragma unroll
         for (int u = 0; u < KP; ++u) p += f2[u];
     }
@@ -1462,7 +1462,7 @@ __device__ __forceinline__ int32_t b_part_f32(const DevModel &M, const TokenZ &t
         for (int32_t base = KP; base < nl && kf < 0; base += KP) {
             int32_t k2[KP];
             float f2[KP];
-            lane_terms_f32<KP, DOC, CT, WIN>(M, S.lst, g16o, tk.vk, Rf, S.mt, pad, first, base, nl, k2, f2);
+            lane_terms_f32<KP, DOC, CT, EARLY>(M, S.lst, g16o, tk.vk, Rf, S.mt, pad, first, base, nl, k2, f2);
 #pragma unroll
             for (int u = 0; u < KP; ++u) {
                 const float c2 = c + f2[u];
@@ -1584,7 +1584,9 @@ __device__ __forceinline__ int32_t b_part_fp64(uint32_t *ckg, uint16_t *g16, flo
 // draw_token with the b-part in fp32 (b_part_f32), the fp64 b_part for the
 // draws it leaves undecided: the same results.  Rf (LDS) holds fp32(R_k);
 // the fp64 path reads R_k from global memory.
-template <int G, typename CT, bool WIN>
+// EARLY: each b-term round's LDS reads issued before its gathered draws are
+// used (the z-step's choice; the fold-in kernel draws faster without)
+template <int G, typename CT, bool WIN, bool EARLY = WIN>
 __device__ __forceinline__ int32_t draw_token_f32(const DevModel &M, const TokenZ &tk, DocState<CT, WIN> &S,
                                                   const float *Rf, const int g, const int32_t side_ratio,
                                                   ZCount32 &cnt)
@@ -1615,13 +1617,13 @@ __device__ __forceinline__ int32_t draw_token_f32(const DevModel &M, const Token
         const bool over2 = __builtin_amdgcn_ballot_w64(J > (KP / 2) * G) != 0;
         const bool over3 = __builtin_amdgcn_ballot_w64(J > (3 * KP / 4) * G) != 0;
         if (doc)
-            knew = !over2 ? b_part_f32<G, true, CT, KP / 2>(M, tk, S, Rf, g)
-                          : (!over3 ? b_part_f32<G, true, CT, 3 * KP / 4>(M, tk, S, Rf, g)
-                                    : b_part_f32<G, true, CT, KP>(M, tk, S, Rf, g));
+            knew = !over2 ? b_part_f32<G, true, CT, KP / 2, WIN, EARLY>(M, tk, S, Rf, g)
+                          : (!over3 ? b_part_f32<G, true, CT, 3 * KP / 4, WIN, EARLY>(M, tk, S, Rf, g)
+                                    : b_part_f32<G, true, CT, KP, WIN, EARLY>(M, tk, S, Rf, g));
         else
-            knew = !over2 ? b_part_f32<G, false, CT, KP / 2>(M, tk, S, Rf, g)
-                          : (!over3 ? b_part_f32<G, false, CT, 3 * KP / 4>(M, tk, S, Rf, g)
-                                    : b_part_f32<G, false, CT, KP>(M, tk, S, Rf, g));
+            knew = !over2 ? b_part_f32<G, false, CT, KP / 2, WIN, EARLY>(M, tk, S, Rf, g)
+                          : (!over3 ? b_part_f32<G, false, CT, 3 * KP / 4, WIN, EARLY>(M, tk, S, Rf, g)
+                                    : b_part_f32<G, false, CT, KP, WIN, EARLY>(M, tk, S, Rf, g));
         if (__builtin_amdgcn_ballot_w64(knew == -2) != 0) {
             // a draw too close to a boundary for fp32: the fp64 b-part
             const int32_t k64 = doc ? b_part_fp64<G, true, CT, KP>(M.ckg, M.g16, M.phid, M.Rd, M.sigma_a,
@@ -2624,8 +2626,10 @@ template <int G, bool SYM>
 __device__ void foldin_slot(const DevModel &M, const DevFoldin &F, int32_t sid, const float *Rf, uint16_t *mt,
                             TokenZ *tok)
 {
-    const int32_t Kp = (M.K + 1) & ~1;
-    DocState<uint16_t> S;
+    // the count table (K u16, rounded to 16 bytes), then the topic list with
+    // room for its windows (launch_foldin_step sizes the same layout)
+    const int32_t Kp = (M.K + 7) & ~7;
+    DocState<uint16_t, true> S;
     S.mt = mt;
     S.lst = mt + Kp;
     const int lane = __lane_id();
@@ -2695,7 +2699,7 @@ __device__ void foldin_slot(const DevModel &M, const DevFoldin &F, int32_t sid, 
             // the decision, the fp64 b-part elsewhere (the same results)
             for (int jj = 0; jj < nb; ++jj) {
                 const TokenZ tk = tok[jj];
-                int32_t k = draw_token_f32<G, uint16_t>(M, tk, S, Rf, g, 1, st);
+                int32_t k = draw_token_f32<G, uint16_t, true, false>(M, tk, S, Rf, g, 1, st);
                 if (k < 0) k = -1 - k;
                 if (g == jj) znew = k;
             }
@@ -2769,9 +2773,12 @@ hipError_t launch_foldin_step(const DevModel &m, const DevFoldin &f, const int32
                               hipStream_t s)
 {
     if (n_active == 0) return hipSuccess;
-    // per group (u16 units): the count table, then the topic list, K
-    // entries each (rounded to keep the next table 4-byte aligned)
-    const int per_group = 2 * ((m.K + 1) & ~1);
+    // per group (u16 units): the count table (K entries), then the topic
+    // list (K entries, at least W slots a lane and W more for its windows),
+    // each rounded to 16 bytes
+    const int32_t W = f.group == 16 ? 8 : 4;   // the list's window (slots per lane)
+    const int32_t lcap = m.K > W * f.group + W ? m.K : W * f.group + W;
+    const int per_group = ((m.K + 7) & ~7) + ((lcap + 7) & ~7);
     const int ngw = 64 / f.group;
     const int64_t waves = (n_active + ngw - 1) / ngw;
     const unsigned blocks = (unsigned)((waves + 3) / 4);
