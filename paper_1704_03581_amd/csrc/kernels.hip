@@ -2822,8 +2822,10 @@ template <int G>
 __device__ void ltr_particle(const DevModel &M, const DevHeldout &H, int64_t d, int32_t r, const float *Rf,
                              uint16_t *mt, TokenZ *tok)
 {
-    const int32_t Kp = (M.K + 1) & ~1;
-    DocState<uint16_t> S;
+    // the count table (K u16, rounded to 16 bytes), then the topic list with
+    // room for its windows (launch_heldout sizes the same layout)
+    const int32_t Kp = (M.K + 7) & ~7;
+    DocState<uint16_t, true> S;
     S.mt = mt;
     S.lst = mt + Kp;
     S.L = 0;
@@ -2853,6 +2855,8 @@ __device__ void ltr_particle(const DevModel &M, const DevHeldout &H, int64_t d, 
     }
     if (r == 0 && g == 0) H.kept[d] = nk;
     for (int32_t k = g; k < Kp; k += G) mt[k] = 0;
+    // the empty list: every window slot holds the padding value
+    for (int32_t j = g; j < win_of<G>() * G + win_of<G>(); j += G) S.lst[j] = (uint16_t)LIST_PAD;
     __threadfence();
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -2878,7 +2882,7 @@ __device__ void ltr_particle(const DevModel &M, const DevHeldout &H, int64_t d, 
             const int nb = n - q0 < G ? n - q0 : G;
             for (int jj = 0; jj < nb; ++jj) {
                 const TokenZ tk = tok[jj];
-                int32_t k = draw_token_f32<G, uint16_t>(M, tk, S, Rf, g, 1, st32);
+                int32_t k = draw_token_f32<G, uint16_t, true, false>(M, tk, S, Rf, g, 1, st32);
                 if (k < 0) k = -1 - k;
                 if (g == jj) znew = k;
             }
@@ -2954,7 +2958,12 @@ __global__ void __launch_bounds__(256) ltr_finish_kernel(DevHeldout H)
 hipError_t launch_heldout(const DevModel &m, const DevHeldout &h, hipStream_t s)
 {
     if (h.D == 0) return hipSuccess;
-    const int per_group = 2 * ((m.K + 1) & ~1);
+    // per particle (u16 units): the count table (K entries), then the topic
+    // list (K entries, at least W slots a lane and W more for its windows),
+    // each rounded to 16 bytes
+    const int32_t W = h.group == 16 ? 8 : 4;
+    const int32_t lcap = m.K > W * h.group + W ? m.K : W * h.group + W;
+    const int per_group = ((m.K + 7) & ~7) + ((lcap + 7) & ~7);
     const int ngw = 64 / h.group;
     const int64_t groups = h.D * h.R;
     const int64_t waves = (groups + ngw - 1) / ngw;
